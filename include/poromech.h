@@ -1,0 +1,207 @@
+/*
+ * poromech.h -- C ABI of the MI355X (gfx950) solver for one backward-Euler
+ * step of hybridized three-field poromechanics: Q1 displacement u, P0 cell
+ * pressure p, face traces pi of the hybridized lowest-order Raviart-Thomas
+ * Darcy velocity, with macro-element pressure-jump stabilization.
+ *
+ * The linear system solved per step is the stabilized, statically condensed
+ * block system (paper: Frigo, Castelletto, Ferronato, White, "Efficient
+ * solvers for hybridized three-field mixed finite element coupled
+ * poromechanics", eq. stab_A):
+ *
+ *     [ A_uu   A_up              0        ] [u ]   [f_u ]
+ *     [ A_pu   Abar_pp + A_stab  dt A_ppi ] [p ] = [f_p ]
+ *     [ 0      A_pip             A_pipi   ] [pi]   [f_pi]
+ *
+ * solved by right-preconditioned flexible GMRES with the block upper
+ * triangular preconditioner of eq. hybridPrec (B~_p diagonal of eq. app_Bp,
+ * aggregation-AMG V-cycles for A_uu and C~_pi).
+ *
+ * Mesh: structured nx x ny x nz hexahedra (each count even: the stabilization
+ * works on aligned 2x2x2 macro-elements), trilinear geometry given by node
+ * coordinates.  Numbering:
+ *   node (i,j,k)   i + (nx+1)*(j + (ny+1)*k)
+ *   cell (i,j,k)   i + nx*(j + ny*k)
+ *   faces          x-normal (i<=nx,j<ny,k<nz) i+(nx+1)*(j+ny*k), then y-normal
+ *                  (offset n_fx) i+nx*(j+(ny+1)*k), then z-normal
+ *                  (offset n_fx+n_fy) i+nx*(j+ny*k)
+ *   u dof          3*node + component
+ *   system vector  [u (n_u) ; p (n_p = cells) ; pi (n_pi = faces)]
+ * Boundary conditions: bottom (k=0) nodes fixed (u = 0); top (k=nz) faces
+ * drained (pi = p_top) and loaded by a uniform traction; all other boundary
+ * parts traction-free and no-flow.  PM_BC_ROLLERS additionally fixes the
+ * normal displacement of the four lateral sides.  Dirichlet dofs stay in the
+ * system as identity rows and columns, so sizes match the paper's table
+ * tab:grids.
+ *
+ * Conventions for every entry point:
+ *   - return 0 on success or a negative PM_E* code; the message of the last
+ *     error is returned by pm_last_error(ctx).  No C++ exception crosses it.
+ *   - "device" pointers are HIP device (or managed) memory owned by the
+ *     caller; "host or device" inputs are copied (hipMemcpyDefault).
+ *   - every kernel is enqueued on the stream passed to pm_setup; calls that
+ *     return results to the host (pm_solve, pm_solve_transpose) synchronize
+ *     that stream; the others are asynchronous.
+ *   - a context is not thread-safe; use one context per host thread.
+ */
+#ifndef POROMECH_H
+#define POROMECH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PM_OK = 0,
+  PM_EINVAL = -1,       /* invalid argument (odd dims, non-positive field, det J <= 0, null) */
+  PM_ENOMEM = -2,       /* device allocation failed */
+  PM_EHIP = -3,         /* HIP runtime error (message in pm_last_error) */
+  PM_ENOCONV = -4,      /* max_it reached; outputs hold the last iterate, info filled */
+  PM_EBREAKDOWN = -5,   /* NaN/Inf in a reduction or Krylov breakdown */
+  PM_ESTATE = -6,       /* call out of order (e.g. solve before assemble) */
+  PM_EINTERNAL = -7     /* internal capacity exceeded (e.g. AMG row too wide) */
+};
+
+enum { PM_BC_COLUMN = 0, PM_BC_ROLLERS = 1 };
+
+typedef struct pm_ctx pm_ctx;
+
+typedef struct {
+  int32_t nx, ny, nz;        /* cells per axis, each >= 2 and even */
+  const double* coords;      /* host or device, (nx+1)(ny+1)(nz+1) x 3, node order; NULL: uniform box */
+  double Lx, Ly, Lz;         /* box size used when coords == NULL */
+} pm_mesh;
+
+typedef struct {
+  const double* E;           /* host or device, n_cells, Young's modulus > 0 */
+  const double* kappa;       /* host or device, n_cells x 3, diagonal permeability > 0 */
+  double nu;                 /* Poisson ratio in (0, 0.5) */
+  double biot;               /* Biot coefficient b */
+  double S_eps;              /* constrained specific storage >= 0 */
+  double mu;                 /* fluid viscosity > 0 */
+} pm_material;
+
+typedef struct {
+  double traction_top[3];    /* traction on the top face (e.g. {0,0,-1}) */
+  double p_top;              /* prescribed face pressure on the top face */
+  int32_t kind;              /* PM_BC_COLUMN or PM_BC_ROLLERS */
+} pm_bc;
+
+typedef struct {
+  double rtol;               /* FGMRES stop: ||b - A x||_2 <= rtol ||b||_2 */
+  int32_t restart;           /* FGMRES restart length m (>= 1) */
+  int32_t max_it;            /* iteration cap */
+  int32_t precond_fp32;      /* 1: AMG hierarchies, V-cycles and Schur apply in FP32 */
+  int32_t stabilize;         /* 1: add the macro-element pressure-jump term */
+  int32_t increment_stab;    /* 1: stabilization acts on p_n - p_{n-1} (RHS term A_stab p_{n-1}) */
+  int32_t cheb_degree;       /* Chebyshev smoother degree per pre/post smoothing (>= 1) */
+  int32_t coarse_max;        /* AMG: stop coarsening below this many block rows */
+  double theta_u;            /* AMG strength threshold, displacement block */
+  double theta_pi;           /* AMG strength threshold, face-pressure Schur block */
+} pm_opts;
+
+typedef struct {
+  int32_t iters;             /* FGMRES iterations of the last solve */
+  int32_t levels_u, levels_pi;
+  double relres_est;         /* Givens residual estimate / ||b|| */
+  double relres_true;        /* ||b - A x|| / ||b|| recomputed in FP64 */
+  double t_asm, t_setup, t_solve;   /* seconds: assembly, AMG + B~/C~ setup, Krylov solve */
+  double opcx_u, opcx_pi;    /* AMG operator complexities */
+} pm_info;
+
+/* Default options: rtol 1e-8, restart 100, max_it 1000, FP64, stabilize,
+ * increment form, Chebyshev degree 2, coarse_max 64, theta 0 / 0.08. */
+void pm_default_opts(pm_opts* opts);
+
+/* Create a context: validates and copies mesh coordinates and material
+ * fields to the device and allocates the operator storage.  dt > 0.
+ * stream: a hipStream_t (NULL = default stream).  On error *out is NULL. */
+int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, double dt,
+             const pm_opts* opts, void* stream, pm_ctx** out);
+
+/* Element kernels (Q1 stiffness and coupling: Appendix A eq. MFE_matrix; RT0
+ * mass and its static condensation: eq. hmfeSys/A_33H), macro-element
+ * stabilization (eq. J_def, 3D beta_M of Sec. 3), global assembly with the
+ * Dirichlet identity rows, B~_p (eq. app_Bp), C~_pi (Sec. 4) and both AMG
+ * hierarchies.  Fails with PM_EINVAL on an inverted hexahedron. */
+int pm_assemble(pm_ctx* ctx);
+
+/* Change dt: rebuilds the dt-dependent blocks, B~_p, C~_pi and the C~_pi
+ * hierarchy; the A_uu hierarchy is reused. */
+int pm_set_dt(pm_ctx* ctx, double dt);
+
+/* Replace E (n_cells) and/or kappa (n_cells x 3) (host or device; NULL keeps
+ * the current field) and re-assemble everything. */
+int pm_update_material(pm_ctx* ctx, const double* E, const double* kappa);
+
+/* Right-hand side of the step (Appendix A eq. MHFE_vector with the f~_n of
+ * Sec. 2.1, no fluid source): traction load, A_pu u_prev + S_eps|T| p_prev
+ * (+ A_stab p_prev in increment form), Dirichlet values and lifting.
+ * u_prev (n_u), p_prev (n_p) device, may be NULL (state at rest);
+ * b device, N = n_u + n_p + n_pi. */
+int pm_build_rhs(pm_ctx* ctx, const double* u_prev, const double* p_prev, double* b);
+
+/* Solve A_H x = b (device b, N).  Zero initial guess.  Outputs (device,
+ * caller-owned): u (n_u), pi (n_pi), p (n_p); any may be NULL.  info may be
+ * NULL.  Returns PM_ENOCONV if max_it is reached (outputs = last iterate). */
+int pm_solve(pm_ctx* ctx, const double* b, double* u, double* pi, double* p, pm_info* info);
+
+/* Solve A_H^T lam = g (adjoint) with FGMRES preconditioned by M^T (block
+ * lower triangular: forward substitution u -> p -> pi, same V-cycles).
+ * g device, N; outputs as in pm_solve. */
+int pm_solve_transpose(pm_ctx* ctx, const double* g, double* lu, double* lpi, double* lp,
+                       pm_info* info);
+
+/* Accumulate per-cell gradients of a scalar loss L:
+ *   dlogk[T] += -lam^T (dA/dlog kappa_T) x
+ *   dlogE[T] += -lam^T (dA/dlog E_T) x + lam^T (db/dlog E_T)
+ * where lam solves A_H^T lam = dL/dx (Dirichlet rows of lam ignored), x is
+ * the step solution [u;p;pi] and p_prev the previous pressure (NULL = 0;
+ * it enters only through the increment-form stabilization).  All device;
+ * lam, x: N; p_prev: n_p; dlogk, dlogE: n_p (accumulated, not cleared). */
+int pm_grad(pm_ctx* ctx, const double* lam, const double* x, const double* p_prev,
+            double* dlogk, double* dlogE);
+
+/* Adjoint coupling of consecutive steps: c_u += -A_up lam_p, c_p +=
+ * (S_eps|T| + A_stab) lam_p (increment form), i.e. (d b_{n+1}/d x_n)^T lam
+ * for lam = lam_{n+1}; lam device N, c device N (accumulated). */
+int pm_rhs_adjoint(pm_ctx* ctx, const double* lam, double* c);
+
+/* Cell fluxes w_T = M_T^-1 (p_T 1 - pi_T), outward per local face
+ * (-x,+x,-y,+y,-z,+z); p (n_p), pi (n_pi, holding the drained values), w
+ * (n_p x 6, cell-major) device. */
+int pm_reconstruct_w(pm_ctx* ctx, const double* p, const double* pi, double* w);
+
+/* Operator applications for testing and benchmarking, all device, FP64:
+ *   PM_OP_AH       y = A_H x            (N -> N)
+ *   PM_OP_AHT      y = A_H^T x          (N -> N)
+ *   PM_OP_MINV     y = M^-1 x           (N -> N, AMG inner solves)
+ *   PM_OP_MINVT    y = M^-T x           (N -> N)
+ *   PM_OP_CPI      y = C~_pi x          (n_pi -> n_pi, assembled, Dirichlet rows identity)
+ *   PM_OP_BP       y = B~_p x           (n_p -> n_p, diagonal)
+ *   PM_OP_AUU      y = A_uu x           (n_u -> n_u, assembled, Dirichlet rows identity)
+ *   PM_OP_VCYCLE_U y = one V-cycle for A_uu applied to x (zero initial guess)
+ *   PM_OP_VCYCLE_PI y = one V-cycle for C~_pi applied to x */
+enum { PM_OP_AH = 0, PM_OP_AHT = 1, PM_OP_MINV = 2, PM_OP_MINVT = 3, PM_OP_CPI = 4,
+       PM_OP_BP = 5, PM_OP_AUU = 6, PM_OP_VCYCLE_U = 7, PM_OP_VCYCLE_PI = 8 };
+int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
+
+/* Sizes: out[0..5] = n_u, n_p, n_pi, N, n_nodes, n_macro. */
+int pm_sizes(const pm_ctx* ctx, int64_t* out);
+
+/* Info of the last solve and the last assembly timings. */
+int pm_get_info(const pm_ctx* ctx, pm_info* info);
+
+/* Message of the last error of ctx (or of the last failed pm_setup if ctx
+ * is NULL).  Never NULL. */
+const char* pm_last_error(const pm_ctx* ctx);
+
+/* Free every device buffer of ctx (after synchronizing its stream). */
+void pm_destroy(pm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POROMECH_H */

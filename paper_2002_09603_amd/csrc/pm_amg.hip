@@ -1,0 +1,894 @@
+// Smoothed-aggregation AMG for the two SPD inner blocks of the block
+// triangular preconditioner: A_uu (3x3 node blocks, translations per
+// displacement component as near kernel: the "separate displacement
+// component" variant) and C~_pi (scalar).  The paper uses PETSc GAMG and
+// hypre BoomerAMG (Sec. 5); this is the project's own GPU design:
+//
+//  setup per level: symmetric strength of connection on block norms ->
+//  distance-2 maximal independent set (Luby-type rounds on packed
+//  (state, hash, id) tuples) -> aggregates = roots + distance-1 + distance-2
+//  attachment -> tentative P (identity block per node) -> Jacobi-smoothed
+//  P = (I - 4/(3 lmax) D^-1 A) P_tent -> Galerkin A_c = P^T (A P) by SpGEMM;
+//  coarsest level inverted densely (Gauss-Jordan, FP64).
+//
+//  cycle: V(k,k) with Chebyshev(D^-1 A) smoothing (same polynomial before and
+//  after, so the cycle is a symmetric operator and serves M^T as well).
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+
+#include "pm_internal.h"
+
+namespace pm {
+
+void Level::free_all() {
+  A.free_all();
+  As.free_all();
+  P.free_all();
+  R.free_all();
+  dfree(dinv);
+  dfree(dinv32);
+  dfree(x);
+  dfree(b);
+  dfree(r);
+  dfree(d);
+  dfree(t);
+  dfree(xf);
+  dfree(bf);
+  dfree(rf);
+  dfree(df);
+  dfree(tf);
+  dinv = nullptr;
+  dinv32 = nullptr;
+  x = b = r = d = t = nullptr;
+  xf = bf = rf = df = tf = nullptr;
+}
+
+void Hierarchy::free_all() {
+  for (auto& l : L) l.free_all();
+  L.clear();
+  dfree(coarse_inv);
+  dfree(cwork);
+  coarse_inv = nullptr;
+  cwork = nullptr;
+  ncoarse = 0;
+}
+
+namespace {
+
+enum : uint8_t { kUnd = 1, kIn = 2, kOut = 0 };
+
+__device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+template <int BS>
+__device__ inline double block_norm(const double* v) {
+  double s = 0.0;
+  for (int q = 0; q < BS * BS; ++q) s += v[q] * v[q];
+  return sqrt(s);
+}
+
+// strength: strong[e] = 1 for off-diagonal |A_ij| >= theta sqrt(|A_ii||A_jj|), |A_ij| > 0
+template <int BS>
+__global__ void k_diag_norm(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ val, double* __restrict__ dn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (col[e] == i) v = block_norm<BS>(val + (size_t)e * BS * BS);
+  dn[i] = v;
+}
+
+template <int BS>
+__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                           const double* __restrict__ val, const double* __restrict__ dn, double theta,
+                           uint8_t* __restrict__ strong, uint8_t* __restrict__ state) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int ns = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int j = col[e];
+    uint8_t s = 0;
+    if (j != i) {
+      const double a = block_norm<BS>(val + (size_t)e * BS * BS);
+      s = (a > 0.0 && a >= theta * sqrt(dn[i] * dn[j])) ? 1 : 0;
+    }
+    strong[e] = s;
+    ns += s;
+  }
+  state[i] = ns > 0 ? kUnd : kOut;  // isolated rows (e.g. Dirichlet) are never aggregated
+}
+
+__device__ inline uint64_t pack_tuple(uint8_t st, int i, uint32_t salt) {
+  const uint64_t rank = st == kIn ? 2 : (st == kUnd ? 1 : 0);
+  const uint64_t pr = mix32((uint32_t)i * 2654435761u + salt) & 0x3FFFFFFFu;
+  return (rank << 62) | (pr << 32) | (uint32_t)i;
+}
+
+__global__ void k_mis_init(int n, const uint8_t* __restrict__ state, uint32_t salt, uint64_t* __restrict__ T0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) T0[i] = pack_tuple(state[i], i, salt);
+}
+
+__global__ void k_mis_max(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                          const uint8_t* __restrict__ strong, const uint64_t* __restrict__ Tin,
+                          uint64_t* __restrict__ Tout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t m = Tin[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (strong[e]) {
+      const uint64_t v = Tin[col[e]];
+      m = v > m ? v : m;
+    }
+  Tout[i] = m;
+}
+
+__global__ void k_mis_update(int n, const uint64_t* __restrict__ T0, const uint64_t* __restrict__ T2,
+                             uint8_t* __restrict__ state, int* __restrict__ und) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] != kUnd) return;
+  if (T2[i] == T0[i]) {
+    state[i] = kIn;
+  } else if ((T2[i] >> 62) == 2) {
+    state[i] = kOut;
+  } else {
+    atomicAdd(und, 1);
+  }
+}
+
+__global__ void k_root_flags(int n, const uint8_t* __restrict__ state, int* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = state[i] == kIn;
+}
+
+__global__ void k_agg_phase1(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                             const uint8_t* __restrict__ strong, const uint8_t* __restrict__ state,
+                             const int* __restrict__ root_id, int* __restrict__ agg1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a = -1;
+  if (state[i] == kIn) {
+    a = root_id[i];
+  } else {
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+      if (strong[e] && state[col[e]] == kIn) {
+        a = root_id[col[e]];
+        break;
+      }
+  }
+  agg1[i] = a;
+}
+
+template <int BS>
+__global__ void k_agg_phase2(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                             const double* __restrict__ val, const uint8_t* __restrict__ strong,
+                             const int* __restrict__ agg1, int* __restrict__ agg, int* __restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a = agg1[i];
+  if (a < 0) {
+    bool has_strong = false;
+    double best = -1.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      if (!strong[e]) continue;
+      has_strong = true;
+      const int j = col[e];
+      if (agg1[j] < 0) continue;
+      const double s = block_norm<BS>(val + (size_t)e * BS * BS);
+      if (s > best) {
+        best = s;
+        a = agg1[j];
+      }
+    }
+    if (has_strong && a < 0) atomicOr(status, kStatusCapacity);
+  }
+  agg[i] = a;
+}
+
+__global__ void k_count_aggregated(int n, const int* __restrict__ agg, int* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = agg[i] >= 0;
+}
+
+template <int BS>
+__global__ void k_ptent(int n, const int* __restrict__ agg, const int* __restrict__ rp, int* __restrict__ col,
+                        double* __restrict__ val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || agg[i] < 0) return;
+  const int e = rp[i];
+  col[e] = agg[i];
+  for (int a = 0; a < BS; ++a)
+    for (int b = 0; b < BS; ++b) val[(size_t)e * BS * BS + a * BS + b] = a == b ? 1.0 : 0.0;
+}
+
+// P = P_tent - omega D^-1 (A P_tent), in place on the pattern of A P_tent
+template <int BS>
+__global__ void k_smooth_p(int n, const int* __restrict__ agg, const double* __restrict__ dinv, double omega,
+                           const int* __restrict__ rp, const int* __restrict__ col, double* __restrict__ val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* D = dinv + (size_t)i * BS * BS;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    double* v = val + (size_t)e * BS * BS;
+    double o[BS * BS];
+    for (int a = 0; a < BS; ++a)
+      for (int b = 0; b < BS; ++b) {
+        double s = 0.0;
+        for (int t = 0; t < BS; ++t) s += D[a * BS + t] * v[t * BS + b];
+        o[a * BS + b] = -omega * s + ((col[e] == agg[i] && a == b) ? 1.0 : 0.0);
+      }
+    for (int q = 0; q < BS * BS; ++q) v[q] = o[q];
+  }
+}
+
+// filtered operator for prolongator smoothing: strong off-diagonal blocks
+// kept, weak ones lumped into the diagonal block (row sums preserved)
+__global__ void k_filter_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                               const uint8_t* __restrict__ strong, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) c += (col[e] == i) || strong[e];
+  cnt[i] = c;
+}
+
+template <int BS>
+__global__ void k_filter_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                              const double* __restrict__ val, const uint8_t* __restrict__ strong,
+                              const int* __restrict__ frp, int* __restrict__ fcol, double* __restrict__ fval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double lump[BS * BS];
+  for (int q = 0; q < BS * BS; ++q) lump[q] = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (col[e] != i && !strong[e])
+      for (int q = 0; q < BS * BS; ++q) lump[q] += val[(size_t)e * BS * BS + q];
+  int p = frp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const bool diag = col[e] == i;
+    if (!diag && !strong[e]) continue;
+    fcol[p] = col[e];
+    for (int q = 0; q < BS * BS; ++q) fval[(size_t)p * BS * BS + q] = val[(size_t)e * BS * BS + q] + (diag ? lump[q] : 0.0);
+    ++p;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions (sum of squares), two stages
+constexpr int kRedBlocks = 1024;
+
+template <class T>
+__global__ void __launch_bounds__(256) k_sumsq_part(const T* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = (double)x[i];
+    s += v * v;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ part, int np, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_rand_vec(int64_t n, double* __restrict__ x, uint32_t salt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (double)(mix32((uint32_t)i ^ salt) & 0xFFFFFF) / 16777216.0 + 0.5;
+}
+
+template <int BS>
+__global__ void k_dinv_apply_scaled(int n, const double* __restrict__ dinv, const double* __restrict__ y,
+                                    double scale, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* D = dinv + (size_t)i * BS * BS;
+  for (int a = 0; a < BS; ++a) {
+    double s = 0.0;
+    for (int b = 0; b < BS; ++b) s += D[a * BS + b] * y[(size_t)i * BS + b];
+    out[(size_t)i * BS + a] = s * scale;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cycle kernels (T = double or float)
+template <int BS, class T>
+__device__ inline void dinv_mul(const T* __restrict__ D, const T r[BS], T out[BS]) {
+  for (int a = 0; a < BS; ++a) {
+    T s = 0;
+    for (int b = 0; b < BS; ++b) s += D[a * BS + b] * r[b];
+    out[a] = s;
+  }
+}
+
+// first Chebyshev step from x = 0: d = D^-1 b / theta, x = d
+template <int BS, class T>
+__global__ void k_cheb_first(int n, const T* __restrict__ dinv, const T* __restrict__ b, T inv_theta,
+                             T* __restrict__ x, T* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T bi[BS], z[BS];
+  for (int a = 0; a < BS; ++a) bi[a] = b[(size_t)i * BS + a];
+  dinv_mul<BS, T>(dinv + (size_t)i * BS * BS, bi, z);
+  for (int a = 0; a < BS; ++a) {
+    const T v = z[a] * inv_theta;
+    d[(size_t)i * BS + a] = v;
+    x[(size_t)i * BS + a] = v;
+  }
+}
+
+// fused step: r = D^-1 (b - A x_in); d = c1 d + c2 r; x_out = x_in + d
+template <int BS, class T>
+__global__ void __launch_bounds__(256) k_cheb_step(int n, const int* __restrict__ sptr, const int* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ dinv,
+                                                   const T* __restrict__ b, const T* __restrict__ xin,
+                                                   T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = r / kSlice, lane = r % kSlice;
+  if (s * kSlice >= n) return;
+  const int e0 = sptr[s], e1 = sptr[s + 1];
+  T acc[BS];
+  for (int q = 0; q < BS; ++q) acc[q] = 0;
+  for (int c = e0; c < e1; ++c) {
+    const int j = col[(size_t)c * kSlice + lane];
+    const T* v = val + (size_t)c * BS * BS * kSlice + lane;
+    T xj[BS];
+    for (int q = 0; q < BS; ++q) xj[q] = xin[(size_t)j * BS + q];
+    for (int a = 0; a < BS; ++a)
+      for (int q = 0; q < BS; ++q) acc[a] += v[(a * BS + q) * kSlice] * xj[q];
+  }
+  if (r >= n) return;
+  T res[BS], z[BS];
+  for (int a = 0; a < BS; ++a) res[a] = b[(size_t)r * BS + a] - acc[a];
+  dinv_mul<BS, T>(dinv + (size_t)r * BS * BS, res, z);
+  for (int a = 0; a < BS; ++a) {
+    const size_t k = (size_t)r * BS + a;
+    const T dn = c1 * d[k] + c2 * z[a];
+    d[k] = dn;
+    xout[k] = xin[k] + dn;
+  }
+}
+
+// residual r = b - A x
+template <int BS, class T>
+__global__ void __launch_bounds__(256) k_residual(int n, const int* __restrict__ sptr, const int* __restrict__ col,
+                                                  const T* __restrict__ val, const T* __restrict__ b,
+                                                  const T* __restrict__ x, T* __restrict__ rr) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = r / kSlice, lane = r % kSlice;
+  if (s * kSlice >= n) return;
+  const int e0 = sptr[s], e1 = sptr[s + 1];
+  T acc[BS];
+  for (int q = 0; q < BS; ++q) acc[q] = 0;
+  for (int c = e0; c < e1; ++c) {
+    const int j = col[(size_t)c * kSlice + lane];
+    const T* v = val + (size_t)c * BS * BS * kSlice + lane;
+    T xj[BS];
+    for (int q = 0; q < BS; ++q) xj[q] = x[(size_t)j * BS + q];
+    for (int a = 0; a < BS; ++a)
+      for (int q = 0; q < BS; ++q) acc[a] += v[(a * BS + q) * kSlice] * xj[q];
+  }
+  if (r >= n) return;
+  for (int a = 0; a < BS; ++a) rr[(size_t)r * BS + a] = b[(size_t)r * BS + a] - acc[a];
+}
+
+// y = A x (ADD = false) or y += A x (ADD = true): restriction and prolongation
+template <int BS, class T, bool ADD>
+__global__ void __launch_bounds__(256) k_sell_apply(int n, const int* __restrict__ sptr, const int* __restrict__ col,
+                                                    const T* __restrict__ val, const T* __restrict__ xc,
+                                                    T* __restrict__ x) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = r / kSlice, lane = r % kSlice;
+  if (s * kSlice >= n) return;
+  const int e0 = sptr[s], e1 = sptr[s + 1];
+  T acc[BS];
+  for (int q = 0; q < BS; ++q) acc[q] = 0;
+  for (int c = e0; c < e1; ++c) {
+    const int j = col[(size_t)c * kSlice + lane];
+    const T* v = val + (size_t)c * BS * BS * kSlice + lane;
+    T xj[BS];
+    for (int q = 0; q < BS; ++q) xj[q] = xc[(size_t)j * BS + q];
+    for (int a = 0; a < BS; ++a)
+      for (int q = 0; q < BS; ++q) acc[a] += v[(a * BS + q) * kSlice] * xj[q];
+  }
+  if (r >= n) return;
+  for (int a = 0; a < BS; ++a) {
+    if (ADD)
+      x[(size_t)r * BS + a] += acc[a];
+    else
+      x[(size_t)r * BS + a] = acc[a];
+  }
+}
+
+// dense coarse level
+__global__ void k_dense_from_csr(int nb, int bs, const int* __restrict__ rp, const int* __restrict__ col,
+                                 const double* __restrict__ val, double* __restrict__ M, int ld) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    for (int a = 0; a < bs; ++a)
+      for (int b = 0; b < bs; ++b)
+        M[(size_t)(i * bs + a) * ld + (size_t)col[e] * bs + b] = val[(size_t)e * bs * bs + a * bs + b];
+}
+
+__global__ void k_set_identity_right(int n, double* __restrict__ M) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) M[(size_t)i * 2 * n + n + i] = 1.0;
+}
+
+// Gauss-Jordan step k, part 1: save column k, scale row k by its pivot
+__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k, double* __restrict__ M, double* __restrict__ colk,
+                                                  int* __restrict__ status) {
+  __shared__ double piv;
+  if (threadIdx.x == 0) {
+    piv = M[(size_t)k * 2 * n + k];
+    if (!(piv > 0.0)) atomicOr(status, kStatusBadPivot);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = (i == k) ? 0.0 : M[(size_t)i * 2 * n + k];
+  __syncthreads();
+  const double r = 1.0 / piv;
+  for (int j = threadIdx.x; j < 2 * n; j += blockDim.x) M[(size_t)k * 2 * n + j] *= r;
+}
+
+// part 2: eliminate column k from all other rows
+__global__ void k_gj_elim(int n, int k, double* __restrict__ M, const double* __restrict__ colk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t w = 2 * (int64_t)n;
+  if (t >= (int64_t)n * w) return;
+  const int i = (int)(t / w), j = (int)(t % w);
+  if (i == k) return;
+  M[t] -= colk[i] * M[(size_t)k * w + j];
+}
+
+__global__ void k_extract_inverse(int n, const double* __restrict__ M, double* __restrict__ inv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  const double a = M[(size_t)i * 2 * n + n + j], b = M[(size_t)j * 2 * n + n + i];
+  inv[t] = 0.5 * (a + b);
+}
+
+// y = Ainv x (one wavefront per row; x may be float or double)
+template <class T>
+__global__ void __launch_bounds__(256) k_dense_gemv(int n, const double* __restrict__ Ainv, const T* __restrict__ x,
+                                                    T* __restrict__ y) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += Ainv[(size_t)row * n + j] * (double)x[j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[row] = (T)s;
+}
+
+__global__ void k_to_float(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+template <int BS>
+void launch_cheb_first(hipStream_t s, int n, const double* dinv, const double* b, double it, double* x, double* d) {
+  k_cheb_first<BS, double><<<blocks_for(n), kBlock, 0, s>>>(n, dinv, b, it, x, d);
+}
+template <int BS>
+void launch_cheb_first(hipStream_t s, int n, const float* dinv, const float* b, float it, float* x, float* d) {
+  k_cheb_first<BS, float><<<blocks_for(n), kBlock, 0, s>>>(n, dinv, b, it, x, d);
+}
+
+// ---------------------------------------------------------------------------
+double sum_squares(hipStream_t s, const double* x, int64_t n, double* part, double* out_dev) {
+  k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(x, n, part);
+  k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, out_dev);
+  double h = 0.0;
+  PM_HIP(hipMemcpyAsync(&h, out_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+// lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start
+double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) {
+  const int64_t n = (int64_t)A.n * A.bs;
+  double* v = dalloc<double>(n);
+  double* w = dalloc<double>(n);
+  double* part = dalloc<double>(kRedBlocks);
+  double* out = dalloc<double>(1);
+  k_rand_vec<<<blocks_for(n), kBlock, 0, s>>>(n, v, 0x9e3779b9u);
+  double nv = std::sqrt(sum_squares(s, v, n, part, out));
+  double lam = 0.0;
+  for (int k = 0; k < its; ++k) {
+    sell_spmv(s, A, v, w);
+    if (A.bs == 3)
+      k_dinv_apply_scaled<3><<<blocks_for(A.n), kBlock, 0, s>>>(A.n, dinv, w, 1.0 / nv, v);
+    else
+      k_dinv_apply_scaled<1><<<blocks_for(A.n), kBlock, 0, s>>>(A.n, dinv, w, 1.0 / nv, v);
+    const double nn = std::sqrt(sum_squares(s, v, n, part, out));
+    lam = nn;  // ||D^-1 A v|| / ||v|| with ||v|| normalised
+    nv = nn;
+    if (!(nn > 0.0)) break;
+  }
+  dfree(v);
+  dfree(w);
+  dfree(part);
+  dfree(out);
+  return lam;
+}
+
+// lambda_max(D^-1 A) for a CSR operator (power iteration, fixed start)
+double estimate_lmax_csr(hipStream_t s, const Csr& A, const double* dinv, int its) {
+  Sell S;
+  csr_to_sell(s, A, S, false);
+  const double l = estimate_lmax(s, S, dinv, its);
+  S.free_all();
+  return l;
+}
+
+void dense_inverse(hipStream_t s, const Csr& A, Hierarchy& H) {
+  const int n = A.n * A.bs;
+  if (n > 6000) throw Error(PM_EINTERNAL, "AMG: coarsening stalled with " + std::to_string(n) + " unknowns left");
+  H.ncoarse = n;
+  double* M = dalloc<double>((int64_t)n * 2 * n);
+  double* colk = dalloc<double>(n);
+  int* status = dalloc<int>(1);
+  PM_HIP(hipMemsetAsync(M, 0, sizeof(double) * (size_t)n * 2 * n, s));
+  PM_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
+  k_dense_from_csr<<<blocks_for(A.n), kBlock, 0, s>>>(A.n, A.bs, A.rowptr, A.col, A.val, M, 2 * n);
+  k_set_identity_right<<<blocks_for(n), kBlock, 0, s>>>(n, M);
+  PM_CHECK_LAUNCH();
+  const int64_t tot = (int64_t)n * 2 * n;
+  for (int k = 0; k < n; ++k) {
+    k_gj_pivot<<<1, 256, 0, s>>>(n, k, M, colk, status);
+    k_gj_elim<<<blocks_for(tot), kBlock, 0, s>>>(n, k, M, colk);
+  }
+  PM_CHECK_LAUNCH();
+  H.coarse_inv = dalloc<double>((int64_t)n * n);
+  k_extract_inverse<<<blocks_for((int64_t)n * n), kBlock, 0, s>>>(n, M, H.coarse_inv);
+  PM_CHECK_LAUNCH();
+  H.cwork = dalloc<double>(2 * (int64_t)n);
+  int st = 0;
+  PM_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  dfree(M);
+  dfree(colk);
+  dfree(status);
+  if (st) throw Error(PM_EBREAKDOWN, "AMG: coarsest operator is not positive definite");
+}
+
+template <int BS>
+void aggregate(hipStream_t s, const Csr& A, double theta, int* agg, int* nagg_out, uint8_t* strong) {
+  const int n = A.n;
+  double* dn = dalloc<double>(n);
+  uint8_t* state = dalloc<uint8_t>(n);
+  uint64_t* T0 = dalloc<uint64_t>(n);
+  uint64_t* T1 = dalloc<uint64_t>(n);
+  uint64_t* T2 = dalloc<uint64_t>(n);
+  int* und = dalloc<int>(1);
+  k_diag_norm<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, dn);
+  k_strength<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, dn, theta, strong, state);
+  PM_CHECK_LAUNCH();
+  for (int round = 0; round < 1000; ++round) {
+    PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
+    k_mis_init<<<blocks_for(n), kBlock, 0, s>>>(n, state, 0x12345u, T0);
+    k_mis_max<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, T0, T1);
+    k_mis_max<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, T1, T2);
+    k_mis_update<<<blocks_for(n), kBlock, 0, s>>>(n, T0, T2, state, und);
+    PM_CHECK_LAUNCH();
+    int h = 0;
+    PM_HIP(hipMemcpyAsync(&h, und, sizeof(int), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (h == 0) break;
+    if (round == 999) throw Error(PM_EINTERNAL, "AMG: independent-set rounds did not terminate");
+  }
+  int* flags = dalloc<int>(n);
+  int* root_id = dalloc<int>(n + 1);
+  k_root_flags<<<blocks_for(n), kBlock, 0, s>>>(n, state, flags);
+  int nagg = 0;
+  exclusive_scan(s, flags, root_id, n, &nagg);
+  int* agg1 = dalloc<int>(n);
+  k_agg_phase1<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, state, root_id, agg1);
+  PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
+  k_agg_phase2<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, agg1, agg, und);
+  PM_CHECK_LAUNCH();
+  int st = 0;
+  PM_HIP(hipMemcpyAsync(&st, und, sizeof(int), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  for (void* p : {(void*)dn, (void*)state, (void*)T0, (void*)T1, (void*)T2, (void*)und,
+                  (void*)flags, (void*)root_id, (void*)agg1})
+    dfree(p);
+  if (st) throw Error(PM_EINTERNAL, "AMG: aggregation left a connected node unassigned");
+  *nagg_out = nagg;
+}
+
+template <int BS>
+void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Acoarse) {
+  const Csr& A = L.A;
+  const int n = A.n;
+  int* agg = dalloc<int>(n);
+  uint8_t* strong = dalloc<uint8_t>(A.nnzb);
+  int nagg = 0;
+  aggregate<BS>(s, A, prm.theta, agg, &nagg, strong);
+  // tentative prolongator
+  Csr Pt;
+  Pt.bs = BS;
+  Pt.n = n;
+  Pt.m = nagg;
+  int* f = dalloc<int>(n);
+  k_count_aggregated<<<blocks_for(n), kBlock, 0, s>>>(n, agg, f);
+  Pt.rowptr = dalloc<int>(n + 1);
+  int nnz = 0;
+  exclusive_scan(s, f, Pt.rowptr, n, &nnz);
+  Pt.nnzb = nnz;
+  Pt.col = dalloc<int>(nnz);
+  Pt.val = dalloc<double>((int64_t)nnz * BS * BS);
+  k_ptent<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, Pt.rowptr, Pt.col, Pt.val);
+  PM_CHECK_LAUNCH();
+  // filtered operator A_F (strong couplings, weak ones lumped on the diagonal)
+  Csr AF;
+  AF.bs = BS;
+  AF.n = AF.m = n;
+  k_filter_count<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, f);
+  AF.rowptr = dalloc<int>(n + 1);
+  int fnnz = 0;
+  exclusive_scan(s, f, AF.rowptr, n, &fnnz);
+  dfree(f);
+  AF.nnzb = fnnz;
+  AF.col = dalloc<int>(fnnz);
+  AF.val = dalloc<double>((int64_t)fnnz * BS * BS);
+  k_filter_fill<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, AF.rowptr, AF.col, AF.val);
+  PM_CHECK_LAUNCH();
+  dfree(strong);
+  double* dinvF = dalloc<double>((int64_t)n * BS * BS);
+  block_diag_inverse(s, AF, dinvF);
+  const double lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
+  // smoothed prolongator P = (I - 4/(3 lmax) D_F^-1 A_F) P_tent on the pattern of A_F P_tent
+  Csr P;
+  spgemm(s, AF, Pt, P);
+  Pt.free_all();
+  AF.free_all();
+  const double omega = 4.0 / (3.0 * lF);
+  k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, dinvF, omega, P.rowptr, P.col, P.val);
+  PM_CHECK_LAUNCH();
+  dfree(dinvF);
+  dfree(agg);
+  // Galerkin coarse operator
+  Csr AP, R;
+  spgemm(s, A, P, AP);
+  csr_transpose(s, P, R);
+  spgemm(s, R, AP, Acoarse);
+  AP.free_all();
+  csr_to_sell(s, P, L.P, prm.fp32);
+  csr_to_sell(s, R, L.R, prm.fp32);
+  P.free_all();
+  R.free_all();
+}
+
+void alloc_level_vectors(Level& L, bool fp32) {
+  const int64_t m = (int64_t)L.n * L.bs;
+  L.x = dalloc<double>(m);
+  L.b = dalloc<double>(m);
+  L.r = dalloc<double>(m);
+  L.d = dalloc<double>(m);
+  L.t = dalloc<double>(m);
+  if (fp32) {
+    L.xf = dalloc<float>(m);
+    L.bf = dalloc<float>(m);
+    L.rf = dalloc<float>(m);
+    L.df = dalloc<float>(m);
+    L.tf = dalloc<float>(m);
+  }
+}
+
+// Chebyshev smoothing of A x = b on level L, x0 = 0 if zero_init.
+// Returns the buffer holding the result (x or t).
+template <int BS, class T>
+T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T* x, T* t, T* d, bool zero_init,
+             const T* val, const T* dinv) {
+  const double lo = prm.cheb_lower * L.lmax, hi = prm.cheb_upper * L.lmax;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  const int n = L.n;
+  const int nth = L.As.nslices * kSlice;
+  T* cur = x;
+  T* nxt = t;
+  int k0 = 0;
+  if (zero_init) {
+    k_cheb_first<BS, T><<<blocks_for(n), kBlock, 0, s>>>(n, dinv, b, (T)(1.0 / theta), cur, d);
+    k0 = 1;
+  }
+  for (int k = k0; k < prm.cheb_degree; ++k) {
+    double c1, c2;
+    if (k == 0) {
+      c1 = 0.0;
+      c2 = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / delta;
+      rho = rn;
+    }
+    k_cheb_step<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, val, dinv, b, cur, nxt, d, (T)c1,
+                                                          (T)c2);
+    T* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  return cur;
+}
+
+template <int BS, class T>
+void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, const T* b, T* x);
+
+template <int BS, class T>
+struct LevelPtrs;
+template <int BS>
+struct LevelPtrs<BS, double> {
+  static double* X(Level& L) { return L.x; }
+  static double* B(Level& L) { return L.b; }
+  static double* Rr(Level& L) { return L.r; }
+  static double* D(Level& L) { return L.d; }
+  static double* Tt(Level& L) { return L.t; }
+  static const double* AV(const Sell& S) { return S.val; }
+  static const double* DI(const Level& L) { return L.dinv; }
+};
+template <int BS>
+struct LevelPtrs<BS, float> {
+  static float* X(Level& L) { return L.xf; }
+  static float* B(Level& L) { return L.bf; }
+  static float* Rr(Level& L) { return L.rf; }
+  static float* D(Level& L) { return L.df; }
+  static float* Tt(Level& L) { return L.tf; }
+  static const float* AV(const Sell& S) { return S.val32; }
+  static const float* DI(const Level& L) { return L.dinv32; }
+};
+
+template <int BS, class T>
+void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, const T* b, T* x) {
+  using LP = LevelPtrs<BS, T>;
+  Level& L = H.L[l];
+  const int n = L.n;
+  if (l == (int)H.L.size() - 1) {
+    k_dense_gemv<T><<<(H.ncoarse + 3) / 4, 256, 0, s>>>(H.ncoarse, H.coarse_inv, b, x);
+    PM_CHECK_LAUNCH();
+    return;
+  }
+  const T* AV = LP::AV(L.As);
+  const T* DI = LP::DI(L);
+  T* d = LP::D(L);
+  T* t = LP::Tt(L);
+  T* r = LP::Rr(L);
+  // pre-smoothing from zero
+  T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI);
+  // residual, restriction
+  const int nth = L.As.nslices * kSlice;
+  k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
+  Level& C = H.L[l + 1];
+  const int cth = L.R.nslices * kSlice;
+  k_sell_apply<BS, T, false><<<blocks_for(cth), kBlock, 0, s>>>(L.R.n, L.R.sptr, L.R.col, LP::AV(L.R), r, LP::B(C));
+  vcycle_level<BS, T>(s, H, prm, l + 1, LP::B(C), LP::X(C));
+  const int pth = L.P.nslices * kSlice;
+  k_sell_apply<BS, T, true><<<blocks_for(pth), kBlock, 0, s>>>(L.P.n, L.P.sptr, L.P.col, LP::AV(L.P), LP::X(C), cur);
+  PM_CHECK_LAUNCH();
+  // post-smoothing from the corrected iterate
+  T* other = (cur == x) ? t : x;
+  T* res = chebyshev<BS, T>(s, L, prm, b, cur, other, d, false, AV, DI);
+  if (res != x) PM_HIP(hipMemcpyAsync(x, res, sizeof(T) * (size_t)n * BS, hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace
+
+void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H) {
+  H.free_all();
+  H.bs = A0.bs;
+  H.fp32 = prm.fp32;
+  H.prm = prm;
+  double nnz_total = 0.0, nnz0 = (double)A0.nnzb;
+  const char* env = getenv("PM_AMG_VERBOSE");
+  const bool verbose = env && env[0] == '1';
+  Csr cur;
+  // copy of level-0 operator (the hierarchy owns its matrices)
+  cur.bs = A0.bs;
+  cur.n = A0.n;
+  cur.m = A0.m;
+  cur.nnzb = A0.nnzb;
+  cur.rowptr = dalloc<int>(A0.n + 1);
+  cur.col = dalloc<int>(A0.nnzb);
+  cur.val = dalloc<double>(A0.nnzb * A0.bs * A0.bs);
+  PM_HIP(hipMemcpyAsync(cur.rowptr, A0.rowptr, sizeof(int) * (A0.n + 1), hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipMemcpyAsync(cur.col, A0.col, sizeof(int) * A0.nnzb, hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipMemcpyAsync(cur.val, A0.val, sizeof(double) * A0.nnzb * A0.bs * A0.bs, hipMemcpyDeviceToDevice, s));
+  for (int l = 0;; ++l) {
+    H.L.emplace_back();
+    Level& L = H.L.back();
+    L.bs = cur.bs;
+    L.n = cur.n;
+    L.A = cur;
+    cur = Csr();
+    nnz_total += (double)L.A.nnzb;
+    const bool last = (L.n <= prm.coarse_max) || (l + 1 >= prm.max_levels);
+    alloc_level_vectors(L, prm.fp32);
+    csr_to_sell(s, L.A, L.As, prm.fp32);
+    if (last) {
+      dense_inverse(s, L.A, H);
+      break;
+    }
+    L.dinv = dalloc<double>((int64_t)L.n * L.bs * L.bs);
+    block_diag_inverse(s, L.A, L.dinv);
+    if (prm.fp32) {
+      L.dinv32 = dalloc<float>((int64_t)L.n * L.bs * L.bs);
+      k_to_float<<<blocks_for((int64_t)L.n * L.bs * L.bs), kBlock, 0, s>>>((int64_t)L.n * L.bs * L.bs, L.dinv,
+                                                                         L.dinv32);
+      PM_CHECK_LAUNCH();
+    }
+    L.lmax = estimate_lmax(s, L.As, L.dinv, prm.power_its);
+    if (verbose)
+      fprintf(stderr, "[amg bs=%d] level %d: rows %d, blocks %lld (%.1f/row), lmax(D^-1 A) %.4f\n", L.bs, l, L.n,
+              (long long)L.A.nnzb, (double)L.A.nnzb / std::max(1, L.n), L.lmax);
+    Csr Ac;
+    const auto tl0 = std::chrono::steady_clock::now();
+    if (L.bs == 3)
+      build_level_transfer<3>(s, L, prm, Ac);
+    else
+      build_level_transfer<1>(s, L, prm, Ac);
+    if (verbose) {
+      PM_HIP(hipStreamSynchronize(s));
+      fprintf(stderr, "[amg bs=%d] level %d transfer + Galerkin product: %.3f s\n", L.bs, l,
+              std::chrono::duration<double>(std::chrono::steady_clock::now() - tl0).count());
+    }
+    if (Ac.n == 0 || Ac.n >= L.n) {
+      // coarsening stalled: make this the coarsest level
+      Ac.free_all();
+      L.P.free_all();
+      L.R.free_all();
+      dense_inverse(s, L.A, H);
+      break;
+    }
+    cur = Ac;
+  }
+  H.opcx = nnz_total / nnz0;
+  if (verbose)
+    fprintf(stderr, "[amg bs=%d] %zu levels, coarsest %d unknowns (dense), operator complexity %.3f\n", H.bs,
+            H.L.size(), H.ncoarse, H.opcx);
+  PM_HIP(hipStreamSynchronize(s));
+}
+
+void amg_vcycle(hipStream_t s, Hierarchy& H, const double* b, double* x) {
+  const AmgParams& prm = H.prm;
+  if (H.bs == 3)
+    vcycle_level<3, double>(s, H, prm, 0, b, x);
+  else
+    vcycle_level<1, double>(s, H, prm, 0, b, x);
+}
+
+void amg_vcycle32(hipStream_t s, Hierarchy& H, const float* b, float* x) {
+  const AmgParams& prm = H.prm;
+  if (H.bs == 3)
+    vcycle_level<3, float>(s, H, prm, 0, b, x);
+  else
+    vcycle_level<1, float>(s, H, prm, 0, b, x);
+}
+
+}  // namespace pm

@@ -1,0 +1,579 @@
+// Element kernels, static condensation, stabilization, global assembly,
+// B~_p, C~_pi and the right-hand side of one backward-Euler step.
+//
+// Paper references: Appendix A eq. MFE_matrix (Q1 stiffness, coupling),
+// eq. MHFE_matrix (RT0 mass, A_wp, A_wpi), Sec. 2.2 eq. hmfeSys / A_33H
+// (condensed blocks), Sec. 3 eq. J_def and the 3D beta_M (stabilization),
+// Sec. 4 eq. app_Bp (B~_p), C~_pi = A_pipi - dt A_pip B~_p^-1 A_ppi.
+//
+// All assembly is a row gather (one thread per output row), so results are
+// bitwise reproducible; no floating-point atomics.
+#include "pm_geom.h"
+#include "pm_internal.h"
+
+namespace pm {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Q1 element stiffness: one thread per (local node a, cell); the thread owns
+// rows 3a..3a+2 of the 24x24 K_T and integrates them with 2x2x2 Gauss.
+// Ke layout: Ke[(row*24 + col)*nc + cell].
+__global__ void __launch_bounds__(256) k_q1_stiffness(Grid G, const double* __restrict__ coords,
+                                                      const double* __restrict__ E, double nu,
+                                                      double* __restrict__ Ke, int* status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 8 * G.nc) return;
+  const int a = (int)(t / G.nc);
+  const int64_t c = t - (int64_t)a * G.nc;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double X[8][3];
+  load_cell_coords(G, coords, i, j, k, X);
+  const double Ec = E[c];
+  const double lam = Ec * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = Ec / (2.0 * (1.0 + nu));
+  double K[3][24];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 24; ++q) K[r][q] = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    double xi[3], J[3][3], Ji[3][3];
+    gauss_point(q, xi);
+    const double det = jacobian(X, xi, J);
+    if (!(det > 0.0)) {
+      atomicOr(status, kStatusInverted);
+      return;
+    }
+    inv3(J, det, Ji);
+    double ga[3], gr[3];
+    ref_grad(a, xi, gr);
+    for (int d = 0; d < 3; ++d) ga[d] = gr[0] * Ji[0][d] + gr[1] * Ji[1][d] + gr[2] * Ji[2][d];
+    for (int b = 0; b < 8; ++b) {
+      double gb[3];
+      ref_grad(b, xi, gr);
+      for (int d = 0; d < 3; ++d) gb[d] = gr[0] * Ji[0][d] + gr[1] * Ji[1][d] + gr[2] * Ji[2][d];
+      const double dd = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+      for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+          double v = lam * ga[r] * gb[s] + mu * ga[s] * gb[r];
+          if (r == s) v += mu * dd;
+          K[r][3 * b + s] += v * det;
+        }
+    }
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 24; ++q) Ke[((size_t)(3 * a + r) * 24 + q) * G.nc + c] = K[r][q];
+}
+
+// Per cell: coupling column a_T (24), volume, RT0 mass, its inverse, g, alpha.
+__global__ void __launch_bounds__(256) k_cell_data(Grid G, const double* __restrict__ coords,
+                                                   const double* __restrict__ kappa, double mu_f,
+                                                   double biot, double* __restrict__ ae,
+                                                   double* __restrict__ vol, double* __restrict__ Minv,
+                                                   double* __restrict__ gvec, double* __restrict__ alpha,
+                                                   int* status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double X[8][3];
+  load_cell_coords(G, coords, i, j, k, X);
+  const double kinv[3] = {mu_f / kappa[3 * c + 0], mu_f / kappa[3 * c + 1], mu_f / kappa[3 * c + 2]};
+  double A[24], M[6][6], V = 0.0;
+  for (int q = 0; q < 24; ++q) A[q] = 0.0;
+  for (int f = 0; f < 6; ++f)
+    for (int h = 0; h < 6; ++h) M[f][h] = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    double xi[3], J[3][3], Ji[3][3];
+    gauss_point(q, xi);
+    const double det = jacobian(X, xi, J);
+    if (!(det > 0.0)) {
+      atomicOr(status, kStatusInverted);
+      return;
+    }
+    inv3(J, det, Ji);
+    V += det;
+    for (int a = 0; a < 8; ++a) {
+      double gr[3];
+      ref_grad(a, xi, gr);
+      for (int d = 0; d < 3; ++d)
+        A[3 * a + d] -= biot * (gr[0] * Ji[0][d] + gr[1] * Ji[1][d] + gr[2] * Ji[2][d]) * det;
+    }
+    // RT0 reference basis of face f = 2d+s is cf * e_d; mapped by J / det J
+    double cf[6];
+    for (int d = 0; d < 3; ++d) {
+      cf[2 * d + 0] = -(1.0 - xi[d]) * 0.125;
+      cf[2 * d + 1] = (1.0 + xi[d]) * 0.125;
+    }
+    double JKJ[3][3];  // (J^T mu kappa^-1 J)[d][e]
+    for (int d = 0; d < 3; ++d)
+      for (int e = 0; e < 3; ++e)
+        JKJ[d][e] = J[0][d] * kinv[0] * J[0][e] + J[1][d] * kinv[1] * J[1][e] + J[2][d] * kinv[2] * J[2][e];
+    const double rdet = 1.0 / det;
+    for (int f = 0; f < 6; ++f)
+      for (int h = 0; h < 6; ++h) M[f][h] += cf[f] * cf[h] * JKJ[f >> 1][h >> 1] * rdet;
+  }
+  // Cholesky M = L L^T, then M^-1 = L^-T L^-1 (symmetric by construction)
+  double L[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int s = 0; s < 6; ++s) L[r][s] = 0.0;
+  for (int r = 0; r < 6; ++r) {
+    double d = M[r][r];
+    for (int s = 0; s < r; ++s) d -= L[r][s] * L[r][s];
+    if (!(d > 0.0)) {
+      atomicOr(status, kStatusBadPivot);
+      return;
+    }
+    L[r][r] = sqrt(d);
+    for (int t = r + 1; t < 6; ++t) {
+      double v = M[t][r];
+      for (int s = 0; s < r; ++s) v -= L[t][s] * L[r][s];
+      L[t][r] = v / L[r][r];
+    }
+  }
+  double Li[6][6];  // L^-1 (lower)
+  for (int r = 0; r < 6; ++r)
+    for (int s = 0; s < 6; ++s) Li[r][s] = 0.0;
+  for (int s = 0; s < 6; ++s) {
+    Li[s][s] = 1.0 / L[s][s];
+    for (int r = s + 1; r < 6; ++r) {
+      double v = 0.0;
+      for (int t = s; t < r; ++t) v -= L[r][t] * Li[t][s];
+      Li[r][s] = v / L[r][r];
+    }
+  }
+  double Mi[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int s = 0; s <= r; ++s) {
+      double v = 0.0;
+      for (int t = r; t < 6; ++t) v += Li[t][r] * Li[t][s];
+      Mi[r][s] = v;
+      Mi[s][r] = v;
+    }
+  double al = 0.0;
+  for (int r = 0; r < 6; ++r) {
+    double gr = 0.0;
+    for (int s = 0; s < 6; ++s) {
+      gr += Mi[r][s];
+      Minv[(size_t)(r * 6 + s) * G.nc + c] = Mi[r][s];
+    }
+    gvec[(size_t)r * G.nc + c] = gr;
+    al += gr;
+  }
+  alpha[c] = al;
+  vol[c] = V;
+  for (int q = 0; q < 24; ++q) ae[(size_t)q * G.nc + c] = A[q];
+}
+
+// beta_M |M| per macro-element (3D beta of Sec. 3, volume-weighted mean E)
+__global__ void k_stab_weights(Grid G, const double* __restrict__ E, const double* __restrict__ vol,
+                               double nu, double biot, double* __restrict__ stabw) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int mx = G.nx >> 1, my = G.ny >> 1, mz = G.nz >> 1;
+  if (m >= (int64_t)mx * my * mz) return;
+  const int I = (int)(m % mx), J = (int)((m / mx) % my), K = (int)(m / ((int64_t)mx * my));
+  double V = 0.0, EV = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int64_t c = G.cell(2 * I + (a & 1), 2 * J + ((a >> 1) & 1), 2 * K + ((a >> 2) & 1));
+    V += vol[c];
+    EV += E[c] * vol[c];
+  }
+  const double Eb = EV / V;
+  const double lam = Eb * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double G2 = Eb / (2.0 * (1.0 + nu));
+  const double beta = 9.0 * biot * biot / (32.0 * (lam + 4.0 * G2));
+  stabw[m] = beta * V;
+}
+
+// Dirichlet masks
+__global__ void k_masks(Grid G, int kind, uint8_t* __restrict__ ufix, uint8_t* __restrict__ pifix) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < G.nn) {
+    int i, j, k;
+    G.node_ijk(t, i, j, k);
+    const bool bottom = (k == 0);
+    ufix[3 * t + 0] = bottom || (kind == PM_BC_ROLLERS && (i == 0 || i == G.nx));
+    ufix[3 * t + 1] = bottom || (kind == PM_BC_ROLLERS && (j == 0 || j == G.ny));
+    ufix[3 * t + 2] = bottom;
+  }
+  if (t < G.nf) {
+    bool top = false;
+    if (t >= G.nfx + G.nfy) {
+      const int64_t g = t - G.nfx - G.nfy;
+      top = (g / ((int64_t)G.nx * G.ny)) == G.nz;
+    }
+    pifix[t] = top;
+  }
+}
+
+// A_uu row counts (structured 27-point block pattern)
+__global__ void k_auu_count(Grid G, int* __restrict__ cnt) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return;
+  int i, j, k;
+  G.node_ijk(n, i, j, k);
+  const int cx = 1 + (i > 0) + (i < G.nx), cy = 1 + (j > 0) + (j < G.ny), cz = 1 + (k > 0) + (k < G.nz);
+  cnt[n] = cx * cy * cz;
+}
+
+// A_uu row gather: block (n,m) = sum over the cells containing both nodes of
+// K_T[a(n), b(m)], then the Dirichlet identity rows/columns.
+__global__ void __launch_bounds__(256) k_auu_fill(Grid G, const double* __restrict__ Ke,
+                                                  const uint8_t* __restrict__ ufix,
+                                                  const int* __restrict__ rowptr, int* __restrict__ col,
+                                                  double* __restrict__ val, double* __restrict__ diag) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return;
+  int i, j, k;
+  G.node_ijk(n, i, j, k);
+  int64_t pos = rowptr[n];
+  bool fr[3];
+  for (int r = 0; r < 3; ++r) fr[r] = ufix[3 * n + r];
+  for (int dk = -1; dk <= 1; ++dk) {
+    const int k2 = k + dk;
+    if (k2 < 0 || k2 > G.nz) continue;
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int j2 = j + dj;
+      if (j2 < 0 || j2 > G.ny) continue;
+      for (int di = -1; di <= 1; ++di) {
+        const int i2 = i + di;
+        if (i2 < 0 || i2 > G.nx) continue;
+        const int64_t m = G.node(i2, j2, k2);
+        double B[9];
+        for (int e = 0; e < 9; ++e) B[e] = 0.0;
+        // cells containing both nodes: ci in {i-1,i} and {i2-1,i2}, inside the grid
+        for (int ck = max(max(k, k2) - 1, 0); ck <= min(min(k, k2), G.nz - 1); ++ck)
+          for (int cj = max(max(j, j2) - 1, 0); cj <= min(min(j, j2), G.ny - 1); ++cj)
+            for (int ci = max(max(i, i2) - 1, 0); ci <= min(min(i, i2), G.nx - 1); ++ci) {
+              const int64_t c = G.cell(ci, cj, ck);
+              const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
+              const int b = (i2 - ci) + 2 * (j2 - cj) + 4 * (k2 - ck);
+              for (int r = 0; r < 3; ++r)
+                for (int s = 0; s < 3; ++s)
+                  B[r * 3 + s] += Ke[((size_t)(3 * a + r) * 24 + 3 * b + s) * G.nc + c];
+            }
+        for (int r = 0; r < 3; ++r)
+          for (int s = 0; s < 3; ++s) {
+            const bool fixed = fr[r] || ufix[3 * m + s];
+            double v = fixed ? 0.0 : B[r * 3 + s];
+            if (m == n && r == s && fr[r]) v = 1.0;
+            val[(size_t)pos * 9 + r * 3 + s] = v;
+            if (m == n && r == s) diag[3 * n + r] = v;
+          }
+        col[pos] = (int)m;
+        ++pos;
+      }
+    }
+  }
+}
+
+// B~_p = S|T| + dt alpha_T + (A_stab)_TT + sum_{free i} (A_up)_{iT}^2 / (A_uu)_ii
+__global__ void k_bp(Grid G, const double* __restrict__ ae, const double* __restrict__ vol,
+                     const double* __restrict__ alpha, const double* __restrict__ stabw,
+                     const double* __restrict__ diag, const uint8_t* __restrict__ ufix, double S,
+                     double dt, int stabilize, double* __restrict__ bp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double v = S * vol[c] + dt * alpha[c];
+  if (stabilize) v += 3.0 * stabw[G.macro(i, j, k)];
+  double fs = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    for (int d = 0; d < 3; ++d) {
+      if (ufix[3 * n + d]) continue;
+      const double x = ae[(size_t)(3 * a + d) * G.nc + c];
+      fs += x * x / diag[3 * n + d];
+    }
+  }
+  bp[c] = v + fs;
+}
+
+// C~_pi rows: count, then fill (sorted columns)
+__device__ inline int cpi_row_entries(const Grid& G, int64_t f, const uint8_t* __restrict__ pifix,
+                                      const double* __restrict__ Minv, const double* __restrict__ gv,
+                                      const double* __restrict__ bp, double dt, int64_t cols[12],
+                                      double vals[12], bool want_vals) {
+  if (pifix[f]) {
+    cols[0] = f;
+    vals[0] = 1.0;
+    return 1;
+  }
+  int64_t cc[2];
+  int lf[2];
+  G.face_cells(f, cc, lf);
+  int cnt = 0;
+  for (int s = 0; s < 2; ++s) {
+    const int64_t c = cc[s];
+    if (c < 0) continue;
+    int i, j, k;
+    G.cell_ijk(c, i, j, k);
+    int64_t F[6];
+    G.cell_faces(i, j, k, F);
+    double gl = 0.0, sc = 0.0;
+    if (want_vals) {
+      gl = gv[(size_t)lf[s] * G.nc + c];
+      sc = dt / bp[c];
+    }
+    for (int e = 0; e < 6; ++e) {
+      if (pifix[F[e]]) continue;
+      double v = 0.0;
+      if (want_vals)
+        v = Minv[(size_t)(lf[s] * 6 + e) * G.nc + c] - sc * gl * gv[(size_t)e * G.nc + c];
+      int p = 0;
+      while (p < cnt && cols[p] != F[e]) ++p;
+      if (p == cnt) {
+        cols[cnt] = F[e];
+        vals[cnt] = v;
+        ++cnt;
+      } else {
+        vals[p] += v;
+      }
+    }
+  }
+  // insertion sort by column
+  for (int a = 1; a < cnt; ++a) {
+    const int64_t kc = cols[a];
+    const double kv = vals[a];
+    int b = a - 1;
+    while (b >= 0 && cols[b] > kc) {
+      cols[b + 1] = cols[b];
+      vals[b + 1] = vals[b];
+      --b;
+    }
+    cols[b + 1] = kc;
+    vals[b + 1] = kv;
+  }
+  return cnt;
+}
+
+__global__ void k_cpi_count(Grid G, const uint8_t* __restrict__ pifix, int* __restrict__ cnt) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  int64_t cols[12];
+  double vals[12];
+  cnt[f] = cpi_row_entries(G, f, pifix, nullptr, nullptr, nullptr, 0.0, cols, vals, false);
+}
+
+__global__ void k_cpi_fill(Grid G, const uint8_t* __restrict__ pifix, const double* __restrict__ Minv,
+                           const double* __restrict__ gv, const double* __restrict__ bp, double dt,
+                           const int* __restrict__ rowptr, int* __restrict__ col,
+                           double* __restrict__ val) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  int64_t cols[12];
+  double vals[12];
+  const int cnt = cpi_row_entries(G, f, pifix, Minv, gv, bp, dt, cols, vals, true);
+  const int64_t p0 = rowptr[f];
+  for (int e = 0; e < cnt; ++e) {
+    col[p0 + e] = (int)cols[e];
+    val[p0 + e] = vals[e];
+  }
+}
+
+// right-hand side (eq. MHFE_vector, f~_n of Sec. 2.1; no fluid source)
+__global__ void k_rhs_u(Grid G, const double* __restrict__ coords, double t0, double t1, double t2,
+                        const uint8_t* __restrict__ ufix, double* __restrict__ bu) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return;
+  int i, j, k;
+  G.node_ijk(n, i, j, k);
+  double f[3] = {0.0, 0.0, 0.0};
+  if (k == G.nz) {
+    // top faces around the node: cells (ci,cj,nz-1), local face nodes 4..7
+    for (int cj = max(j - 1, 0); cj <= min(j, G.ny - 1); ++cj)
+      for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
+        double Xf[4][3];
+        for (int a = 0; a < 4; ++a) {
+          const int64_t m = G.node(ci + (a & 1), cj + (a >> 1), G.nz);
+          for (int d = 0; d < 3; ++d) Xf[a][d] = coords[3 * m + d];
+        }
+        const int la = (i - ci) + 2 * (j - cj);
+        const double sa0 = (la & 1) ? 1.0 : -1.0, sa1 = (la >> 1) ? 1.0 : -1.0;
+        for (int q = 0; q < 4; ++q) {
+          const double x = (q & 1) ? kGauss : -kGauss, y = (q >> 1) ? kGauss : -kGauss;
+          double tx[3] = {0, 0, 0}, ty[3] = {0, 0, 0};
+          for (int a = 0; a < 4; ++a) {
+            const double s0 = (a & 1) ? 1.0 : -1.0, s1 = (a >> 1) ? 1.0 : -1.0;
+            const double dx = 0.25 * s0 * (1.0 + s1 * y), dy = 0.25 * s1 * (1.0 + s0 * x);
+            for (int d = 0; d < 3; ++d) {
+              tx[d] += dx * Xf[a][d];
+              ty[d] += dy * Xf[a][d];
+            }
+          }
+          const double cx = tx[1] * ty[2] - tx[2] * ty[1], cy = tx[2] * ty[0] - tx[0] * ty[2],
+                       cz = tx[0] * ty[1] - tx[1] * ty[0];
+          const double dS = sqrt(cx * cx + cy * cy + cz * cz);
+          const double N = 0.25 * (1.0 + sa0 * x) * (1.0 + sa1 * y);
+          f[0] += N * t0 * dS;
+          f[1] += N * t1 * dS;
+          f[2] += N * t2 * dS;
+        }
+      }
+  }
+  for (int d = 0; d < 3; ++d) bu[3 * n + d] = ufix[3 * n + d] ? 0.0 : f[d];
+}
+
+__global__ void k_rhs_p(Grid G, const double* __restrict__ ae, const double* __restrict__ vol,
+                        const double* __restrict__ gv, const double* __restrict__ stabw,
+                        const uint8_t* __restrict__ pifix, const double* __restrict__ u_prev,
+                        const double* __restrict__ p_prev, double S, double dt, double p_top,
+                        int stab_rhs, double* __restrict__ bpv) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double v = 0.0;
+  if (u_prev) {
+    for (int a = 0; a < 8; ++a) {
+      const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+      for (int d = 0; d < 3; ++d) v -= ae[(size_t)(3 * a + d) * G.nc + c] * u_prev[3 * n + d];
+    }
+  }
+  if (p_prev) {
+    v += S * vol[c] * p_prev[c];
+    if (stab_rhs) {
+      const double w = stabw[G.macro(i, j, k)];
+      const double pc = p_prev[c];
+      v += w * ((pc - p_prev[G.cell(i ^ 1, j, k)]) + (pc - p_prev[G.cell(i, j ^ 1, k)]) +
+                (pc - p_prev[G.cell(i, j, k ^ 1)]));
+    }
+  }
+  // lifting of the prescribed face pressures: -dt * (-g_T) p_top on drained faces
+  int64_t F[6];
+  G.cell_faces(i, j, k, F);
+  for (int e = 0; e < 6; ++e)
+    if (pifix[F[e]]) v += dt * gv[(size_t)e * G.nc + c] * p_top;
+  bpv[c] = v;
+}
+
+__global__ void k_rhs_pi(Grid G, const double* __restrict__ Minv, const uint8_t* __restrict__ pifix,
+                         double p_top, double* __restrict__ bpi) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  if (pifix[f]) {
+    bpi[f] = p_top;
+    return;
+  }
+  double v = 0.0;
+  int64_t cc[2];
+  int lf[2];
+  G.face_cells(f, cc, lf);
+  for (int s = 0; s < 2; ++s) {
+    const int64_t c = cc[s];
+    if (c < 0) continue;
+    int i, j, k;
+    G.cell_ijk(c, i, j, k);
+    int64_t F[6];
+    G.cell_faces(i, j, k, F);
+    for (int e = 0; e < 6; ++e)
+      if (pifix[F[e]]) v -= Minv[(size_t)(lf[s] * 6 + e) * G.nc + c] * p_top;
+  }
+  bpi[f] = v;
+}
+
+}  // namespace
+
+Grid grid_of(const pm_ctx* c) {
+  Grid G;
+  G.nx = c->nx;
+  G.ny = c->ny;
+  G.nz = c->nz;
+  G.nn = c->nn;
+  G.nc = c->nc;
+  G.nfx = c->nfx;
+  G.nfy = c->nfy;
+  G.nfz = c->nfz;
+  G.nf = c->nf;
+  return G;
+}
+
+void check_status(pm_ctx* c, const char* where) {
+  int st = 0;
+  PM_HIP(hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->s));
+  PM_HIP(hipStreamSynchronize(c->s));
+  if (st & kStatusInverted)
+    throw Error(PM_EINVAL, std::string(where) + ": non-positive Jacobian determinant (inverted hexahedron)");
+  if (st & kStatusBadPivot)
+    throw Error(PM_EINVAL, std::string(where) + ": RT0 mass matrix not positive definite");
+  if (st & kStatusNonFinite) throw Error(PM_EBREAKDOWN, std::string(where) + ": non-finite value");
+  if (st & kStatusCapacity) throw Error(PM_EINTERNAL, std::string(where) + ": internal capacity exceeded");
+}
+
+static void build_cpi(pm_ctx* c) {
+  const Grid G = grid_of(c);
+  hipStream_t s = c->s;
+  k_bp<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->ae, c->vol, c->alpha, c->stabw, c->auu_diag, c->ufix,
+                                           c->S, c->dt, c->opts.stabilize, c->bp);
+  PM_CHECK_LAUNCH();
+  if (!c->Cpi.rowptr) {
+    c->Cpi.bs = 1;
+    c->Cpi.n = c->Cpi.m = (int)G.nf;
+    c->Cpi.rowptr = dalloc<int>(G.nf + 1);
+    int* cnt = dalloc<int>(G.nf);
+    k_cpi_count<<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->pifix, cnt);
+    PM_CHECK_LAUNCH();
+    int total = 0;
+    exclusive_scan(s, cnt, c->Cpi.rowptr, (int)G.nf, &total);
+    dfree(cnt);
+    c->Cpi.nnzb = total;
+    c->Cpi.col = dalloc<int>(total);
+    c->Cpi.val = dalloc<double>(total);
+  }
+  k_cpi_fill<<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->pifix, c->Minv, c->g, c->bp, c->dt, c->Cpi.rowptr,
+                                                 c->Cpi.col, c->Cpi.val);
+  PM_CHECK_LAUNCH();
+}
+
+void assemble_all(pm_ctx* c) {
+  const Grid G = grid_of(c);
+  hipStream_t s = c->s;
+  PM_HIP(hipMemsetAsync(c->status, 0, sizeof(int), s));
+  k_masks<<<blocks_for(std::max(G.nn, G.nf)), kBlock, 0, s>>>(G, c->bc_kind, c->ufix, c->pifix);
+  PM_CHECK_LAUNCH();
+  k_cell_data<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->coords, c->kappa, c->mu, c->biot, c->ae, c->vol,
+                                                  c->Minv, c->g, c->alpha, c->status);
+  PM_CHECK_LAUNCH();
+  k_q1_stiffness<<<blocks_for(8 * G.nc), kBlock, 0, s>>>(G, c->coords, c->E, c->nu, c->Ke, c->status);
+  PM_CHECK_LAUNCH();
+  check_status(c, "element kernels");
+  k_stab_weights<<<blocks_for(c->nmacro), kBlock, 0, s>>>(G, c->E, c->vol, c->nu, c->biot, c->stabw);
+  PM_CHECK_LAUNCH();
+  if (!c->Auu.rowptr) {
+    c->Auu.bs = 3;
+    c->Auu.n = c->Auu.m = (int)G.nn;
+    c->Auu.rowptr = dalloc<int>(G.nn + 1);
+    int* cnt = dalloc<int>(G.nn);
+    k_auu_count<<<blocks_for(G.nn), kBlock, 0, s>>>(G, cnt);
+    PM_CHECK_LAUNCH();
+    int total = 0;
+    exclusive_scan(s, cnt, c->Auu.rowptr, (int)G.nn, &total);
+    dfree(cnt);
+    c->Auu.nnzb = total;
+    c->Auu.col = dalloc<int>(total);
+    c->Auu.val = dalloc<double>((int64_t)total * 9);
+  }
+  k_auu_fill<<<blocks_for(G.nn), kBlock, 0, s>>>(G, c->Ke, c->ufix, c->Auu.rowptr, c->Auu.col, c->Auu.val,
+                                                 c->auu_diag);
+  PM_CHECK_LAUNCH();
+  build_cpi(c);
+}
+
+void rebuild_dt(pm_ctx* c) { build_cpi(c); }
+
+void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b) {
+  const Grid G = grid_of(c);
+  hipStream_t s = c->s;
+  k_rhs_u<<<blocks_for(G.nn), kBlock, 0, s>>>(G, c->coords, c->trac[0], c->trac[1], c->trac[2], c->ufix, b);
+  PM_CHECK_LAUNCH();
+  k_rhs_p<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->ae, c->vol, c->g, c->stabw, c->pifix, u_prev, p_prev,
+                                              c->S, c->dt, c->p_top,
+                                              (c->opts.stabilize && c->opts.increment_stab) ? 1 : 0,
+                                              b + c->n_u);
+  PM_CHECK_LAUNCH();
+  k_rhs_pi<<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->Minv, c->pifix, c->p_top, b + c->n_u + c->n_p);
+  PM_CHECK_LAUNCH();
+}
+
+}  // namespace pm

@@ -1,0 +1,402 @@
+// C ABI entry points (include/poromech.h): argument validation, context
+// lifetime, timing, and conversion of internal errors to return codes.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "pm_internal.h"
+
+using pm::Error;
+
+namespace {
+
+thread_local std::string g_setup_error = "no error";
+
+// y = d .* x
+__global__ void k_diag_mul(int64_t n, const double* __restrict__ d, const double* __restrict__ x,
+                           double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = d[i] * x[i];
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class F>
+int guarded(pm_ctx* c, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    if (c) c->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return PM_EINTERNAL;
+  }
+}
+
+void free_ctx_buffers(pm_ctx* c) {
+  using pm::dfree;
+  for (void* p : {(void*)c->coords, (void*)c->E, (void*)c->kappa, (void*)c->Ke, (void*)c->ae, (void*)c->vol,
+                  (void*)c->Minv, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
+                  (void*)c->ufix, (void*)c->pifix, (void*)c->status, (void*)c->V, (void*)c->Z, (void*)c->wvec,
+                  (void*)c->rvec, (void*)c->xvec, (void*)c->red, (void*)c->hcol, (void*)c->pw64, (void*)c->pw32})
+    dfree(p);
+  if (c->hhost) (void)hipHostFree(c->hhost);
+  c->Auu.free_all();
+  c->Cpi.free_all();
+  c->Hu.free_all();
+  c->Hpi.free_all();
+}
+
+void copy_in(pm_ctx* c, double* dst, const double* src, int64_t n) {
+  PM_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDefault, c->s));
+}
+
+// validates positivity of a device field (host copy; setup-time only)
+void check_positive(pm_ctx* c, const double* dev, int64_t n, const char* what) {
+  std::vector<double> h(n);
+  PM_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * n, hipMemcpyDeviceToHost, c->s));
+  PM_HIP(hipStreamSynchronize(c->s));
+  for (int64_t i = 0; i < n; ++i)
+    if (!(h[i] > 0.0) || !std::isfinite(h[i]))
+      throw Error(PM_EINVAL, std::string(what) + " must be positive and finite (index " + std::to_string(i) + ")");
+}
+
+pm::AmgParams params_u(const pm_ctx* c) {
+  pm::AmgParams p;
+  p.theta = c->opts.theta_u;
+  p.coarse_max = c->opts.coarse_max;
+  p.cheb_degree = c->opts.cheb_degree;
+  p.fp32 = c->opts.precond_fp32 != 0;
+  return p;
+}
+
+pm::AmgParams params_pi(const pm_ctx* c) {
+  pm::AmgParams p = params_u(c);
+  p.theta = c->opts.theta_pi;
+  p.coarse_max = c->opts.coarse_max * 3;
+  return p;
+}
+
+void setup_hierarchies(pm_ctx* c, bool with_u) {
+  if (with_u) {
+    pm::amg_setup(c->s, c->Auu, params_u(c), c->Hu);
+    c->hier_u_ok = true;
+  }
+  pm::amg_setup(c->s, c->Cpi, params_pi(c), c->Hpi);
+  c->info.levels_u = (int)c->Hu.L.size();
+  c->info.levels_pi = (int)c->Hpi.L.size();
+  c->info.opcx_u = c->Hu.opcx;
+  c->info.opcx_pi = c->Hpi.opcx;
+}
+
+void assemble_and_setup(pm_ctx* c) {
+  PM_HIP(hipStreamSynchronize(c->s));
+  const double t0 = now_s();
+  c->Ke = pm::dalloc<double>(576 * c->nc);
+  try {
+    pm::assemble_all(c);
+  } catch (...) {
+    pm::dfree(c->Ke);
+    c->Ke = nullptr;
+    throw;
+  }
+  PM_HIP(hipStreamSynchronize(c->s));
+  pm::dfree(c->Ke);
+  c->Ke = nullptr;
+  const double t1 = now_s();
+  setup_hierarchies(c, true);
+  PM_HIP(hipStreamSynchronize(c->s));
+  const double t2 = now_s();
+  c->info.t_asm = t1 - t0;
+  c->info.t_setup = t2 - t1;
+  c->assembled = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pm_default_opts(pm_opts* o) {
+  if (!o) return;
+  o->rtol = 1e-8;
+  o->restart = 100;
+  o->max_it = 1000;
+  o->precond_fp32 = 0;
+  o->stabilize = 1;
+  o->increment_stab = 1;
+  o->cheb_degree = 2;
+  o->coarse_max = 64;
+  o->theta_u = 0.0;
+  o->theta_pi = 0.08;
+}
+
+int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, double dt, const pm_opts* opts,
+             void* stream, pm_ctx** out) {
+  if (!out) {
+    g_setup_error = "pm_setup: out is NULL";
+    return PM_EINVAL;
+  }
+  *out = nullptr;
+  pm_ctx* c = new (std::nothrow) pm_ctx();
+  if (!c) {
+    g_setup_error = "pm_setup: host allocation failed";
+    return PM_ENOMEM;
+  }
+  const int rc = guarded(c, [&]() -> int {
+    if (!mesh || !mat || !bc) throw Error(PM_EINVAL, "pm_setup: mesh, material and bc are required");
+    if (mesh->nx < 2 || mesh->ny < 2 || mesh->nz < 2 || (mesh->nx & 1) || (mesh->ny & 1) || (mesh->nz & 1))
+      throw Error(PM_EINVAL, "pm_setup: nx, ny, nz must be even and >= 2 (2x2x2 macro-elements)");
+    if (!mat->E || !mat->kappa) throw Error(PM_EINVAL, "pm_setup: E and kappa are required");
+    if (!(mat->nu > 0.0 && mat->nu < 0.5)) throw Error(PM_EINVAL, "pm_setup: nu must lie in (0, 0.5)");
+    if (!(mat->mu > 0.0) || !(mat->S_eps >= 0.0) || !std::isfinite(mat->biot))
+      throw Error(PM_EINVAL, "pm_setup: mu > 0, S_eps >= 0 and a finite Biot coefficient are required");
+    if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(PM_EINVAL, "pm_setup: dt must be positive");
+    if (bc->kind != PM_BC_COLUMN && bc->kind != PM_BC_ROLLERS) throw Error(PM_EINVAL, "pm_setup: unknown bc kind");
+    c->s = (hipStream_t)stream;
+    c->nx = mesh->nx;
+    c->ny = mesh->ny;
+    c->nz = mesh->nz;
+    const int64_t nx = c->nx, ny = c->ny, nz = c->nz;
+    c->nn = (nx + 1) * (ny + 1) * (nz + 1);
+    c->nc = nx * ny * nz;
+    c->nfx = (nx + 1) * ny * nz;
+    c->nfy = nx * (ny + 1) * nz;
+    c->nfz = nx * ny * (nz + 1);
+    c->nf = c->nfx + c->nfy + c->nfz;
+    c->nmacro = c->nc / 8;
+    c->n_u = 3 * c->nn;
+    c->n_p = c->nc;
+    c->n_pi = c->nf;
+    c->N = c->n_u + c->n_p + c->n_pi;
+    if (c->N >= ((int64_t)1 << 31) / 9) throw Error(PM_EINVAL, "pm_setup: problem too large for 32-bit indices");
+    c->nu = mat->nu;
+    c->biot = mat->biot;
+    c->S = mat->S_eps;
+    c->mu = mat->mu;
+    c->dt = dt;
+    for (int d = 0; d < 3; ++d) c->trac[d] = bc->traction_top[d];
+    c->p_top = bc->p_top;
+    c->bc_kind = bc->kind;
+    if (opts) c->opts = *opts; else pm_default_opts(&c->opts);
+    if (c->opts.restart < 1 || c->opts.max_it < 1 || c->opts.cheb_degree < 1 || c->opts.coarse_max < 1 ||
+        !(c->opts.rtol > 0.0))
+      throw Error(PM_EINVAL, "pm_setup: invalid solver options");
+    c->coords = pm::dalloc<double>(3 * c->nn);
+    c->E = pm::dalloc<double>(c->nc);
+    c->kappa = pm::dalloc<double>(3 * c->nc);
+    if (mesh->coords) {
+      copy_in(c, c->coords, mesh->coords, 3 * c->nn);
+    } else {
+      if (!(mesh->Lx > 0 && mesh->Ly > 0 && mesh->Lz > 0)) throw Error(PM_EINVAL, "pm_setup: box size must be positive");
+      std::vector<double> X(3 * c->nn);
+      for (int64_t k = 0; k <= nz; ++k)
+        for (int64_t j = 0; j <= ny; ++j)
+          for (int64_t i = 0; i <= nx; ++i) {
+            const int64_t n = i + (nx + 1) * (j + (ny + 1) * k);
+            X[3 * n + 0] = mesh->Lx * (double)i / (double)nx;
+            X[3 * n + 1] = mesh->Ly * (double)j / (double)ny;
+            X[3 * n + 2] = mesh->Lz * (double)k / (double)nz;
+          }
+      PM_HIP(hipMemcpyAsync(c->coords, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, c->s));
+      PM_HIP(hipStreamSynchronize(c->s));
+    }
+    copy_in(c, c->E, mat->E, c->nc);
+    copy_in(c, c->kappa, mat->kappa, 3 * c->nc);
+    check_positive(c, c->E, c->nc, "E");
+    check_positive(c, c->kappa, 3 * c->nc, "kappa");
+    c->ae = pm::dalloc<double>(24 * c->nc);
+    c->vol = pm::dalloc<double>(c->nc);
+    c->Minv = pm::dalloc<double>(36 * c->nc);
+    c->g = pm::dalloc<double>(6 * c->nc);
+    c->alpha = pm::dalloc<double>(c->nc);
+    c->stabw = pm::dalloc<double>(c->nmacro);
+    c->bp = pm::dalloc<double>(c->nc);
+    c->auu_diag = pm::dalloc<double>(c->n_u);
+    c->ufix = pm::dalloc<uint8_t>(c->n_u);
+    c->pifix = pm::dalloc<uint8_t>(c->n_pi);
+    c->status = pm::dalloc<int>(1);
+    c->wvec = pm::dalloc<double>(c->N);
+    c->rvec = pm::dalloc<double>(c->N);
+    c->xvec = pm::dalloc<double>(c->N);
+    c->pw64 = pm::dalloc<double>(c->N);
+    if (c->opts.precond_fp32) c->pw32 = pm::dalloc<float>(3 * c->N);
+    return PM_OK;
+  });
+  if (rc != PM_OK) {
+    g_setup_error = c->err;
+    free_ctx_buffers(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return PM_OK;
+}
+
+int pm_assemble(pm_ctx* c) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    assemble_and_setup(c);
+    return PM_OK;
+  });
+}
+
+int pm_set_dt(pm_ctx* c, double dt) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(PM_EINVAL, "pm_set_dt: dt must be positive");
+    c->dt = dt;
+    if (!c->assembled) return PM_OK;
+    PM_HIP(hipStreamSynchronize(c->s));
+    const double t0 = now_s();
+    pm::rebuild_dt(c);
+    setup_hierarchies(c, false);
+    PM_HIP(hipStreamSynchronize(c->s));
+    c->info.t_setup = now_s() - t0;
+    return PM_OK;
+  });
+}
+
+int pm_update_material(pm_ctx* c, const double* E, const double* kappa) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (E) {
+      copy_in(c, c->E, E, c->nc);
+      check_positive(c, c->E, c->nc, "E");
+    }
+    if (kappa) {
+      copy_in(c, c->kappa, kappa, 3 * c->nc);
+      check_positive(c, c->kappa, 3 * c->nc, "kappa");
+    }
+    if (c->assembled) assemble_and_setup(c);
+    return PM_OK;
+  });
+}
+
+int pm_build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!b) throw Error(PM_EINVAL, "pm_build_rhs: b is NULL");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_build_rhs: call pm_assemble first");
+    pm::build_rhs(c, u_prev, p_prev, b);
+    return PM_OK;
+  });
+}
+
+static int solve_common(pm_ctx* c, const double* b, double* u, double* pi, double* p, pm_info* info, bool tr) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!b) throw Error(PM_EINVAL, "pm_solve: b is NULL");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_solve: call pm_assemble first");
+    PM_HIP(hipStreamSynchronize(c->s));
+    const double t0 = now_s();
+    pm_info li = c->info;
+    const int rc = pm::fgmres(c, b, c->xvec, tr, &li);
+    if (u) PM_HIP(hipMemcpyAsync(u, c->xvec, sizeof(double) * c->n_u, hipMemcpyDeviceToDevice, c->s));
+    if (p) PM_HIP(hipMemcpyAsync(p, c->xvec + c->n_u, sizeof(double) * c->n_p, hipMemcpyDeviceToDevice, c->s));
+    if (pi)
+      PM_HIP(hipMemcpyAsync(pi, c->xvec + c->n_u + c->n_p, sizeof(double) * c->n_pi, hipMemcpyDeviceToDevice, c->s));
+    PM_HIP(hipStreamSynchronize(c->s));
+    li.t_solve = now_s() - t0;
+    c->info = li;
+    if (info) *info = li;
+    if (rc == PM_ENOCONV) c->err = "FGMRES reached max_it before rtol";
+    return rc;
+  });
+}
+
+int pm_solve(pm_ctx* c, const double* b, double* u, double* pi, double* p, pm_info* info) {
+  return solve_common(c, b, u, pi, p, info, false);
+}
+
+int pm_solve_transpose(pm_ctx* c, const double* g, double* lu, double* lpi, double* lp, pm_info* info) {
+  return solve_common(c, g, lu, lpi, lp, info, true);
+}
+
+int pm_grad(pm_ctx* c, const double* lam, const double* x, const double* p_prev, double* dlogk, double* dlogE) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!lam || !x || !dlogk || !dlogE) throw Error(PM_EINVAL, "pm_grad: NULL argument");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_grad: call pm_assemble first");
+    pm::grad(c, lam, x, p_prev, dlogk, dlogE);
+    return PM_OK;
+  });
+}
+
+int pm_rhs_adjoint(pm_ctx* c, const double* lam, double* cvec) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!lam || !cvec) throw Error(PM_EINVAL, "pm_rhs_adjoint: NULL argument");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_rhs_adjoint: call pm_assemble first");
+    pm::rhs_adjoint(c, lam, cvec);
+    return PM_OK;
+  });
+}
+
+int pm_reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!p || !pi || !w) throw Error(PM_EINVAL, "pm_reconstruct_w: NULL argument");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_reconstruct_w: call pm_assemble first");
+    pm::reconstruct_w(c, p, pi, w);
+    return PM_OK;
+  });
+}
+
+int pm_apply(pm_ctx* c, int which, const double* x, double* y) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!x || !y) throw Error(PM_EINVAL, "pm_apply: NULL argument");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_apply: call pm_assemble first");
+    switch (which) {
+      case PM_OP_AH: pm::apply_AH(c, x, y, false); break;
+      case PM_OP_AHT: pm::apply_AH(c, x, y, true); break;
+      case PM_OP_MINV: pm::apply_Minv(c, x, y, false); break;
+      case PM_OP_MINVT: pm::apply_Minv(c, x, y, true); break;
+      case PM_OP_CPI: pm::apply_csr(c, c->Cpi, x, y); break;
+      case PM_OP_BP:
+        k_diag_mul<<<pm::blocks_for(c->n_p), pm::kBlock, 0, c->s>>>(c->n_p, c->bp, x, y);
+        PM_CHECK_LAUNCH();
+        break;
+      case PM_OP_AUU: pm::apply_csr(c, c->Auu, x, y); break;
+      case PM_OP_VCYCLE_U: pm::amg_vcycle(c->s, c->Hu, x, y); break;
+      case PM_OP_VCYCLE_PI: pm::amg_vcycle(c->s, c->Hpi, x, y); break;
+      default: throw Error(PM_EINVAL, "pm_apply: unknown operator");
+    }
+    return PM_OK;
+  });
+}
+
+int pm_sizes(const pm_ctx* c, int64_t* out) {
+  if (!c || !out) return PM_EINVAL;
+  out[0] = c->n_u;
+  out[1] = c->n_p;
+  out[2] = c->n_pi;
+  out[3] = c->N;
+  out[4] = c->nn;
+  out[5] = c->nmacro;
+  return PM_OK;
+}
+
+int pm_get_info(const pm_ctx* c, pm_info* info) {
+  if (!c || !info) return PM_EINVAL;
+  *info = c->info;
+  return PM_OK;
+}
+
+const char* pm_last_error(const pm_ctx* c) {
+  if (!c) return g_setup_error.c_str();
+  return c->err.empty() ? "no error" : c->err.c_str();
+}
+
+void pm_destroy(pm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->s);
+  free_ctx_buffers(c);
+  delete c;
+}
+
+}  // extern "C"
+

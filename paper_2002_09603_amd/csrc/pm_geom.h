@@ -1,0 +1,151 @@
+// Device helpers for the structured hexahedral mesh and the trilinear map.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pm {
+
+// Structured grid description passed by value to kernels.
+struct Grid {
+  int nx, ny, nz;
+  int64_t nn, nc, nfx, nfy, nfz, nf;
+  __host__ __device__ int64_t node(int i, int j, int k) const {
+    return i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
+  }
+  __host__ __device__ int64_t cell(int i, int j, int k) const {
+    return i + (int64_t)nx * (j + (int64_t)ny * k);
+  }
+  __host__ __device__ int64_t fx(int i, int j, int k) const {
+    return i + (int64_t)(nx + 1) * (j + (int64_t)ny * k);
+  }
+  __host__ __device__ int64_t fy(int i, int j, int k) const {
+    return nfx + i + (int64_t)nx * (j + (int64_t)(ny + 1) * k);
+  }
+  __host__ __device__ int64_t fz(int i, int j, int k) const {
+    return nfx + nfy + i + (int64_t)nx * (j + (int64_t)ny * k);
+  }
+  __host__ __device__ int64_t macro(int ci, int cj, int ck) const {
+    return (ci >> 1) + (int64_t)(nx >> 1) * ((cj >> 1) + (int64_t)(ny >> 1) * (ck >> 1));
+  }
+  // local faces (-x,+x,-y,+y,-z,+z) of cell (i,j,k)
+  __host__ __device__ void cell_faces(int i, int j, int k, int64_t f[6]) const {
+    f[0] = fx(i, j, k);
+    f[1] = fx(i + 1, j, k);
+    f[2] = fy(i, j, k);
+    f[3] = fy(i, j + 1, k);
+    f[4] = fz(i, j, k);
+    f[5] = fz(i, j, k + 1);
+  }
+  __host__ __device__ void cell_ijk(int64_t c, int& i, int& j, int& k) const {
+    i = (int)(c % nx);
+    int64_t r = c / nx;
+    j = (int)(r % ny);
+    k = (int)(r / ny);
+  }
+  __host__ __device__ void node_ijk(int64_t n, int& i, int& j, int& k) const {
+    i = (int)(n % (nx + 1));
+    int64_t r = n / (nx + 1);
+    j = (int)(r % (ny + 1));
+    k = (int)(r / (ny + 1));
+  }
+  // cells adjacent to face f: cell ids (or -1) and the local face index in each
+  __host__ __device__ void face_cells(int64_t f, int64_t c[2], int lf[2]) const {
+    int i, j, k;
+    if (f < nfx) {
+      i = (int)(f % (nx + 1));
+      int64_t r = f / (nx + 1);
+      j = (int)(r % ny);
+      k = (int)(r / ny);
+      c[0] = i > 0 ? cell(i - 1, j, k) : -1;
+      lf[0] = 1;
+      c[1] = i < nx ? cell(i, j, k) : -1;
+      lf[1] = 0;
+    } else if (f < nfx + nfy) {
+      int64_t g = f - nfx;
+      i = (int)(g % nx);
+      int64_t r = g / nx;
+      j = (int)(r % (ny + 1));
+      k = (int)(r / (ny + 1));
+      c[0] = j > 0 ? cell(i, j - 1, k) : -1;
+      lf[0] = 3;
+      c[1] = j < ny ? cell(i, j, k) : -1;
+      lf[1] = 2;
+    } else {
+      int64_t g = f - nfx - nfy;
+      i = (int)(g % nx);
+      int64_t r = g / nx;
+      j = (int)(r % ny);
+      k = (int)(r / ny);
+      c[0] = k > 0 ? cell(i, j, k - 1) : -1;
+      lf[0] = 5;
+      c[1] = k < nz ? cell(i, j, k) : -1;
+      lf[1] = 4;
+    }
+  }
+};
+
+constexpr double kGauss = 0.57735026918962576451;  // 1/sqrt(3)
+
+__host__ __device__ inline void gauss_point(int q, double xi[3]) {
+  xi[0] = (q & 1) ? kGauss : -kGauss;
+  xi[1] = ((q >> 1) & 1) ? kGauss : -kGauss;
+  xi[2] = ((q >> 2) & 1) ? kGauss : -kGauss;
+}
+
+// reference gradient of the trilinear shape function of local node a
+__host__ __device__ inline void ref_grad(int a, const double xi[3], double g[3]) {
+  const double sx = (a & 1) ? 1.0 : -1.0;
+  const double sy = ((a >> 1) & 1) ? 1.0 : -1.0;
+  const double sz = ((a >> 2) & 1) ? 1.0 : -1.0;
+  const double tx = 1.0 + sx * xi[0], ty = 1.0 + sy * xi[1], tz = 1.0 + sz * xi[2];
+  g[0] = 0.125 * sx * ty * tz;
+  g[1] = 0.125 * sy * tx * tz;
+  g[2] = 0.125 * sz * tx * ty;
+}
+
+// J[i][j] = d x_i / d xi_j; returns det J
+__host__ __device__ inline double jacobian(const double X[8][3], const double xi[3], double J[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) J[i][j] = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    double g[3];
+    ref_grad(a, xi, g);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) J[i][j] += X[a][i] * g[j];
+  }
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// inverse of J (given det)
+__host__ __device__ inline void inv3(const double J[3][3], double det, double Ji[3][3]) {
+  const double r = 1.0 / det;
+  Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * r;
+  Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+  Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+  Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * r;
+  Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+  Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+  Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * r;
+  Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+  Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+}
+
+// load the 8 node coordinates of cell (i,j,k)
+__device__ inline void load_cell_coords(const Grid& G, const double* __restrict__ coords, int i, int j,
+                                        int k, double X[8][3]) {
+  for (int a = 0; a < 8; ++a) {
+    const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    X[a][0] = coords[3 * n + 0];
+    X[a][1] = coords[3 * n + 1];
+    X[a][2] = coords[3 * n + 2];
+  }
+}
+
+// status word bits written by kernels (read back by the host)
+enum : int { kStatusInverted = 1, kStatusNonFinite = 2, kStatusCapacity = 4, kStatusBadPivot = 8 };
+
+}  // namespace pm

@@ -1,0 +1,204 @@
+// Internal declarations of the poromechanics step library (gfx950).
+// Not part of the C ABI: see include/poromech.h for the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "poromech.h"
+#include "pm_geom.h"
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws pm::Error; the C ABI layer converts it to a
+// return code and keeps the message in the context.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define PM_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::pm::Error(PM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_) +   \
+                                     " (" + __FILE__ + ":" + std::to_string(__LINE__) + ")"); \
+  } while (0)
+
+#define PM_CHECK_LAUNCH() PM_HIP(hipGetLastError())
+
+constexpr int kSlice = 64;   // SELL slice height = one wavefront of rows
+constexpr int kBlock = 256;  // default threads per workgroup for streaming kernels
+
+inline int blocks_for(int64_t n, int bs = kBlock) { return (int)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------------------
+// device memory
+void* dmalloc(size_t bytes);
+void dfree(void* p);
+template <class T> T* dalloc(int64_t n) { return (T*)dmalloc(sizeof(T) * (size_t)(n > 0 ? n : 1)); }
+
+// Block compressed sparse row, square blocks of size bs (1 or 3), row-major
+// blocks, columns sorted ascending within a row.
+struct Csr {
+  int bs = 1;
+  int n = 0, m = 0;       // block rows, block columns
+  int64_t nnzb = 0;
+  int* rowptr = nullptr;  // n+1
+  int* col = nullptr;     // nnzb
+  double* val = nullptr;  // nnzb*bs*bs
+  void free_all();
+};
+
+// Sliced ELL with slices of 64 block rows.  Entry column c of a slice holds one
+// block per row (lane): col[c*64 + lane], val[(c*bs*bs + e)*64 + lane].
+// Padding slots have col = -1 and zero values.
+struct Sell {
+  int bs = 1;
+  int n = 0, m = 0;
+  int nslices = 0;
+  int64_t ncols = 0;        // total entry columns over all slices
+  int* sptr = nullptr;      // nslices+1 (entry-column offsets)
+  int* col = nullptr;       // ncols*64
+  double* val = nullptr;    // ncols*64*bs*bs
+  float* val32 = nullptr;   // FP32 copy (mixed precision) or null
+  void free_all();
+};
+
+// One AMG level: operator, smoother data, transfers to the next level.
+struct Level {
+  int bs = 1, n = 0;
+  Csr A;                     // kept for the Galerkin products
+  Sell As;                   // operator used by the cycle
+  double* dinv = nullptr;    // n*bs*bs inverse diagonal blocks
+  float* dinv32 = nullptr;
+  Sell P, R;                 // to/from level+1 (empty on the coarsest level)
+  double lmax = 0.0;         // estimate of lambda_max(D^-1 A)
+  // work vectors (n*bs each)
+  double *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
+  float *xf = nullptr, *bf = nullptr, *rf = nullptr, *df = nullptr, *tf = nullptr;
+  void free_all();
+};
+
+struct AmgParams {
+  double theta = 0.0;
+  int coarse_max = 64;
+  int max_levels = 12;
+  int cheb_degree = 2;
+  double cheb_lower = 1.0 / 30.0;  // Chebyshev interval [lower*lmax, upper*lmax]
+  double cheb_upper = 1.1;
+  int power_its = 15;
+  bool fp32 = false;
+};
+
+struct Hierarchy {
+  int bs = 1;
+  std::vector<Level> L;
+  double* coarse_inv = nullptr;  // dense inverse of the coarsest operator (FP64)
+  int ncoarse = 0;               // scalar size of the coarsest operator
+  double* cwork = nullptr;       // 2*ncoarse scratch
+  double opcx = 0.0;
+  bool fp32 = false;
+  AmgParams prm;
+  void free_all();
+};
+
+}  // namespace pm
+
+// ---------------------------------------------------------------------------
+// the context (opaque in the C ABI)
+struct pm_ctx {
+  hipStream_t s = nullptr;
+  int nx = 0, ny = 0, nz = 0;
+  int64_t nn = 0, nc = 0, nfx = 0, nfy = 0, nfz = 0, nf = 0, nmacro = 0;
+  int64_t n_u = 0, n_p = 0, n_pi = 0, N = 0;
+  double nu = 0.25, biot = 1.0, S = 0.0, mu = 1.0, dt = 1e-2;
+  double trac[3] = {0, 0, -1};
+  double p_top = 0.0;
+  int bc_kind = PM_BC_COLUMN;
+  pm_opts opts{};
+  // inputs on the device
+  double* coords = nullptr;  // nn*3
+  double* E = nullptr;       // nc
+  double* kappa = nullptr;   // nc*3
+  // element data (structure-of-arrays, index [k*nc + cell])
+  double* Ke = nullptr;      // 576*nc element stiffness (assembly scratch)
+  double* ae = nullptr;      // 24*nc coupling column of A_up
+  double* vol = nullptr;     // nc
+  double* Minv = nullptr;    // 36*nc inverse RT0 mass
+  double* g = nullptr;       // 6*nc  M^-1 1
+  double* alpha = nullptr;   // nc    1^T M^-1 1
+  double* stabw = nullptr;   // nmacro: beta_M |M|
+  double* bp = nullptr;      // nc: B~_p
+  double* auu_diag = nullptr;// n_u scalar diagonal of A_uu
+  uint8_t* ufix = nullptr;   // n_u
+  uint8_t* pifix = nullptr;  // n_pi
+  int* status = nullptr;     // device status word (inverted element, NaN, ...)
+  // assembled operators
+  pm::Csr Auu, Cpi;
+  pm::Hierarchy Hu, Hpi;
+  bool assembled = false;
+  bool hier_u_ok = false;
+  // Krylov workspace
+  int m_alloc = 0;
+  double* V = nullptr;       // (m+1)*N
+  double* Z = nullptr;       // m*N
+  double* wvec = nullptr;    // N
+  double* rvec = nullptr;    // N
+  double* xvec = nullptr;    // N
+  double* red = nullptr;     // reduction partials
+  double* hcol = nullptr;    // device scalars (m+2)
+  double* hhost = nullptr;   // pinned host copy
+  // preconditioner work (FP64 and FP32)
+  double* pw64 = nullptr;    // N
+  float* pw32 = nullptr;     // 2*N
+  pm_info info{};
+  std::string err;
+};
+
+namespace pm {
+// topology helpers (host side)
+inline int64_t node_id(const pm_ctx* c, int i, int j, int k) {
+  return i + (int64_t)(c->nx + 1) * (j + (int64_t)(c->ny + 1) * k);
+}
+
+// assembly (pm_assemble.hip)
+Grid grid_of(const pm_ctx* c);
+void assemble_all(pm_ctx* c);          // element kernels, A_uu, B~p, C~pi (no AMG)
+void rebuild_dt(pm_ctx* c);            // B~p, C~pi for the current dt
+void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
+void check_status(pm_ctx* c, const char* where);
+
+// operators (pm_ops.hip)
+void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose);
+void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose);
+void apply_csr(pm_ctx* c, const Csr& A, const double* x, double* y);
+void reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w);
+void grad(pm_ctx* c, const double* lam, const double* x, const double* p_prev, double* dk,
+          double* dE);
+void rhs_adjoint(pm_ctx* c, const double* lam, double* cvec);
+
+// sparse utilities (pm_sparse.hip)
+void exclusive_scan(hipStream_t s, const int* in, int* out, int n, int* total_host);
+void csr_to_sell(hipStream_t s, const Csr& A, Sell& S, bool with_fp32);
+void sell_spmv(hipStream_t s, const Sell& A, const double* x, double* y);
+void sell_spmv32(hipStream_t s, const Sell& A, const float* x, float* y);
+void csr_transpose(hipStream_t s, const Csr& A, Csr& T);
+void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C);
+void block_diag_inverse(hipStream_t s, const Csr& A, double* dinv);
+
+// AMG (pm_amg.hip)
+void amg_setup(hipStream_t s, const Csr& A, const AmgParams& prm, Hierarchy& H);
+void amg_vcycle(hipStream_t s, Hierarchy& H, const double* b, double* x);       // FP64
+void amg_vcycle32(hipStream_t s, Hierarchy& H, const float* b, float* x);       // FP32 levels
+
+// Krylov (pm_krylov.hip)
+int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info);
+double dot(pm_ctx* c, const double* a, const double* b, int64_t n);
+}  // namespace pm

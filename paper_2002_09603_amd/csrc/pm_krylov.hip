@@ -1,0 +1,280 @@
+// Flexible GMRES (right preconditioning, zero initial guess) in FP64 with
+// classical Gram-Schmidt and one re-orthogonalization (CGS2).  Solver
+// settings of Sec. 5: stop when ||b - A x||_2 <= rtol ||b||_2.  The
+// preconditioner may be the FP32 one (the flexible variant keeps the outer
+// recurrence exact in FP64 for a varying inner operator).
+//
+// Device side: fused multi-dot partial sums (deterministic two-stage
+// reductions), multi-AXPY, norms.  Host side: Givens rotations on the small
+// Hessenberg column; one device->host copy per iteration.
+#include <cmath>
+
+#include "pm_internal.h"
+
+namespace pm {
+
+namespace {
+
+constexpr int kDotBlocks = 512;  // partial sums per dot product
+constexpr int kDotGroup = 8;     // basis vectors per multi-dot pass
+
+// part[(i0+g)*kDotBlocks + block] = sum_chunk V_{i0+g} . w, g < cnt
+__global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, int64_t N, int i0, int cnt,
+                                                  const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[kDotGroup][256];
+  double acc[kDotGroup];
+  for (int g = 0; g < kDotGroup; ++g) acc[g] = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
+    const double wk = w[k];
+    for (int g = 0; g < kDotGroup; ++g)
+      if (g < cnt) acc[g] += V[(size_t)(i0 + g) * N + k] * wk;
+  }
+  for (int g = 0; g < kDotGroup; ++g) sh[g][threadIdx.x] = acc[g];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int g = 0; g < kDotGroup; ++g) sh[g][threadIdx.x] += sh[g][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < cnt) part[(size_t)(i0 + threadIdx.x) * kDotBlocks + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+// h[i] = sum_{b < np} part[i*kDotBlocks + b], one workgroup per i
+__global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ part, int cnt, int np,
+                                                   double* __restrict__ h) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
+  if (i >= cnt) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < np; b += 256) s += part[(size_t)i * kDotBlocks + b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[i] = sh[0];
+}
+
+// w -= sum_{i<cnt} coef[i] V_i  (coef on the device)
+__global__ void __launch_bounds__(256) k_multiaxpy(const double* __restrict__ V, int64_t N, int cnt,
+                                                   const double* __restrict__ coef, double* __restrict__ w,
+                                                   double sign) {
+  __shared__ double c[512];
+  for (int i = threadIdx.x; i < cnt; i += 256) c[i] = coef[i];
+  __syncthreads();
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int i = 0; i < cnt; ++i) s += c[i] * V[(size_t)i * N + k];
+    w[k] += sign * s;
+  }
+}
+
+__global__ void k_scale_const(int64_t N, const double* __restrict__ w, double s, double* __restrict__ v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) v[k] = w[k] * s;
+}
+
+__global__ void k_sub(int64_t N, const double* __restrict__ b, const double* __restrict__ a, double* __restrict__ r) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) r[k] = b[k] - a[k];
+}
+
+// sum of squares -> out (two-stage, deterministic)
+__global__ void __launch_bounds__(256) k_sq_part(const double* __restrict__ x, int64_t N, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) s += x[k] * x[k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_dot_part(const double* __restrict__ x, const double* __restrict__ y,
+                                                  int64_t N, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) s += x[k] * y[k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+int grid_for(int64_t N) { return (int)std::min<int64_t>(kDotBlocks, (N + 255) / 256); }
+
+}  // namespace
+
+static void ensure_krylov(pm_ctx* c, int m) {
+  if (c->m_alloc >= m && c->V) return;
+  dfree(c->V);
+  dfree(c->Z);
+  c->V = dalloc<double>((int64_t)(m + 1) * c->N);
+  c->Z = dalloc<double>((int64_t)m * c->N);
+  if (!c->red) c->red = dalloc<double>((int64_t)kDotBlocks * 520);
+  dfree(c->hcol);
+  c->hcol = dalloc<double>(3 * (m + 2) + 8);
+  if (c->hhost) (void)hipHostFree(c->hhost);
+  PM_HIP(hipHostMalloc((void**)&c->hhost, sizeof(double) * (m + 8), hipHostMallocDefault));
+  c->m_alloc = m;
+}
+
+// ||x||^2 into dev[0]; optionally returned to the host (synchronizes)
+static double norm_sq(pm_ctx* c, const double* x, double* dev, bool to_host) {
+  const int64_t N = c->N;
+  const int gb = grid_for(N);
+  k_sq_part<<<gb, 256, 0, c->s>>>(x, N, c->red);
+  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 1, gb, dev);
+  PM_CHECK_LAUNCH();
+  if (!to_host) return 0.0;
+  double h = 0.0;
+  PM_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  PM_HIP(hipStreamSynchronize(c->s));
+  return h;
+}
+
+double dot(pm_ctx* c, const double* a, const double* b, int64_t n) {
+  const int gb = grid_for(n);
+  k_dot_part<<<gb, 256, 0, c->s>>>(a, b, n, c->red);
+  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 1, gb, c->hcol);
+  PM_CHECK_LAUNCH();
+  double h = 0.0;
+  PM_HIP(hipMemcpyAsync(&h, c->hcol, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  PM_HIP(hipStreamSynchronize(c->s));
+  return h;
+}
+
+// CGS pass: hpass[0..nv) = V^T w ; w -= V hpass
+static void cgs_pass(pm_ctx* c, int nv, double* hpass) {
+  const int64_t N = c->N;
+  const int gb = grid_for(N);
+  for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
+    const int cnt = std::min(kDotGroup, nv - i0);
+    k_multidot<<<gb, 256, 0, c->s>>>(c->V, N, i0, cnt, c->wvec, c->red);
+  }
+  k_dot_final<<<nv, 256, 0, c->s>>>(c->red, nv, gb, hpass);
+  k_multiaxpy<<<std::min<int64_t>(2048, (N + 255) / 256), 256, 0, c->s>>>(c->V, N, nv, hpass, c->wvec, -1.0);
+  PM_CHECK_LAUNCH();
+}
+
+__global__ void k_add_vec(int n, const double* __restrict__ a, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] += a[i];
+}
+
+int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info) {
+  const int m = std::max(1, c->opts.restart);
+  const int max_it = std::max(1, c->opts.max_it);
+  const double rtol = c->opts.rtol;
+  if (m > 500) throw Error(PM_EINVAL, "restart length too large (max 500)");
+  ensure_krylov(c, m);
+  const int64_t N = c->N;
+  hipStream_t s = c->s;
+  const int gN = blocks_for(N);
+  double* h1 = c->hcol;               // pass-1 coefficients + norm (m+2)
+  double* h2 = c->hcol + (m + 2);     // pass-2 coefficients, then y (m+2)
+  double* dev_nrm = c->hcol + 2 * (m + 2);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  PM_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+  const double bnorm = std::sqrt(norm_sq(c, b, dev_nrm, true));
+  if (!std::isfinite(bnorm)) throw Error(PM_EBREAKDOWN, "fgmres: right-hand side is not finite");
+  if (info) {
+    info->iters = 0;
+    info->relres_est = 0.0;
+    info->relres_true = 0.0;
+  }
+  if (bnorm == 0.0) return PM_OK;
+  int its = 0;
+  double est = 1.0, relres_true = 1.0, beta = bnorm;
+  bool converged = false;
+  PM_HIP(hipMemcpyAsync(c->rvec, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  while (true) {
+    k_scale_const<<<gN, kBlock, 0, s>>>(N, c->rvec, 1.0 / beta, c->V);
+    PM_CHECK_LAUNCH();
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jdone = 0;
+    for (int j = 0; j < m && its < max_it; ++j) {
+      double* vj = c->V + (size_t)j * N;
+      double* zj = c->Z + (size_t)j * N;
+      apply_Minv(c, vj, zj, transpose);
+      apply_AH(c, zj, c->wvec, transpose);
+      const int nv = j + 1;
+      cgs_pass(c, nv, h1);
+      cgs_pass(c, nv, h2);
+      k_add_vec<<<blocks_for(nv), kBlock, 0, s>>>(nv, h2, h1);
+      norm_sq(c, c->wvec, h1 + nv, false);
+      PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s));
+      PM_HIP(hipStreamSynchronize(s));
+      const double hn = std::sqrt(c->hhost[nv]);
+      bool bad = !std::isfinite(hn);
+      for (int i = 0; i < nv; ++i) {
+        H[(size_t)i * m + j] = c->hhost[i];
+        bad = bad || !std::isfinite(c->hhost[i]);
+      }
+      if (bad) throw Error(PM_EBREAKDOWN, "fgmres: non-finite value in the Arnoldi process");
+      H[(size_t)nv * m + j] = hn;
+      if (hn > 0.0) {
+        k_scale_const<<<gN, kBlock, 0, s>>>(N, c->wvec, 1.0 / hn, c->V + (size_t)(j + 1) * N);
+        PM_CHECK_LAUNCH();
+      }
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, bb);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? bb / den : 0.0;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      jdone = j + 1;
+      est = std::fabs(g[j + 1]) / bnorm;
+      if (est <= rtol || hn == 0.0) break;
+    }
+    // y = H^-1 g (upper triangular); x += Z y
+    for (int i = jdone - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int k = i + 1; k < jdone; ++k) v -= H[(size_t)i * m + k] * y[k];
+      const double d = H[(size_t)i * m + i];
+      if (d == 0.0) throw Error(PM_EBREAKDOWN, "fgmres: singular Hessenberg matrix");
+      y[i] = v / d;
+    }
+    if (jdone > 0) {
+      PM_HIP(hipMemcpyAsync(h2, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
+      k_multiaxpy<<<std::min<int64_t>(2048, (N + 255) / 256), 256, 0, s>>>(c->Z, N, jdone, h2, x, 1.0);
+      PM_CHECK_LAUNCH();
+    }
+    // true residual in FP64; restart from it if needed
+    apply_AH(c, x, c->wvec, transpose);
+    k_sub<<<gN, kBlock, 0, s>>>(N, b, c->wvec, c->rvec);
+    PM_CHECK_LAUNCH();
+    beta = std::sqrt(norm_sq(c, c->rvec, dev_nrm, true));
+    relres_true = beta / bnorm;
+    if (!std::isfinite(relres_true)) throw Error(PM_EBREAKDOWN, "fgmres: non-finite residual");
+    if (relres_true <= rtol) {
+      converged = true;
+      break;
+    }
+    if (its >= max_it || beta == 0.0) break;
+  }
+  if (info) {
+    info->iters = its;
+    info->relres_est = est;
+    info->relres_true = relres_true;
+  }
+  return converged ? PM_OK : PM_ENOCONV;
+}
+
+}  // namespace pm

@@ -1,0 +1,458 @@
+// Block operator A_H (eq. stab_A) and its transpose, the block upper
+// triangular preconditioner M^-1 of eq. hybridPrec (back substitution
+// pi -> p -> u) and M^-T (forward substitution u -> p -> pi), the cell flux
+// reconstruction of Sec. 2.2 and the adjoint gradient kernels.
+//
+// The u-rows use the assembled A_uu (sliced ELL, fused with the coupling
+// gather); the p- and pi-rows are applied element by element from the
+// per-cell data (coupling column a_T, RT0 inverse mass, g_T = M_T^-1 1,
+// alpha_T, beta_M |M|) with implicit structured indexing: this moves fewer
+// bytes than assembled CSR for these blocks and needs no index arrays.
+// Dirichlet dofs are identity rows with zeroed columns (masks ufix, pifix).
+#include "pm_internal.h"
+
+namespace pm {
+
+namespace {
+
+// u-rows: y_u = A_uu u + sgn * A_up p     (sgn = +1: A_H; -1: A_H^T, since A_pu = -A_up^T)
+template <class T>
+__global__ void __launch_bounds__(256) k_ah_u(Grid G, int n, const int* __restrict__ sptr,
+                                              const int* __restrict__ col, const T* __restrict__ val,
+                                              const double* __restrict__ ae, const uint8_t* __restrict__ ufix,
+                                              const T* __restrict__ u, const T* __restrict__ p, double sgn,
+                                              T* __restrict__ y) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = r / kSlice, lane = r % kSlice;
+  if (s * kSlice >= n) return;
+  const int e0 = sptr[s], e1 = sptr[s + 1];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int c = e0; c < e1; ++c) {
+    const int j = col[(size_t)c * kSlice + lane];
+    const T* v = val + (size_t)c * 9 * kSlice + lane;
+    const double x0 = u[3 * (size_t)j], x1 = u[3 * (size_t)j + 1], x2 = u[3 * (size_t)j + 2];
+    for (int a = 0; a < 3; ++a)
+      acc[a] += (double)v[(3 * a + 0) * kSlice] * x0 + (double)v[(3 * a + 1) * kSlice] * x1 +
+                (double)v[(3 * a + 2) * kSlice] * x2;
+  }
+  if (r >= n) return;
+  int i, j, k;
+  G.node_ijk(r, i, j, k);
+  double cp[3] = {0.0, 0.0, 0.0};
+  for (int ck = max(k - 1, 0); ck <= min(k, G.nz - 1); ++ck)
+    for (int cj = max(j - 1, 0); cj <= min(j, G.ny - 1); ++cj)
+      for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
+        const int64_t c = G.cell(ci, cj, ck);
+        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
+        const double pc = (double)p[c];
+        for (int d = 0; d < 3; ++d) cp[d] += ae[(size_t)(3 * a + d) * G.nc + c] * pc;
+      }
+  for (int d = 0; d < 3; ++d) {
+    const size_t q = 3 * (size_t)r + d;
+    y[q] = (T)(acc[d] + (ufix[q] ? 0.0 : sgn * cp[d]));
+  }
+}
+
+// p-rows: y_p = su * sum a_T u + (S|T| + dt alpha) p + A_stab p + spi * sum_e (-g_e) pi_e
+//   A_H:   su = -1, spi = dt      A_H^T: su = +1, spi = 1
+template <class T>
+__global__ void k_ah_p(Grid G, const double* __restrict__ ae, const double* __restrict__ vol,
+                       const double* __restrict__ alpha, const double* __restrict__ gv,
+                       const double* __restrict__ stabw, const uint8_t* __restrict__ ufix,
+                       const uint8_t* __restrict__ pifix, const T* __restrict__ u, const T* __restrict__ p,
+                       const T* __restrict__ pi, double S, double dt, int stabilize, double su, double spi,
+                       T* __restrict__ y) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double v = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    for (int d = 0; d < 3; ++d) {
+      const size_t q = 3 * (size_t)n + d;
+      if (!ufix[q]) v += ae[(size_t)(3 * a + d) * G.nc + c] * (double)u[q];
+    }
+  }
+  v *= su;
+  const double pc = (double)p[c];
+  v += (S * vol[c] + dt * alpha[c]) * pc;
+  if (stabilize) {
+    const double w = stabw[G.macro(i, j, k)];
+    v += w * ((pc - (double)p[G.cell(i ^ 1, j, k)]) + (pc - (double)p[G.cell(i, j ^ 1, k)]) +
+              (pc - (double)p[G.cell(i, j, k ^ 1)]));
+  }
+  int64_t F[6];
+  G.cell_faces(i, j, k, F);
+  double t = 0.0;
+  for (int e = 0; e < 6; ++e)
+    if (!pifix[F[e]]) t -= gv[(size_t)e * G.nc + c] * (double)pi[F[e]];
+  y[c] = (T)(v + spi * t);
+}
+
+// pi-rows: y_pi = sp * sum_T (-g_T[lf]) p_T + sum_T M_T^-1 pi_T (free faces);  fixed: y = pi
+//   A_H: sp = 1    A_H^T: sp = dt
+template <class T>
+__global__ void k_ah_pi(Grid G, const double* __restrict__ Minv, const double* __restrict__ gv,
+                        const uint8_t* __restrict__ pifix, const T* __restrict__ p, const T* __restrict__ pi,
+                        double sp, T* __restrict__ y) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  if (pifix[f]) {
+    y[f] = pi[f];
+    return;
+  }
+  int64_t cc[2];
+  int lf[2];
+  G.face_cells(f, cc, lf);
+  double v = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int64_t c = cc[s];
+    if (c < 0) continue;
+    int i, j, k;
+    G.cell_ijk(c, i, j, k);
+    int64_t F[6];
+    G.cell_faces(i, j, k, F);
+    v -= sp * gv[(size_t)lf[s] * G.nc + c] * (double)p[c];
+    for (int e = 0; e < 6; ++e)
+      if (!pifix[F[e]]) v += Minv[(size_t)(lf[s] * 6 + e) * G.nc + c] * (double)pi[F[e]];
+  }
+  y[f] = (T)v;
+}
+
+// preconditioner pieces -------------------------------------------------------
+// z_p = (r_p - dt A_ppi z_pi) / B~_p
+template <class T>
+__global__ void k_prec_p(Grid G, const double* __restrict__ gv, const double* __restrict__ bp,
+                         const uint8_t* __restrict__ pifix, const T* __restrict__ rp, const T* __restrict__ zpi,
+                         double dt, T* __restrict__ zp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  int64_t F[6];
+  G.cell_faces(i, j, k, F);
+  double t = 0.0;
+  for (int e = 0; e < 6; ++e)
+    if (!pifix[F[e]]) t -= gv[(size_t)e * G.nc + c] * (double)zpi[F[e]];
+  zp[c] = (T)(((double)rp[c] - dt * t) / bp[c]);
+}
+
+// t_u = r_u - A_up z_p
+template <class T>
+__global__ void k_prec_u(Grid G, const double* __restrict__ ae, const uint8_t* __restrict__ ufix,
+                         const T* __restrict__ ru, const T* __restrict__ zp, T* __restrict__ tu) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return;
+  int i, j, k;
+  G.node_ijk(n, i, j, k);
+  double cp[3] = {0.0, 0.0, 0.0};
+  for (int ck = max(k - 1, 0); ck <= min(k, G.nz - 1); ++ck)
+    for (int cj = max(j - 1, 0); cj <= min(j, G.ny - 1); ++cj)
+      for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
+        const int64_t c = G.cell(ci, cj, ck);
+        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
+        const double pc = (double)zp[c];
+        for (int d = 0; d < 3; ++d) cp[d] += ae[(size_t)(3 * a + d) * G.nc + c] * pc;
+      }
+  for (int d = 0; d < 3; ++d) {
+    const size_t q = 3 * (size_t)n + d;
+    tu[q] = (T)((double)ru[q] - (ufix[q] ? 0.0 : cp[d]));
+  }
+}
+
+// transpose pieces: z_p = (r_p - A_up^T z_u) / B~_p ;  t_pi = r_pi - dt A_ppi^T z_p
+template <class T>
+__global__ void k_precT_p(Grid G, const double* __restrict__ ae, const double* __restrict__ bp,
+                          const uint8_t* __restrict__ ufix, const T* __restrict__ rp, const T* __restrict__ zu,
+                          T* __restrict__ zp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double v = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    for (int d = 0; d < 3; ++d) {
+      const size_t q = 3 * (size_t)n + d;
+      if (!ufix[q]) v += ae[(size_t)(3 * a + d) * G.nc + c] * (double)zu[q];
+    }
+  }
+  zp[c] = (T)(((double)rp[c] - v) / bp[c]);
+}
+
+template <class T>
+__global__ void k_precT_pi(Grid G, const double* __restrict__ gv, const uint8_t* __restrict__ pifix,
+                           const T* __restrict__ rpi, const T* __restrict__ zp, double dt, T* __restrict__ tpi) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  if (pifix[f]) {
+    tpi[f] = rpi[f];
+    return;
+  }
+  int64_t cc[2];
+  int lf[2];
+  G.face_cells(f, cc, lf);
+  double v = 0.0;
+  for (int s = 0; s < 2; ++s)
+    if (cc[s] >= 0) v -= gv[(size_t)lf[s] * G.nc + cc[s]] * (double)zp[cc[s]];
+  tpi[f] = (T)((double)rpi[f] - dt * v);
+}
+
+__global__ void k_d2f(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_f2d(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+// flux reconstruction w_T = M_T^-1 (p_T 1 - pi_T)
+__global__ void k_recon_w(Grid G, const double* __restrict__ Minv, const double* __restrict__ p,
+                          const double* __restrict__ pi, double* __restrict__ w) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  int64_t F[6];
+  G.cell_faces(i, j, k, F);
+  double d[6];
+  for (int e = 0; e < 6; ++e) d[e] = p[c] - pi[F[e]];
+  for (int r = 0; r < 6; ++r) {
+    double v = 0.0;
+    for (int e = 0; e < 6; ++e) v += Minv[(size_t)(r * 6 + e) * G.nc + c] * d[e];
+    w[6 * c + r] = v;
+  }
+}
+
+// per-cell gradients (see pm_grad in poromech.h)
+__global__ void k_grad(Grid G, const double* __restrict__ coords, const double* __restrict__ E, double nu,
+                       const double* __restrict__ vol, const double* __restrict__ Minv,
+                       const double* __restrict__ gv, const double* __restrict__ alpha,
+                       const double* __restrict__ stabw, const uint8_t* __restrict__ ufix,
+                       const uint8_t* __restrict__ pifix, const double* __restrict__ lam,
+                       const double* __restrict__ x, const double* __restrict__ p_prev, int64_t n_u,
+                       int64_t n_p, double dt, int stabilize, double* __restrict__ dk, double* __restrict__ dE) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  const double* lu = lam;
+  const double* lp = lam + n_u;
+  const double* lpi = lam + n_u + n_p;
+  const double* u = x;
+  const double* p = x + n_u;
+  const double* pi = x + n_u + n_p;
+  int64_t F[6];
+  G.cell_faces(i, j, k, F);
+  // kappa: condensed element block (linear in kappa_T)
+  const double pc = p[c];
+  double rp = dt * alpha[c] * pc;
+  for (int e = 0; e < 6; ++e) rp -= dt * gv[(size_t)e * G.nc + c] * pi[F[e]];
+  double sk = lp[c] * rp;
+  for (int r = 0; r < 6; ++r) {
+    if (pifix[F[r]]) continue;
+    double v = -gv[(size_t)r * G.nc + c] * pc;
+    for (int e = 0; e < 6; ++e) v += Minv[(size_t)(r * 6 + e) * G.nc + c] * pi[F[e]];
+    sk += lpi[F[r]] * v;
+  }
+  dk[c] += -sk;
+  // E: Q1 stiffness energy lam^T K_T u (linear in E_T), by quadrature
+  double X[8][3], ul[8][3], ll[8][3];
+  load_cell_coords(G, coords, i, j, k, X);
+  for (int a = 0; a < 8; ++a) {
+    const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    for (int d = 0; d < 3; ++d) {
+      ul[a][d] = u[3 * n + d];
+      ll[a][d] = ufix[3 * n + d] ? 0.0 : lu[3 * n + d];
+    }
+  }
+  const double Ec = E[c];
+  const double lmb = Ec * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = Ec / (2.0 * (1.0 + nu));
+  double se = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    double xi[3], J[3][3], Ji[3][3];
+    gauss_point(q, xi);
+    const double det = jacobian(X, xi, J);
+    inv3(J, det, Ji);
+    double gu[3][3] = {{0}}, gl[3][3] = {{0}};  // grad u, grad lam: [comp][dir]
+    for (int a = 0; a < 8; ++a) {
+      double gr[3], gx[3];
+      ref_grad(a, xi, gr);
+      for (int d = 0; d < 3; ++d) gx[d] = gr[0] * Ji[0][d] + gr[1] * Ji[1][d] + gr[2] * Ji[2][d];
+      for (int cc = 0; cc < 3; ++cc)
+        for (int d = 0; d < 3; ++d) {
+          gu[cc][d] += ul[a][cc] * gx[d];
+          gl[cc][d] += ll[a][cc] * gx[d];
+        }
+    }
+    double eu[3][3], el[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        eu[a][b] = 0.5 * (gu[a][b] + gu[b][a]);
+        el[a][b] = 0.5 * (gl[a][b] + gl[b][a]);
+      }
+    const double tu = eu[0][0] + eu[1][1] + eu[2][2], tl = el[0][0] + el[1][1] + el[2][2];
+    double dd = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) dd += el[a][b] * eu[a][b];
+    se += (lmb * tl * tu + 2.0 * mu * dd) * det;
+  }
+  double ge = -se;
+  // E: stabilization coefficient of the macro-element
+  if (stabilize) {
+    const int i0 = i & ~1, j0 = j & ~1, k0 = k & ~1;
+    int64_t mc[8];
+    double W = 0.0;
+    for (int a = 0; a < 8; ++a) {
+      mc[a] = G.cell(i0 + (a & 1), j0 + ((a >> 1) & 1), k0 + ((a >> 2) & 1));
+      W += E[mc[a]] * vol[mc[a]];
+    }
+    double Lq = 0.0;
+    for (int a = 0; a < 8; ++a)
+      for (int d = 0; d < 3; ++d) {
+        const int b = a ^ (1 << d);
+        if ((a >> d) & 1) continue;
+        const double dpa = p[mc[a]] - (p_prev ? p_prev[mc[a]] : 0.0);
+        const double dpb = p[mc[b]] - (p_prev ? p_prev[mc[b]] : 0.0);
+        Lq += (lp[mc[a]] - lp[mc[b]]) * (dpa - dpb);
+      }
+    ge += stabw[G.macro(i, j, k)] * (Ec * vol[c] / W) * Lq;
+  }
+  dE[c] += ge;
+}
+
+// (d b_{n+1} / d x_n)^T lam: c_u += -A_up lam_p ; c_p += (S|T| + A_stab) lam_p
+__global__ void k_rhs_adj_u(Grid G, const double* __restrict__ ae, const double* __restrict__ lp,
+                            double* __restrict__ cu) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return;
+  int i, j, k;
+  G.node_ijk(n, i, j, k);
+  double cp[3] = {0.0, 0.0, 0.0};
+  for (int ck = max(k - 1, 0); ck <= min(k, G.nz - 1); ++ck)
+    for (int cj = max(j - 1, 0); cj <= min(j, G.ny - 1); ++cj)
+      for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
+        const int64_t c = G.cell(ci, cj, ck);
+        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
+        for (int d = 0; d < 3; ++d) cp[d] += ae[(size_t)(3 * a + d) * G.nc + c] * lp[c];
+      }
+  for (int d = 0; d < 3; ++d) cu[3 * n + d] -= cp[d];
+}
+
+__global__ void k_rhs_adj_p(Grid G, const double* __restrict__ vol, const double* __restrict__ stabw,
+                            const double* __restrict__ lp, double S, int stab, double* __restrict__ cp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double v = S * vol[c] * lp[c];
+  if (stab) {
+    const double w = stabw[G.macro(i, j, k)];
+    const double l0 = lp[c];
+    v += w * ((l0 - lp[G.cell(i ^ 1, j, k)]) + (l0 - lp[G.cell(i, j ^ 1, k)]) + (l0 - lp[G.cell(i, j, k ^ 1)]));
+  }
+  cp[c] += v;
+}
+
+template <class T>
+void ah_launch(pm_ctx* c, const T* x, T* y, bool transpose, const Sell& Auu, const T* auu_val) {
+  const Grid G = grid_of(c);
+  const T* u = x;
+  const T* p = x + c->n_u;
+  const T* pi = x + c->n_u + c->n_p;
+  T* yu = y;
+  T* yp = y + c->n_u;
+  T* ypi = y + c->n_u + c->n_p;
+  const int nth = Auu.nslices * kSlice;
+  k_ah_u<T><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.col, auu_val, c->ae, c->ufix, u, p,
+                                                  transpose ? -1.0 : 1.0, yu);
+  k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->ae, c->vol, c->alpha, c->g, c->stabw, c->ufix, c->pifix,
+                                                   u, p, pi, c->S, c->dt, c->opts.stabilize,
+                                                   transpose ? 1.0 : -1.0, transpose ? 1.0 : c->dt, yp);
+  k_ah_pi<T><<<blocks_for(G.nf), kBlock, 0, c->s>>>(G, c->Minv, c->g, c->pifix, p, pi,
+                                                    transpose ? c->dt : 1.0, ypi);
+  PM_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose) {
+  const Sell& A = c->Hu.L[0].As;
+  ah_launch<double>(c, x, y, transpose, A, A.val);
+}
+
+template <class T>
+static void prec_apply_t(pm_ctx* c, const T* r, T* z, T* tmp, bool transpose) {
+  const Grid G = grid_of(c);
+  hipStream_t s = c->s;
+  const T* ru = r;
+  const T* rp = r + c->n_u;
+  const T* rpi = r + c->n_u + c->n_p;
+  T* zu = z;
+  T* zp = z + c->n_u;
+  T* zpi = z + c->n_u + c->n_p;
+  auto vc = [&](pm::Hierarchy& H, const T* b, T* x) {
+    if constexpr (sizeof(T) == 8)
+      amg_vcycle(s, H, (const double*)b, (double*)x);
+    else
+      amg_vcycle32(s, H, (const float*)b, (float*)x);
+  };
+  if (!transpose) {
+    vc(c->Hpi, rpi, zpi);
+    k_prec_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->g, c->bp, c->pifix, rp, zpi, c->dt, zp);
+    k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, c->ae, c->ufix, ru, zp, tmp);
+    PM_CHECK_LAUNCH();
+    vc(c->Hu, tmp, zu);
+  } else {
+    vc(c->Hu, ru, zu);
+    k_precT_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->ae, c->bp, c->ufix, rp, zu, zp);
+    k_precT_pi<T><<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->g, c->pifix, rpi, zp, c->dt, tmp);
+    PM_CHECK_LAUNCH();
+    vc(c->Hpi, tmp, zpi);
+  }
+}
+
+void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose) {
+  if (!c->opts.precond_fp32) {
+    prec_apply_t<double>(c, r, z, c->pw64, transpose);
+    return;
+  }
+  const int64_t N = c->N;
+  float* rf = c->pw32;
+  float* zf = c->pw32 + N;
+  float* tf = c->pw32 + 2 * N;
+  k_d2f<<<blocks_for(N), kBlock, 0, c->s>>>(N, r, rf);
+  PM_CHECK_LAUNCH();
+  prec_apply_t<float>(c, rf, zf, tf, transpose);
+  k_f2d<<<blocks_for(N), kBlock, 0, c->s>>>(N, zf, z);
+  PM_CHECK_LAUNCH();
+}
+
+void reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w) {
+  const Grid G = grid_of(c);
+  k_recon_w<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Minv, p, pi, w);
+  PM_CHECK_LAUNCH();
+}
+
+void grad(pm_ctx* c, const double* lam, const double* x, const double* p_prev, double* dk, double* dE) {
+  const Grid G = grid_of(c);
+  k_grad<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->coords, c->E, c->nu, c->vol, c->Minv, c->g, c->alpha,
+                                                c->stabw, c->ufix, c->pifix, lam, x,
+                                                c->opts.increment_stab ? p_prev : nullptr, c->n_u, c->n_p, c->dt,
+                                                c->opts.stabilize, dk, dE);
+  PM_CHECK_LAUNCH();
+}
+
+void rhs_adjoint(pm_ctx* c, const double* lam, double* cvec) {
+  const Grid G = grid_of(c);
+  const double* lp = lam + c->n_u;
+  k_rhs_adj_u<<<blocks_for(G.nn), kBlock, 0, c->s>>>(G, c->ae, lp, cvec);
+  k_rhs_adj_p<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->vol, c->stabw, lp, c->S,
+                                                     (c->opts.stabilize && c->opts.increment_stab) ? 1 : 0,
+                                                     cvec + c->n_u);
+  PM_CHECK_LAUNCH();
+}
+
+}  // namespace pm

@@ -1,0 +1,184 @@
+"""Python face of the C ABI: a thin object wrapper that marshals torch device
+tensors (or host arrays) into ``pm_*`` calls.  All arithmetic runs in the HIP
+library; this module only allocates output tensors and passes pointers and
+the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _capi
+from ._capi import check, lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        assert t.dtype == np.float64 and t.flags.c_contiguous
+        return t.ctypes.data
+    assert t.dtype == torch.float64 and t.is_contiguous(), "expected a contiguous float64 tensor"
+    return t.data_ptr()
+
+
+def _dev_f64(x, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=device)
+
+
+@dataclass
+class Options:
+    rtol: float = 1e-8
+    restart: int = 100
+    max_it: int = 1000
+    precond_fp32: bool = False
+    stabilize: bool = True
+    increment_stab: bool = True
+    cheb_degree: int = 2
+    coarse_max: int = 64
+    theta_u: float = 0.0
+    theta_pi: float = 0.08
+
+    def to_c(self) -> _capi.pm_opts:
+        o = _capi.pm_opts()
+        o.rtol = self.rtol
+        o.restart = self.restart
+        o.max_it = self.max_it
+        o.precond_fp32 = int(self.precond_fp32)
+        o.stabilize = int(self.stabilize)
+        o.increment_stab = int(self.increment_stab)
+        o.cheb_degree = self.cheb_degree
+        o.coarse_max = self.coarse_max
+        o.theta_u = self.theta_u
+        o.theta_pi = self.theta_pi
+        return o
+
+
+class PoroSolver:
+    """One hybridized poromechanics step on one GPU (see include/poromech.h).
+
+    ``coords`` (n_nodes x 3, or None for a uniform box of size ``L``),
+    ``E`` (n_cells), ``kappa`` (n_cells x 3): numpy arrays or tensors.
+    """
+
+    def __init__(self, nx, ny, nz, E, kappa, coords=None, L=(1.0, 1.0, 1.0), nu=0.25, biot=1.0,
+                 S_eps=0.0, mu=1.0, dt=1e-2, traction=(0.0, 0.0, -1.0), p_top=0.0, rollers=False,
+                 opts: Optional[Options] = None, device="cuda"):
+        self.device = torch.device(device)
+        self.opts = opts or Options()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        E_d = _dev_f64(E, self.device)
+        k_d = _dev_f64(kappa, self.device)
+        X_d = None if coords is None else _dev_f64(coords, self.device)
+        mesh = _capi.pm_mesh(self.nx, self.ny, self.nz, _ptr(X_d), float(L[0]), float(L[1]), float(L[2]))
+        mat = _capi.pm_material(_ptr(E_d), _ptr(k_d), float(nu), float(biot), float(S_eps), float(mu))
+        bc = _capi.pm_bc((C.c_double * 3)(*[float(t) for t in traction]), float(p_top),
+                         _capi.PM_BC_ROLLERS if rollers else _capi.PM_BC_COLUMN)
+        o = self.opts.to_c()
+        self._ctx = C.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib.pm_setup(C.byref(mesh), C.byref(mat), C.byref(bc), float(dt), C.byref(o), C.c_void_p(stream),
+                          C.byref(self._ctx))
+        if rc != _capi.PM_OK:
+            raise _capi.PMError(rc, lib.pm_last_error(None).decode())
+        sz = (C.c_int64 * 6)()
+        check(lib.pm_sizes(self._ctx, sz), self._ctx)
+        self.n_u, self.n_p, self.n_pi, self.N, self.n_nodes, self.n_macro = [int(v) for v in sz]
+
+    # -- lifecycle -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib.pm_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty(self, n):
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    # -- C ABI calls -------------------------------------------------------------
+    def assemble(self):
+        check(lib.pm_assemble(self._ctx), self._ctx)
+        return self
+
+    def set_dt(self, dt):
+        check(lib.pm_set_dt(self._ctx, float(dt)), self._ctx)
+
+    def update_material(self, E=None, kappa=None):
+        E_d = None if E is None else _dev_f64(E, self.device)
+        k_d = None if kappa is None else _dev_f64(kappa, self.device)
+        check(lib.pm_update_material(self._ctx, _ptr(E_d), _ptr(k_d)), self._ctx)
+
+    def build_rhs(self, u_prev=None, p_prev=None, out=None):
+        b = self._empty(self.N) if out is None else out
+        check(lib.pm_build_rhs(self._ctx, _ptr(u_prev), _ptr(p_prev), _ptr(b)), self._ctx)
+        return b
+
+    def _solve(self, fn, b, raise_noconv):
+        u, pi, p = self._empty(self.n_u), self._empty(self.n_pi), self._empty(self.n_p)
+        info = _capi.pm_info()
+        rc = fn(self._ctx, _ptr(b), _ptr(u), _ptr(pi), _ptr(p), C.byref(info))
+        if rc != _capi.PM_OK and (rc != _capi.PM_ENOCONV or raise_noconv):
+            check(rc, self._ctx)
+        d = info.as_dict()
+        d["converged"] = rc == _capi.PM_OK
+        return u, pi, p, d
+
+    def solve(self, b, raise_noconv=True):
+        """A_H x = b -> (u, pi, p, info)."""
+        return self._solve(lib.pm_solve, b, raise_noconv)
+
+    def solve_transpose(self, g, raise_noconv=True):
+        """A_H^T lam = g -> (lam_u, lam_pi, lam_p, info)."""
+        return self._solve(lib.pm_solve_transpose, g, raise_noconv)
+
+    def grad(self, lam, x, p_prev=None, dlogk=None, dlogE=None):
+        dk = torch.zeros(self.n_p, dtype=torch.float64, device=self.device) if dlogk is None else dlogk
+        dE = torch.zeros(self.n_p, dtype=torch.float64, device=self.device) if dlogE is None else dlogE
+        check(lib.pm_grad(self._ctx, _ptr(lam), _ptr(x), _ptr(p_prev), _ptr(dk), _ptr(dE)), self._ctx)
+        return dk, dE
+
+    def rhs_adjoint(self, lam, c):
+        check(lib.pm_rhs_adjoint(self._ctx, _ptr(lam), _ptr(c)), self._ctx)
+        return c
+
+    def reconstruct_w(self, p, pi):
+        w = self._empty(6 * self.n_p)
+        check(lib.pm_reconstruct_w(self._ctx, _ptr(p), _ptr(pi), _ptr(w)), self._ctx)
+        return w.view(self.n_p, 6)
+
+    def apply(self, which, x):
+        n_out = {_capi.PM_OP_CPI: self.n_pi, _capi.PM_OP_BP: self.n_p, _capi.PM_OP_AUU: self.n_u,
+                 _capi.PM_OP_VCYCLE_U: self.n_u, _capi.PM_OP_VCYCLE_PI: self.n_pi}.get(which, self.N)
+        y = self._empty(n_out)
+        check(lib.pm_apply(self._ctx, int(which), _ptr(x), _ptr(y)), self._ctx)
+        return y
+
+    def info(self):
+        i = _capi.pm_info()
+        check(lib.pm_get_info(self._ctx, C.byref(i)), self._ctx)
+        return i.as_dict()
+
+    def pack(self, u, p, pi):
+        return torch.cat([u, p, pi])
+
+    def split(self, x):
+        return x[:self.n_u], x[self.n_u:self.n_u + self.n_p], x[self.n_u + self.n_p:]
+
+
+def from_problem(prob, opts: Optional[Options] = None, device="cuda") -> PoroSolver:
+    """Build a solver from a ``synth.Problem``-like object (attributes only)."""
+    return PoroSolver(prob.nx, prob.ny, prob.nz, prob.E, prob.kappa, coords=prob.coords, nu=prob.nu,
+                      biot=prob.biot, S_eps=prob.S_eps, mu=prob.mu, dt=prob.dt, traction=prob.traction,
+                      p_top=prob.p_top, rollers=getattr(prob, "rollers", False),
+                      opts=opts or Options(stabilize=getattr(prob, "stabilize", True)), device=device)
