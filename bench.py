@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of one backward-Euler step of hybridized poromechanics on one GPU.
+
+Workload (default ``layered128``): 128^3 hexahedral unit cube, 14,877,827
+unknowns (6,440,067 displacement, 6,340,608 face pressure, 2,097,152 cell
+pressure), layered anisotropic permeability (kxx = kyy = 1e-2, kzz = 1e-6 in
+alternating 8-cell layers, isotropic 1e-6 in the others, log-normal sigma=1
+noise), E = 1e4, nu = 0.25, b = 1, S_eps = 0, dt = 1e-2, bottom fixed, top
+loaded and drained.  Mixed precision: AMG V-cycles and the Schur-complement
+apply in FP32 inside FP64 flexible GMRES (FP64 residual, Arnoldi, coarse
+solves), stopped at a relative residual of 1e-8.
+
+One step = the whole hot path on inputs already resident on the device:
+element kernels and static condensation, stabilization, assembly, B~_p,
+C~_pi, both AMG setups, right-hand side, the preconditioned FGMRES solve and
+the flux reconstruction.  The metric is the step's time to solution (s).
+
+Also reported: iterations and phase times, the FP64-preconditioned GPU solve
+of the same system (time, iterations, per-field difference), the roofline of
+the dominant kernel (algorithmic bytes over HIP-event durations of its
+launches inside the timed steps), and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def _cpu_baseline(sample_n: int, full_unknowns: int):
+    """FP64 oracle on a bounded sample of the same workload recipe: assembly
+    plus FGMRES with the paper's exact-inner-solve preconditioner M_I^(h),
+    relative residual 1e-8, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.solve import BlockPrec, fgmres
+    from oracle.system import build_system
+    from synth import make_config
+
+    prob = make_config("layered128", n=sample_n)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        A, b, B = build_system(prob)
+        P = BlockPrec(B)
+        x, its, _ = fgmres(lambda v: A @ v, b, P.apply, rtol=1e-8, restart=200)
+        t = time.perf_counter() - t0
+    n = prob.n_total
+    return {"value": round(t * full_unknowns / n, 3),
+            "unit": "s (projected linearly in unknowns to the full workload; a lower bound, the "
+                    "oracle's sparse LU work grows faster than linearly)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"layered workload recipe at {sample_n}^3 ({n} unknowns): FP64 assembly + FGMRES "
+                      f"with exact inner LU solves (M_I^(h)), rtol 1e-8, {its} iterations, "
+                      f"{t:.2f} s measured"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128, help="cells per axis of the layered workload")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="cells per axis of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioned comparison solve")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not supported",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_09603_amd import _capi
+    from paper_2002_09603_amd.solver import Options, from_problem
+    from synth import make_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = make_config("layered128", n=args.n)
+    opts = Options(rtol=1e-8, precond_fp32=True, restart=100, max_it=1000)
+    s = from_problem(prob, opts, device=dev)
+    b = torch.empty(s.N, dtype=torch.float64, device=dev)
+
+    def step():
+        s.assemble()
+        s.build_rhs(out=b)
+        u, pi, p, info = s.solve(b)
+        w = s.reconstruct_w(p, pi)
+        return u, pi, p, w, info
+
+    # warm-up; the last warm-up step records every instrumented kernel to find the dominant one
+    all_mask = sum(1 << k for k in _capi.PROF_KERNELS)
+    for i in range(max(args.warmup, 1)):
+        if i == max(args.warmup, 1) - 1:
+            s.profile_begin(all_mask)
+        step()
+    torch.cuda.synchronize()
+    totals = {k: s.profile_end(k) for k in _capi.PROF_KERNELS}
+    dom = max(totals, key=lambda k: totals[k][1])
+    s.profile_begin(1 << dom)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        u, pi, p, w, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_l, ms_l, by_l = s.profile_end(dom)
+    s.profile_begin(0)
+    ms_per_step = 1000.0 * elapsed / args.steps
+    achieved = (by_l / 1e9) / (ms_l / 1e3) if ms_l > 0 else 0.0
+    last = infos[-1]
+
+    out = {
+        "metric": "time-to-solution (s) & FGMRES its at relres 1e-8, 128^3 grid; HBM GB/s of SpMV/V-cycle",
+        "value": round(ms_per_step / 1000.0, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 Krylov / f32 preconditioner",
+        "data": "synthetic",
+        "config": {"workload": f"layered{args.n}: {args.n}^3 hex unit cube, layered anisotropic kappa "
+                               "(1e-2,1e-2,1e-6 / 1e-6 in 8-cell layers, lognormal sigma 1), E 1e4, nu 0.25, "
+                               "S_eps 0, dt 1e-2; mixed-precision block-triangular AMG preconditioner, "
+                               "FP64 FGMRES(100), rtol 1e-8",
+                   "unknowns": s.N, "n_u": s.n_u, "n_pi": s.n_pi, "n_p": s.n_p},
+        "iterations": last["iters"],
+        "relres_true": last["relres_true"],
+        "t_asm_s": round(last["t_asm"], 4),
+        "t_setup_s": round(last["t_setup"], 4),
+        "t_solve_s": round(last["t_solve"], 4),
+        "amg_levels": [last["levels_u"], last["levels_pi"]],
+        "amg_operator_complexity": [round(last["opcx_u"], 3), round(last["opcx_pi"], 3)],
+        "roofline": {"bound": "hbm", "kernel": _capi.PROF_KERNELS[dom],
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launches": n_l, "avg_launch_us": round(1000.0 * ms_l / max(n_l, 1), 1),
+                     "algorithmic_bytes_per_launch": round(by_l / max(n_l, 1))},
+        "kernel_share_last_warmup": {_capi.PROF_KERNELS[k]: {"launches": v[0], "ms": round(v[1], 2),
+                                                              "GB/s": round(v[2] / 1e6 / v[1], 1) if v[1] else 0}
+                                     for k, v in totals.items()},
+    }
+
+    if not args.no_fp64:
+        s64 = from_problem(prob, Options(rtol=1e-8, precond_fp32=False, restart=100, max_it=1000), device=dev)
+        s64.assemble()
+        b64 = s64.build_rhs()
+        s64.solve(b64)  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s64.assemble()
+        s64.build_rhs(out=b64)
+        u64, pi64, p64, i64 = s64.solve(b64)
+        s64.reconstruct_w(p64, pi64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+
+        def rel(a, r):
+            return float(torch.linalg.norm(a - r) / torch.linalg.norm(r))
+        out["fp64_precond_solve"] = {
+            "time_to_solution_s": round(t64, 4), "iterations": i64["iters"],
+            "t_setup_s": round(i64["t_setup"], 4), "t_solve_s": round(i64["t_solve"], 4),
+            "mixed_vs_fp64_rel_l2": {"u": rel(u, u64), "p": rel(p, p64), "pi": rel(pi, pi64)}}
+        s64.close()
+    s.close()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(args.cpu_sample, out["config"]["unknowns"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -188,6 +188,26 @@ enum { PM_OP_AH = 0, PM_OP_AHT = 1, PM_OP_MINV = 2, PM_OP_MINVT = 3, PM_OP_CPI =
        PM_OP_BP = 5, PM_OP_AUU = 6, PM_OP_VCYCLE_U = 7, PM_OP_VCYCLE_PI = 8 };
 int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
 
+/* Kernel timing for roofline measurements.  pm_profile_begin clears the
+ * records and, for every kernel whose bit (1 << id) is set in mask, records a
+ * pair of HIP events on the launching stream around each later launch, with
+ * the algorithmic bytes that launch must move (stored values and indices,
+ * each input vector read once, each output written once).  pm_profile_end
+ * synchronizes the recorded events and returns, for kernel id, the number of
+ * launches, their summed duration (ms) and summed algorithmic bytes; it does
+ * not stop the recording (call pm_profile_begin(ctx, 0) for that).  Ids:
+ *   1 u-rows of A_H (assembled A_uu, FP64, fused coupling gather)
+ *   2 fused Chebyshev smoothing step on the finest A_uu level
+ *   3 fused Chebyshev smoothing step on the finest C~_pi level
+ *   4 FGMRES multi-dot (Gram-Schmidt projections)
+ *   5 FGMRES multi-AXPY
+ *   6 restriction from the finest A_uu level
+ * The recorder is process-wide (one context at a time). */
+enum { PM_PROF_AH_U = 1, PM_PROF_CHEB_U0 = 2, PM_PROF_CHEB_PI0 = 3, PM_PROF_MULTIDOT = 4,
+       PM_PROF_MULTIAXPY = 5, PM_PROF_RESTRICT_U0 = 6 };
+int pm_profile_begin(pm_ctx* ctx, uint32_t mask);
+int pm_profile_end(pm_ctx* ctx, int id, int64_t* launches, double* ms, double* bytes);
+
 /* Sizes: out[0..5] = n_u, n_p, n_pi, N, n_nodes, n_macro. */
 int pm_sizes(const pm_ctx* ctx, int64_t* out);
 

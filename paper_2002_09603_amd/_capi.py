@@ -18,6 +18,10 @@ PM_BC_COLUMN, PM_BC_ROLLERS = 0, 1
 PM_OP_AH, PM_OP_AHT, PM_OP_MINV, PM_OP_MINVT, PM_OP_CPI, PM_OP_BP, PM_OP_AUU, \
     PM_OP_VCYCLE_U, PM_OP_VCYCLE_PI = range(9)
 
+PROF_KERNELS = {1: "k_ah_u<double>", 2: "k_cheb_step<3,float|double> (finest A_uu level)",
+                3: "k_cheb_step<1,float|double> (finest C~pi level)", 4: "k_multidot", 5: "k_multiaxpy",
+                6: "k_sell_apply<3,...,false> (restriction, finest A_uu level)"}
+
 ERROR_NAMES = {PM_EINVAL: "PM_EINVAL", PM_ENOMEM: "PM_ENOMEM", PM_EHIP: "PM_EHIP",
                PM_ENOCONV: "PM_ENOCONV", PM_EBREAKDOWN: "PM_EBREAKDOWN",
                PM_ESTATE: "PM_ESTATE", PM_EINTERNAL: "PM_EINTERNAL"}
@@ -70,6 +74,9 @@ _SIGS = [
     ("pm_rhs_adjoint", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pm_reconstruct_w", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pm_apply", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    ("pm_profile_begin", C.c_int, [C.c_void_p, C.c_uint32]),
+    ("pm_profile_end", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double)]),
     ("pm_sizes", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("pm_get_info", C.c_int, [C.c_void_p, C.POINTER(pm_info)]),
     ("pm_last_error", C.c_char_p, [C.c_void_p]),

@@ -705,7 +705,7 @@ void alloc_level_vectors(Level& L, bool fp32) {
 // Returns the buffer holding the result (x or t).
 template <int BS, class T>
 T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T* x, T* t, T* d, bool zero_init,
-             const T* val, const T* dinv) {
+             const T* val, const T* dinv, int prof_id) {
   const double lo = prm.cheb_lower * L.lmax, hi = prm.cheb_upper * L.lmax;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
   const double sigma = theta / delta;
@@ -730,8 +730,13 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
       c2 = 2.0 * rn / delta;
       rho = rn;
     }
+    g_prof.begin(s, prof_id);
     k_cheb_step<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, val, dinv, b, cur, nxt, d, (T)c1,
                                                           (T)c2);
+    // algorithmic bytes: blocks + column ids, x/b/d read, x/d written, D^-1 blocks
+    g_prof.end(s, prof_id,
+               (double)L.As.nnzb * (BS * BS * sizeof(T) + 4) + (double)n * BS * sizeof(T) * 5 +
+                   (double)n * BS * BS * sizeof(T));
     T* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -781,20 +786,24 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   T* t = LP::Tt(L);
   T* r = LP::Rr(L);
   // pre-smoothing from zero
-  T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI);
+  const int prof_id = l == 0 ? (BS == 3 ? kProfChebU0 : kProfChebPi0) : 0;
+  T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI, prof_id);
   // residual, restriction
   const int nth = L.As.nslices * kSlice;
   k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
   Level& C = H.L[l + 1];
   const int cth = L.R.nslices * kSlice;
+  const int rprof = (l == 0 && BS == 3) ? kProfRestrictU0 : 0;
+  g_prof.begin(s, rprof);
   k_sell_apply<BS, T, false><<<blocks_for(cth), kBlock, 0, s>>>(L.R.n, L.R.sptr, L.R.col, LP::AV(L.R), r, LP::B(C));
+  g_prof.end(s, rprof, (double)L.R.nnzb * (BS * BS * sizeof(T) + 4) + (double)(n + C.n) * BS * sizeof(T));
   vcycle_level<BS, T>(s, H, prm, l + 1, LP::B(C), LP::X(C));
   const int pth = L.P.nslices * kSlice;
   k_sell_apply<BS, T, true><<<blocks_for(pth), kBlock, 0, s>>>(L.P.n, L.P.sptr, L.P.col, LP::AV(L.P), LP::X(C), cur);
   PM_CHECK_LAUNCH();
   // post-smoothing from the corrected iterate
   T* other = (cur == x) ? t : x;
-  T* res = chebyshev<BS, T>(s, L, prm, b, cur, other, d, false, AV, DI);
+  T* res = chebyshev<BS, T>(s, L, prm, b, cur, other, d, false, AV, DI, prof_id);
   if (res != x) PM_HIP(hipMemcpyAsync(x, res, sizeof(T) * (size_t)n * BS, hipMemcpyDeviceToDevice, s));
 }
 

@@ -369,6 +369,25 @@ int pm_apply(pm_ctx* c, int which, const double* x, double* y) {
   });
 }
 
+int pm_profile_begin(pm_ctx* c, uint32_t mask) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (mask & ~((1u << pm::kProfCount) - 2u)) throw Error(PM_EINVAL, "pm_profile_begin: unknown kernel id in mask");
+    pm::g_prof.reset(mask);
+    return PM_OK;
+  });
+}
+
+int pm_profile_end(pm_ctx* c, int id, int64_t* launches, double* ms, double* bytes) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (id < 1 || id >= pm::kProfCount || !launches || !ms || !bytes)
+      throw Error(PM_EINVAL, "pm_profile_end: bad kernel id or NULL output");
+    pm::g_prof.collect(id, launches, ms, bytes);
+    return PM_OK;
+  });
+}
+
 int pm_sizes(const pm_ctx* c, int64_t* out) {
   if (!c || !out) return PM_EINVAL;
   out[0] = c->n_u;

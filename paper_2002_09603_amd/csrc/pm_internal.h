@@ -39,6 +39,36 @@ constexpr int kBlock = 256;  // default threads per workgroup for streaming kern
 inline int blocks_for(int64_t n, int bs = kBlock) { return (int)((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------------------------
+// kernel profiler: HIP events around the launches of selected kernels on
+// their own stream, with the algorithmic bytes each launch must move
+enum ProfKernel : int {
+  kProfAHu = 1,          // u-rows of A_H (assembled A_uu SELL, FP64, fused coupling)
+  kProfChebU0 = 2,       // fused Chebyshev step on the finest A_uu level
+  kProfChebPi0 = 3,      // fused Chebyshev step on the finest C~_pi level
+  kProfMultidot = 4,     // FGMRES multi-dot (Gram-Schmidt projections)
+  kProfMultiaxpy = 5,    // FGMRES multi-AXPY
+  kProfRestrictU0 = 6,   // restriction from the finest A_uu level
+  kProfCount = 7
+};
+
+struct Profiler {
+  unsigned mask = 0;
+  struct Rec {
+    hipEvent_t a = nullptr, b = nullptr;
+    double bytes = 0.0;
+  };
+  std::vector<Rec> recs[kProfCount];
+  size_t used[kProfCount] = {0};
+  bool on(int k) const { return (mask >> k) & 1u; }
+  void begin(hipStream_t s, int k);
+  void end(hipStream_t s, int k, double bytes);
+  void reset(unsigned m);
+  // sums over recorded launches of kernel k (synchronizes the events)
+  void collect(int k, int64_t* n, double* ms, double* bytes);
+};
+extern Profiler g_prof;
+
+// ---------------------------------------------------------------------------
 // device memory
 void* dmalloc(size_t bytes);
 void dfree(void* p);
@@ -64,6 +94,7 @@ struct Sell {
   int n = 0, m = 0;
   int nslices = 0;
   int64_t ncols = 0;        // total entry columns over all slices
+  int64_t nnzb = 0;         // stored blocks of the source matrix (no padding)
   int* sptr = nullptr;      // nslices+1 (entry-column offsets)
   int* col = nullptr;       // ncols*64
   double* val = nullptr;    // ncols*64*bs*bs

@@ -15,59 +15,84 @@ namespace pm {
 
 namespace {
 
-constexpr int kDotBlocks = 512;  // partial sums per dot product
-constexpr int kDotGroup = 8;     // basis vectors per multi-dot pass
+constexpr int kDotBlocks = 2048;  // partial sums per dot product (8 workgroups per CU)
+constexpr int kDotGroup = 8;      // basis vectors per multi-dot pass
+constexpr int kPartRows = 504;    // rows of the partial-sum buffer (basis vectors + 2 norms)
 
-// part[(i0+g)*kDotBlocks + block] = sum_chunk V_{i0+g} . w, g < cnt
+// part[(i0+g)*kDotBlocks + block] = sum_chunk V_{i0+g} . w for g < cnt; with
+// self_row >= 0 also part[self_row*kDotBlocks + block] = sum_chunk w . w
 __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, int64_t N, int i0, int cnt,
-                                                  const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double sh[kDotGroup][256];
-  double acc[kDotGroup];
-  for (int g = 0; g < kDotGroup; ++g) acc[g] = 0.0;
+                                                  const double* __restrict__ w, double* __restrict__ part,
+                                                  int self_row) {
+  __shared__ double sh[kDotGroup + 1][256];
+  double acc[kDotGroup + 1];
+  for (int g = 0; g <= kDotGroup; ++g) acc[g] = 0.0;
+  const double* Vi = V + (size_t)i0 * N;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
     const double wk = w[k];
+#pragma unroll
     for (int g = 0; g < kDotGroup; ++g)
-      if (g < cnt) acc[g] += V[(size_t)(i0 + g) * N + k] * wk;
+      if (g < cnt) acc[g] += Vi[(size_t)g * N + k] * wk;
+    acc[kDotGroup] += wk * wk;
   }
-  for (int g = 0; g < kDotGroup; ++g) sh[g][threadIdx.x] = acc[g];
+  for (int g = 0; g <= kDotGroup; ++g) sh[g][threadIdx.x] = acc[g];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off)
-      for (int g = 0; g < kDotGroup; ++g) sh[g][threadIdx.x] += sh[g][threadIdx.x + off];
+      for (int g = 0; g <= kDotGroup; ++g) sh[g][threadIdx.x] += sh[g][threadIdx.x + off];
     __syncthreads();
   }
   if (threadIdx.x < cnt) part[(size_t)(i0 + threadIdx.x) * kDotBlocks + blockIdx.x] = sh[threadIdx.x][0];
+  if (self_row >= 0 && threadIdx.x == 0) part[(size_t)self_row * kDotBlocks + blockIdx.x] = sh[kDotGroup][0];
 }
 
-// h[i] = sum_{b < np} part[i*kDotBlocks + b], one workgroup per i
-__global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ part, int cnt, int np,
+// h[row0 + i] = sum_{b < np} part[(row0 + i)*kDotBlocks + b], one workgroup per i
+__global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ part, int row0, int cnt, int np,
                                                    double* __restrict__ h) {
   __shared__ double sh[256];
   const int i = blockIdx.x;
   if (i >= cnt) return;
   double s = 0.0;
-  for (int b = threadIdx.x; b < np; b += 256) s += part[(size_t)i * kDotBlocks + b];
+  for (int b = threadIdx.x; b < np; b += 256) s += part[(size_t)(row0 + i) * kDotBlocks + b];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) h[i] = sh[0];
+  if (threadIdx.x == 0) h[row0 + i] = sh[0];
 }
 
-// w -= sum_{i<cnt} coef[i] V_i  (coef on the device)
+// w += sign * sum_{i<cnt} coef[i] V_i (coef on the device); with norm_row >= 0
+// also part[norm_row*kDotBlocks + block] = sum_chunk w_new . w_new
 __global__ void __launch_bounds__(256) k_multiaxpy(const double* __restrict__ V, int64_t N, int cnt,
                                                    const double* __restrict__ coef, double* __restrict__ w,
-                                                   double sign) {
+                                                   double sign, double* __restrict__ part, int norm_row) {
   __shared__ double c[512];
+  __shared__ double sh[256];
   for (int i = threadIdx.x; i < cnt; i += 256) c[i] = coef[i];
   __syncthreads();
+  double nn = 0.0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
-    double s = 0.0;
-    for (int i = 0; i < cnt; ++i) s += c[i] * V[(size_t)i * N + k];
-    w[k] += sign * s;
+    double s0 = 0.0, s1 = 0.0;
+    int i = 0;
+    for (; i + 1 < cnt; i += 2) {
+      s0 += c[i] * V[(size_t)i * N + k];
+      s1 += c[i + 1] * V[(size_t)(i + 1) * N + k];
+    }
+    if (i < cnt) s0 += c[i] * V[(size_t)i * N + k];
+    const double wn = w[k] + sign * (s0 + s1);
+    w[k] = wn;
+    nn += wn * wn;
   }
+  if (norm_row < 0) return;
+  sh[threadIdx.x] = nn;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)norm_row * kDotBlocks + blockIdx.x] = sh[0];
 }
 
 __global__ void k_scale_const(int64_t N, const double* __restrict__ w, double s, double* __restrict__ v) {
@@ -110,6 +135,7 @@ __global__ void __launch_bounds__(256) k_dot_part(const double* __restrict__ x, 
 
 int grid_for(int64_t N) { return (int)std::min<int64_t>(kDotBlocks, (N + 255) / 256); }
 
+
 }  // namespace
 
 static void ensure_krylov(pm_ctx* c, int m) {
@@ -118,7 +144,7 @@ static void ensure_krylov(pm_ctx* c, int m) {
   dfree(c->Z);
   c->V = dalloc<double>((int64_t)(m + 1) * c->N);
   c->Z = dalloc<double>((int64_t)m * c->N);
-  if (!c->red) c->red = dalloc<double>((int64_t)kDotBlocks * 520);
+  if (!c->red) c->red = dalloc<double>((int64_t)kDotBlocks * kPartRows);
   dfree(c->hcol);
   c->hcol = dalloc<double>(3 * (m + 2) + 8);
   if (c->hhost) (void)hipHostFree(c->hhost);
@@ -131,7 +157,7 @@ static double norm_sq(pm_ctx* c, const double* x, double* dev, bool to_host) {
   const int64_t N = c->N;
   const int gb = grid_for(N);
   k_sq_part<<<gb, 256, 0, c->s>>>(x, N, c->red);
-  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 1, gb, dev);
+  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 0, 1, gb, dev);
   PM_CHECK_LAUNCH();
   if (!to_host) return 0.0;
   double h = 0.0;
@@ -143,7 +169,7 @@ static double norm_sq(pm_ctx* c, const double* x, double* dev, bool to_host) {
 double dot(pm_ctx* c, const double* a, const double* b, int64_t n) {
   const int gb = grid_for(n);
   k_dot_part<<<gb, 256, 0, c->s>>>(a, b, n, c->red);
-  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 1, gb, c->hcol);
+  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 0, 1, gb, c->hcol);
   PM_CHECK_LAUNCH();
   double h = 0.0;
   PM_HIP(hipMemcpyAsync(&h, c->hcol, sizeof(double), hipMemcpyDeviceToHost, c->s));
@@ -151,16 +177,22 @@ double dot(pm_ctx* c, const double* a, const double* b, int64_t n) {
   return h;
 }
 
-// CGS pass: hpass[0..nv) = V^T w ; w -= V hpass
-static void cgs_pass(pm_ctx* c, int nv, double* hpass) {
+// One classical Gram-Schmidt pass against V[0..nv): hpass[0..nv) = V^T w,
+// w -= V hpass.  With self_norm, hpass[nv] = ||w||^2 before the pass.  The
+// partial sums of ||w_new||^2 are left in row nv+1 of the partial buffer.
+static void cgs_pass(pm_ctx* c, int nv, double* hpass, bool self_norm) {
   const int64_t N = c->N;
   const int gb = grid_for(N);
   for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
     const int cnt = std::min(kDotGroup, nv - i0);
-    k_multidot<<<gb, 256, 0, c->s>>>(c->V, N, i0, cnt, c->wvec, c->red);
+    g_prof.begin(c->s, kProfMultidot);
+    k_multidot<<<gb, 256, 0, c->s>>>(c->V, N, i0, cnt, c->wvec, c->red, (self_norm && i0 == 0) ? nv : -1);
+    g_prof.end(c->s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
   }
-  k_dot_final<<<nv, 256, 0, c->s>>>(c->red, nv, gb, hpass);
-  k_multiaxpy<<<std::min<int64_t>(2048, (N + 255) / 256), 256, 0, c->s>>>(c->V, N, nv, hpass, c->wvec, -1.0);
+  k_dot_final<<<nv + (self_norm ? 1 : 0), 256, 0, c->s>>>(c->red, 0, nv + (self_norm ? 1 : 0), gb, hpass);
+  g_prof.begin(c->s, kProfMultiaxpy);
+  k_multiaxpy<<<gb, 256, 0, c->s>>>(c->V, N, nv, hpass, c->wvec, -1.0, c->red, nv + 1);
+  g_prof.end(c->s, kProfMultiaxpy, (double)(nv + 2) * N * 8.0);
   PM_CHECK_LAUNCH();
 }
 
@@ -207,13 +239,15 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
       apply_Minv(c, vj, zj, transpose);
       apply_AH(c, zj, c->wvec, transpose);
       const int nv = j + 1;
-      cgs_pass(c, nv, h1);
-      cgs_pass(c, nv, h2);
+      // CGS2: two projection passes; h1[nv+1] = ||w||^2 after both
+      cgs_pass(c, nv, h1, false);
+      cgs_pass(c, nv, h2, false);
+      k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, grid_for(N), h1);
       k_add_vec<<<blocks_for(nv), kBlock, 0, s>>>(nv, h2, h1);
-      norm_sq(c, c->wvec, h1 + nv, false);
-      PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s));
+      PM_CHECK_LAUNCH();
+      PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
       PM_HIP(hipStreamSynchronize(s));
-      const double hn = std::sqrt(c->hhost[nv]);
+      const double hn = std::sqrt(c->hhost[nv + 1]);
       bool bad = !std::isfinite(hn);
       for (int i = 0; i < nv; ++i) {
         H[(size_t)i * m + j] = c->hhost[i];
@@ -253,7 +287,7 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
     }
     if (jdone > 0) {
       PM_HIP(hipMemcpyAsync(h2, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
-      k_multiaxpy<<<std::min<int64_t>(2048, (N + 255) / 256), 256, 0, s>>>(c->Z, N, jdone, h2, x, 1.0);
+      k_multiaxpy<<<grid_for(N), 256, 0, s>>>(c->Z, N, jdone, h2, x, 1.0, c->red, -1);
       PM_CHECK_LAUNCH();
     }
     // true residual in FP64; restart from it if needed

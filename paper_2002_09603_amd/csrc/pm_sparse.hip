@@ -21,6 +21,47 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+Profiler g_prof;
+
+void Profiler::begin(hipStream_t s, int k) {
+  if (!on(k)) return;
+  auto& v = recs[k];
+  if (used[k] == v.size()) {
+    Rec r;
+    PM_HIP(hipEventCreate(&r.a));
+    PM_HIP(hipEventCreate(&r.b));
+    v.push_back(r);
+  }
+  PM_HIP(hipEventRecord(v[used[k]].a, s));
+}
+
+void Profiler::end(hipStream_t s, int k, double bytes) {
+  if (!on(k)) return;
+  Rec& r = recs[k][used[k]];
+  PM_HIP(hipEventRecord(r.b, s));
+  r.bytes = bytes;
+  ++used[k];
+}
+
+void Profiler::reset(unsigned m) {
+  mask = m;
+  for (int k = 0; k < kProfCount; ++k) used[k] = 0;
+}
+
+void Profiler::collect(int k, int64_t* n, double* ms, double* bytes) {
+  double t = 0.0, b = 0.0;
+  for (size_t i = 0; i < used[k]; ++i) {
+    PM_HIP(hipEventSynchronize(recs[k][i].b));
+    float e = 0.0f;
+    PM_HIP(hipEventElapsedTime(&e, recs[k][i].a, recs[k][i].b));
+    t += e;
+    b += recs[k][i].bytes;
+  }
+  *n = (int64_t)used[k];
+  *ms = t;
+  *bytes = b;
+}
+
 void Csr::free_all() {
   dfree(rowptr);
   dfree(col);
@@ -43,6 +84,7 @@ void Sell::free_all() {
   val32 = nullptr;
   n = m = nslices = 0;
   ncols = 0;
+  nnzb = 0;
 }
 
 namespace {
@@ -450,6 +492,7 @@ void csr_to_sell(hipStream_t s, const Csr& A, Sell& S, bool with_fp32) {
   S.n = A.n;
   S.m = A.m;
   S.nslices = (A.n + kSlice - 1) / kSlice;
+  S.nnzb = A.nnzb;
   int* w = dalloc<int>(S.nslices);
   k_slice_width<<<blocks_for(S.nslices), kBlock, 0, s>>>(A.rowptr, A.n, S.nslices, w);
   PM_CHECK_LAUNCH();

@@ -164,6 +164,14 @@ class PoroSolver:
         check(lib.pm_apply(self._ctx, int(which), _ptr(x), _ptr(y)), self._ctx)
         return y
 
+    def profile_begin(self, mask):
+        check(lib.pm_profile_begin(self._ctx, int(mask)), self._ctx)
+
+    def profile_end(self, kernel_id):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        check(lib.pm_profile_end(self._ctx, int(kernel_id), C.byref(n), C.byref(ms), C.byref(by)), self._ctx)
+        return int(n.value), float(ms.value), float(by.value)
+
     def info(self):
         i = _capi.pm_info()
         check(lib.pm_get_info(self._ctx, C.byref(i)), self._ctx)
