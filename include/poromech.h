@@ -96,8 +96,12 @@ typedef struct {
   int32_t precond_fp32;      /* 1: AMG hierarchies, V-cycles and Schur apply in FP32 */
   int32_t stabilize;         /* 1: add the macro-element pressure-jump term */
   int32_t increment_stab;    /* 1: stabilization acts on p_n - p_{n-1} (RHS term A_stab p_{n-1}) */
-  int32_t cheb_degree;       /* Chebyshev smoother degree per pre/post smoothing (>= 1) */
+  int32_t cheb_degree;       /* Chebyshev smoother degree per pre/post smoothing, A_uu (>= 1) */
   int32_t coarse_max;        /* AMG: stop coarsening below this many block rows */
+  int32_t cheb_degree_pi;    /* Chebyshev smoother degree, C~_pi hierarchy (>= 1) */
+  int32_t cycles_u;          /* V-cycles per application of the A_uu block (>= 1) */
+  int32_t cycles_pi;         /* V-cycles per application of the C~_pi block (>= 1) */
+  int32_t orth_passes;       /* classical Gram-Schmidt passes per Arnoldi step: 1 or 2 */
   double theta_u;            /* AMG strength threshold, displacement block */
   double theta_pi;           /* AMG strength threshold, face-pressure Schur block */
 } pm_opts;
@@ -112,7 +116,9 @@ typedef struct {
 } pm_info;
 
 /* Default options: rtol 1e-8, restart 100, max_it 1000, FP64, stabilize,
- * increment form, Chebyshev degree 2, coarse_max 64, theta 0 / 0.08. */
+ * increment form, Chebyshev degree 2 (A_uu) / 2 (C~_pi), coarse_max 64, one
+ * V-cycle per block, two Gram-Schmidt passes, strength thresholds theta
+ * 0 (A_uu) / 0.08 (C~_pi). */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

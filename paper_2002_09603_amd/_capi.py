@@ -45,6 +45,8 @@ class pm_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_it", C.c_int32),
                 ("precond_fp32", C.c_int32), ("stabilize", C.c_int32), ("increment_stab", C.c_int32),
                 ("cheb_degree", C.c_int32), ("coarse_max", C.c_int32),
+                ("cheb_degree_pi", C.c_int32), ("cycles_u", C.c_int32), ("cycles_pi", C.c_int32),
+                ("orth_passes", C.c_int32),
                 ("theta_u", C.c_double), ("theta_pi", C.c_double)]
 
 

@@ -49,8 +49,14 @@ void Hierarchy::free_all() {
   L.clear();
   dfree(coarse_inv);
   dfree(cwork);
+  dfree(r0);
+  dfree(c0);
+  dfree(r0f);
+  dfree(c0f);
   coarse_inv = nullptr;
   cwork = nullptr;
+  r0 = c0 = nullptr;
+  r0f = c0f = nullptr;
   ncoarse = 0;
 }
 
@@ -878,26 +884,60 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H)
     cur = Ac;
   }
   H.opcx = nnz_total / nnz0;
+  if (prm.cycles > 1) {
+    const int64_t m0 = (int64_t)A0.n * A0.bs;
+    H.r0 = dalloc<double>(m0);
+    H.c0 = dalloc<double>(m0);
+    if (prm.fp32) {
+      H.r0f = dalloc<float>(m0);
+      H.c0f = dalloc<float>(m0);
+    }
+  }
   if (verbose)
     fprintf(stderr, "[amg bs=%d] %zu levels, coarsest %d unknowns (dense), operator complexity %.3f\n", H.bs,
             H.L.size(), H.ncoarse, H.opcx);
   PM_HIP(hipStreamSynchronize(s));
 }
 
+namespace {
+
+template <class T>
+__global__ void k_axpy_inplace(int64_t n, const T* __restrict__ a, T* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += a[i];
+}
+
+// x = B b with B = k iterated V-cycles (x_{j+1} = x_j + V (b - A x_j), x_0 = 0);
+// the composite is symmetric when V is, so it also serves the transpose.
+template <int BS, class T>
+void iterated_cycles(hipStream_t s, Hierarchy& H, const T* b, T* x, T* r0, T* c0) {
+  using LP = LevelPtrs<BS, T>;
+  vcycle_level<BS, T>(s, H, H.prm, 0, b, x);
+  Level& L = H.L[0];
+  const int64_t m = (int64_t)L.n * BS;
+  for (int c = 1; c < H.prm.cycles; ++c) {
+    const int nth = L.As.nslices * kSlice;
+    k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(L.n, L.As.sptr, L.As.col, LP::AV(L.As), b, x, r0);
+    vcycle_level<BS, T>(s, H, H.prm, 0, r0, c0);
+    k_axpy_inplace<T><<<blocks_for(m), kBlock, 0, s>>>(m, c0, x);
+    PM_CHECK_LAUNCH();
+  }
+}
+
+}  // namespace
+
 void amg_vcycle(hipStream_t s, Hierarchy& H, const double* b, double* x) {
-  const AmgParams& prm = H.prm;
   if (H.bs == 3)
-    vcycle_level<3, double>(s, H, prm, 0, b, x);
+    iterated_cycles<3, double>(s, H, b, x, H.r0, H.c0);
   else
-    vcycle_level<1, double>(s, H, prm, 0, b, x);
+    iterated_cycles<1, double>(s, H, b, x, H.r0, H.c0);
 }
 
 void amg_vcycle32(hipStream_t s, Hierarchy& H, const float* b, float* x) {
-  const AmgParams& prm = H.prm;
   if (H.bs == 3)
-    vcycle_level<3, float>(s, H, prm, 0, b, x);
+    iterated_cycles<3, float>(s, H, b, x, H.r0f, H.c0f);
   else
-    vcycle_level<1, float>(s, H, prm, 0, b, x);
+    iterated_cycles<1, float>(s, H, b, x, H.r0f, H.c0f);
 }
 
 }  // namespace pm

@@ -23,8 +23,11 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+int g_live_contexts = 0;
+
 template <class F>
 int guarded(pm_ctx* c, F&& f) {
+  if (c) pm::set_alloc_stream(c->s);
   try {
     return f();
   } catch (const Error& e) {
@@ -69,6 +72,7 @@ pm::AmgParams params_u(const pm_ctx* c) {
   p.theta = c->opts.theta_u;
   p.coarse_max = c->opts.coarse_max;
   p.cheb_degree = c->opts.cheb_degree;
+  p.cycles = c->opts.cycles_u;
   p.fp32 = c->opts.precond_fp32 != 0;
   return p;
 }
@@ -77,6 +81,8 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   pm::AmgParams p = params_u(c);
   p.theta = c->opts.theta_pi;
   p.coarse_max = c->opts.coarse_max * 3;
+  p.cheb_degree = c->opts.cheb_degree_pi;
+  p.cycles = c->opts.cycles_pi;
   return p;
 }
 
@@ -129,6 +135,10 @@ void pm_default_opts(pm_opts* o) {
   o->increment_stab = 1;
   o->cheb_degree = 2;
   o->coarse_max = 64;
+  o->cheb_degree_pi = 2;
+  o->cycles_u = 1;
+  o->cycles_pi = 1;
+  o->orth_passes = 2;
   o->theta_u = 0.0;
   o->theta_pi = 0.08;
 }
@@ -156,6 +166,7 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(PM_EINVAL, "pm_setup: dt must be positive");
     if (bc->kind != PM_BC_COLUMN && bc->kind != PM_BC_ROLLERS) throw Error(PM_EINVAL, "pm_setup: unknown bc kind");
     c->s = (hipStream_t)stream;
+    pm::set_alloc_stream(c->s);
     c->nx = mesh->nx;
     c->ny = mesh->ny;
     c->nz = mesh->nz;
@@ -182,7 +193,8 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     c->bc_kind = bc->kind;
     if (opts) c->opts = *opts; else pm_default_opts(&c->opts);
     if (c->opts.restart < 1 || c->opts.max_it < 1 || c->opts.cheb_degree < 1 || c->opts.coarse_max < 1 ||
-        !(c->opts.rtol > 0.0))
+        c->opts.cheb_degree_pi < 1 || c->opts.cycles_u < 1 || c->opts.cycles_pi < 1 || c->opts.cycles_u > 8 ||
+        c->opts.cycles_pi > 8 || c->opts.orth_passes < 1 || c->opts.orth_passes > 2 || !(c->opts.rtol > 0.0))
       throw Error(PM_EINVAL, "pm_setup: invalid solver options");
     c->coords = pm::dalloc<double>(3 * c->nn);
     c->E = pm::dalloc<double>(c->nc);
@@ -232,6 +244,7 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     return rc;
   }
   *out = c;
+  ++g_live_contexts;
   return PM_OK;
 }
 
@@ -413,8 +426,13 @@ const char* pm_last_error(const pm_ctx* c) {
 void pm_destroy(pm_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->s);
+  pm::set_alloc_stream(c->s);
   free_ctx_buffers(c);
   delete c;
+  if (--g_live_contexts <= 0) {
+    g_live_contexts = 0;
+    pm::release_device_cache();
+  }
 }
 
 }  // extern "C"

@@ -72,6 +72,8 @@ extern Profiler g_prof;
 // device memory
 void* dmalloc(size_t bytes);
 void dfree(void* p);
+void set_alloc_stream(hipStream_t s);   // stream whose free lists dmalloc/dfree use
+void release_device_cache();            // hipFree every cached block
 template <class T> T* dalloc(int64_t n) { return (T*)dmalloc(sizeof(T) * (size_t)(n > 0 ? n : 1)); }
 
 // Block compressed sparse row, square blocks of size bs (1 or 3), row-major
@@ -122,6 +124,7 @@ struct AmgParams {
   int coarse_max = 64;
   int max_levels = 12;
   int cheb_degree = 2;
+  int cycles = 1;                  // V-cycles per application
   double cheb_lower = 1.0 / 30.0;  // Chebyshev interval [lower*lmax, upper*lmax]
   double cheb_upper = 1.1;
   int power_its = 15;
@@ -134,6 +137,8 @@ struct Hierarchy {
   double* coarse_inv = nullptr;  // dense inverse of the coarsest operator (FP64)
   int ncoarse = 0;               // scalar size of the coarsest operator
   double* cwork = nullptr;       // 2*ncoarse scratch
+  double *r0 = nullptr, *c0 = nullptr;   // finest-level residual/correction of iterated cycles
+  float *r0f = nullptr, *c0f = nullptr;
   double opcx = 0.0;
   bool fp32 = false;
   AmgParams prm;

@@ -239,11 +239,11 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
       apply_Minv(c, vj, zj, transpose);
       apply_AH(c, zj, c->wvec, transpose);
       const int nv = j + 1;
-      // CGS2: two projection passes; h1[nv+1] = ||w||^2 after both
+      // classical Gram-Schmidt, one or two passes; h1[nv+1] = ||w||^2 after them
       cgs_pass(c, nv, h1, false);
-      cgs_pass(c, nv, h2, false);
+      if (c->opts.orth_passes > 1) cgs_pass(c, nv, h2, false);
       k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, grid_for(N), h1);
-      k_add_vec<<<blocks_for(nv), kBlock, 0, s>>>(nv, h2, h1);
+      if (c->opts.orth_passes > 1) k_add_vec<<<blocks_for(nv), kBlock, 0, s>>>(nv, h2, h1);
       PM_CHECK_LAUNCH();
       PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
       PM_HIP(hipStreamSynchronize(s));

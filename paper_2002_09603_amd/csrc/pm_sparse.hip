@@ -3,22 +3,95 @@
 // row-wise Gustavson SpGEMM with per-wavefront LDS hashing, and inverses of
 // the diagonal blocks.  Every result is bitwise reproducible: no
 // floating-point atomics; summation orders are fixed.
+#include <mutex>
+#include <unordered_map>
+
 #include "pm_internal.h"
 
 namespace pm {
 
+// Caching device allocator.  Setup rebuilds many temporaries per step;
+// returning freed blocks to per-(stream, size class) free lists avoids the
+// device-wide synchronization of hipFree and repeated hipMalloc calls.  A
+// block freed on one stream is only reused by allocations on the same stream,
+// so stream order protects kernels still reading it.
+namespace {
+std::mutex g_alloc_mu;
+struct AllocKey {
+  hipStream_t s;
+  size_t bytes;
+  bool operator==(const AllocKey& o) const { return s == o.s && bytes == o.bytes; }
+};
+struct AllocKeyHash {
+  size_t operator()(const AllocKey& k) const { return std::hash<size_t>()(k.bytes) ^ (std::hash<void*>()((void*)k.s) << 1); }
+};
+std::unordered_map<AllocKey, std::vector<void*>, AllocKeyHash> g_free;
+std::unordered_map<void*, AllocKey> g_live;
+size_t g_cached_bytes = 0;
+thread_local hipStream_t g_cur_stream = nullptr;
+
+size_t size_class(size_t b) {
+  if (b <= (1u << 20)) {
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+  }
+  const size_t g = 2u << 20;
+  return (b + g - 1) / g * g;
+}
+
+void release_cached_locked() {
+  for (auto& kv : g_free)
+    for (void* p : kv.second) (void)hipFree(p);
+  g_free.clear();
+  g_cached_bytes = 0;
+}
+}  // namespace
+
+void set_alloc_stream(hipStream_t s) { g_cur_stream = s; }
+
+void release_device_cache() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  release_cached_locked();
+}
+
 void* dmalloc(size_t bytes) {
+  const AllocKey key{g_cur_stream, size_class(bytes)};
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  auto it = g_free.find(key);
+  if (it != g_free.end() && !it->second.empty()) {
+    void* p = it->second.back();
+    it->second.pop_back();
+    g_cached_bytes -= key.bytes;
+    g_live[p] = key;
+    return p;
+  }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
+  hipError_t e = hipMalloc(&p, key.bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release_cached_locked();
+    e = hipMalloc(&p, key.bytes);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error(PM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
   }
+  g_live[p] = key;
   return p;
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) {
+    (void)hipFree(p);
+    return;
+  }
+  g_free[it->second].push_back(p);
+  g_cached_bytes += it->second.bytes;
+  g_live.erase(it);
 }
 
 Profiler g_prof;

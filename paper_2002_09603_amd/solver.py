@@ -42,6 +42,10 @@ class Options:
     increment_stab: bool = True
     cheb_degree: int = 2
     coarse_max: int = 64
+    cheb_degree_pi: int = 2
+    cycles_u: int = 1
+    cycles_pi: int = 1
+    orth_passes: int = 2
     theta_u: float = 0.0
     theta_pi: float = 0.08
 
@@ -55,6 +59,10 @@ class Options:
         o.increment_stab = int(self.increment_stab)
         o.cheb_degree = self.cheb_degree
         o.coarse_max = self.coarse_max
+        o.cheb_degree_pi = self.cheb_degree_pi
+        o.cycles_u = self.cycles_u
+        o.cycles_pi = self.cycles_pi
+        o.orth_passes = self.orth_passes
         o.theta_u = self.theta_u
         o.theta_pi = self.theta_pi
         return o
