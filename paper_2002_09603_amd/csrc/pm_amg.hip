@@ -651,7 +651,8 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   Pt.val = dalloc<double>((int64_t)nnz * BS * BS);
   k_ptent<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, Pt.rowptr, Pt.col, Pt.val);
   PM_CHECK_LAUNCH();
-  // filtered operator A_F (strong couplings, weak ones lumped on the diagonal)
+  // filtered operator A_F (strong couplings, weak ones lumped on the diagonal);
+  // when every coupling is strong A_F = A and the level's D^-1, lmax serve
   Csr AF;
   AF.bs = BS;
   AF.n = AF.m = n;
@@ -660,22 +661,29 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   int fnnz = 0;
   exclusive_scan(s, f, AF.rowptr, n, &fnnz);
   dfree(f);
-  AF.nnzb = fnnz;
-  AF.col = dalloc<int>(fnnz);
-  AF.val = dalloc<double>((int64_t)fnnz * BS * BS);
-  k_filter_fill<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, AF.rowptr, AF.col, AF.val);
-  PM_CHECK_LAUNCH();
-  dfree(strong);
-  double* dinvF = dalloc<double>((int64_t)n * BS * BS);
-  block_diag_inverse(s, AF, dinvF);
-  const double lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
-  // smoothed prolongator P = (I - 4/(3 lmax) D_F^-1 A_F) P_tent on the pattern of A_F P_tent
+  const bool filtered = fnnz != A.nnzb;
+  double* dinvF = nullptr;
+  double lF = L.lmax;
   Csr P;
-  spgemm(s, AF, Pt, P);
+  if (filtered) {
+    AF.nnzb = fnnz;
+    AF.col = dalloc<int>(fnnz);
+    AF.val = dalloc<double>((int64_t)fnnz * BS * BS);
+    k_filter_fill<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, AF.rowptr, AF.col, AF.val);
+    PM_CHECK_LAUNCH();
+    dinvF = dalloc<double>((int64_t)n * BS * BS);
+    block_diag_inverse(s, AF, dinvF);
+    lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
+    // smoothed prolongator P = (I - 4/(3 lmax) D_F^-1 A_F) P_tent on the pattern of A_F P_tent
+    spgemm(s, AF, Pt, P);
+  } else {
+    spgemm(s, A, Pt, P);
+  }
+  dfree(strong);
   Pt.free_all();
   AF.free_all();
   const double omega = 4.0 / (3.0 * lF);
-  k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, dinvF, omega, P.rowptr, P.col, P.val);
+  k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, filtered ? dinvF : L.dinv, omega, P.rowptr, P.col, P.val);
   PM_CHECK_LAUNCH();
   dfree(dinvF);
   dfree(agg);

@@ -222,6 +222,7 @@ void rhs_adjoint(pm_ctx* c, const double* lam, double* cvec);
 
 // sparse utilities (pm_sparse.hip)
 void exclusive_scan(hipStream_t s, const int* in, int* out, int n, int* total_host);
+void exclusive_scan64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n, int64_t* total_host);
 void csr_to_sell(hipStream_t s, const Csr& A, Sell& S, bool with_fp32);
 void sell_spmv(hipStream_t s, const Sell& A, const double* x, double* y);
 void sell_spmv32(hipStream_t s, const Sell& A, const float* x, float* y);

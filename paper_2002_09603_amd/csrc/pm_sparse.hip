@@ -163,15 +163,16 @@ void Sell::free_all() {
 namespace {
 
 // ---------------------------------------------------------------------------
-// exclusive scan of int (three phases, 2048 elements per block)
+// exclusive scan (three phases, 2048 elements per block), int32 or int64
 constexpr int kScanT = 256, kScanItems = 8, kScanTile = kScanT * kScanItems;
 
-__global__ void __launch_bounds__(kScanT) k_scan_tiles(const int* __restrict__ in, int* __restrict__ out,
-                                                       int* __restrict__ tile_sums, int n) {
-  __shared__ int sh[kScanT];
+template <class T>
+__global__ void __launch_bounds__(kScanT) k_scan_tiles(const T* __restrict__ in, T* __restrict__ out,
+                                                       T* __restrict__ tile_sums, int64_t n) {
+  __shared__ T sh[kScanT];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int sum = 0;
+  T v[kScanItems];
+  T sum = 0;
   for (int e = 0; e < kScanItems; ++e) {
     const int64_t idx = base + e;
     v[e] = idx < n ? in[idx] : 0;
@@ -180,12 +181,12 @@ __global__ void __launch_bounds__(kScanT) k_scan_tiles(const int* __restrict__ i
   sh[threadIdx.x] = sum;
   __syncthreads();
   for (int off = 1; off < kScanT; off <<= 1) {
-    const int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    const T t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
     __syncthreads();
     sh[threadIdx.x] += t;
     __syncthreads();
   }
-  int run = sh[threadIdx.x] - sum;  // exclusive prefix of this thread
+  T run = sh[threadIdx.x] - sum;  // exclusive prefix of this thread
   for (int e = 0; e < kScanItems; ++e) {
     const int64_t idx = base + e;
     if (idx < n) out[idx] = run;
@@ -194,19 +195,20 @@ __global__ void __launch_bounds__(kScanT) k_scan_tiles(const int* __restrict__ i
   if (threadIdx.x == kScanT - 1) tile_sums[blockIdx.x] = sh[kScanT - 1];
 }
 
-__global__ void __launch_bounds__(1024) k_scan_small(int* __restrict__ a, int n, int* __restrict__ total) {
-  // single workgroup exclusive scan of a (in place), sequential over chunks
-  __shared__ int sh[1024];
-  __shared__ int carry;
+template <class T>
+__global__ void __launch_bounds__(1024) k_scan_small(T* __restrict__ a, int n, T* __restrict__ total) {
+  // single workgroup exclusive scan of the tile sums (in place)
+  __shared__ T sh[1024];
+  __shared__ T carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int base = 0; base < n; base += 1024) {
     const int idx = base + threadIdx.x;
-    const int v = idx < n ? a[idx] : 0;
+    const T v = idx < n ? a[idx] : 0;
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-      const int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      const T t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
       __syncthreads();
       sh[threadIdx.x] += t;
       __syncthreads();
@@ -219,11 +221,31 @@ __global__ void __launch_bounds__(1024) k_scan_small(int* __restrict__ a, int n,
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void k_scan_add(int* __restrict__ out, const int* __restrict__ tile_off, int n, int total_pos,
-                           const int* __restrict__ total) {
+template <class T>
+__global__ void k_scan_add(T* __restrict__ out, const T* __restrict__ tile_off, int64_t n, const T* __restrict__ total) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < n) out[idx] += tile_off[idx / kScanTile];
-  if (idx == 0) out[total_pos] = *total;
+  if (idx == 0) out[n] = *total;
+}
+
+template <class T>
+void scan_impl(hipStream_t s, const T* in, T* out, int64_t n, T* total_host) {
+  // out has n+1 entries; out[n] = total
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  T* tiles = dalloc<T>(ntiles + 1);
+  T* total = dalloc<T>(1);
+  if (n > 0) {
+    k_scan_tiles<T><<<(unsigned)ntiles, kScanT, 0, s>>>(in, out, tiles, n);
+    PM_CHECK_LAUNCH();
+  }
+  k_scan_small<T><<<1, 1024, 0, s>>>(tiles, (int)ntiles, total);
+  PM_CHECK_LAUNCH();
+  k_scan_add<T><<<blocks_for(std::max<int64_t>(n, 1)), kBlock, 0, s>>>(out, tiles, n, total);
+  PM_CHECK_LAUNCH();
+  if (total_host) PM_HIP(hipMemcpyAsync(total_host, total, sizeof(T), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  dfree(tiles);
+  dfree(total);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,169 +364,6 @@ __global__ void __launch_bounds__(64) k_tr_sort(const int* __restrict__ trow, co
   }
 }
 
-// ---------------------------------------------------------------------------
-// SpGEMM C = A*B (row-wise Gustavson).  Symbolic phase: open-addressing hash
-// of the column ids of each product row in LDS.  Two tiers: 4 rows per
-// workgroup with 2048-slot tables, then one row per workgroup with 8192-slot
-// tables for the rows that overflowed the first tier.
-template <int HASH>
-__device__ inline int hash_slot(int key) {
-  return (int)((unsigned)key * 2654435761u) & (HASH - 1);
-}
-
-// Inserts the columns of row `row` of A*B into the wave's table T; keys are
-// appended to K (capacity KMAX).  Returns the number of distinct keys, or
-// KMAX+1 if the table or the key list overflowed.
-template <int HASH, int KMAX>
-__device__ int symbolic_row(int row, const int* __restrict__ arp, const int* __restrict__ acol,
-                            const int* __restrict__ brp, const int* __restrict__ bcol, int* T, int* K, int* nk,
-                            int lane) {
-  for (int i = lane; i < HASH; i += 64) T[i] = -1;
-  if (lane == 0) *nk = 0;
-  __syncthreads();
-  for (int e = arp[row]; e < arp[row + 1]; ++e) {
-    const int k = acol[e];
-    for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
-      const int key = bcol[f];
-      int h = hash_slot<HASH>(key);
-      bool placed = false;
-      for (int probe = 0; probe < HASH; ++probe) {
-        const int prev = atomicCAS(&T[h], -1, key);
-        if (prev == -1) {
-          const int pos = atomicAdd(nk, 1);
-          if (pos < KMAX) K[pos] = key;
-          placed = true;
-          break;
-        }
-        if (prev == key) {
-          placed = true;
-          break;
-        }
-        h = (h + 1) & (HASH - 1);
-      }
-      if (!placed) atomicAdd(nk, KMAX + 1);
-    }
-  }
-  __syncthreads();
-  const int u = *nk;
-  return u > KMAX ? KMAX + 1 : u;
-}
-
-template <int KMAX>
-__device__ void write_sorted(const int* K, int u, int* __restrict__ dst, int lane) {
-  for (int a = lane; a < u; a += 64) {
-    const int key = K[a];
-    int rank = 0;
-    for (int b = 0; b < u; ++b) rank += K[b] < key;
-    dst[rank] = key;
-  }
-}
-
-// tier 1: 4 rows per workgroup.  cnt[row] = distinct columns, or -1 (overflow)
-template <bool FILL>
-__global__ void __launch_bounds__(256) k_spgemm_sym1(int n, const int* __restrict__ arp, const int* __restrict__ acol,
-                                                     const int* __restrict__ brp, const int* __restrict__ bcol,
-                                                     int* __restrict__ cnt, const int* __restrict__ crp,
-                                                     int* __restrict__ ccol) {
-  constexpr int H = 2048, KM = 1536;
-  __shared__ int tab[4][H];
-  __shared__ int keys[4][KM];
-  __shared__ int nk[4];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + w;
-  // every wave of the block runs the barriers; rows past n use an empty range
-  const bool valid = row < n && (!FILL || cnt[row] >= 0);
-  const int r = valid ? row : 0;
-  int u;
-  if (valid) {
-    u = symbolic_row<H, KM>(r, arp, acol, brp, bcol, tab[w], keys[w], &nk[w], lane);
-  } else {
-    // keep the barrier count uniform across the block
-    __syncthreads();
-    __syncthreads();
-    u = 0;
-  }
-  if (!valid) return;
-  if (!FILL) {
-    if (lane == 0) cnt[row] = u > KM ? -1 : u;
-  } else {
-    write_sorted<KM>(keys[w], u, ccol + crp[row], lane);
-  }
-}
-
-// tier 2: one row per workgroup, only rows flagged -1 by tier 1
-template <bool FILL>
-__global__ void __launch_bounds__(64) k_spgemm_sym2(int n, const int* __restrict__ arp, const int* __restrict__ acol,
-                                                    const int* __restrict__ brp, const int* __restrict__ bcol,
-                                                    const int* __restrict__ flag, int* __restrict__ cnt,
-                                                    const int* __restrict__ crp, int* __restrict__ ccol,
-                                                    int* __restrict__ status) {
-  constexpr int H = 8192, KM = 6144;
-  __shared__ int tab[H];
-  __shared__ int keys[KM];
-  __shared__ int nk;
-  const int row = blockIdx.x, lane = threadIdx.x;
-  if (row >= n || flag[row] >= 0) return;   // uniform over the block
-  const int u = symbolic_row<H, KM>(row, arp, acol, brp, bcol, tab, keys, &nk, lane);
-  if (u > KM) {
-    if (lane == 0) atomicOr(status, kStatusCapacity);
-    return;
-  }
-  if (!FILL) {
-    if (lane == 0) cnt[row] = u;
-  } else {
-    write_sorted<KM>(keys, u, ccol + crp[row], lane);
-  }
-}
-
-// Numeric phase: one wavefront per row; A entries in order, lanes over the
-// entries of the B row (each output slot is written by one lane per step,
-// steps separated by a barrier), so the summation order is fixed.  The row's
-// accumulator lives in LDS when it fits, else directly in the output.
-template <int BS, int CAP>
-__global__ void __launch_bounds__(64) k_spgemm_numeric(int n, const int* __restrict__ arp,
-                                                       const int* __restrict__ acol, const double* __restrict__ aval,
-                                                       const int* __restrict__ brp, const int* __restrict__ bcol,
-                                                       const double* __restrict__ bval, const int* __restrict__ crp,
-                                                       const int* __restrict__ ccol, double* __restrict__ cval) {
-  __shared__ int cols_l[CAP];
-  __shared__ double acc_l[CAP * BS * BS];
-  const int row = blockIdx.x, lane = threadIdx.x;
-  if (row >= n) return;
-  const int c0 = crp[row], u = crp[row + 1] - c0;
-  const bool in_lds = u <= CAP;
-  const int* cols = in_lds ? (const int*)cols_l : ccol + c0;
-  double* acc = in_lds ? (double*)acc_l : cval + (size_t)c0 * BS * BS;
-  if (in_lds)
-    for (int i = lane; i < u; i += 64) cols_l[i] = ccol[c0 + i];
-  for (int i = lane; i < u * BS * BS; i += 64) acc[i] = 0.0;
-  __syncthreads();
-  for (int e = arp[row]; e < arp[row + 1]; ++e) {
-    const int k = acol[e];
-    double a[BS * BS];
-    for (int q = 0; q < BS * BS; ++q) a[q] = aval[(size_t)e * BS * BS + q];
-    for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
-      const int key = bcol[f];
-      int lo = 0, hi = u - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cols[mid] < key) lo = mid + 1; else hi = mid;
-      }
-      double* dst = acc + (size_t)lo * BS * BS;
-      const double* b = bval + (size_t)f * BS * BS;
-      for (int i = 0; i < BS; ++i)
-        for (int j = 0; j < BS; ++j) {
-          double sacc = dst[i * BS + j];
-          for (int t = 0; t < BS; ++t) sacc += a[i * BS + t] * b[t * BS + j];
-          dst[i * BS + j] = sacc;
-        }
-    }
-    __syncthreads();
-  }
-  if (in_lds)
-    for (int i = lane; i < u * BS * BS; i += 64) cval[(size_t)c0 * BS * BS + i] = acc[i];
-}
-
 // inverse of the diagonal block of every block row
 template <int BS>
 __global__ void k_diag_inv(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -538,25 +397,11 @@ __global__ void k_diag_inv(int n, const int* __restrict__ rowptr, const int* __r
 }  // namespace
 
 void exclusive_scan(hipStream_t s, const int* in, int* out, int n, int* total_host) {
-  // out has n+1 entries; out[n] = total
-  const int ntiles = (n + kScanTile - 1) / kScanTile;
-  int* tiles = dalloc<int>(ntiles + 1);
-  int* total = dalloc<int>(1);
-  if (n > 0) {
-    k_scan_tiles<<<ntiles, kScanT, 0, s>>>(in, out, tiles, n);
-    PM_CHECK_LAUNCH();
-  }
-  k_scan_small<<<1, 1024, 0, s>>>(tiles, ntiles, total);
-  PM_CHECK_LAUNCH();
-  k_scan_add<<<blocks_for(std::max(n, 1)), kBlock, 0, s>>>(out, tiles, n, n, total);
-  PM_CHECK_LAUNCH();
-  if (total_host) {
-    PM_HIP(hipMemcpyAsync(total_host, total, sizeof(int), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipStreamSynchronize(s));
-  }
-  PM_HIP(hipStreamSynchronize(s));
-  dfree(tiles);
-  dfree(total);
+  scan_impl<int>(s, in, out, n, total_host);
+}
+
+void exclusive_scan64(hipStream_t s, const int64_t* in, int64_t* out, int64_t n, int64_t* total_host) {
+  scan_impl<int64_t>(s, in, out, n, total_host);
 }
 
 void csr_to_sell(hipStream_t s, const Csr& A, Sell& S, bool with_fp32) {
@@ -646,59 +491,6 @@ void csr_transpose(hipStream_t s, const Csr& A, Csr& T) {
   dfree(cnt);
   dfree(tsrc);
   dfree(ttmp);
-}
-
-void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C) {
-  if (A.bs != B.bs || A.m != B.n) throw Error(PM_EINTERNAL, "spgemm: shape mismatch");
-  C.free_all();
-  C.bs = A.bs;
-  C.n = A.n;
-  C.m = B.m;
-  int* status = dalloc<int>(1);
-  PM_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
-  int* cnt = dalloc<int>(A.n);
-  int* flag = dalloc<int>(A.n);
-  const int nb = (A.n + 3) / 4;
-  if (A.n > 0) {
-    k_spgemm_sym1<false><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, B.rowptr, B.col, cnt, nullptr, nullptr);
-    PM_CHECK_LAUNCH();
-    PM_HIP(hipMemcpyAsync(flag, cnt, sizeof(int) * A.n, hipMemcpyDeviceToDevice, s));
-    k_spgemm_sym2<false><<<A.n, 64, 0, s>>>(A.n, A.rowptr, A.col, B.rowptr, B.col, flag, cnt, nullptr, nullptr,
-                                            status);
-    PM_CHECK_LAUNCH();
-  }
-  int st = 0;
-  PM_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
-  PM_HIP(hipStreamSynchronize(s));
-  if (st) {
-    dfree(status);
-    dfree(cnt);
-    dfree(flag);
-    throw Error(PM_EINTERNAL, "spgemm: a product row has more distinct columns than the hash capacity");
-  }
-  C.rowptr = dalloc<int>(A.n + 1);
-  int total = 0;
-  exclusive_scan(s, cnt, C.rowptr, A.n, &total);
-  C.nnzb = total;
-  C.col = dalloc<int>(total);
-  C.val = dalloc<double>((int64_t)total * A.bs * A.bs);
-  if (A.n > 0) {
-    k_spgemm_sym1<true><<<nb, 256, 0, s>>>(A.n, A.rowptr, A.col, B.rowptr, B.col, flag, C.rowptr, C.col);
-    k_spgemm_sym2<true><<<A.n, 64, 0, s>>>(A.n, A.rowptr, A.col, B.rowptr, B.col, flag, nullptr, C.rowptr, C.col,
-                                           status);
-    PM_CHECK_LAUNCH();
-    if (A.bs == 3)
-      k_spgemm_numeric<3, 224><<<A.n, 64, 0, s>>>(A.n, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val, C.rowptr,
-                                                  C.col, C.val);
-    else
-      k_spgemm_numeric<1, 1536><<<A.n, 64, 0, s>>>(A.n, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
-                                                   C.rowptr, C.col, C.val);
-    PM_CHECK_LAUNCH();
-  }
-  PM_HIP(hipStreamSynchronize(s));
-  dfree(cnt);
-  dfree(flag);
-  dfree(status);
 }
 
 void block_diag_inverse(hipStream_t s, const Csr& A, double* dinv) {

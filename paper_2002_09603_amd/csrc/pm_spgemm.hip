@@ -1,0 +1,280 @@
+// Sparse matrix-matrix product C = A * B for the Galerkin products of the AMG
+// setup (block CSR, square blocks of size 1 or 3), row-wise (Gustavson).
+//
+// Rows are binned by ub = sum over the row of A of the lengths of the B rows
+// it touches (an upper bound on the row's distinct columns):
+//   small   ub <= 64   16 lanes per row (4 rows per wavefront)
+//   medium  ub <= 512  one wavefront per row
+//   large   otherwise  one wavefront per row, 8192-slot hash
+// Symbolic: one pass; each group hashes its row's column ids in LDS, ranks
+// the distinct ids (sorted order) and writes them to a scratch array at the
+// row's ub offset; a compaction copies them into C after a scan of the counts.
+// Numeric: the entries of A's row are taken in order; lanes of the group
+// cover the entries of the corresponding B row, whose columns are distinct,
+// so each accumulator slot has one writer per step and the summation order is
+// fixed (bitwise reproducible).  Accumulators live in LDS (large rows fall
+// back to the output array when they do not fit).
+#include "pm_internal.h"
+
+namespace pm {
+
+namespace {
+
+enum { kSmallUb = 64, kMediumUb = 512 };
+
+__global__ void k_ub(int n, const int* __restrict__ arp, const int* __restrict__ acol, const int* __restrict__ brp,
+                     int* __restrict__ ub) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = 0;
+  for (int e = arp[i]; e < arp[i + 1]; ++e) s += brp[acol[e] + 1] - brp[acol[e]];
+  ub[i] = s;
+}
+
+// Row lists per class: class 0 if v <= t0, 1 if v <= t1, else 2.  One atomic
+// per wavefront and class (ballot + prefix popcount); the order of rows within
+// a list does not affect any result.
+__global__ void __launch_bounds__(256) k_classify(int n, const int* __restrict__ v, int t0, int t1,
+                                                  int* __restrict__ counters, int* __restrict__ lists) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int c = 3;  // out of range
+  if (i < n) {
+    const int u = v[i];
+    c = u <= t0 ? 0 : (u <= t1 ? 1 : 2);
+  }
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int k = 0; k < 3; ++k) {
+    const unsigned long long m = __ballot(c == k);
+    if (m == 0ull) continue;
+    int base = 0;
+    const int leader = __ffsll((long long)m) - 1;
+    if (lane == leader) base = atomicAdd(&counters[k], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (c == k) lists[(size_t)k * n + base + __popcll(m & below)] = i;
+  }
+}
+
+template <int H>
+__device__ inline int hslot(int key) {
+  return (int)((unsigned)key * 2654435761u) & (H - 1);
+}
+
+// Symbolic phase for one class.  G lanes per row, GPB groups per block,
+// hash of H slots, at most KM distinct keys per row.
+template <int G, int GPB, int H, int KM>
+__global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict__ list, const int* __restrict__ arp,
+                                                 const int* __restrict__ acol, const int* __restrict__ brp,
+                                                 const int* __restrict__ bcol, const int64_t* __restrict__ ubofs,
+                                                 int* __restrict__ tmp, int* __restrict__ cnt,
+                                                 int* __restrict__ status) {
+  __shared__ int tab[GPB][H];
+  __shared__ int keys[GPB][KM];
+  __shared__ int nk[GPB];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  const int li = blockIdx.x * GPB + grp;
+  const bool valid = li < nlist;
+  const int row = valid ? list[li] : 0;
+  for (int q = lane; q < H; q += G) tab[grp][q] = -1;
+  if (lane == 0) nk[grp] = 0;
+  __syncthreads();
+  if (valid) {
+    for (int e = arp[row]; e < arp[row + 1]; ++e) {
+      const int k = acol[e];
+      for (int f = brp[k] + lane; f < brp[k + 1]; f += G) {
+        const int key = bcol[f];
+        int h = hslot<H>(key);
+        bool placed = false;
+        for (int probe = 0; probe < H; ++probe) {
+          const int prev = atomicCAS(&tab[grp][h], -1, key);
+          if (prev == -1) {
+            const int pos = atomicAdd(&nk[grp], 1);
+            if (pos < KM) keys[grp][pos] = key;
+            placed = true;
+            break;
+          }
+          if (prev == key) {
+            placed = true;
+            break;
+          }
+          h = (h + 1) & (H - 1);
+        }
+        if (!placed) atomicAdd(&nk[grp], KM + 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  const int u = nk[grp];
+  if (u > KM) {
+    if (lane == 0) atomicOr(status, kStatusCapacity);
+    return;
+  }
+  int* dst = tmp + ubofs[row];
+  for (int a = lane; a < u; a += G) {
+    const int key = keys[grp][a];
+    int rank = 0;
+    for (int b = 0; b < u; ++b) rank += keys[grp][b] < key;
+    dst[rank] = key;
+  }
+  if (lane == 0) cnt[row] = u;
+}
+
+// copy the sorted keys of each row from the scratch (ub offsets) into C
+__global__ void k_compact(int n, const int64_t* __restrict__ ubofs, const int* __restrict__ tmp,
+                          const int* __restrict__ crp, int* __restrict__ ccol) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(t >> 4), lane = (int)(t & 15);
+  if (row >= n) return;
+  const int c0 = crp[row], u = crp[row + 1] - c0;
+  const int* src = tmp + ubofs[row];
+  for (int a = lane; a < u; a += 16) ccol[c0 + a] = src[a];
+}
+
+// Numeric phase for one class: G lanes per row, GPB groups per block, LDS
+// accumulator of CAP blocks per group.  Rows wider than CAP (large class
+// only) accumulate in the output array instead.
+template <int BS, int G, int GPB, int CAP>
+__global__ void __launch_bounds__(G* GPB) k_num(int nlist, const int* __restrict__ list, const int* __restrict__ arp,
+                                                 const int* __restrict__ acol, const double* __restrict__ aval,
+                                                 const int* __restrict__ brp, const int* __restrict__ bcol,
+                                                 const double* __restrict__ bval, const int* __restrict__ crp,
+                                                 const int* __restrict__ ccol, double* __restrict__ cval) {
+  __shared__ int cols_l[GPB][CAP];
+  __shared__ double acc_l[GPB][CAP * BS * BS];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  const int li = blockIdx.x * GPB + grp;
+  if (li >= nlist) return;  // groups never synchronize across rows: per-wave ordering only
+  const int row = list[li];
+  const int c0 = crp[row], u = crp[row + 1] - c0;
+  const bool in_lds = u <= CAP;
+  const int* cols = in_lds ? (const int*)cols_l[grp] : ccol + c0;
+  double* acc = in_lds ? (double*)acc_l[grp] : cval + (size_t)c0 * BS * BS;
+  if (in_lds)
+    for (int i = lane; i < u; i += G) cols_l[grp][i] = ccol[c0 + i];
+  for (int i = lane; i < u * BS * BS; i += G) acc[i] = 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = arp[row]; e < arp[row + 1]; ++e) {
+    const int k = acol[e];
+    double a[BS * BS];
+    for (int q = 0; q < BS * BS; ++q) a[q] = aval[(size_t)e * BS * BS + q];
+    for (int f = brp[k] + lane; f < brp[k + 1]; f += G) {
+      const int key = bcol[f];
+      int lo = 0, hi = u - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cols[mid] < key) lo = mid + 1; else hi = mid;
+      }
+      double* dst = acc + (size_t)lo * BS * BS;
+      const double* b = bval + (size_t)f * BS * BS;
+      for (int i = 0; i < BS; ++i)
+        for (int j = 0; j < BS; ++j) {
+          double sacc = dst[i * BS + j];
+          for (int t = 0; t < BS; ++t) sacc += a[i * BS + t] * b[t * BS + j];
+          dst[i * BS + j] = sacc;
+        }
+    }
+    // the next entry of A may update the same slots from other lanes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (in_lds)
+    for (int i = lane; i < u * BS * BS; i += G) cval[(size_t)c0 * BS * BS + i] = acc[i];
+}
+
+template <int BS>
+void numeric_launch(hipStream_t s, const int* counts, const int* lists, int n, const Csr& A, const Csr& B, Csr& C) {
+  if (counts[0] > 0)
+    k_num<BS, 16, 4, 64><<<(counts[0] + 3) / 4, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr,
+                                                            B.col, B.val, C.rowptr, C.col, C.val);
+  if (counts[1] > 0)
+    k_num<BS, 64, 1, (BS == 3 ? 512 : 512)><<<counts[1], 64, 0, s>>>(counts[1], lists + (size_t)n, A.rowptr, A.col,
+                                                                      A.val, B.rowptr, B.col, B.val, C.rowptr,
+                                                                      C.col, C.val);
+  if (counts[2] > 0)
+    k_num<BS, 64, 1, (BS == 3 ? 224 : 1536)><<<counts[2], 64, 0, s>>>(counts[2], lists + 2 * (size_t)n, A.rowptr,
+                                                                       A.col, A.val, B.rowptr, B.col, B.val,
+                                                                       C.rowptr, C.col, C.val);
+  PM_CHECK_LAUNCH();
+}
+
+__global__ void k_i64_from_i32(int n, const int* __restrict__ a, int64_t* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+}  // namespace
+
+void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C) {
+  if (A.bs != B.bs || A.m != B.n) throw Error(PM_EINTERNAL, "spgemm: shape mismatch");
+  C.free_all();
+  C.bs = A.bs;
+  C.n = A.n;
+  C.m = B.m;
+  const int n = A.n;
+  C.rowptr = dalloc<int>(n + 1);
+  if (n == 0) {
+    PM_HIP(hipMemsetAsync(C.rowptr, 0, sizeof(int), s));
+    C.nnzb = 0;
+    C.col = dalloc<int>(0);
+    C.val = dalloc<double>(0);
+    return;
+  }
+  int* ub = dalloc<int>(n);
+  int* counters = dalloc<int>(4);
+  int* lists = dalloc<int>(3 * (int64_t)n);
+  int64_t* ub64 = dalloc<int64_t>(n);
+  int64_t* ubofs = dalloc<int64_t>(n + 1);
+  int* cnt = dalloc<int>(n);
+  PM_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(int), s));
+  k_ub<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
+  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, ub, kSmallUb, kMediumUb, counters, lists);
+  k_i64_from_i32<<<blocks_for(n), kBlock, 0, s>>>(n, ub, ub64);
+  PM_CHECK_LAUNCH();
+  int h[4] = {0, 0, 0, 0};
+  int64_t tmp_total = 0;
+  PM_HIP(hipMemcpyAsync(h, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  exclusive_scan64(s, ub64, ubofs, n, &tmp_total);
+  int* tmp = dalloc<int>(std::max<int64_t>(tmp_total, 1));
+  int* status = counters + 3;  // cleared above
+  if (h[0] > 0)
+    k_sym<16, 16, 128, 64><<<(h[0] + 15) / 16, 256, 0, s>>>(h[0], lists, A.rowptr, A.col, B.rowptr, B.col, ubofs,
+                                                            tmp, cnt, status);
+  if (h[1] > 0)
+    k_sym<64, 4, 1024, 512><<<(h[1] + 3) / 4, 256, 0, s>>>(h[1], lists + (size_t)n, A.rowptr, A.col, B.rowptr,
+                                                           B.col, ubofs, tmp, cnt, status);
+  if (h[2] > 0)
+    k_sym<64, 1, 8192, 6144><<<h[2], 64, 0, s>>>(h[2], lists + 2 * (size_t)n, A.rowptr, A.col, B.rowptr, B.col,
+                                                 ubofs, tmp, cnt, status);
+  PM_CHECK_LAUNCH();
+  int st = 0;
+  PM_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (st) {
+    for (void* p : {(void*)ub, (void*)counters, (void*)lists, (void*)ub64, (void*)ubofs, (void*)cnt, (void*)tmp})
+      dfree(p);
+    throw Error(PM_EINTERNAL, "spgemm: a product row has more distinct columns than the hash capacity");
+  }
+  int total = 0;
+  exclusive_scan(s, cnt, C.rowptr, n, &total);
+  C.nnzb = total;
+  C.col = dalloc<int>(total);
+  C.val = dalloc<double>((int64_t)total * A.bs * A.bs);
+  k_compact<<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, ubofs, tmp, C.rowptr, C.col);
+  // numeric phase binned by the exact number of distinct columns
+  PM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(int), s));
+  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, cnt, 64, 512, counters, lists);
+  PM_CHECK_LAUNCH();
+  PM_HIP(hipMemcpyAsync(h, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (A.bs == 3)
+    numeric_launch<3>(s, h, lists, n, A, B, C);
+  else
+    numeric_launch<1>(s, h, lists, n, A, B, C);
+  PM_HIP(hipStreamSynchronize(s));
+  for (void* p : {(void*)ub, (void*)counters, (void*)lists, (void*)ub64, (void*)ubofs, (void*)cnt, (void*)tmp})
+    dfree(p);
+}
+
+}  // namespace pm
