@@ -104,6 +104,9 @@ typedef struct {
   int32_t orth_passes;       /* classical Gram-Schmidt passes per Arnoldi step: 1 or 2 */
   double theta_u;            /* AMG strength threshold, displacement block */
   double theta_pi;           /* AMG strength threshold, face-pressure Schur block */
+  int32_t agg_dist_u;        /* AMG aggregation: roots form a distance-1 or distance-2 independent set */
+  int32_t agg_dist_pi;
+  double cheb_lower;         /* Chebyshev interval [cheb_lower, 1.1] x lambda_max(D^-1 A), in (0, 1) */
 } pm_opts;
 
 typedef struct {
@@ -118,7 +121,8 @@ typedef struct {
 /* Default options: rtol 1e-8, restart 100, max_it 1000, FP64, stabilize,
  * increment form, Chebyshev degree 2 (A_uu) / 2 (C~_pi), coarse_max 64, one
  * V-cycle per block, two Gram-Schmidt passes, strength thresholds theta
- * 0 (A_uu) / 0.08 (C~_pi). */
+ * 0 (A_uu) / 0.08 (C~_pi), distance-2 aggregation roots, Chebyshev interval
+ * from lambda_max/30. */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

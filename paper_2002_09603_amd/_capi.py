@@ -20,7 +20,7 @@ PM_OP_AH, PM_OP_AHT, PM_OP_MINV, PM_OP_MINVT, PM_OP_CPI, PM_OP_BP, PM_OP_AUU, \
 
 PROF_KERNELS = {1: "k_ah_u<double>", 2: "k_cheb_step<3,float|double> (finest A_uu level)",
                 3: "k_cheb_step<1,float|double> (finest C~pi level)", 4: "k_multidot", 5: "k_multiaxpy",
-                6: "k_sell_apply<3,...,false> (restriction, finest A_uu level)"}
+                6: "k_csr16<3,float|double> (restriction from the finest A_uu level)"}
 
 ERROR_NAMES = {PM_EINVAL: "PM_EINVAL", PM_ENOMEM: "PM_ENOMEM", PM_EHIP: "PM_EHIP",
                PM_ENOCONV: "PM_ENOCONV", PM_EBREAKDOWN: "PM_EBREAKDOWN",
@@ -47,7 +47,8 @@ class pm_opts(C.Structure):
                 ("cheb_degree", C.c_int32), ("coarse_max", C.c_int32),
                 ("cheb_degree_pi", C.c_int32), ("cycles_u", C.c_int32), ("cycles_pi", C.c_int32),
                 ("orth_passes", C.c_int32),
-                ("theta_u", C.c_double), ("theta_pi", C.c_double)]
+                ("theta_u", C.c_double), ("theta_pi", C.c_double),
+                ("agg_dist_u", C.c_int32), ("agg_dist_pi", C.c_int32), ("cheb_lower", C.c_double)]
 
 
 class pm_info(C.Structure):

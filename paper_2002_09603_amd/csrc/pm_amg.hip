@@ -156,19 +156,26 @@ __global__ void k_root_flags(int n, const uint8_t* __restrict__ state, int* __re
   if (i < n) f[i] = state[i] == kIn;
 }
 
+// distance-1 attachment: a node joins its most strongly coupled root
+template <int BS>
 __global__ void k_agg_phase1(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                             const uint8_t* __restrict__ strong, const uint8_t* __restrict__ state,
-                             const int* __restrict__ root_id, int* __restrict__ agg1) {
+                             const double* __restrict__ val, const uint8_t* __restrict__ strong,
+                             const uint8_t* __restrict__ state, const int* __restrict__ root_id,
+                             int* __restrict__ agg1) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int a = -1;
   if (state[i] == kIn) {
     a = root_id[i];
   } else {
+    double best = -1.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e)
       if (strong[e] && state[col[e]] == kIn) {
-        a = root_id[col[e]];
-        break;
+        const double sv = block_norm<BS>(val + (size_t)e * BS * BS);
+        if (sv > best) {
+          best = sv;
+          a = root_id[col[e]];
+        }
       }
   }
   agg1[i] = a;
@@ -430,6 +437,36 @@ __global__ void __launch_bounds__(256) k_sell_apply(int n, const int* __restrict
   }
 }
 
+// y = A x for a block CSR matrix with long rows (the restriction P^T):
+// 16 lanes per row stride over its entries, then reduce with shuffles
+template <int BS, class T>
+__global__ void __launch_bounds__(256) k_csr16(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                               const T* __restrict__ val, const T* __restrict__ x,
+                                               T* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(t >> 4), lane = threadIdx.x & 15;
+  T acc[BS];
+  for (int a = 0; a < BS; ++a) acc[a] = 0;
+  if (row < n) {
+    for (int e = rp[row] + lane; e < rp[row + 1]; e += 16) {
+      const int j = col[e];
+      const T* v = val + (size_t)e * BS * BS;
+      T xj[BS];
+      for (int q = 0; q < BS; ++q) xj[q] = x[(size_t)j * BS + q];
+      for (int a = 0; a < BS; ++a)
+        for (int q = 0; q < BS; ++q) acc[a] += v[a * BS + q] * xj[q];
+    }
+  }
+  for (int off = 8; off > 0; off >>= 1)
+    for (int a = 0; a < BS; ++a) acc[a] += __shfl_xor(acc[a], off, 16);
+  if (row < n && lane < BS) {
+    T r = acc[0];
+    for (int a = 1; a < BS; ++a)
+      if (lane == a) r = acc[a];
+    y[(size_t)row * BS + lane] = r;
+  }
+}
+
 // dense coarse level
 __global__ void k_dense_from_csr(int nb, int bs, const int* __restrict__ rp, const int* __restrict__ col,
                                  const double* __restrict__ val, double* __restrict__ M, int ld) {
@@ -584,7 +621,7 @@ void dense_inverse(hipStream_t s, const Csr& A, Hierarchy& H) {
 }
 
 template <int BS>
-void aggregate(hipStream_t s, const Csr& A, double theta, int* agg, int* nagg_out, uint8_t* strong) {
+void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, int* nagg_out, uint8_t* strong) {
   const int n = A.n;
   double* dn = dalloc<double>(n);
   uint8_t* state = dalloc<uint8_t>(n);
@@ -599,8 +636,8 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int* agg, int* nagg_ou
     PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
     k_mis_init<<<blocks_for(n), kBlock, 0, s>>>(n, state, 0x12345u, T0);
     k_mis_max<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, T0, T1);
-    k_mis_max<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, T1, T2);
-    k_mis_update<<<blocks_for(n), kBlock, 0, s>>>(n, T0, T2, state, und);
+    if (dist == 2) k_mis_max<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, T1, T2);
+    k_mis_update<<<blocks_for(n), kBlock, 0, s>>>(n, T0, dist == 2 ? T2 : T1, state, und);
     PM_CHECK_LAUNCH();
     int h = 0;
     PM_HIP(hipMemcpyAsync(&h, und, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -614,7 +651,7 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int* agg, int* nagg_ou
   int nagg = 0;
   exclusive_scan(s, flags, root_id, n, &nagg);
   int* agg1 = dalloc<int>(n);
-  k_agg_phase1<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, state, root_id, agg1);
+  k_agg_phase1<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, state, root_id, agg1);
   PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
   k_agg_phase2<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, agg1, agg, und);
   PM_CHECK_LAUNCH();
@@ -635,7 +672,7 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   int* agg = dalloc<int>(n);
   uint8_t* strong = dalloc<uint8_t>(A.nnzb);
   int nagg = 0;
-  aggregate<BS>(s, A, prm.theta, agg, &nagg, strong);
+  aggregate<BS>(s, A, prm.theta, prm.agg_dist, agg, &nagg, strong);
   // tentative prolongator
   Csr Pt;
   Pt.bs = BS;
@@ -694,9 +731,14 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   spgemm(s, R, AP, Acoarse);
   AP.free_all();
   csr_to_sell(s, P, L.P, prm.fp32);
-  csr_to_sell(s, R, L.R, prm.fp32);
+  L.R = R;
+  if (prm.fp32) {
+    const int64_t nv = R.nnzb * BS * BS;
+    L.R.val32 = dalloc<float>(nv);
+    k_to_float<<<blocks_for(nv), kBlock, 0, s>>>(nv, R.val, L.R.val32);
+    PM_CHECK_LAUNCH();
+  }
   P.free_all();
-  R.free_all();
 }
 
 void alloc_level_vectors(Level& L, bool fp32) {
@@ -771,6 +813,7 @@ struct LevelPtrs<BS, double> {
   static double* D(Level& L) { return L.d; }
   static double* Tt(Level& L) { return L.t; }
   static const double* AV(const Sell& S) { return S.val; }
+  static const double* CV(const Csr& S) { return S.val; }
   static const double* DI(const Level& L) { return L.dinv; }
 };
 template <int BS>
@@ -781,6 +824,7 @@ struct LevelPtrs<BS, float> {
   static float* D(Level& L) { return L.df; }
   static float* Tt(Level& L) { return L.tf; }
   static const float* AV(const Sell& S) { return S.val32; }
+  static const float* CV(const Csr& S) { return S.val32; }
   static const float* DI(const Level& L) { return L.dinv32; }
 };
 
@@ -806,10 +850,10 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   const int nth = L.As.nslices * kSlice;
   k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
   Level& C = H.L[l + 1];
-  const int cth = L.R.nslices * kSlice;
   const int rprof = (l == 0 && BS == 3) ? kProfRestrictU0 : 0;
   g_prof.begin(s, rprof);
-  k_sell_apply<BS, T, false><<<blocks_for(cth), kBlock, 0, s>>>(L.R.n, L.R.sptr, L.R.col, LP::AV(L.R), r, LP::B(C));
+  k_csr16<BS, T><<<blocks_for((int64_t)L.R.n * 16), kBlock, 0, s>>>(L.R.n, L.R.rowptr, L.R.col, LP::CV(L.R), r,
+                                                                    LP::B(C));
   g_prof.end(s, rprof, (double)L.R.nnzb * (BS * BS * sizeof(T) + 4) + (double)(n + C.n) * BS * sizeof(T));
   vcycle_level<BS, T>(s, H, prm, l + 1, LP::B(C), LP::X(C));
   const int pth = L.P.nslices * kSlice;

@@ -73,6 +73,8 @@ pm::AmgParams params_u(const pm_ctx* c) {
   p.coarse_max = c->opts.coarse_max;
   p.cheb_degree = c->opts.cheb_degree;
   p.cycles = c->opts.cycles_u;
+  p.agg_dist = c->opts.agg_dist_u;
+  p.cheb_lower = c->opts.cheb_lower;
   p.fp32 = c->opts.precond_fp32 != 0;
   return p;
 }
@@ -83,6 +85,7 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   p.coarse_max = c->opts.coarse_max * 3;
   p.cheb_degree = c->opts.cheb_degree_pi;
   p.cycles = c->opts.cycles_pi;
+  p.agg_dist = c->opts.agg_dist_pi;
   return p;
 }
 
@@ -140,6 +143,9 @@ void pm_default_opts(pm_opts* o) {
   o->cycles_pi = 1;
   o->orth_passes = 2;
   o->theta_u = 0.0;
+  o->agg_dist_u = 2;
+  o->agg_dist_pi = 2;
+  o->cheb_lower = 1.0 / 30.0;
   o->theta_pi = 0.08;
 }
 
@@ -194,7 +200,9 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     if (opts) c->opts = *opts; else pm_default_opts(&c->opts);
     if (c->opts.restart < 1 || c->opts.max_it < 1 || c->opts.cheb_degree < 1 || c->opts.coarse_max < 1 ||
         c->opts.cheb_degree_pi < 1 || c->opts.cycles_u < 1 || c->opts.cycles_pi < 1 || c->opts.cycles_u > 8 ||
-        c->opts.cycles_pi > 8 || c->opts.orth_passes < 1 || c->opts.orth_passes > 2 || !(c->opts.rtol > 0.0))
+        c->opts.cycles_pi > 8 || c->opts.orth_passes < 1 || c->opts.orth_passes > 2 || !(c->opts.rtol > 0.0) ||
+        c->opts.agg_dist_u < 1 || c->opts.agg_dist_u > 2 || c->opts.agg_dist_pi < 1 || c->opts.agg_dist_pi > 2 ||
+        !(c->opts.cheb_lower > 0.0 && c->opts.cheb_lower < 1.0))
       throw Error(PM_EINVAL, "pm_setup: invalid solver options");
     c->coords = pm::dalloc<double>(3 * c->nn);
     c->E = pm::dalloc<double>(c->nc);

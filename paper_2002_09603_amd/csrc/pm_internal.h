@@ -85,6 +85,7 @@ struct Csr {
   int* rowptr = nullptr;  // n+1
   int* col = nullptr;     // nnzb
   double* val = nullptr;  // nnzb*bs*bs
+  float* val32 = nullptr; // optional FP32 copy of val
   void free_all();
 };
 
@@ -111,7 +112,8 @@ struct Level {
   Sell As;                   // operator used by the cycle
   double* dinv = nullptr;    // n*bs*bs inverse diagonal blocks
   float* dinv32 = nullptr;
-  Sell P, R;                 // to/from level+1 (empty on the coarsest level)
+  Sell P;                    // prolongation from level+1 (empty on the coarsest level)
+  Csr R;                     // restriction P^T (long rows: applied with 16 lanes per row)
   double lmax = 0.0;         // estimate of lambda_max(D^-1 A)
   // work vectors (n*bs each)
   double *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
@@ -125,6 +127,7 @@ struct AmgParams {
   int max_levels = 12;
   int cheb_degree = 2;
   int cycles = 1;                  // V-cycles per application
+  int agg_dist = 2;                // aggregation roots: distance-1 or distance-2 independent set
   double cheb_lower = 1.0 / 30.0;  // Chebyshev interval [lower*lmax, upper*lmax]
   double cheb_upper = 1.1;
   int power_its = 15;

@@ -139,9 +139,11 @@ void Csr::free_all() {
   dfree(rowptr);
   dfree(col);
   dfree(val);
+  dfree(val32);
   rowptr = nullptr;
   col = nullptr;
   val = nullptr;
+  val32 = nullptr;
   n = m = 0;
   nnzb = 0;
 }

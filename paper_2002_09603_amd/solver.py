@@ -48,6 +48,9 @@ class Options:
     orth_passes: int = 2
     theta_u: float = 0.0
     theta_pi: float = 0.08
+    agg_dist_u: int = 2
+    agg_dist_pi: int = 2
+    cheb_lower: float = 1.0 / 30.0
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -65,6 +68,9 @@ class Options:
         o.orth_passes = self.orth_passes
         o.theta_u = self.theta_u
         o.theta_pi = self.theta_pi
+        o.agg_dist_u = self.agg_dist_u
+        o.agg_dist_pi = self.agg_dist_pi
+        o.cheb_lower = self.cheb_lower
         return o
 
 
