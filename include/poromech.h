@@ -107,6 +107,7 @@ typedef struct {
   int32_t agg_dist_u;        /* AMG aggregation: roots form a distance-1 or distance-2 independent set */
   int32_t agg_dist_pi;
   double cheb_lower;         /* Chebyshev interval [cheb_lower, 1.1] x lambda_max(D^-1 A), in (0, 1) */
+  double rtol_transpose;     /* stopping tolerance of pm_solve_transpose (0: use rtol) */
 } pm_opts;
 
 typedef struct {
@@ -143,7 +144,7 @@ int pm_assemble(pm_ctx* ctx);
 int pm_set_dt(pm_ctx* ctx, double dt);
 
 /* Replace E (n_cells) and/or kappa (n_cells x 3) (host or device; NULL keeps
- * the current field) and re-assemble everything. */
+ * the current field) and assemble everything (as pm_assemble). */
 int pm_update_material(pm_ctx* ctx, const double* E, const double* kappa);
 
 /* Right-hand side of the step (Appendix A eq. MHFE_vector with the f~_n of

@@ -146,6 +146,7 @@ void pm_default_opts(pm_opts* o) {
   o->agg_dist_u = 2;
   o->agg_dist_pi = 2;
   o->cheb_lower = 1.0 / 30.0;
+  o->rtol_transpose = 0.0;
   o->theta_pi = 0.08;
 }
 
@@ -291,7 +292,7 @@ int pm_update_material(pm_ctx* c, const double* E, const double* kappa) {
       copy_in(c, c->kappa, kappa, 3 * c->nc);
       check_positive(c, c->kappa, 3 * c->nc, "kappa");
     }
-    if (c->assembled) assemble_and_setup(c);
+    assemble_and_setup(c);
     return PM_OK;
   });
 }
@@ -314,7 +315,16 @@ static int solve_common(pm_ctx* c, const double* b, double* u, double* pi, doubl
     PM_HIP(hipStreamSynchronize(c->s));
     const double t0 = now_s();
     pm_info li = c->info;
-    const int rc = pm::fgmres(c, b, c->xvec, tr, &li);
+    const double rtol_saved = c->opts.rtol;
+    if (tr && c->opts.rtol_transpose > 0.0) c->opts.rtol = c->opts.rtol_transpose;
+    int rc;
+    try {
+      rc = pm::fgmres(c, b, c->xvec, tr, &li);
+    } catch (...) {
+      c->opts.rtol = rtol_saved;
+      throw;
+    }
+    c->opts.rtol = rtol_saved;
     if (u) PM_HIP(hipMemcpyAsync(u, c->xvec, sizeof(double) * c->n_u, hipMemcpyDeviceToDevice, c->s));
     if (p) PM_HIP(hipMemcpyAsync(p, c->xvec + c->n_u, sizeof(double) * c->n_p, hipMemcpyDeviceToDevice, c->s));
     if (pi)

@@ -51,6 +51,7 @@ class Options:
     agg_dist_u: int = 2
     agg_dist_pi: int = 2
     cheb_lower: float = 1.0 / 30.0
+    rtol_transpose: float = 0.0
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -71,6 +72,7 @@ class Options:
         o.agg_dist_u = self.agg_dist_u
         o.agg_dist_pi = self.agg_dist_pi
         o.cheb_lower = self.cheb_lower
+        o.rtol_transpose = self.rtol_transpose
         return o
 
 
@@ -86,6 +88,7 @@ class PoroSolver:
                  opts: Optional[Options] = None, device="cuda"):
         self.device = torch.device(device)
         self.opts = opts or Options()
+        self.dt = float(dt)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         E_d = _dev_f64(E, self.device)
         k_d = _dev_f64(kappa, self.device)
@@ -126,7 +129,11 @@ class PoroSolver:
         return self
 
     def set_dt(self, dt):
+        """Change dt (rebuilds C~_pi and its hierarchy); no-op if unchanged."""
+        if float(dt) == self.dt:
+            return
         check(lib.pm_set_dt(self._ctx, float(dt)), self._ctx)
+        self.dt = float(dt)
 
     def update_material(self, E=None, kappa=None):
         E_d = None if E is None else _dev_f64(E, self.device)
