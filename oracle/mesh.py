@@ -59,6 +59,26 @@ class Mesh:
     def fz_id(self, i, j, k):
         return self.n_fx + self.n_fy + i + self.nx * (j + self.ny * k)
 
+    def face_cells(self, f):
+        """Cells sharing face f (one or two)."""
+        nx, ny, nz = self.nx, self.ny, self.nz
+        if f < self.n_fx:
+            i, r = f % (nx + 1), f // (nx + 1)
+            j, k = r % ny, r // ny
+            cand = [(i - 1, j, k), (i, j, k)]
+        elif f < self.n_fx + self.n_fy:
+            g = f - self.n_fx
+            i, r = g % nx, g // nx
+            j, k = r % (ny + 1), r // (ny + 1)
+            cand = [(i, j - 1, k), (i, j, k)]
+        else:
+            g = f - self.n_fx - self.n_fy
+            i, r = g % nx, g // nx
+            j, k = r % ny, r // ny
+            cand = [(i, j, k - 1), (i, j, k)]
+        return [self.cell_id(a, b, c) for (a, b, c) in cand
+                if 0 <= a < nx and 0 <= b < ny and 0 <= c < nz]
+
     # -- node / face sets ------------------------------------------------------
     def node_ijk(self):
         k, j, i = np.meshgrid(np.arange(self.nz + 1), np.arange(self.ny + 1),

@@ -1,0 +1,61 @@
+"""Full-size checks in the launch configurations the benchmark times.
+
+The oracle cannot factor these systems, so it assembles sampled rows of A_H
+and b one by one from the element integrals of their support cells
+(``oracle.sampled``).  Checked: the GPU right-hand side and the GPU operator
+applied to the GPU solution agree with the oracle's rows entrywise (FP64,
+1e-12 of the row scale), and the sampled residual entries of the GPU solution
+are within the solver tolerance of ||b||."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle.sampled import system_rows  # noqa: E402
+from paper_2002_09603_amd import _capi  # noqa: E402
+from paper_2002_09603_amd.solver import Options, from_problem  # noqa: E402
+from synth import make_config  # noqa: E402
+
+BENCH_OPTS = dict(rtol=1e-8, precond_fp32=True, restart=50, max_it=1000, orth_passes=1)
+
+CASES = [
+    ("layered128", None, 0.0, BENCH_OPTS),
+    ("cube64", None, 0.0, dict(rtol=1e-8, restart=50)),
+    ("cube64", None, 1e-4, dict(rtol=1e-8, restart=50)),
+    ("perturbed96", None, 0.0, dict(rtol=1e-8, restart=50)),
+]
+
+
+@pytest.mark.parametrize("name,n,S,opts", CASES, ids=[f"{c[0]}-S{c[2]}" for c in CASES])
+def test_sampled_rows_and_residual_at_full_size(name, n, S, opts):
+    prob = make_config(name, n=n, S_eps=S)
+    print(f"[full size] {name} {prob.nx}x{prob.ny}x{prob.nz} S_eps={S} N={prob.n_total}", flush=True)
+    s = from_problem(prob, Options(**opts)).assemble()
+    b = s.build_rhs()
+    u, pi, p, info = s.solve(b)
+    print("   info", {k: info[k] for k in ("iters", "relres_true", "t_setup", "t_solve")}, flush=True)
+    assert info["converged"] and info["relres_true"] <= opts["rtol"]
+    x = torch.cat([u, p, pi])
+    Ax = s.apply(_capi.PM_OP_AH, x)
+    rng = np.random.default_rng(2024)
+    n_u, n_p, n_pi = s.n_u, s.n_p, s.n_pi
+    rows = np.unique(np.concatenate([
+        rng.choice(n_u, 120, replace=False), n_u + rng.choice(n_p, 60, replace=False),
+        n_u + n_p + rng.choice(n_pi, 120, replace=False),
+        [0, n_u - 1, n_u, n_u + n_p - 1, n_u + n_p, s.N - 1],
+        # top-layer nodes (traction) and top faces (drained)
+        3 * (prob.n_nodes - 1 - rng.choice((prob.nx + 1) * (prob.ny + 1), 10, replace=False)),
+        s.N - 1 - rng.choice(prob.nx * prob.ny, 10, replace=False)]))
+    Ar, br = system_rows(prob, rows)
+    xh = x.cpu().numpy()
+    bh = b.cpu().numpy()
+    scale_b = np.abs(Ar) @ np.abs(xh) + np.abs(br) + 1e-300
+    assert np.all(np.abs(bh[rows] - br) <= 1e-12 * np.maximum(np.abs(br), np.abs(bh).max() * 1e-3) + 1e-300)
+    assert np.all(np.abs(Ar @ xh - Ax.cpu().numpy()[rows]) <= 1e-12 * scale_b)
+    res = br - Ar @ xh
+    assert np.abs(res).max() <= 1.5 * opts["rtol"] * np.linalg.norm(bh)
+    s.close()

@@ -301,3 +301,17 @@ def test_dirichlet_rows_hold_prescribed_values():
     u, p, pi = split(B, x)
     assert np.all(u[B.u_fixed] == 0.0)
     assert np.allclose(pi[B.pi_fixed], 0.25)
+
+
+def test_sampled_rows_equal_full_assembly():
+    from oracle.sampled import system_rows
+    for prob in (make_config("perturbed96", n=4), make_config("layered128", n=4).with_(p_top=0.2)):
+        A, b, B = build_system(prob)
+        rng = np.random.default_rng(5)
+        rows = np.unique(np.concatenate([rng.choice(B.n_u, 12, replace=False),
+                                         B.n_u + rng.choice(B.n_p, 8, replace=False),
+                                         B.n_u + B.n_p + rng.choice(B.n_pi, 12, replace=False),
+                                         [0, B.n_u - 1, B.n_u + B.n_p + B.n_pi - 1]]))
+        Ar, br = system_rows(prob, rows)
+        assert abs(Ar - A[rows]).max() <= 1e-12 * abs(A).max()
+        assert np.allclose(br, b[rows], rtol=1e-12, atol=1e-15 * np.abs(b).max())
