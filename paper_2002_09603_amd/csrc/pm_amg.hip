@@ -366,14 +366,7 @@ __global__ void __launch_bounds__(256) k_cheb_step(int n, const int* __restrict_
   const int e0 = sptr[s], e1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
-  for (int c = e0; c < e1; ++c) {
-    const int j = col[(size_t)c * kSlice + lane];
-    const T* v = val + (size_t)c * BS * BS * kSlice + lane;
-    T xj[BS];
-    for (int q = 0; q < BS; ++q) xj[q] = xin[(size_t)j * BS + q];
-    for (int a = 0; a < BS; ++a)
-      for (int q = 0; q < BS; ++q) acc[a] += v[(a * BS + q) * kSlice] * xj[q];
-  }
+  sell_row<BS, SellUnroll<BS>::value, T, T>(e0, e1, col, val, xin, lane, acc);
   if (r >= n) return;
   T res[BS], z[BS];
   for (int a = 0; a < BS; ++a) res[a] = b[(size_t)r * BS + a] - acc[a];
@@ -397,14 +390,7 @@ __global__ void __launch_bounds__(256) k_residual(int n, const int* __restrict__
   const int e0 = sptr[s], e1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
-  for (int c = e0; c < e1; ++c) {
-    const int j = col[(size_t)c * kSlice + lane];
-    const T* v = val + (size_t)c * BS * BS * kSlice + lane;
-    T xj[BS];
-    for (int q = 0; q < BS; ++q) xj[q] = x[(size_t)j * BS + q];
-    for (int a = 0; a < BS; ++a)
-      for (int q = 0; q < BS; ++q) acc[a] += v[(a * BS + q) * kSlice] * xj[q];
-  }
+  sell_row<BS, SellUnroll<BS>::value, T, T>(e0, e1, col, val, x, lane, acc);
   if (r >= n) return;
   for (int a = 0; a < BS; ++a) rr[(size_t)r * BS + a] = b[(size_t)r * BS + a] - acc[a];
 }
@@ -420,14 +406,7 @@ __global__ void __launch_bounds__(256) k_sell_apply(int n, const int* __restrict
   const int e0 = sptr[s], e1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
-  for (int c = e0; c < e1; ++c) {
-    const int j = col[(size_t)c * kSlice + lane];
-    const T* v = val + (size_t)c * BS * BS * kSlice + lane;
-    T xj[BS];
-    for (int q = 0; q < BS; ++q) xj[q] = xc[(size_t)j * BS + q];
-    for (int a = 0; a < BS; ++a)
-      for (int q = 0; q < BS; ++q) acc[a] += v[(a * BS + q) * kSlice] * xj[q];
-  }
+  sell_row<BS, SellUnroll<BS>::value, T, T>(e0, e1, col, val, xc, lane, acc);
   if (r >= n) return;
   for (int a = 0; a < BS; ++a) {
     if (ADD)

@@ -242,3 +242,54 @@ void amg_vcycle32(hipStream_t s, Hierarchy& H, const float* b, float* x);       
 int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info);
 double dot(pm_ctx* c, const double* a, const double* b, int64_t n);
 }  // namespace pm
+
+namespace pm {
+// Row accumulation acc += sum over entry columns [e0, e1) of one SELL slice
+// (lane = row within the slice).  Entry columns are taken in groups of U: the
+// column ids, then the matrix blocks and the gathered x blocks of the whole
+// group are loaded before any use, so each group costs two dependent memory
+// latencies instead of two per entry.  The summation order is the entry order.
+template <int BS, int U, class T, class TA>
+__device__ inline void sell_row(int e0, int e1, const int* __restrict__ col, const T* __restrict__ val,
+                                const T* __restrict__ x, int lane, TA acc[BS]) {
+  int c = e0;
+  for (; c + U <= e1; c += U) {
+    int j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = col[(size_t)(c + u) * kSlice + lane];
+    T v[U][BS * BS];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < BS * BS; ++q)
+        v[u][q] = __builtin_nontemporal_load(val + ((size_t)(c + u) * BS * BS + q) * kSlice + lane);
+    T xj[U][BS];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < BS; ++q) xj[u][q] = x[(size_t)j[u] * BS + q];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int a = 0; a < BS; ++a)
+#pragma unroll
+        for (int q = 0; q < BS; ++q) acc[a] += (TA)v[u][a * BS + q] * (TA)xj[u][q];
+  }
+  for (; c < e1; ++c) {
+    const int jj = col[(size_t)c * kSlice + lane];
+    T xj[BS];
+#pragma unroll
+    for (int q = 0; q < BS; ++q) xj[q] = x[(size_t)jj * BS + q];
+#pragma unroll
+    for (int a = 0; a < BS; ++a)
+#pragma unroll
+      for (int q = 0; q < BS; ++q)
+        acc[a] += (TA)val[((size_t)c * BS * BS + a * BS + q) * kSlice + lane] * (TA)xj[q];
+  }
+}
+
+template <int BS>
+struct SellUnroll {
+  static constexpr int value = BS == 3 ? 3 : 4;
+};
+}  // namespace pm

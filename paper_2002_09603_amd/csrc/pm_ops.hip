@@ -27,14 +27,7 @@ __global__ void __launch_bounds__(256) k_ah_u(Grid G, int n, const int* __restri
   if (s * kSlice >= n) return;
   const int e0 = sptr[s], e1 = sptr[s + 1];
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int c = e0; c < e1; ++c) {
-    const int j = col[(size_t)c * kSlice + lane];
-    const T* v = val + (size_t)c * 9 * kSlice + lane;
-    const double x0 = u[3 * (size_t)j], x1 = u[3 * (size_t)j + 1], x2 = u[3 * (size_t)j + 2];
-    for (int a = 0; a < 3; ++a)
-      acc[a] += (double)v[(3 * a + 0) * kSlice] * x0 + (double)v[(3 * a + 1) * kSlice] * x1 +
-                (double)v[(3 * a + 2) * kSlice] * x2;
-  }
+  sell_row<3, 3, T, double>(e0, e1, col, val, u, lane, acc);
   if (r >= n) return;
   int i, j, k;
   G.node_ijk(r, i, j, k);

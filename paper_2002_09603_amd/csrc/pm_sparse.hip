@@ -298,14 +298,7 @@ __global__ void __launch_bounds__(256) k_sell_spmv(int n, const int* __restrict_
   const int c0 = sptr[s], c1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
-  for (int c = c0; c < c1; ++c) {
-    const int j = col[(size_t)c * kSlice + lane];
-    const T* v = val + (size_t)c * BS * BS * kSlice + lane;
-    T xj[BS];
-    for (int q = 0; q < BS; ++q) xj[q] = x[(size_t)j * BS + q];
-    for (int a = 0; a < BS; ++a)
-      for (int b = 0; b < BS; ++b) acc[a] += v[(a * BS + b) * kSlice] * xj[b];
-  }
+  sell_row<BS, SellUnroll<BS>::value, T, T>(c0, c1, col, val, x, lane, acc);
   if (r < n)
     for (int q = 0; q < BS; ++q) y[(size_t)r * BS + q] = acc[q];
 }
