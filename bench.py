@@ -64,6 +64,28 @@ def _cpu_baseline(sample_n: int, full_unknowns: int):
                       f"{t:.2f} s measured"}
 
 
+def _traffic(kernel: str, n: int):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary for this workload (FETCH_SIZE + WRITE_SIZE, calibrated on a
+    plain copy), or None when there is none or the HIP sources have changed
+    since the counters were taken."""
+    from paper_2002_09603_amd.profsummary import sources_sha256
+
+    path = os.path.join(ROOT, "profiles", "traffic_layered%d.md" % n)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("TRAFFIC "):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                rec[kv["kernel"]] = kv
+    kv = rec.get(kernel.split(" ")[0])
+    if kv is None or kv.get("sources_sha256") != sources_sha256():
+        return None
+    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +95,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16, help="cells per axis of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioned comparison solve")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="before the steps, run a plain device copy (elementwise negation) that reads and "
+                         "writes MIB MiB each, to calibrate HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -95,6 +120,13 @@ def main():
     opts = Options(rtol=1e-8, precond_fp32=True, restart=50, max_it=1000, orth_passes=1)
     s = from_problem(prob, opts, device=dev)
     b = torch.empty(s.N, dtype=torch.float64, device=dev)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         s.assemble()
@@ -155,7 +187,8 @@ def main():
         "amg_operator_complexity": [round(last["opcx_u"], 3), round(last["opcx_pi"], 3)],
         "roofline": {"bound": "hbm", "kernel": _capi.PROF_KERNELS[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": _traffic(_capi.PROF_KERNELS[dom], args.n),
                      "launches": n_l, "avg_launch_us": round(1000.0 * ms_l / max(n_l, 1), 1),
                      "algorithmic_bytes_per_launch": round(by_l / max(n_l, 1))},
         "kernel_share_last_warmup": {_capi.PROF_KERNELS[k]: {"launches": v[0], "ms": round(v[1], 2),
