@@ -31,6 +31,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -86,6 +88,79 @@ def _traffic(kernel: str, n: int):
     return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
 
 
+def _time_loop_run(args, dev):
+    """20 backward-Euler steps on 192 x 192 x 96 cells ([0,2]^2 x [0,1],
+    log-normal kappa sigma 3, E = 1e4 exp(0.5 xi), geometric dt 1e-3 -> 1),
+    mixed-precision forward and adjoint, loss = sum over steps of the squared
+    pressure at 64 observation cells, checkpoints every 5 steps."""
+    import torch
+
+    from paper_2002_09603_amd.autograd import time_loop
+    from paper_2002_09603_amd.solver import Options, from_problem
+    from synth import make_config
+
+    prob = make_config("spe192")
+    dts = list(prob.dts)
+    print(f"[spe192] {prob.nx}x{prob.ny}x{prob.nz} cells, {prob.n_total} unknowns, {len(dts)} steps", flush=True)
+    s = from_problem(prob, Options(rtol=1e-8, rtol_transpose=1e-8, precond_fp32=True, restart=50,
+                                   max_it=2000, orth_passes=1), device=dev)
+    log = {"solve": [], "solve_transpose": []}
+    for name in log:
+        fn = getattr(s, name)
+
+        def wrapped(*a, _fn=fn, _rec=log[name], **k):
+            out = _fn(*a, **k)
+            _rec.append(out[-1])
+            print(f"   {len(_rec):3d} {_rec is log['solve'] and 'forward' or 'adjoint'} solve: "
+                  f"{out[-1]['iters']} its, {out[-1]['t_setup'] + out[-1]['t_solve']:.3f} s", flush=True)
+            return out
+        setattr(s, name, wrapped)
+    logk = torch.tensor(np.log(prob.kappa[:, 0]), dtype=torch.float64, device=dev, requires_grad=True)
+    logE = torch.tensor(np.log(prob.E), dtype=torch.float64, device=dev, requires_grad=True)
+    obs = torch.as_tensor(prob.obs_cells, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = time_loop(s, logk, logE, dts, every=5)
+    loss = (P[:, obs] ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n_fwd = len(dts)
+    fwd_its = [i["iters"] for i in log["solve"][:n_fwd]]
+    adj_its = [i["iters"] for i in log["solve_transpose"]]
+    out = {"metric": "time for the 20-step forward + adjoint run with checkpoints every 5 steps (s)",
+           "value": round(t2 - t0, 3), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64 Krylov / f32 preconditioner", "data": "synthetic",
+           "config": {"workload": "spe192: 192x192x96 cells on [0,2]^2x[0,1], kappa lognormal sigma 3, "
+                                  "E 1e4*lognormal sigma 0.5, nu 0.25, S_eps 0, 20 geometric steps "
+                                  "dt 1e-3..1, rtol 1e-8 forward and adjoint",
+                      "unknowns": s.N},
+           "t_forward_s": round(t1 - t0, 3), "t_backward_s": round(t2 - t1, 3),
+           "forward_iterations": fwd_its, "recomputed_forward_solves": len(log["solve"]) - n_fwd,
+           "adjoint_iterations": adj_its, "loss": float(loss.detach()),
+           "grad_norm": {"dlogk": float(logk.grad.norm()), "dlogE": float(logE.grad.norm())}}
+    if args.fd:
+        g = torch.Generator(device="cpu").manual_seed(7)
+        vk = torch.randn(prob.n_cells, generator=g, dtype=torch.float64).to(dev)
+        vE = torch.randn(prob.n_cells, generator=g, dtype=torch.float64).to(dev)
+        s.close()
+        s = from_problem(prob, Options(rtol=1e-11, precond_fp32=True, restart=50, max_it=3000,
+                                       orth_passes=1), device=dev)
+        d = 1e-3
+        with torch.no_grad():
+            lk, lE = logk.detach(), logE.detach()
+            Lp = float((time_loop(s, lk + d * vk, lE + d * vE, dts)[:, obs] ** 2).sum())
+            Lm = float((time_loop(s, lk - d * vk, lE - d * vE, dts)[:, obs] ** 2).sum())
+        fd = (Lp - Lm) / (2 * d)
+        ad = float((logk.grad * vk).sum() + (logE.grad * vE).sum())
+        out["directional_check"] = {"adjoint": ad, "central_difference": fd, "step": d,
+                                    "rel_diff": abs(fd - ad) / abs(ad)}
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +170,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16, help="cells per axis of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioned comparison solve")
+    ap.add_argument("--workload", choices=("layered", "spe192"), default="layered",
+                    help="layered: one step of the layered workload (the benchmark line); spe192: the "
+                         "20-step 192x192x96 forward + adjoint run with checkpoints every 5 steps")
+    ap.add_argument("--fd", action="store_true", help="spe192: also check the gradient against a "
+                    "directional central difference (two more 20-step forward runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the steps, run a plain device copy (elementwise negation) that reads and "
                          "writes MIB MiB each, to calibrate HBM byte counters")
@@ -106,7 +186,6 @@ def main():
               file=sys.stderr, flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2002_09603_amd import _capi
@@ -116,6 +195,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "spe192":
+        return _time_loop_run(args, dev)
     prob = make_config("layered128", n=args.n)
     opts = Options(rtol=1e-8, precond_fp32=True, restart=50, max_it=1000, orth_passes=1)
     s = from_problem(prob, opts, device=dev)

@@ -108,6 +108,8 @@ typedef struct {
   int32_t agg_dist_pi;
   double cheb_lower;         /* Chebyshev interval [cheb_lower, 1.1] x lambda_max(D^-1 A), in (0, 1) */
   double rtol_transpose;     /* stopping tolerance of pm_solve_transpose (0: use rtol) */
+  int32_t restart_transpose; /* restart length of pm_solve_transpose (0: use restart) */
+  int32_t orth_passes_transpose; /* Gram-Schmidt passes of pm_solve_transpose (0: use orth_passes) */
 } pm_opts;
 
 typedef struct {
@@ -123,7 +125,10 @@ typedef struct {
  * increment form, Chebyshev degree 2 (A_uu) / 2 (C~_pi), coarse_max 64, one
  * V-cycle per block, two Gram-Schmidt passes, strength thresholds theta
  * 0 (A_uu) / 0.08 (C~_pi), distance-2 aggregation roots, Chebyshev interval
- * from lambda_max/30. */
+ * from lambda_max/30; transposed solves: rtol, restart 100 and two
+ * Gram-Schmidt passes (restarted GMRES on the transposed preconditioned
+ * operator stagnates with short restarts or one pass on strongly
+ * heterogeneous permeability). */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

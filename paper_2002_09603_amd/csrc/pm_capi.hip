@@ -147,6 +147,8 @@ void pm_default_opts(pm_opts* o) {
   o->agg_dist_pi = 2;
   o->cheb_lower = 1.0 / 30.0;
   o->rtol_transpose = 0.0;
+  o->restart_transpose = 100;
+  o->orth_passes_transpose = 2;
   o->theta_pi = 0.08;
 }
 
@@ -203,7 +205,9 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
         c->opts.cheb_degree_pi < 1 || c->opts.cycles_u < 1 || c->opts.cycles_pi < 1 || c->opts.cycles_u > 8 ||
         c->opts.cycles_pi > 8 || c->opts.orth_passes < 1 || c->opts.orth_passes > 2 || !(c->opts.rtol > 0.0) ||
         c->opts.agg_dist_u < 1 || c->opts.agg_dist_u > 2 || c->opts.agg_dist_pi < 1 || c->opts.agg_dist_pi > 2 ||
-        !(c->opts.cheb_lower > 0.0 && c->opts.cheb_lower < 1.0))
+        !(c->opts.cheb_lower > 0.0 && c->opts.cheb_lower < 1.0) || c->opts.restart > 500 ||
+        c->opts.restart_transpose < 0 || c->opts.restart_transpose > 500 || c->opts.orth_passes_transpose < 0 ||
+        c->opts.orth_passes_transpose > 2 || !(c->opts.rtol_transpose >= 0.0))
       throw Error(PM_EINVAL, "pm_setup: invalid solver options");
     c->coords = pm::dalloc<double>(3 * c->nn);
     c->E = pm::dalloc<double>(c->nc);
@@ -315,16 +319,20 @@ static int solve_common(pm_ctx* c, const double* b, double* u, double* pi, doubl
     PM_HIP(hipStreamSynchronize(c->s));
     const double t0 = now_s();
     pm_info li = c->info;
-    const double rtol_saved = c->opts.rtol;
-    if (tr && c->opts.rtol_transpose > 0.0) c->opts.rtol = c->opts.rtol_transpose;
+    const pm_opts saved = c->opts;
+    if (tr) {
+      if (c->opts.rtol_transpose > 0.0) c->opts.rtol = c->opts.rtol_transpose;
+      if (c->opts.restart_transpose > 0) c->opts.restart = c->opts.restart_transpose;
+      if (c->opts.orth_passes_transpose > 0) c->opts.orth_passes = c->opts.orth_passes_transpose;
+    }
     int rc;
     try {
       rc = pm::fgmres(c, b, c->xvec, tr, &li);
     } catch (...) {
-      c->opts.rtol = rtol_saved;
+      c->opts = saved;
       throw;
     }
-    c->opts.rtol = rtol_saved;
+    c->opts = saved;
     if (u) PM_HIP(hipMemcpyAsync(u, c->xvec, sizeof(double) * c->n_u, hipMemcpyDeviceToDevice, c->s));
     if (p) PM_HIP(hipMemcpyAsync(p, c->xvec + c->n_u, sizeof(double) * c->n_p, hipMemcpyDeviceToDevice, c->s));
     if (pi)

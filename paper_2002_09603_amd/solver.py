@@ -52,6 +52,8 @@ class Options:
     agg_dist_pi: int = 2
     cheb_lower: float = 1.0 / 30.0
     rtol_transpose: float = 0.0
+    restart_transpose: int = 100
+    orth_passes_transpose: int = 2
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -73,6 +75,8 @@ class Options:
         o.agg_dist_pi = self.agg_dist_pi
         o.cheb_lower = self.cheb_lower
         o.rtol_transpose = self.rtol_transpose
+        o.restart_transpose = self.restart_transpose
+        o.orth_passes_transpose = self.orth_passes_transpose
         return o
 
 

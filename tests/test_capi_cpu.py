@@ -30,19 +30,24 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_c(tmp_path):
+    """sizeof and the offset of every field, C compiler vs. ctypes."""
     from paper_2002_09603_amd import _capi
+    structs = [_capi.pm_mesh, _capi.pm_material, _capi.pm_bc, _capi.pm_opts, _capi.pm_info]
+    items, want = [], []
+    for st in structs:
+        items.append(f"sizeof({st.__name__})")
+        want.append(C.sizeof(st))
+        for name, _ in st._fields_:
+            items.append(f"offsetof({st.__name__}, {name})")
+            want.append(getattr(st, name).offset)
+    body = "".join(f'printf("%zu\\n", (size_t){e});' for e in items)
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "poromech.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pm_mesh), sizeof(pm_material),'
-                   'sizeof(pm_bc), sizeof(pm_opts), sizeof(pm_info), offsetof(pm_opts, theta_pi),'
-                   'offsetof(pm_info, opcx_pi));}\n')
+                   "int main(){" + body + "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
-    want = [C.sizeof(_capi.pm_mesh), C.sizeof(_capi.pm_material), C.sizeof(_capi.pm_bc),
-            C.sizeof(_capi.pm_opts), C.sizeof(_capi.pm_info), _capi.pm_opts.theta_pi.offset,
-            _capi.pm_info.opcx_pi.offset]
-    assert got == want
+    assert got == want, [(e, g, w) for e, g, w in zip(items, got, want) if g != w]
 
 
 def test_default_options():
@@ -50,6 +55,7 @@ def test_default_options():
     o = _capi.default_opts()
     assert o.rtol == 1e-8 and o.restart == 100 and o.max_it == 1000 and o.stabilize == 1
     assert o.precond_fp32 == 0 and o.increment_stab == 1 and o.cheb_degree == 2
+    assert o.rtol_transpose == 0.0 and o.restart_transpose == 100 and o.orth_passes_transpose == 2
 
 
 @pytest.mark.parametrize("dims", [(3, 4, 4), (4, 4, 0), (4, 5, 6)])

@@ -99,3 +99,61 @@ def test_time_loop_gradients_match_oracle_and_checkpointing_is_exact():
     assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
     assert rel(grads[1][0].cpu().numpy(), ref["dlogk"]) <= 1e-7
     assert rel(grads[1][1].cpu().numpy(), ref["dlogE"]) <= 1e-7
+
+
+def test_twenty_step_mixed_precision_gradients_match_oracle():
+    """The 20-step workload recipe (log-normal kappa sigma 3, E sigma 0.5,
+    geometric dt 1e-3 -> 1) on 8 x 8 x 4 cells, mixed-precision forward and
+    adjoint with checkpoints every 5 steps, against the oracle's 20-step
+    adjoint (direct solves, all states kept)."""
+    prob = make_config("spe192", n=4)
+    dts = list(prob.dts)
+    assert len(dts) == 20
+    print("[20-step adjoint] 8x8x4, mixed precision, checkpoints every 5", flush=True)
+    ref = multi_step(prob, dts, prob.obs_cells)
+    obs = torch.as_tensor(prob.obs_cells, device=DEV)
+    s = from_problem(prob, Options(rtol=1e-13, rtol_transpose=1e-10, precond_fp32=True, max_it=2000))
+    logk, logE = _logs(prob)
+    P = time_loop(s, logk, logE, dts, every=5)
+    loss = (P[:, obs] ** 2).sum()
+    assert abs(float(loss) - ref["loss"]) <= 1e-9 * ref["loss"]
+    loss.backward()
+    print(f"   dlogk rel {rel(logk.grad.cpu().numpy(), ref['dlogk']):.2e} "
+          f"dlogE rel {rel(logE.grad.cpu().numpy(), ref['dlogE']):.2e}", flush=True)
+    assert rel(logk.grad.cpu().numpy(), ref["dlogk"]) <= 1e-7
+    assert rel(logE.grad.cpu().numpy(), ref["dlogE"]) <= 1e-7
+    s.close()
+
+
+def test_twenty_step_checkpointing_and_directional_differences():
+    """24 x 24 x 12 cells of the same recipe, 20 steps, mixed precision:
+    checkpoints every 5 steps give bitwise the gradients of keeping every
+    state, and the gradient's projection on a random direction (v_k, v_E)
+    matches the central difference of the 20-step loss (step 1e-3, forward
+    solves at relative residual 1e-12) to 1e-5."""
+    prob = make_config("spe192", n=12)
+    dts = list(prob.dts)
+    print(f"[20-step adjoint] {prob.nx}x{prob.ny}x{prob.nz}, mixed precision", flush=True)
+    obs = torch.as_tensor(prob.obs_cells, device=DEV)
+    s = from_problem(prob, Options(rtol=1e-12, rtol_transpose=1e-10, precond_fp32=True, max_it=2000))
+    grads = []
+    for every in (1, 5):
+        logk, logE = _logs(prob)
+        P = time_loop(s, logk, logE, dts, every=every)
+        (P[:, obs] ** 2).sum().backward()
+        grads.append((logk.grad.clone(), logE.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    gk, gE = grads[1]
+    g = torch.Generator(device="cpu").manual_seed(7)
+    vk = torch.randn(prob.n_cells, generator=g, dtype=torch.float64).to(DEV)
+    vE = torch.randn(prob.n_cells, generator=g, dtype=torch.float64).to(DEV)
+    logk, logE = _logs(prob)
+    d = 1e-3
+    with torch.no_grad():
+        Lp = float((time_loop(s, logk + d * vk, logE + d * vE, dts)[:, obs] ** 2).sum())
+        Lm = float((time_loop(s, logk - d * vk, logE - d * vE, dts)[:, obs] ** 2).sum())
+    fd = (Lp - Lm) / (2 * d)
+    ad = float((gk * vk).sum() + (gE * vE).sum())
+    print(f"   directional derivative: adjoint {ad:.10e} fd {fd:.10e}", flush=True)
+    assert abs(fd - ad) <= 1e-5 * abs(ad)
+    s.close()

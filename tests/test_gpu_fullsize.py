@@ -59,3 +59,51 @@ def test_sampled_rows_and_residual_at_full_size(name, n, S, opts):
     res = br - Ar @ xh
     assert np.abs(res).max() <= 1.5 * opts["rtol"] * np.linalg.norm(bh)
     s.close()
+
+
+def test_perturbed96_adjoint_matches_central_differences_at_full_size():
+    """96^3 perturbed mesh, loss = sum of squared pressure at 64 observation
+    cells: per-cell d/dlog kappa and d/dlog E from the adjoint against central
+    differences (step 1e-3 in log space) on the workload's 16 cells.
+
+    At this size one cell changes the loss by ~1e-9 of its value, below what
+    two independent forward solves resolve, so each perturbed solve starts
+    from the unperturbed solution x0: it solves A(theta') dx = b - A(theta') x0
+    (relative residual 1e-10 of that small right-hand side) and the loss
+    difference is summed as (dp+ - dp-)(2 p0 + dp+ + dp-) without
+    cancellation.  The perturbed states are still exact solutions of the
+    perturbed systems, so this is the plain central difference."""
+    from paper_2002_09603_amd.autograd import poro_step
+
+    prob = make_config("perturbed96")
+    print(f"[full-size finite differences] perturbed {prob.nx}^3 N={prob.n_total}", flush=True)
+    assert np.allclose(prob.kappa, prob.kappa[:, :1])
+    s = from_problem(prob, Options(rtol=1e-12, rtol_transpose=1e-10, restart=50, max_it=3000))
+    logk = torch.tensor(np.log(prob.kappa[:, 0]), dtype=torch.float64, device="cuda", requires_grad=True)
+    logE = torch.tensor(np.log(prob.E), dtype=torch.float64, device="cuda", requires_grad=True)
+    obs = torch.as_tensor(prob.obs_cells, device="cuda")
+    u, pi, p = poro_step(s, logk, logE)
+    (p[obs] ** 2).sum().backward()
+    x0 = torch.cat([u, p, pi]).detach()
+    p0 = p.detach()[obs]
+    d = 1e-3
+    worst = 0.0
+    for T in prob.fd_cells:
+        for which in ("k", "E"):
+            dps = []
+            for sign in (1.0, -1.0):
+                lk, lE = logk.detach().clone(), logE.detach().clone()
+                (lk if which == "k" else lE)[int(T)] += sign * d
+                kappa = torch.exp(lk)[:, None].expand(-1, 3).contiguous()
+                s.update_material(torch.exp(lE).contiguous(), kappa)
+                r = s.build_rhs() - s.apply(_capi.PM_OP_AH, x0)
+                du, dpi, dp, info = s.solve(r)
+                dps.append(dp[obs])
+            fd = float(((dps[0] - dps[1]) * (2 * p0 + dps[0] + dps[1])).sum()) / (2 * d)
+            ad = float((logk.grad if which == "k" else logE.grad)[int(T)])
+            err = abs(fd - ad) / max(abs(ad), 1e-300)
+            worst = max(worst, err)
+            print(f"   cell {int(T)} d/dlog{which}: adjoint {ad:.10e} fd {fd:.10e} rel {err:.1e}", flush=True)
+            assert abs(fd - ad) <= 1e-5 * abs(ad) + 1e-300
+    print(f"   worst relative difference {worst:.2e}", flush=True)
+    s.close()
