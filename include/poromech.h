@@ -110,6 +110,9 @@ typedef struct {
   double rtol_transpose;     /* stopping tolerance of pm_solve_transpose (0: use rtol) */
   int32_t restart_transpose; /* restart length of pm_solve_transpose (0: use restart) */
   int32_t orth_passes_transpose; /* Gram-Schmidt passes of pm_solve_transpose (0: use orth_passes) */
+  int32_t lattice_uu;        /* 1: if every cell is a translate of the first (to 1e-12 of the edge
+                                length), apply the finest A_uu level from E_T and one element
+                                matrix instead of the assembled matrix; 0: always assembled */
 } pm_opts;
 
 typedef struct {
@@ -119,6 +122,7 @@ typedef struct {
   double relres_true;        /* ||b - A x|| / ||b|| recomputed in FP64 */
   double t_asm, t_setup, t_solve;   /* seconds: assembly, AMG + B~/C~ setup, Krylov solve */
   double opcx_u, opcx_pi;    /* AMG operator complexities */
+  int32_t lattice_uu;        /* 1 if the finest A_uu level runs on the lattice operator */
 } pm_info;
 
 /* Default options: rtol 1e-8, restart 100, max_it 1000, FP64, stabilize,
@@ -128,7 +132,7 @@ typedef struct {
  * from lambda_max/30; transposed solves: rtol, restart 100 and two
  * Gram-Schmidt passes (restarted GMRES on the transposed preconditioned
  * operator stagnates with short restarts or one pass on strongly
- * heterogeneous permeability). */
+ * heterogeneous permeability); lattice operator on. */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

@@ -531,9 +531,11 @@ double sum_squares(hipStream_t s, const double* x, int64_t n, double* part, doub
   return h;
 }
 
-// lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start
-double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) {
-  const int64_t n = (int64_t)A.n * A.bs;
+// lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start;
+// spmv(v, w) launches w = A v
+template <class F>
+double power_lmax(hipStream_t s, int64_t nb, int bs, const double* dinv, int its, F spmv) {
+  const int64_t n = nb * bs;
   double* v = dalloc<double>(n);
   double* w = dalloc<double>(n);
   double* part = dalloc<double>(kRedBlocks);
@@ -542,11 +544,11 @@ double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) 
   double nv = std::sqrt(sum_squares(s, v, n, part, out));
   double lam = 0.0;
   for (int k = 0; k < its; ++k) {
-    sell_spmv(s, A, v, w);
-    if (A.bs == 3)
-      k_dinv_apply_scaled<3><<<blocks_for(A.n), kBlock, 0, s>>>(A.n, dinv, w, 1.0 / nv, v);
+    spmv(v, w);
+    if (bs == 3)
+      k_dinv_apply_scaled<3><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, 1.0 / nv, v);
     else
-      k_dinv_apply_scaled<1><<<blocks_for(A.n), kBlock, 0, s>>>(A.n, dinv, w, 1.0 / nv, v);
+      k_dinv_apply_scaled<1><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, 1.0 / nv, v);
     const double nn = std::sqrt(sum_squares(s, v, n, part, out));
     lam = nn;  // ||D^-1 A v|| / ||v|| with ||v|| normalised
     nv = nn;
@@ -557,6 +559,10 @@ double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) 
   dfree(part);
   dfree(out);
   return lam;
+}
+
+double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) {
+  return power_lmax(s, A.n, A.bs, dinv, its, [&](const double* v, double* w) { sell_spmv(s, A, v, w); });
 }
 
 // lambda_max(D^-1 A) for a CSR operator (power iteration, fixed start)
@@ -740,7 +746,7 @@ void alloc_level_vectors(Level& L, bool fp32) {
 // Returns the buffer holding the result (x or t).
 template <int BS, class T>
 T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T* x, T* t, T* d, bool zero_init,
-             const T* val, const T* dinv, int prof_id) {
+             const T* val, const T* dinv, int prof_id, const LatticeOp* lat, const Grid& G) {
   const double lo = prm.cheb_lower * L.lmax, hi = prm.cheb_upper * L.lmax;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
   const double sigma = theta / delta;
@@ -766,12 +772,19 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
       rho = rn;
     }
     g_prof.begin(s, prof_id);
-    k_cheb_step<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, val, dinv, b, cur, nxt, d, (T)c1,
-                                                          (T)c2);
-    // algorithmic bytes: blocks + column ids, x/b/d read, x/d written, D^-1 blocks
-    g_prof.end(s, prof_id,
-               (double)L.As.nnzb * (BS * BS * sizeof(T) + 4) + (double)n * BS * sizeof(T) * 5 +
-                   (double)n * BS * BS * sizeof(T));
+    if (BS == 3 && lat) {
+      lattice_cheb_step<T>(s, G, *lat, dinv, b, cur, nxt, d, (T)c1, (T)c2);
+      // algorithmic bytes: x/b/d read, x/d written, D^-1 blocks, cell moduli
+      g_prof.end(s, prof_id, (double)n * BS * sizeof(T) * 5 + (double)n * BS * BS * sizeof(T) +
+                                 (double)G.nc * sizeof(T));
+    } else {
+      k_cheb_step<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, val, dinv, b, cur, nxt, d,
+                                                            (T)c1, (T)c2);
+      // algorithmic bytes: blocks + column ids, x/b/d read, x/d written, D^-1 blocks
+      g_prof.end(s, prof_id,
+                 (double)L.As.nnzb * (BS * BS * sizeof(T) + 4) + (double)n * BS * sizeof(T) * 5 +
+                     (double)n * BS * BS * sizeof(T));
+    }
     T* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -824,10 +837,15 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   T* r = LP::Rr(L);
   // pre-smoothing from zero
   const int prof_id = l == 0 ? (BS == 3 ? kProfChebU0 : kProfChebPi0) : 0;
-  T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI, prof_id);
+  const LatticeOp* lat = (l == 0 && BS == 3) ? H.lat : nullptr;
+  T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI, prof_id, lat, H.grid);
   // residual, restriction
-  const int nth = L.As.nslices * kSlice;
-  k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
+  if (lat) {
+    lattice_residual<T>(s, H.grid, *lat, b, cur, r);
+  } else {
+    const int nth = L.As.nslices * kSlice;
+    k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
+  }
   Level& C = H.L[l + 1];
   const int rprof = (l == 0 && BS == 3) ? kProfRestrictU0 : 0;
   g_prof.begin(s, rprof);
@@ -840,15 +858,18 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   PM_CHECK_LAUNCH();
   // post-smoothing from the corrected iterate
   T* other = (cur == x) ? t : x;
-  T* res = chebyshev<BS, T>(s, L, prm, b, cur, other, d, false, AV, DI, prof_id);
+  T* res = chebyshev<BS, T>(s, L, prm, b, cur, other, d, false, AV, DI, prof_id, lat, H.grid);
   if (res != x) PM_HIP(hipMemcpyAsync(x, res, sizeof(T) * (size_t)n * BS, hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace
 
-void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H) {
+void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H, const LatticeOp* lat,
+               const Grid* G) {
   H.free_all();
   H.bs = A0.bs;
+  H.lat = (lat && lat->on && G && A0.bs == 3) ? lat : nullptr;
+  if (H.lat) H.grid = *G;
   H.fp32 = prm.fp32;
   H.prm = prm;
   double nnz_total = 0.0, nnz0 = (double)A0.nnzb;
@@ -876,7 +897,8 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H)
     nnz_total += (double)L.A.nnzb;
     const bool last = (L.n <= prm.coarse_max) || (l + 1 >= prm.max_levels);
     alloc_level_vectors(L, prm.fp32);
-    csr_to_sell(s, L.A, L.As, prm.fp32);
+    const bool on_lattice = (l == 0 && H.lat);
+    if (!on_lattice) csr_to_sell(s, L.A, L.As, prm.fp32);
     if (last) {
       dense_inverse(s, L.A, H);
       break;
@@ -889,7 +911,11 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H)
                                                                          L.dinv32);
       PM_CHECK_LAUNCH();
     }
-    L.lmax = estimate_lmax(s, L.As, L.dinv, prm.power_its);
+    if (on_lattice)
+      L.lmax = power_lmax(s, L.n, 3, L.dinv, prm.power_its,
+                          [&](const double* v, double* w) { lattice_apply(s, H.grid, *H.lat, v, w); });
+    else
+      L.lmax = estimate_lmax(s, L.As, L.dinv, prm.power_its);
     if (verbose)
       fprintf(stderr, "[amg bs=%d] level %d: rows %d, blocks %lld (%.1f/row), lmax(D^-1 A) %.4f\n", L.bs, l, L.n,
               (long long)L.A.nnzb, (double)L.A.nnzb / std::max(1, L.n), L.lmax);
@@ -947,8 +973,12 @@ void iterated_cycles(hipStream_t s, Hierarchy& H, const T* b, T* x, T* r0, T* c0
   Level& L = H.L[0];
   const int64_t m = (int64_t)L.n * BS;
   for (int c = 1; c < H.prm.cycles; ++c) {
-    const int nth = L.As.nslices * kSlice;
-    k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(L.n, L.As.sptr, L.As.col, LP::AV(L.As), b, x, r0);
+    if (BS == 3 && H.lat) {
+      lattice_residual<T>(s, H.grid, *H.lat, b, x, r0);
+    } else {
+      const int nth = L.As.nslices * kSlice;
+      k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(L.n, L.As.sptr, L.As.col, LP::AV(L.As), b, x, r0);
+    }
     vcycle_level<BS, T>(s, H, H.prm, 0, r0, c0);
     k_axpy_inplace<T><<<blocks_for(m), kBlock, 0, s>>>(m, c0, x);
     PM_CHECK_LAUNCH();

@@ -19,31 +19,18 @@ namespace {
 // Q1 element stiffness: one thread per (local node a, cell); the thread owns
 // rows 3a..3a+2 of the 24x24 K_T and integrates them with 2x2x2 Gauss.
 // Ke layout: Ke[(row*24 + col)*nc + cell].
-__global__ void __launch_bounds__(256) k_q1_stiffness(Grid G, const double* __restrict__ coords,
-                                                      const double* __restrict__ E, double nu,
-                                                      double* __restrict__ Ke, int* status) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 8 * G.nc) return;
-  const int a = (int)(t / G.nc);
-  const int64_t c = t - (int64_t)a * G.nc;
-  int i, j, k;
-  G.cell_ijk(c, i, j, k);
-  double X[8][3];
-  load_cell_coords(G, coords, i, j, k, X);
-  const double Ec = E[c];
+// Rows 3a..3a+2 of K_T for the hexahedron with node coordinates X; false if
+// det J <= 0 at a Gauss point.
+__device__ inline bool q1_rows(const double X[8][3], double Ec, double nu, int a, double K[3][24]) {
   const double lam = Ec * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
   const double mu = Ec / (2.0 * (1.0 + nu));
-  double K[3][24];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 24; ++q) K[r][q] = 0.0;
   for (int q = 0; q < 8; ++q) {
     double xi[3], J[3][3], Ji[3][3];
     gauss_point(q, xi);
     const double det = jacobian(X, xi, J);
-    if (!(det > 0.0)) {
-      atomicOr(status, kStatusInverted);
-      return;
-    }
+    if (!(det > 0.0)) return false;
     inv3(J, det, Ji);
     double ga[3], gr[3];
     ref_grad(a, xi, gr);
@@ -61,8 +48,46 @@ __global__ void __launch_bounds__(256) k_q1_stiffness(Grid G, const double* __re
         }
     }
   }
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_q1_stiffness(Grid G, const double* __restrict__ coords,
+                                                      const double* __restrict__ E, double nu,
+                                                      double* __restrict__ Ke, int* status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 8 * G.nc) return;
+  const int a = (int)(t / G.nc);
+  const int64_t c = t - (int64_t)a * G.nc;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  double X[8][3];
+  load_cell_coords(G, coords, i, j, k, X);
+  double K[3][24];
+  if (!q1_rows(X, E[c], nu, a, K)) {
+    atomicOr(status, kStatusInverted);
+    return;
+  }
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 24; ++q) Ke[((size_t)(3 * a + r) * 24 + q) * G.nc + c] = K[r][q];
+}
+
+// Lattice meshes: unit-modulus stiffness of cell 0 (8 threads, one per local
+// node) and its coupling column, copied from the per-cell array.
+__global__ void k_q1_unit(Grid G, const double* __restrict__ coords, double nu, const double* __restrict__ ae,
+                          double* __restrict__ Kh, double* __restrict__ ah, int* status) {
+  const int a = threadIdx.x;
+  if (a >= 8) return;
+  double X[8][3];
+  load_cell_coords(G, coords, 0, 0, 0, X);
+  double K[3][24];
+  if (!q1_rows(X, 1.0, nu, a, K)) {
+    atomicOr(status, kStatusInverted);
+    return;
+  }
+  for (int r = 0; r < 3; ++r) {
+    for (int q = 0; q < 24; ++q) Kh[(3 * a + r) * 24 + q] = K[r][q];
+    ah[3 * a + r] = ae[(size_t)(3 * a + r) * G.nc];
+  }
 }
 
 // Per cell: coupling column a_T (24), volume, RT0 mass, its inverse, g, alpha.
@@ -191,10 +216,7 @@ __global__ void k_masks(Grid G, int kind, uint8_t* __restrict__ ufix, uint8_t* _
   if (t < G.nn) {
     int i, j, k;
     G.node_ijk(t, i, j, k);
-    const bool bottom = (k == 0);
-    ufix[3 * t + 0] = bottom || (kind == PM_BC_ROLLERS && (i == 0 || i == G.nx));
-    ufix[3 * t + 1] = bottom || (kind == PM_BC_ROLLERS && (j == 0 || j == G.ny));
-    ufix[3 * t + 2] = bottom;
+    for (int d = 0; d < 3; ++d) ufix[3 * t + d] = u_fixed(G, kind, i, j, k, d);
   }
   if (t < G.nf) {
     bool top = false;
@@ -218,8 +240,20 @@ __global__ void k_auu_count(Grid G, int* __restrict__ cnt) {
 
 // A_uu row gather: block (n,m) = sum over the cells containing both nodes of
 // K_T[a(n), b(m)], then the Dirichlet identity rows/columns.
-__global__ void __launch_bounds__(256) k_auu_fill(Grid G, const double* __restrict__ Ke,
-                                                  const uint8_t* __restrict__ ufix,
+// element stiffness sources: per-cell array, or E_T times the lattice matrix
+struct KeCells {
+  const double* Ke;
+  int64_t nc;
+  __device__ double operator()(int row, int col, int64_t c) const { return Ke[((size_t)row * 24 + col) * nc + c]; }
+};
+struct KeLattice {
+  const double* Kh;
+  const double* E;
+  __device__ double operator()(int row, int col, int64_t c) const { return E[c] * Kh[row * 24 + col]; }
+};
+
+template <class KS>
+__global__ void __launch_bounds__(256) k_auu_fill(Grid G, KS Ke, const uint8_t* __restrict__ ufix,
                                                   const int* __restrict__ rowptr, int* __restrict__ col,
                                                   double* __restrict__ val, double* __restrict__ diag) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,7 +284,7 @@ __global__ void __launch_bounds__(256) k_auu_fill(Grid G, const double* __restri
               const int b = (i2 - ci) + 2 * (j2 - cj) + 4 * (k2 - ck);
               for (int r = 0; r < 3; ++r)
                 for (int s = 0; s < 3; ++s)
-                  B[r * 3 + s] += Ke[((size_t)(3 * a + r) * 24 + 3 * b + s) * G.nc + c];
+                  B[r * 3 + s] += Ke(3 * a + r, 3 * b + s, c);
             }
         for (int r = 0; r < 3; ++r)
           for (int s = 0; s < 3; ++s) {
@@ -535,7 +569,15 @@ void assemble_all(pm_ctx* c) {
   k_cell_data<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->coords, c->kappa, c->mu, c->biot, c->ae, c->vol,
                                                   c->Minv, c->g, c->alpha, c->status);
   PM_CHECK_LAUNCH();
-  k_q1_stiffness<<<blocks_for(8 * G.nc), kBlock, 0, s>>>(G, c->coords, c->E, c->nu, c->Ke, c->status);
+  if (c->lattice) {
+    if (!c->lat.Kh) {
+      c->lat.Kh = dalloc<double>(576);
+      c->lat.ah = dalloc<double>(24);
+    }
+    k_q1_unit<<<1, 64, 0, s>>>(G, c->coords, c->nu, c->ae, c->lat.Kh, c->lat.ah, c->status);
+  } else {
+    k_q1_stiffness<<<blocks_for(8 * G.nc), kBlock, 0, s>>>(G, c->coords, c->E, c->nu, c->Ke, c->status);
+  }
   PM_CHECK_LAUNCH();
   check_status(c, "element kernels");
   k_stab_weights<<<blocks_for(c->nmacro), kBlock, 0, s>>>(G, c->E, c->vol, c->nu, c->biot, c->stabw);
@@ -554,9 +596,14 @@ void assemble_all(pm_ctx* c) {
     c->Auu.col = dalloc<int>(total);
     c->Auu.val = dalloc<double>((int64_t)total * 9);
   }
-  k_auu_fill<<<blocks_for(G.nn), kBlock, 0, s>>>(G, c->Ke, c->ufix, c->Auu.rowptr, c->Auu.col, c->Auu.val,
-                                                 c->auu_diag);
+  if (c->lattice)
+    k_auu_fill<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->Auu.rowptr,
+                                                   c->Auu.col, c->Auu.val, c->auu_diag);
+  else
+    k_auu_fill<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->Auu.rowptr, c->Auu.col,
+                                                   c->Auu.val, c->auu_diag);
   PM_CHECK_LAUNCH();
+  if (c->lattice) lattice_finish(c);
   build_cpi(c);
 }
 

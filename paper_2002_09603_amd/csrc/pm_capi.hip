@@ -51,6 +51,7 @@ void free_ctx_buffers(pm_ctx* c) {
   c->Cpi.free_all();
   c->Hu.free_all();
   c->Hpi.free_all();
+  c->lat.free_all();
 }
 
 void copy_in(pm_ctx* c, double* dst, const double* src, int64_t n) {
@@ -91,7 +92,8 @@ pm::AmgParams params_pi(const pm_ctx* c) {
 
 void setup_hierarchies(pm_ctx* c, bool with_u) {
   if (with_u) {
-    pm::amg_setup(c->s, c->Auu, params_u(c), c->Hu);
+    const pm::Grid G = pm::grid_of(c);
+    pm::amg_setup(c->s, c->Auu, params_u(c), c->Hu, c->lattice ? &c->lat : nullptr, &G);
     c->hier_u_ok = true;
   }
   pm::amg_setup(c->s, c->Cpi, params_pi(c), c->Hpi);
@@ -99,12 +101,13 @@ void setup_hierarchies(pm_ctx* c, bool with_u) {
   c->info.levels_pi = (int)c->Hpi.L.size();
   c->info.opcx_u = c->Hu.opcx;
   c->info.opcx_pi = c->Hpi.opcx;
+  c->info.lattice_uu = c->lattice ? 1 : 0;
 }
 
 void assemble_and_setup(pm_ctx* c) {
   PM_HIP(hipStreamSynchronize(c->s));
   const double t0 = now_s();
-  c->Ke = pm::dalloc<double>(576 * c->nc);
+  if (!c->lattice) c->Ke = pm::dalloc<double>(576 * c->nc);
   try {
     pm::assemble_all(c);
   } catch (...) {
@@ -149,6 +152,7 @@ void pm_default_opts(pm_opts* o) {
   o->rtol_transpose = 0.0;
   o->restart_transpose = 100;
   o->orth_passes_transpose = 2;
+  o->lattice_uu = 1;
   o->theta_pi = 0.08;
 }
 
@@ -232,6 +236,11 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     copy_in(c, c->kappa, mat->kappa, 3 * c->nc);
     check_positive(c, c->E, c->nc, "E");
     check_positive(c, c->kappa, 3 * c->nc, "kappa");
+    if (c->opts.lattice_uu && c->nn < (int64_t)INT32_MAX) {
+      double dev = 0.0, hmin = 0.0;
+      pm::lattice_deviation(c->s, pm::grid_of(c), c->coords, &dev, &hmin);
+      c->lattice = dev <= 1e-12 * hmin;
+    }
     c->ae = pm::dalloc<double>(24 * c->nc);
     c->vol = pm::dalloc<double>(c->nc);
     c->Minv = pm::dalloc<double>(36 * c->nc);

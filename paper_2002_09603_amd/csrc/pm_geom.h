@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "poromech.h"
+
 namespace pm {
 
 // Structured grid description passed by value to kernels.
@@ -85,6 +87,16 @@ struct Grid {
     }
   }
 };
+
+// Dirichlet displacement components of node (i,j,k): the bottom face is
+// fixed; PM_BC_ROLLERS also fixes the normal component on the lateral faces.
+__host__ __device__ inline bool u_fixed(const Grid& G, int kind, int i, int j, int k, int comp) {
+  if (k == 0) return true;
+  if (kind != PM_BC_ROLLERS) return false;
+  if (comp == 0) return i == 0 || i == G.nx;
+  if (comp == 1) return j == 0 || j == G.ny;
+  return false;
+}
 
 constexpr double kGauss = 0.57735026918962576451;  // 1/sqrt(3)
 

@@ -134,8 +134,41 @@ struct AmgParams {
   bool fp32 = false;
 };
 
+// A_uu on a mesh whose cells are translates of one parallelepiped: every
+// element stiffness is E_T times the unit-modulus matrix Khat of the first
+// cell and every coupling column is ahat, so the finest level is applied from
+// Khat, ahat and E without an assembled matrix.  Dirichlet rows and columns
+// follow u_fixed (identity rows, zero columns).
+struct LatticeOp {
+  bool on = false;
+  int kind = 0;               // boundary-condition kind
+  double* Kh = nullptr;       // 576, row-major 24x24 (rows 3a+r, columns 3b+s)
+  float* Kh32 = nullptr;
+  double* ah = nullptr;       // 24 coupling column
+  const double* E = nullptr;  // n_c moduli (context-owned)
+  float* E32 = nullptr;       // FP32 copy for mixed precision
+  void free_all();
+};
+
+// Launchers of the lattice kernels (pm_lattice.hip); one thread per node.
+// Chebyshev step: r = D^-1 (b - A x_in); d = c1 d + c2 r; x_out = x_in + d
+template <class T>
+void lattice_cheb_step(hipStream_t s, const Grid& G, const LatticeOp& op, const T* dinv, const T* b, const T* xin,
+                       T* xout, T* d, T c1, T c2);
+template <class T>
+void lattice_residual(hipStream_t s, const Grid& G, const LatticeOp& op, const T* b, const T* x, T* r);
+void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y);
+// u-rows of A_H: y_u = A_uu u + sgn A_up p (free rows), y_u = u (Dirichlet rows)
+void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const double* u, const double* p, double sgn,
+                  double* y);
+// max over nodes of |X(i,j,k) - X(0) - i a - j b - k c| with a, b, c the edge
+// vectors at node 0, and min |a|,|b|,|c| (synchronizes)
+void lattice_deviation(hipStream_t s, const Grid& G, const double* coords, double* dev, double* hmin);
+
 struct Hierarchy {
   int bs = 1;
+  const LatticeOp* lat = nullptr;  // finest level applied on the lattice (A_uu only)
+  Grid grid{};                     // mesh of the lattice operator
   std::vector<Level> L;
   double* coarse_inv = nullptr;  // dense inverse of the coarsest operator (FP64)
   int ncoarse = 0;               // scalar size of the coarsest operator
@@ -167,7 +200,9 @@ struct pm_ctx {
   double* E = nullptr;       // nc
   double* kappa = nullptr;   // nc*3
   // element data (structure-of-arrays, index [k*nc + cell])
-  double* Ke = nullptr;      // 576*nc element stiffness (assembly scratch)
+  double* Ke = nullptr;      // 576*nc element stiffness (assembly scratch; unused on lattices)
+  bool lattice = false;      // cells are translates of one parallelepiped
+  pm::LatticeOp lat;         // finest-level A_uu operator on lattices
   double* ae = nullptr;      // 24*nc coupling column of A_up
   double* vol = nullptr;     // nc
   double* Minv = nullptr;    // 36*nc inverse RT0 mass
@@ -210,6 +245,7 @@ inline int64_t node_id(const pm_ctx* c, int i, int j, int k) {
 // assembly (pm_assemble.hip)
 Grid grid_of(const pm_ctx* c);
 void assemble_all(pm_ctx* c);          // element kernels, A_uu, B~p, C~pi (no AMG)
+void lattice_finish(pm_ctx* c);        // lattice operator tables after assembly (pm_lattice.hip)
 void rebuild_dt(pm_ctx* c);            // B~p, C~pi for the current dt
 void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
 void check_status(pm_ctx* c, const char* where);
@@ -234,7 +270,10 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C);
 void block_diag_inverse(hipStream_t s, const Csr& A, double* dinv);
 
 // AMG (pm_amg.hip)
-void amg_setup(hipStream_t s, const Csr& A, const AmgParams& prm, Hierarchy& H);
+// lat (may be null): apply the finest level of a block-3 hierarchy with the
+// lattice operator on grid G instead of an assembled sliced-ELL matrix
+void amg_setup(hipStream_t s, const Csr& A, const AmgParams& prm, Hierarchy& H, const LatticeOp* lat = nullptr,
+               const Grid* G = nullptr);
 void amg_vcycle(hipStream_t s, Hierarchy& H, const double* b, double* x);       // FP64
 void amg_vcycle32(hipStream_t s, Hierarchy& H, const float* b, float* x);       // FP32 levels
 

@@ -1,0 +1,325 @@
+// Finest-level displacement operator on lattice meshes.
+//
+// When the cells are translates of one parallelepiped (uniform boxes, as in
+// the paper's cantilever and reservoir grids), the Q1 element stiffness of
+// cell T is E_T Khat with one 24x24 matrix Khat for unit modulus (nu is
+// uniform), and the coupling column a_T is one vector ahat.  A row of A_uu is
+// then a sum over the (up to 8) cells around the node of E_T times 3 rows of
+// Khat applied to the 8 nodal displacements of the cell: 576 multiply-adds
+// per node, with Khat and ahat read at wave-uniform addresses (scalar loads)
+// and only the vectors, E and the smoother's diagonal blocks streamed from
+// memory.  This replaces reading the assembled 27-block rows (76 B per block
+// in FP64, 40 B in FP32) on the level where they dominate the V-cycle and the
+// Krylov operator.  Dirichlet rows and columns follow u_fixed, exactly as the
+// assembled matrix does (identity rows, zero columns).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "pm_internal.h"
+
+namespace pm {
+
+void LatticeOp::free_all() {
+  dfree(Kh);
+  dfree(Kh32);
+  dfree(ah);
+  dfree(E32);
+  Kh = nullptr;
+  Kh32 = nullptr;
+  ah = nullptr;
+  E32 = nullptr;
+  E = nullptr;
+  on = false;
+}
+
+namespace {
+
+// Workgroups are dispatched to the 8 XCDs round-robin; give each XCD one
+// contiguous range of nodes so that the neighbour rows and planes a
+// workgroup gathers sit in the L2 of the same XCD.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8;
+  const int64_t id = b % 8, idx = b / 8;
+  return id < r ? id * (q + 1) + idx : r * (q + 1) + (id - r) * q + idx;
+}
+
+__device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j, int& k) {
+  n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return false;
+  const uint32_t nx1 = (uint32_t)G.nx + 1, ny1 = (uint32_t)G.ny + 1;
+  const uint32_t m = (uint32_t)n;  // nn < 2^31 is checked at set-up
+  const uint32_t r = m / nx1;
+  i = (int)(m - r * nx1);
+  k = (int)(r / ny1);
+  j = (int)(r - (uint32_t)k * ny1);
+  return true;
+}
+
+// the 27 neighbour displacements of node (i,j,k); Dirichlet components and
+// nodes outside the mesh read as zero (loads are clamped to node 0)
+template <class T>
+__device__ __forceinline__ void gather27(const Grid& G, int kind, const T* __restrict__ x, int i, int j, int k,
+                                         T u[27][3]) {
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int ni = i + dx - 1, nj = j + dy - 1, nk = k + dz - 1;
+        const bool in = ni >= 0 && ni <= G.nx && nj >= 0 && nj <= G.ny && nk >= 0 && nk <= G.nz;
+        const int64_t nb = in ? G.node(ni, nj, nk) : 0;
+        const int q = dx + 3 * dy + 9 * dz;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T v = x[3 * nb + c];
+          u[q][c] = (in && !u_fixed(G, kind, ni, nj, nk, c)) ? v : (T)0;
+        }
+      }
+}
+
+// acc = sum over the cells T around node (i,j,k) of E_T Khat[3a..3a+2, :] u_T
+template <class T>
+__device__ __forceinline__ void lattice_rows(const Grid& G, const T* __restrict__ Kh, const T* __restrict__ E,
+                                             const T u[27][3], int i, int j, int k, T acc[3]) {
+  acc[0] = acc[1] = acc[2] = (T)0;
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
+        if (ci < 0 || ci >= G.nx || cj < 0 || cj >= G.ny || ck < 0 || ck >= G.nz) continue;
+        const T e = E[G.cell(ci, cj, ck)];
+        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          T sum = (T)0;
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int q = (ox + (b & 1)) + 3 * (oy + ((b >> 1) & 1)) + 9 * (oz + ((b >> 2) & 1));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sum += Kh[(3 * a + r) * 24 + 3 * b + c] * u[q][c];
+          }
+          acc[r] += e * sum;
+        }
+      }
+}
+
+// (A x) at node n: Dirichlet rows are identity
+template <class T>
+__device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const T* __restrict__ Kh,
+                                           const T* __restrict__ E, const T* __restrict__ x, int64_t n, int i, int j,
+                                           int k, T ax[3]) {
+  T u[27][3];
+  gather27<T>(G, kind, x, i, j, k, u);
+  lattice_rows<T>(G, Kh, E, u, i, j, k, ax);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (u_fixed(G, kind, i, j, k, a)) ax[a] = x[3 * n + a];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_lat_cheb(Grid G, int kind, const T* __restrict__ Kh,
+                                                  const T* __restrict__ E, const T* __restrict__ dinv,
+                                                  const T* __restrict__ b, const T* __restrict__ xin,
+                                                  T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
+  int64_t n;
+  int i, j, k;
+  if (!node_of_thread(G, n, i, j, k)) return;
+  T ax[3];
+  lattice_Ax<T>(G, kind, Kh, E, xin, n, i, j, k, ax);
+  T res[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) res[a] = b[3 * n + a] - ax[a];
+  const T* D = dinv + 9 * n;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T z = D[3 * a] * res[0] + D[3 * a + 1] * res[1] + D[3 * a + 2] * res[2];
+    const int64_t q = 3 * n + a;
+    const T dn = c1 * d[q] + c2 * z;
+    d[q] = dn;
+    xout[q] = xin[q] + dn;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_lat_residual(Grid G, int kind, const T* __restrict__ Kh,
+                                                      const T* __restrict__ E, const T* __restrict__ b,
+                                                      const T* __restrict__ x, T* __restrict__ r) {
+  int64_t n;
+  int i, j, k;
+  if (!node_of_thread(G, n, i, j, k)) return;
+  T ax[3];
+  lattice_Ax<T>(G, kind, Kh, E, x, n, i, j, k, ax);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r[3 * n + a] = b[3 * n + a] - ax[a];
+}
+
+__global__ void __launch_bounds__(256) k_lat_apply(Grid G, int kind, const double* __restrict__ Kh,
+                                                   const double* __restrict__ E, const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  int64_t n;
+  int i, j, k;
+  if (!node_of_thread(G, n, i, j, k)) return;
+  double ax[3];
+  lattice_Ax<double>(G, kind, Kh, E, x, n, i, j, k, ax);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) y[3 * n + a] = ax[a];
+}
+
+// u-rows of A_H (sgn = +1) or A_H^T (sgn = -1): A_uu u + sgn A_up p on free rows
+__global__ void __launch_bounds__(256) k_lat_ah_u(Grid G, int kind, const double* __restrict__ Kh,
+                                                  const double* __restrict__ ah, const double* __restrict__ E,
+                                                  const double* __restrict__ u, const double* __restrict__ p,
+                                                  double sgn, double* __restrict__ y) {
+  int64_t n;
+  int i, j, k;
+  if (!node_of_thread(G, n, i, j, k)) return;
+  double uu[27][3];
+  gather27<double>(G, kind, u, i, j, k, uu);
+  double acc[3];
+  lattice_rows<double>(G, Kh, E, uu, i, j, k, acc);
+  double cp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
+        if (ci < 0 || ci >= G.nx || cj < 0 || cj >= G.ny || ck < 0 || ck >= G.nz) continue;
+        const double pc = p[G.cell(ci, cj, ck)];
+        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cp[d] += ah[3 * a + d] * pc;
+      }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t q = 3 * n + d;
+    y[q] = u_fixed(G, kind, i, j, k, d) ? u[q] : acc[d] + sgn * cp[d];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_lat_dev(Grid G, const double* __restrict__ X,
+                                                 unsigned long long* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dev = 0.0;
+  if (n < G.nn) {
+    int i, j, k;
+    G.node_ijk(n, i, j, k);
+    const int64_t n1 = G.node(G.nx > 0 ? 1 : 0, 0, 0), n2 = G.node(0, G.ny > 0 ? 1 : 0, 0),
+                  n3 = G.node(0, 0, G.nz > 0 ? 1 : 0);
+    for (int c = 0; c < 3; ++c) {
+      const double x0 = X[c];
+      const double pred = x0 + i * (X[3 * n1 + c] - x0) + j * (X[3 * n2 + c] - x0) + k * (X[3 * n3 + c] - x0);
+      dev = fmax(dev, fabs(X[3 * n + c] - pred));
+    }
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = dev;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  // non-negative doubles order like their bit patterns
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sh[0]));
+}
+
+__global__ void k_lat_to_float(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+template <class T>
+const T* lat_K(const LatticeOp& op);
+template <>
+const double* lat_K<double>(const LatticeOp& op) { return op.Kh; }
+template <>
+const float* lat_K<float>(const LatticeOp& op) { return op.Kh32; }
+template <class T>
+const T* lat_E(const LatticeOp& op);
+template <>
+const double* lat_E<double>(const LatticeOp& op) { return op.E; }
+template <>
+const float* lat_E<float>(const LatticeOp& op) { return op.E32; }
+
+}  // namespace
+
+template <class T>
+void lattice_cheb_step(hipStream_t s, const Grid& G, const LatticeOp& op, const T* dinv, const T* b, const T* xin,
+                       T* xout, T* d, T c1, T c2) {
+  k_lat_cheb<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, lat_K<T>(op), lat_E<T>(op), dinv, b, xin, xout, d,
+                                                    c1, c2);
+  PM_CHECK_LAUNCH();
+}
+template void lattice_cheb_step<double>(hipStream_t, const Grid&, const LatticeOp&, const double*, const double*,
+                                        const double*, double*, double*, double, double);
+template void lattice_cheb_step<float>(hipStream_t, const Grid&, const LatticeOp&, const float*, const float*,
+                                       const float*, float*, float*, float, float);
+
+template <class T>
+void lattice_residual(hipStream_t s, const Grid& G, const LatticeOp& op, const T* b, const T* x, T* r) {
+  k_lat_residual<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, lat_K<T>(op), lat_E<T>(op), b, x, r);
+  PM_CHECK_LAUNCH();
+}
+template void lattice_residual<double>(hipStream_t, const Grid&, const LatticeOp&, const double*, const double*,
+                                       double*);
+template void lattice_residual<float>(hipStream_t, const Grid&, const LatticeOp&, const float*, const float*,
+                                      float*);
+
+void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y) {
+  k_lat_apply<<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, op.Kh, op.E, x, y);
+  PM_CHECK_LAUNCH();
+}
+
+void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const double* u, const double* p, double sgn,
+                  double* y) {
+  k_lat_ah_u<<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, op.Kh, op.ah, op.E, u, p, sgn, y);
+  PM_CHECK_LAUNCH();
+}
+
+void lattice_deviation(hipStream_t s, const Grid& G, const double* coords, double* dev, double* hmin) {
+  unsigned long long* out = dalloc<unsigned long long>(1);
+  PM_HIP(hipMemsetAsync(out, 0, sizeof(unsigned long long), s));
+  k_lat_dev<<<blocks_for(G.nn), kBlock, 0, s>>>(G, coords, out);
+  PM_CHECK_LAUNCH();
+  unsigned long long bits = 0;
+  double X[4][3];
+  const int64_t ids[4] = {0, G.node(1, 0, 0), G.node(0, 1, 0), G.node(0, 0, 1)};
+  PM_HIP(hipMemcpyAsync(&bits, out, sizeof(bits), hipMemcpyDeviceToHost, s));
+  for (int q = 0; q < 4; ++q)
+    PM_HIP(hipMemcpyAsync(X[q], coords + 3 * ids[q], 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  dfree(out);
+  double d;
+  static_assert(sizeof(d) == sizeof(bits), "");
+  memcpy(&d, &bits, sizeof(d));
+  *dev = d;
+  double h = 1e300;
+  for (int q = 1; q < 4; ++q) {
+    const double e0 = X[q][0] - X[0][0], e1 = X[q][1] - X[0][1], e2 = X[q][2] - X[0][2];
+    h = std::min(h, std::sqrt(e0 * e0 + e1 * e1 + e2 * e2));
+  }
+  *hmin = h;
+}
+
+// After assembly on a lattice: FP32 copies and the operator description.
+void lattice_finish(pm_ctx* c) {
+  LatticeOp& op = c->lat;
+  op.kind = c->bc_kind;
+  op.E = c->E;
+  if (c->opts.precond_fp32) {
+    if (!op.Kh32) op.Kh32 = dalloc<float>(576);
+    if (!op.E32) op.E32 = dalloc<float>(c->nc);
+    k_lat_to_float<<<blocks_for(576), kBlock, 0, c->s>>>(576, op.Kh, op.Kh32);
+    k_lat_to_float<<<blocks_for(c->nc), kBlock, 0, c->s>>>(c->nc, c->E, op.E32);
+    PM_CHECK_LAUNCH();
+  }
+  op.on = true;
+}
+
+}  // namespace pm

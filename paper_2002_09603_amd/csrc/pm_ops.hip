@@ -358,15 +358,24 @@ void ah_launch(pm_ctx* c, const T* x, T* y, bool transpose, const Sell& Auu, con
   T* yu = y;
   T* yp = y + c->n_u;
   T* ypi = y + c->n_u + c->n_p;
-  const int nth = Auu.nslices * kSlice;
   g_prof.begin(c->s, kProfAHu);
-  k_ah_u<T><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.col, auu_val, c->ae, c->ufix, u, p,
-                                                  transpose ? -1.0 : 1.0, yu);
-  // algorithmic bytes: A_uu blocks and column ids, u read, y_u written, coupling
-  // columns a_T, p read, Dirichlet mask
-  g_prof.end(c->s, kProfAHu,
-             (double)Auu.nnzb * (9 * sizeof(T) + 4) + (double)c->n_u * (2 * sizeof(T) + 1) +
-                 (double)c->nc * (24 * 8 + sizeof(T)));
+  if constexpr (sizeof(T) == 8) {
+    if (c->lat.on) {
+      lattice_ah_u(c->s, G, c->lat, u, p, transpose ? -1.0 : 1.0, yu);
+      // algorithmic bytes: u read, y_u written, p and E read
+      g_prof.end(c->s, kProfAHu, (double)c->n_u * 2 * sizeof(T) + (double)c->nc * (sizeof(T) + 8));
+    }
+  }
+  if (!c->lat.on || sizeof(T) != 8) {
+    const int nth = Auu.nslices * kSlice;
+    k_ah_u<T><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.col, auu_val, c->ae, c->ufix, u, p,
+                                                    transpose ? -1.0 : 1.0, yu);
+    // algorithmic bytes: A_uu blocks and column ids, u read, y_u written, coupling
+    // columns a_T, p read, Dirichlet mask
+    g_prof.end(c->s, kProfAHu,
+               (double)Auu.nnzb * (9 * sizeof(T) + 4) + (double)c->n_u * (2 * sizeof(T) + 1) +
+                   (double)c->nc * (24 * 8 + sizeof(T)));
+  }
   k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->ae, c->vol, c->alpha, c->g, c->stabw, c->ufix, c->pifix,
                                                    u, p, pi, c->S, c->dt, c->opts.stabilize,
                                                    transpose ? 1.0 : -1.0, transpose ? 1.0 : c->dt, yp);

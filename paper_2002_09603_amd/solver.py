@@ -54,6 +54,7 @@ class Options:
     rtol_transpose: float = 0.0
     restart_transpose: int = 100
     orth_passes_transpose: int = 2
+    lattice_uu: bool = True
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -77,6 +78,7 @@ class Options:
         o.rtol_transpose = self.rtol_transpose
         o.restart_transpose = self.restart_transpose
         o.orth_passes_transpose = self.orth_passes_transpose
+        o.lattice_uu = int(self.lattice_uu)
         return o
 
 

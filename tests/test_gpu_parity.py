@@ -48,13 +48,16 @@ def _case(name):
     return box_problem(**CASES[name])
 
 
+@pytest.mark.parametrize("lattice", [True, False])
 @pytest.mark.parametrize("name", list(CASES))
-def test_operator_and_block_parity(name):
+def test_operator_and_block_parity(name, lattice):
     prob = _case(name)
-    print(f"[operator parity] {name}", flush=True)
+    print(f"[operator parity] {name} lattice={lattice}", flush=True)
     A, b, B = build_system(prob)
-    s = from_problem(prob).assemble()
+    s = from_problem(prob, Options(lattice_uu=lattice)).assemble()
     assert (s.n_u, s.n_p, s.n_pi) == (B.n_u, B.n_p, B.n_pi)
+    # uniform boxes take the lattice operator when allowed, perturbed meshes never
+    assert s.info()["lattice_uu"] == int(lattice and not CASES[name].get("perturb", False))
     rng = np.random.default_rng(7)
     x = rng.standard_normal(s.N)
     y = _np(s.apply(_capi.PM_OP_AH, _t(x)))
@@ -78,15 +81,20 @@ def test_operator_and_block_parity(name):
     s.close()
 
 
-@pytest.mark.parametrize("fp32", [False, True])
-@pytest.mark.parametrize("name", ["unit8", "box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop"])
-def test_solve_parity(name, fp32):
+SOLVE_CASES = [(n, fp32, True) for n in ("unit8", "box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop")
+               for fp32 in (False, True)] + [("box10x6x4", fp32, False) for fp32 in (False, True)]
+
+
+@pytest.mark.parametrize("name,fp32,lattice", SOLVE_CASES,
+                         ids=[f"{n}-fp32={f}-lattice={l}" for n, f, l in SOLVE_CASES])
+def test_solve_parity(name, fp32, lattice):
     prob = make_config("unit8") if name == "unit8" else _case(name)
-    print(f"[solve parity] {name} fp32={fp32}", flush=True)
+    print(f"[solve parity] {name} fp32={fp32} lattice={lattice}", flush=True)
     A, b, B = build_system(prob)
     x = direct_solve(A, b)
     u0, p0, pi0 = split(B, x)
-    s = from_problem(prob, Options(rtol=1e-13, precond_fp32=fp32, restart=100, max_it=600)).assemble()
+    s = from_problem(prob, Options(rtol=1e-13, precond_fp32=fp32, restart=100, max_it=600,
+                                   lattice_uu=lattice)).assemble()
     u, pi, p, info = s.solve(s.build_rhs())
     print("   info", info, flush=True)
     assert info["converged"] and info["relres_true"] <= 1e-13
