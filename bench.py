@@ -198,7 +198,7 @@ def main():
     if args.workload == "spe192":
         return _time_loop_run(args, dev)
     prob = make_config("layered128", n=args.n)
-    opts = Options(rtol=1e-8, precond_fp32=True, restart=50, max_it=1000, orth_passes=1)
+    opts = Options(rtol=1e-8, precond_fp32=True, restart=24, max_it=1000, orth_passes=1)
     s = from_problem(prob, opts, device=dev)
     b = torch.empty(s.N, dtype=torch.float64, device=dev)
     if args.copy_probe > 0:
@@ -257,7 +257,7 @@ def main():
         "config": {"workload": f"layered{args.n}: {args.n}^3 hex unit cube, layered anisotropic kappa "
                                "(1e-2,1e-2,1e-6 / 1e-6 in 8-cell layers, lognormal sigma 1), E 1e4, nu 0.25, "
                                "S_eps 0, dt 1e-2; mixed-precision block-triangular AMG preconditioner, "
-                               "FP64 FGMRES(50) with one classical Gram-Schmidt pass, rtol 1e-8",
+                               "FP64 FGMRES(24) with one classical Gram-Schmidt pass, rtol 1e-8",
                    "unknowns": s.N, "n_u": s.n_u, "n_pi": s.n_pi, "n_p": s.n_p},
         "iterations": last["iters"],
         "relres_true": last["relres_true"],
@@ -278,7 +278,7 @@ def main():
     }
 
     if not args.no_fp64:
-        s64 = from_problem(prob, Options(rtol=1e-8, precond_fp32=False, restart=50, max_it=1000, orth_passes=1),
+        s64 = from_problem(prob, Options(rtol=1e-8, precond_fp32=False, restart=24, max_it=1000, orth_passes=1),
                            device=dev)
         s64.assemble()
         b64 = s64.build_rhs()

@@ -113,6 +113,8 @@ typedef struct {
   int32_t lattice_uu;        /* 1: if every cell is a translate of the first (to 1e-12 of the edge
                                 length), apply the finest A_uu level from E_T and one element
                                 matrix instead of the assembled matrix; 0: always assembled */
+  double p_trunc_pi;         /* C~_pi hierarchy: drop prolongator entries below this fraction of
+                                their row's largest, rescaling to the row sum (0: keep all) */
 } pm_opts;
 
 typedef struct {
@@ -132,7 +134,8 @@ typedef struct {
  * from lambda_max/30; transposed solves: rtol, restart 100 and two
  * Gram-Schmidt passes (restarted GMRES on the transposed preconditioned
  * operator stagnates with short restarts or one pass on strongly
- * heterogeneous permeability); lattice operator on. */
+ * heterogeneous permeability); lattice operator on; C~_pi prolongator
+ * truncation 0.02. */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

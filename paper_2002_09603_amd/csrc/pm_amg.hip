@@ -80,7 +80,10 @@ __device__ inline double block_norm(const double* v) {
   return sqrt(s);
 }
 
-// strength: strong[e] = 1 for off-diagonal |A_ij| >= theta sqrt(|A_ii||A_jj|), |A_ij| > 0
+// strength: strong[e] = 1 for off-diagonal |A_ij| >= theta sqrt(|A_ii||A_jj|), |A_ij| > 0;
+// kZeroBlock for a stored block that is exactly zero (weak, but dropping it
+// does not change the operator); 0 for the other weak couplings
+constexpr uint8_t kZeroBlock = 2;
 template <int BS>
 __global__ void k_diag_norm(int n, const int* __restrict__ rp, const int* __restrict__ col,
                             const double* __restrict__ val, double* __restrict__ dn) {
@@ -104,10 +107,10 @@ __global__ void k_strength(int n, const int* __restrict__ rp, const int* __restr
     uint8_t s = 0;
     if (j != i) {
       const double a = block_norm<BS>(val + (size_t)e * BS * BS);
-      s = (a > 0.0 && a >= theta * sqrt(dn[i] * dn[j])) ? 1 : 0;
+      s = a == 0.0 ? kZeroBlock : (a >= theta * sqrt(dn[i] * dn[j]) ? 1 : 0);
     }
     strong[e] = s;
-    ns += s;
+    ns += s == 1;
   }
   state[i] = ns > 0 ? kUnd : kOut;  // isolated rows (e.g. Dirichlet) are never aggregated
 }
@@ -123,18 +126,42 @@ __global__ void k_mis_init(int n, const uint8_t* __restrict__ state, uint32_t sa
   if (i < n) T0[i] = pack_tuple(state[i], i, salt);
 }
 
-__global__ void k_mis_max(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                          const uint8_t* __restrict__ strong, const uint64_t* __restrict__ Tin,
-                          uint64_t* __restrict__ Tout) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t m = Tin[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (strong[e]) {
-      const uint64_t v = Tin[col[e]];
-      m = v > m ? v : m;
-    }
-  Tout[i] = m;
+// Tout[i] = max of Tin over i and its strong neighbours; G lanes per row
+// stride over its entries (contiguous loads), then reduce with shuffles
+template <int G>
+__global__ void __launch_bounds__(256) k_mis_max(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                 const uint8_t* __restrict__ strong,
+                                                 const uint64_t* __restrict__ Tin, uint64_t* __restrict__ Tout) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
+  uint64_t m = 0;
+  if (i < n) {
+    if (l == 0) m = Tin[i];
+    const int e1 = rp[i + 1];
+    for (int e = rp[i] + l; e < e1; e += G)
+      if (strong[e] == 1) {
+        const uint64_t v = Tin[col[e]];
+        m = v > m ? v : m;
+      }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)m, o, G), hi = __shfl_xor((uint32_t)(m >> 32), o, G);
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    m = v > m ? v : m;
+  }
+  if (i < n && l == 0) Tout[i] = m;
+}
+
+void launch_mis_max(hipStream_t s, const Csr& A, const uint8_t* strong, const uint64_t* Tin, uint64_t* Tout) {
+  const double avg = (double)A.nnzb / std::max(1, A.n);
+  if (avg <= 12.0)
+    k_mis_max<4><<<blocks_for((int64_t)A.n * 4), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout);
+  else if (avg <= 40.0)
+    k_mis_max<8><<<blocks_for((int64_t)A.n * 8), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout);
+  else
+    k_mis_max<16><<<blocks_for((int64_t)A.n * 16), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout);
+  PM_CHECK_LAUNCH();
 }
 
 __global__ void k_mis_update(int n, const uint64_t* __restrict__ T0, const uint64_t* __restrict__ T2,
@@ -170,7 +197,7 @@ __global__ void k_agg_phase1(int n, const int* __restrict__ rp, const int* __res
   } else {
     double best = -1.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e)
-      if (strong[e] && state[col[e]] == kIn) {
+      if (strong[e] == 1 && state[col[e]] == kIn) {
         const double sv = block_norm<BS>(val + (size_t)e * BS * BS);
         if (sv > best) {
           best = sv;
@@ -192,7 +219,7 @@ __global__ void k_agg_phase2(int n, const int* __restrict__ rp, const int* __res
     bool has_strong = false;
     double best = -1.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      if (!strong[e]) continue;
+      if (strong[e] != 1) continue;
       has_strong = true;
       const int j = col[e];
       if (agg1[j] < 0) continue;
@@ -243,15 +270,79 @@ __global__ void k_smooth_p(int n, const int* __restrict__ agg, const double* __r
   }
 }
 
-// filtered operator for prolongator smoothing: strong off-diagonal blocks
-// kept, weak ones lumped into the diagonal block (row sums preserved)
-__global__ void k_filter_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                               const uint8_t* __restrict__ strong, int* __restrict__ cnt) {
+// Truncation of a scalar prolongator: entries below tau * (largest |entry| of
+// the row) are dropped and the kept ones rescaled to the row's former sum, so
+// that interpolation of the near-kernel (constants) is unchanged.
+__global__ void k_trunc_count(int n, const int* __restrict__ rp, const double* __restrict__ val, double tau,
+                              int* __restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  double mx = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) mx = fmax(mx, fabs(val[e]));
   int c = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) c += (col[e] == i) || strong[e];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) c += fabs(val[e]) >= tau * mx;
   cnt[i] = c;
+}
+
+__global__ void k_trunc_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                             const double* __restrict__ val, double tau, const int* __restrict__ trp,
+                             int* __restrict__ tcol, double* __restrict__ tval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double mx = 0.0, all = 0.0, kept = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) mx = fmax(mx, fabs(val[e]));
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    all += val[e];
+    if (fabs(val[e]) >= tau * mx) kept += val[e];
+  }
+  const double scale = kept != 0.0 ? all / kept : 1.0;
+  int p = trp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (fabs(val[e]) >= tau * mx) {
+      tcol[p] = col[e];
+      tval[p] = val[e] * scale;
+      ++p;
+    }
+}
+
+void truncate_p(hipStream_t s, Csr& P, double tau) {
+  int* cnt = dalloc<int>(P.n);
+  k_trunc_count<<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.val, tau, cnt);
+  PM_CHECK_LAUNCH();
+  Csr T;
+  T.bs = 1;
+  T.n = P.n;
+  T.m = P.m;
+  T.rowptr = dalloc<int>(P.n + 1);
+  int nnz = 0;
+  exclusive_scan(s, cnt, T.rowptr, P.n, &nnz);
+  dfree(cnt);
+  T.nnzb = nnz;
+  T.col = dalloc<int>(nnz);
+  T.val = dalloc<double>(nnz);
+  k_trunc_fill<<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.col, P.val, tau, T.rowptr, T.col, T.val);
+  PM_CHECK_LAUNCH();
+  P.free_all();
+  P = T;
+}
+
+// filtered operator for prolongator smoothing: strong off-diagonal blocks
+// kept, weak ones lumped into the diagonal block (row sums preserved)
+// entries kept in A_F (diagonal and strong); weak_rows counts the rows that
+// drop a nonzero block
+__global__ void k_filter_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                               const uint8_t* __restrict__ strong, int* __restrict__ cnt,
+                               int* __restrict__ weak_rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0, w = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const bool diag = col[e] == i;
+    c += diag || strong[e] == 1;
+    w += !diag && strong[e] == 0;
+  }
+  cnt[i] = c;
+  if (w) atomicAdd(weak_rows, 1);
 }
 
 template <int BS>
@@ -263,12 +354,12 @@ __global__ void k_filter_fill(int n, const int* __restrict__ rp, const int* __re
   double lump[BS * BS];
   for (int q = 0; q < BS * BS; ++q) lump[q] = 0.0;
   for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (col[e] != i && !strong[e])
+    if (col[e] != i && strong[e] == 0)
       for (int q = 0; q < BS * BS; ++q) lump[q] += val[(size_t)e * BS * BS + q];
   int p = frp[i];
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     const bool diag = col[e] == i;
-    if (!diag && !strong[e]) continue;
+    if (!diag && strong[e] != 1) continue;
     fcol[p] = col[e];
     for (int q = 0; q < BS * BS; ++q) fval[(size_t)p * BS * BS + q] = val[(size_t)e * BS * BS + q] + (diag ? lump[q] : 0.0);
     ++p;
@@ -446,6 +537,81 @@ __global__ void __launch_bounds__(256) k_csr16(int n, const int* __restrict__ rp
   }
 }
 
+// Levels with long rows (coarse Galerkin operators): G lanes per block row
+// stride over its CSR entries, the partial sums are combined with a fixed
+// xor tree (deterministic), and lane a < BS finishes component a.
+template <int BS, class T, int G>
+__device__ inline void csr_row_lanes(int row, int lane, const int* __restrict__ rp, const int* __restrict__ col,
+                                     const T* __restrict__ val, const T* __restrict__ x, T acc[BS]) {
+  for (int a = 0; a < BS; ++a) acc[a] = 0;
+  const int e1 = rp[row + 1];
+  for (int e = rp[row] + lane; e < e1; e += G) {
+    const int j = col[e];
+    const T* v = val + (size_t)e * BS * BS;
+    T xj[BS];
+    for (int q = 0; q < BS; ++q) xj[q] = x[(size_t)j * BS + q];
+    for (int a = 0; a < BS; ++a)
+      for (int q = 0; q < BS; ++q) acc[a] += v[a * BS + q] * xj[q];
+  }
+}
+
+template <int BS, class T, int G>
+__device__ inline void lanes_reduce(T acc[BS]) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1)
+    for (int a = 0; a < BS; ++a) acc[a] += __shfl_xor(acc[a], off, G);
+}
+
+// Chebyshev step on a CSR level: r = D^-1 (b - A x_in); d = c1 d + c2 r; x_out = x_in + d
+template <int BS, class T, int G>
+__global__ void __launch_bounds__(256) k_cheb_step_csr(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                       const T* __restrict__ val, const T* __restrict__ dinv,
+                                                       const T* __restrict__ b, const T* __restrict__ xin,
+                                                       T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(t / G), lane = (int)(t % G);
+  T acc[BS];
+  if (row < n)
+    csr_row_lanes<BS, T, G>(row, lane, rp, col, val, xin, acc);
+  else
+    for (int a = 0; a < BS; ++a) acc[a] = 0;
+  lanes_reduce<BS, T, G>(acc);
+  if (row >= n || lane >= BS) return;
+  T res[BS];
+  for (int a = 0; a < BS; ++a) res[a] = b[(size_t)row * BS + a] - acc[a];
+  T z = 0;
+  for (int q = 0; q < BS; ++q) z += dinv[(size_t)row * BS * BS + lane * BS + q] * res[q];
+  const size_t k = (size_t)row * BS + lane;
+  const T dn = c1 * d[k] + c2 * z;
+  d[k] = dn;
+  xout[k] = xin[k] + dn;
+}
+
+// residual r = b - A x (RES) or product r = A x on a CSR level
+template <int BS, class T, int G, bool RES>
+__global__ void __launch_bounds__(256) k_residual_csr(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                      const T* __restrict__ val, const T* __restrict__ b,
+                                                      const T* __restrict__ x, T* __restrict__ rr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(t / G), lane = (int)(t % G);
+  T acc[BS];
+  if (row < n)
+    csr_row_lanes<BS, T, G>(row, lane, rp, col, val, x, acc);
+  else
+    for (int a = 0; a < BS; ++a) acc[a] = 0;
+  lanes_reduce<BS, T, G>(acc);
+  if (row >= n || lane >= BS) return;
+  T v = acc[0];
+  for (int a = 1; a < BS; ++a)
+    if (lane == a) v = acc[a];
+  rr[(size_t)row * BS + lane] = RES ? b[(size_t)row * BS + lane] - v : v;
+}
+
+template <int BS>
+struct CsrLanes {
+  static constexpr int value = BS == 3 ? 8 : 16;
+};
+
 // dense coarse level
 __global__ void k_dense_from_csr(int nb, int bs, const int* __restrict__ rp, const int* __restrict__ col,
                                  const double* __restrict__ val, double* __restrict__ M, int ld) {
@@ -620,8 +786,8 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
   for (int round = 0; round < 1000; ++round) {
     PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
     k_mis_init<<<blocks_for(n), kBlock, 0, s>>>(n, state, 0x12345u, T0);
-    k_mis_max<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, T0, T1);
-    if (dist == 2) k_mis_max<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, T1, T2);
+    launch_mis_max(s, A, strong, T0, T1);
+    if (dist == 2) launch_mis_max(s, A, strong, T1, T2);
     k_mis_update<<<blocks_for(n), kBlock, 0, s>>>(n, T0, dist == 2 ? T2 : T1, state, und);
     PM_CHECK_LAUNCH();
     int h = 0;
@@ -674,16 +840,22 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   k_ptent<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, Pt.rowptr, Pt.col, Pt.val);
   PM_CHECK_LAUNCH();
   // filtered operator A_F (strong couplings, weak ones lumped on the diagonal);
-  // when every coupling is strong A_F = A and the level's D^-1, lmax serve
+  // when no nonzero coupling is weak A_F = A and the level's D^-1, lmax serve
   Csr AF;
   AF.bs = BS;
   AF.n = AF.m = n;
-  k_filter_count<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, f);
+  int* weak_rows = dalloc<int>(1);
+  PM_HIP(hipMemsetAsync(weak_rows, 0, sizeof(int), s));
+  k_filter_count<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, f, weak_rows);
   AF.rowptr = dalloc<int>(n + 1);
   int fnnz = 0;
   exclusive_scan(s, f, AF.rowptr, n, &fnnz);
   dfree(f);
-  const bool filtered = fnnz != A.nnzb;
+  int nweak = 0;
+  PM_HIP(hipMemcpyAsync(&nweak, weak_rows, sizeof(int), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  dfree(weak_rows);
+  const bool filtered = nweak > 0;
   double* dinvF = nullptr;
   double lF = L.lmax;
   Csr P;
@@ -707,6 +879,7 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   const double omega = 4.0 / (3.0 * lF);
   k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, filtered ? dinvF : L.dinv, omega, P.rowptr, P.col, P.val);
   PM_CHECK_LAUNCH();
+  if (BS == 1 && prm.p_trunc > 0.0) truncate_p(s, P, prm.p_trunc);
   dfree(dinvF);
   dfree(agg);
   // Galerkin coarse operator
@@ -772,7 +945,12 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
       rho = rn;
     }
     g_prof.begin(s, prof_id);
-    if (BS == 3 && lat) {
+    if (L.csr_cycle) {
+      constexpr int GL = CsrLanes<BS>::value;
+      k_cheb_step_csr<BS, T, GL><<<blocks_for((int64_t)n * GL), kBlock, 0, s>>>(
+          n, L.A.rowptr, L.A.col, val, dinv, b, cur, nxt, d, (T)c1, (T)c2);
+      g_prof.end(s, prof_id, 0.0);
+    } else if (BS == 3 && lat) {
       lattice_cheb_step<T>(s, G, *lat, dinv, b, cur, nxt, d, (T)c1, (T)c2);
       // algorithmic bytes: x/b/d read, x/d written, D^-1 blocks, cell moduli
       g_prof.end(s, prof_id, (double)n * BS * sizeof(T) * 5 + (double)n * BS * BS * sizeof(T) +
@@ -830,7 +1008,7 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
     PM_CHECK_LAUNCH();
     return;
   }
-  const T* AV = LP::AV(L.As);
+  const T* AV = L.csr_cycle ? LP::CV(L.A) : LP::AV(L.As);
   const T* DI = LP::DI(L);
   T* d = LP::D(L);
   T* t = LP::Tt(L);
@@ -842,6 +1020,10 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   // residual, restriction
   if (lat) {
     lattice_residual<T>(s, H.grid, *lat, b, cur, r);
+  } else if (L.csr_cycle) {
+    constexpr int GL = CsrLanes<BS>::value;
+    k_residual_csr<BS, T, GL, true><<<blocks_for((int64_t)n * GL), kBlock, 0, s>>>(n, L.A.rowptr, L.A.col, AV, b,
+                                                                                   cur, r);
   } else {
     const int nth = L.As.nslices * kSlice;
     k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
@@ -898,7 +1080,17 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
     const bool last = (L.n <= prm.coarse_max) || (l + 1 >= prm.max_levels);
     alloc_level_vectors(L, prm.fp32);
     const bool on_lattice = (l == 0 && H.lat);
-    if (!on_lattice) csr_to_sell(s, L.A, L.As, prm.fp32);
+    L.csr_cycle = !last && l > 0 && (double)L.A.nnzb >= 16.0 * L.n;
+    if (L.csr_cycle) {
+      if (prm.fp32) {
+        const int64_t nv = L.A.nnzb * L.bs * L.bs;
+        L.A.val32 = dalloc<float>(nv);
+        k_to_float<<<blocks_for(nv), kBlock, 0, s>>>(nv, L.A.val, L.A.val32);
+        PM_CHECK_LAUNCH();
+      }
+    } else if (!on_lattice) {
+      csr_to_sell(s, L.A, L.As, prm.fp32);
+    }
     if (last) {
       dense_inverse(s, L.A, H);
       break;
@@ -911,10 +1103,21 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
                                                                          L.dinv32);
       PM_CHECK_LAUNCH();
     }
-    if (on_lattice)
+    if (on_lattice) {
       L.lmax = power_lmax(s, L.n, 3, L.dinv, prm.power_its,
                           [&](const double* v, double* w) { lattice_apply(s, H.grid, *H.lat, v, w); });
-    else
+    } else if (L.csr_cycle) {
+      const Csr& A = L.A;
+      L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](const double* v, double* w) {
+        if (L.bs == 3)
+          k_residual_csr<3, double, 8, false><<<blocks_for((int64_t)A.n * 8), kBlock, 0, s>>>(
+              A.n, A.rowptr, A.col, A.val, nullptr, v, w);
+        else
+          k_residual_csr<1, double, 16, false><<<blocks_for((int64_t)A.n * 16), kBlock, 0, s>>>(
+              A.n, A.rowptr, A.col, A.val, nullptr, v, w);
+        PM_CHECK_LAUNCH();
+      });
+    } else
       L.lmax = estimate_lmax(s, L.As, L.dinv, prm.power_its);
     if (verbose)
       fprintf(stderr, "[amg bs=%d] level %d: rows %d, blocks %lld (%.1f/row), lmax(D^-1 A) %.4f\n", L.bs, l, L.n,

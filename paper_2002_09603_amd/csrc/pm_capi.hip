@@ -87,6 +87,7 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   p.cheb_degree = c->opts.cheb_degree_pi;
   p.cycles = c->opts.cycles_pi;
   p.agg_dist = c->opts.agg_dist_pi;
+  p.p_trunc = c->opts.p_trunc_pi;
   return p;
 }
 
@@ -153,6 +154,7 @@ void pm_default_opts(pm_opts* o) {
   o->restart_transpose = 100;
   o->orth_passes_transpose = 2;
   o->lattice_uu = 1;
+  o->p_trunc_pi = 0.02;
   o->theta_pi = 0.08;
 }
 
@@ -211,7 +213,8 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
         c->opts.agg_dist_u < 1 || c->opts.agg_dist_u > 2 || c->opts.agg_dist_pi < 1 || c->opts.agg_dist_pi > 2 ||
         !(c->opts.cheb_lower > 0.0 && c->opts.cheb_lower < 1.0) || c->opts.restart > 500 ||
         c->opts.restart_transpose < 0 || c->opts.restart_transpose > 500 || c->opts.orth_passes_transpose < 0 ||
-        c->opts.orth_passes_transpose > 2 || !(c->opts.rtol_transpose >= 0.0))
+        c->opts.orth_passes_transpose > 2 || !(c->opts.rtol_transpose >= 0.0) ||
+        !(c->opts.p_trunc_pi >= 0.0 && c->opts.p_trunc_pi < 1.0))
       throw Error(PM_EINVAL, "pm_setup: invalid solver options");
     c->coords = pm::dalloc<double>(3 * c->nn);
     c->E = pm::dalloc<double>(c->nc);

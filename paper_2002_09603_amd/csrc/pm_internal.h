@@ -109,7 +109,8 @@ struct Sell {
 struct Level {
   int bs = 1, n = 0;
   Csr A;                     // kept for the Galerkin products
-  Sell As;                   // operator used by the cycle
+  Sell As;                   // operator used by the cycle (sliced ELL) ...
+  bool csr_cycle = false;    // ... or A itself, G lanes per row (coarse levels with long rows)
   double* dinv = nullptr;    // n*bs*bs inverse diagonal blocks
   float* dinv32 = nullptr;
   Sell P;                    // prolongation from level+1 (empty on the coarsest level)
@@ -131,6 +132,7 @@ struct AmgParams {
   double cheb_lower = 1.0 / 30.0;  // Chebyshev interval [lower*lmax, upper*lmax]
   double cheb_upper = 1.1;
   int power_its = 15;
+  double p_trunc = 0.0;            // scalar prolongator truncation threshold (0: none)
   bool fp32 = false;
 };
 

@@ -56,56 +56,83 @@ __device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j,
   return true;
 }
 
-// the 27 neighbour displacements of node (i,j,k); Dirichlet components and
-// nodes outside the mesh read as zero (loads are clamped to node 0)
-template <class T>
-__device__ __forceinline__ void gather27(const Grid& G, int kind, const T* __restrict__ x, int i, int j, int k,
-                                         T u[27][3]) {
+// One plane (fixed nk) of the 3x3 neighbour displacements of node (i,j,k).
+// Indices are clamped into the mesh: a neighbour outside it only belongs to
+// cells outside the mesh, whose modulus is taken as zero below.  MASK zeroes
+// Dirichlet components (zero columns of A_uu).
+template <class T, bool MASK>
+__device__ __forceinline__ void load_plane(const Grid& G, int kind, const T* __restrict__ x, int i, int j, int nk,
+                                           T u[9][3]) {
+  const int kc = min(max(nk, 0), G.nz);
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
+  for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+    for (int dx = 0; dx < 3; ++dx) {
+      const int ni = i + dx - 1, nj = j + dy - 1;
+      const int64_t nb = G.node(min(max(ni, 0), G.nx), min(max(nj, 0), G.ny), kc);
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int ni = i + dx - 1, nj = j + dy - 1, nk = k + dz - 1;
-        const bool in = ni >= 0 && ni <= G.nx && nj >= 0 && nj <= G.ny && nk >= 0 && nk <= G.nz;
-        const int64_t nb = in ? G.node(ni, nj, nk) : 0;
-        const int q = dx + 3 * dy + 9 * dz;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T v = x[3 * nb + c];
-          u[q][c] = (in && !u_fixed(G, kind, ni, nj, nk, c)) ? v : (T)0;
-        }
+      for (int c = 0; c < 3; ++c) {
+        const T v = x[3 * nb + c];
+        u[dx + 3 * dy][c] = (MASK && u_fixed(G, kind, ni, nj, nk, c)) ? (T)0 : v;
       }
+    }
 }
 
-// acc = sum over the cells T around node (i,j,k) of E_T Khat[3a..3a+2, :] u_T
+// acc += contributions of the 4 cells of layer oz around node (i,j,k); lo and
+// hi are the neighbour planes below and above that cell layer
 template <class T>
-__device__ __forceinline__ void lattice_rows(const Grid& G, const T* __restrict__ Kh, const T* __restrict__ E,
-                                             const T u[27][3], int i, int j, int k, T acc[3]) {
-  acc[0] = acc[1] = acc[2] = (T)0;
+__device__ __forceinline__ void cell_layer(const Grid& G, const T* __restrict__ Kh, const T* __restrict__ E,
+                                           const T lo[9][3], const T hi[9][3], int oz, int i, int j, int k,
+                                           T acc[3]) {
+  const int ck = k - 1 + oz;
+  const bool kin = ck >= 0 && ck < G.nz;
+  const int ckc = min(max(ck, 0), G.nz - 1);
 #pragma unroll
-  for (int oz = 0; oz < 2; ++oz)
+  for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
-    for (int oy = 0; oy < 2; ++oy)
+    for (int ox = 0; ox < 2; ++ox) {
+      const int ci = i - 1 + ox, cj = j - 1 + oy;
+      const bool in = kin && ci >= 0 && ci < G.nx && cj >= 0 && cj < G.ny;
+      const T ev = E[G.cell(min(max(ci, 0), G.nx - 1), min(max(cj, 0), G.ny - 1), ckc)];
+      const T e = in ? ev : (T)0;
+      const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
 #pragma unroll
-      for (int ox = 0; ox < 2; ++ox) {
-        const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
-        if (ci < 0 || ci >= G.nx || cj < 0 || cj >= G.ny || ck < 0 || ck >= G.nz) continue;
-        const T e = E[G.cell(ci, cj, ck)];
-        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+      for (int r = 0; r < 3; ++r) {
+        T sum = (T)0;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          T sum = (T)0;
+        for (int b = 0; b < 8; ++b) {
+          const int q = (ox + (b & 1)) + 3 * (oy + ((b >> 1) & 1));
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const int q = (ox + (b & 1)) + 3 * (oy + ((b >> 1) & 1)) + 9 * (oz + ((b >> 2) & 1));
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sum += Kh[(3 * a + r) * 24 + 3 * b + c] * u[q][c];
+          for (int c = 0; c < 3; ++c) {
+            const T uv = ((b >> 2) & 1) ? hi[q][c] : lo[q][c];
+            sum += Kh[(3 * a + r) * 24 + 3 * b + c] * uv;
           }
-          acc[r] += e * sum;
         }
+        acc[r] += e * sum;
       }
+    }
+}
+
+// acc = sum over the cells T around node (i,j,k) of E_T Khat[3a..3a+2, :] u_T,
+// the neighbour planes loaded one at a time
+template <class T, bool MASK>
+__device__ __forceinline__ void lattice_rows(const Grid& G, int kind, const T* __restrict__ Kh,
+                                             const T* __restrict__ E, const T* __restrict__ x, int i, int j, int k,
+                                             T acc[3]) {
+  acc[0] = acc[1] = acc[2] = (T)0;
+  T pa[9][3], pb[9][3];
+  load_plane<T, MASK>(G, kind, x, i, j, k - 1, pa);
+  load_plane<T, MASK>(G, kind, x, i, j, k, pb);
+  cell_layer<T>(G, Kh, E, pa, pb, 0, i, j, k, acc);
+  load_plane<T, MASK>(G, kind, x, i, j, k + 1, pa);
+  cell_layer<T>(G, Kh, E, pb, pa, 1, i, j, k, acc);
+}
+
+// no Dirichlet component among the 27 neighbours of node (i,j,k)
+__device__ inline bool free_neighbourhood(const Grid& G, int kind, int i, int j, int k) {
+  if (k < 2) return false;
+  if (kind != PM_BC_ROLLERS) return true;
+  return i >= 2 && i <= G.nx - 2 && j >= 2 && j <= G.ny - 2;
 }
 
 // (A x) at node n: Dirichlet rows are identity
@@ -113,9 +140,10 @@ template <class T>
 __device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const T* __restrict__ Kh,
                                            const T* __restrict__ E, const T* __restrict__ x, int64_t n, int i, int j,
                                            int k, T ax[3]) {
-  T u[27][3];
-  gather27<T>(G, kind, x, i, j, k, u);
-  lattice_rows<T>(G, Kh, E, u, i, j, k, ax);
+  if (free_neighbourhood(G, kind, i, j, k))
+    lattice_rows<T, false>(G, kind, Kh, E, x, i, j, k, ax);
+  else
+    lattice_rows<T, true>(G, kind, Kh, E, x, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
     if (u_fixed(G, kind, i, j, k, a)) ax[a] = x[3 * n + a];
@@ -178,10 +206,11 @@ __global__ void __launch_bounds__(256) k_lat_ah_u(Grid G, int kind, const double
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
-  double uu[27][3];
-  gather27<double>(G, kind, u, i, j, k, uu);
   double acc[3];
-  lattice_rows<double>(G, Kh, E, uu, i, j, k, acc);
+  if (free_neighbourhood(G, kind, i, j, k))
+    lattice_rows<double, false>(G, kind, Kh, E, u, i, j, k, acc);
+  else
+    lattice_rows<double, true>(G, kind, Kh, E, u, i, j, k, acc);
   double cp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int oz = 0; oz < 2; ++oz)

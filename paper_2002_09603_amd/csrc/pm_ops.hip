@@ -15,6 +15,17 @@ namespace pm {
 
 namespace {
 
+// coupling columns a_T: per-cell array, or one column for every cell of a lattice
+struct AeCells {
+  const double* ae;
+  int64_t nc;
+  __device__ double operator()(int q, int64_t c) const { return ae[(size_t)q * nc + c]; }
+};
+struct AeLattice {
+  const double* ah;
+  __device__ double operator()(int q, int64_t) const { return ah[q]; }
+};
+
 // u-rows: y_u = A_uu u + sgn * A_up p     (sgn = +1: A_H; -1: A_H^T, since A_pu = -A_up^T)
 template <class T>
 __global__ void __launch_bounds__(256) k_ah_u(Grid G, int n, const int* __restrict__ sptr,
@@ -48,8 +59,8 @@ __global__ void __launch_bounds__(256) k_ah_u(Grid G, int n, const int* __restri
 
 // p-rows: y_p = su * sum a_T u + (S|T| + dt alpha) p + A_stab p + spi * sum_e (-g_e) pi_e
 //   A_H:   su = -1, spi = dt      A_H^T: su = +1, spi = 1
-template <class T>
-__global__ void k_ah_p(Grid G, const double* __restrict__ ae, const double* __restrict__ vol,
+template <class T, class AE>
+__global__ void k_ah_p(Grid G, AE ae, const double* __restrict__ vol,
                        const double* __restrict__ alpha, const double* __restrict__ gv,
                        const double* __restrict__ stabw, const uint8_t* __restrict__ ufix,
                        const uint8_t* __restrict__ pifix, const T* __restrict__ u, const T* __restrict__ p,
@@ -64,7 +75,7 @@ __global__ void k_ah_p(Grid G, const double* __restrict__ ae, const double* __re
     const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
     for (int d = 0; d < 3; ++d) {
       const size_t q = 3 * (size_t)n + d;
-      if (!ufix[q]) v += ae[(size_t)(3 * a + d) * G.nc + c] * (double)u[q];
+      if (!ufix[q]) v += ae(3 * a + d, c) * (double)u[q];
     }
   }
   v *= su;
@@ -132,8 +143,8 @@ __global__ void k_prec_p(Grid G, const double* __restrict__ gv, const double* __
 }
 
 // t_u = r_u - A_up z_p
-template <class T>
-__global__ void k_prec_u(Grid G, const double* __restrict__ ae, const uint8_t* __restrict__ ufix,
+template <class T, class AE>
+__global__ void k_prec_u(Grid G, AE ae, const uint8_t* __restrict__ ufix,
                          const T* __restrict__ ru, const T* __restrict__ zp, T* __restrict__ tu) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= G.nn) return;
@@ -146,7 +157,7 @@ __global__ void k_prec_u(Grid G, const double* __restrict__ ae, const uint8_t* _
         const int64_t c = G.cell(ci, cj, ck);
         const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
         const double pc = (double)zp[c];
-        for (int d = 0; d < 3; ++d) cp[d] += ae[(size_t)(3 * a + d) * G.nc + c] * pc;
+        for (int d = 0; d < 3; ++d) cp[d] += ae(3 * a + d, c) * pc;
       }
   for (int d = 0; d < 3; ++d) {
     const size_t q = 3 * (size_t)n + d;
@@ -155,8 +166,8 @@ __global__ void k_prec_u(Grid G, const double* __restrict__ ae, const uint8_t* _
 }
 
 // transpose pieces: z_p = (r_p - A_up^T z_u) / B~_p ;  t_pi = r_pi - dt A_ppi^T z_p
-template <class T>
-__global__ void k_precT_p(Grid G, const double* __restrict__ ae, const double* __restrict__ bp,
+template <class T, class AE>
+__global__ void k_precT_p(Grid G, AE ae, const double* __restrict__ bp,
                           const uint8_t* __restrict__ ufix, const T* __restrict__ rp, const T* __restrict__ zu,
                           T* __restrict__ zp) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,7 +179,7 @@ __global__ void k_precT_p(Grid G, const double* __restrict__ ae, const double* _
     const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
     for (int d = 0; d < 3; ++d) {
       const size_t q = 3 * (size_t)n + d;
-      if (!ufix[q]) v += ae[(size_t)(3 * a + d) * G.nc + c] * (double)zu[q];
+      if (!ufix[q]) v += ae(3 * a + d, c) * (double)zu[q];
     }
   }
   zp[c] = (T)(((double)rp[c] - v) / bp[c]);
@@ -376,9 +387,15 @@ void ah_launch(pm_ctx* c, const T* x, T* y, bool transpose, const Sell& Auu, con
                (double)Auu.nnzb * (9 * sizeof(T) + 4) + (double)c->n_u * (2 * sizeof(T) + 1) +
                    (double)c->nc * (24 * 8 + sizeof(T)));
   }
-  k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->ae, c->vol, c->alpha, c->g, c->stabw, c->ufix, c->pifix,
-                                                   u, p, pi, c->S, c->dt, c->opts.stabilize,
-                                                   transpose ? 1.0 : -1.0, transpose ? 1.0 : c->dt, yp);
+  const double su = transpose ? 1.0 : -1.0, spi = transpose ? 1.0 : c->dt;
+  if (c->lat.on)
+    k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, AeLattice{c->lat.ah}, c->vol, c->alpha, c->g, c->stabw,
+                                                     c->ufix, c->pifix, u, p, pi, c->S, c->dt, c->opts.stabilize,
+                                                     su, spi, yp);
+  else
+    k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, AeCells{c->ae, G.nc}, c->vol, c->alpha, c->g, c->stabw,
+                                                     c->ufix, c->pifix, u, p, pi, c->S, c->dt, c->opts.stabilize,
+                                                     su, spi, yp);
   k_ah_pi<T><<<blocks_for(G.nf), kBlock, 0, c->s>>>(G, c->Minv, c->g, c->pifix, p, pi,
                                                     transpose ? c->dt : 1.0, ypi);
   PM_CHECK_LAUNCH();
@@ -410,12 +427,18 @@ static void prec_apply_t(pm_ctx* c, const T* r, T* z, T* tmp, bool transpose) {
   if (!transpose) {
     vc(c->Hpi, rpi, zpi);
     k_prec_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->g, c->bp, c->pifix, rp, zpi, c->dt, zp);
-    k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, c->ae, c->ufix, ru, zp, tmp);
+    if (c->lat.on)
+      k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, AeLattice{c->lat.ah}, c->ufix, ru, zp, tmp);
+    else
+      k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, AeCells{c->ae, G.nc}, c->ufix, ru, zp, tmp);
     PM_CHECK_LAUNCH();
     vc(c->Hu, tmp, zu);
   } else {
     vc(c->Hu, ru, zu);
-    k_precT_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->ae, c->bp, c->ufix, rp, zu, zp);
+    if (c->lat.on)
+      k_precT_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, AeLattice{c->lat.ah}, c->bp, c->ufix, rp, zu, zp);
+    else
+      k_precT_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, AeCells{c->ae, G.nc}, c->bp, c->ufix, rp, zu, zp);
     k_precT_pi<T><<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->g, c->pifix, rpi, zp, c->dt, tmp);
     PM_CHECK_LAUNCH();
     vc(c->Hpi, tmp, zpi);

@@ -55,6 +55,7 @@ class Options:
     restart_transpose: int = 100
     orth_passes_transpose: int = 2
     lattice_uu: bool = True
+    p_trunc_pi: float = 0.02
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -79,6 +80,7 @@ class Options:
         o.restart_transpose = self.restart_transpose
         o.orth_passes_transpose = self.orth_passes_transpose
         o.lattice_uu = int(self.lattice_uu)
+        o.p_trunc_pi = self.p_trunc_pi
         return o
 
 
