@@ -115,6 +115,8 @@ typedef struct {
                                 matrix instead of the assembled matrix; 0: always assembled */
   double p_trunc_pi;         /* C~_pi hierarchy: drop prolongator entries below this fraction of
                                 their row's largest, rescaling to the row sum (0: keep all) */
+  int32_t cell_pi;           /* 1: apply the finest C~_pi level cell by cell from packed symmetric
+                                6x6 element matrices; 0: assembled matrix */
 } pm_opts;
 
 typedef struct {
@@ -135,7 +137,7 @@ typedef struct {
  * Gram-Schmidt passes (restarted GMRES on the transposed preconditioned
  * operator stagnates with short restarts or one pass on strongly
  * heterogeneous permeability); lattice operator on; C~_pi prolongator
- * truncation 0.02. */
+ * truncation 0.02; cell-by-cell finest C~_pi level. */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

@@ -919,7 +919,7 @@ void alloc_level_vectors(Level& L, bool fp32) {
 // Returns the buffer holding the result (x or t).
 template <int BS, class T>
 T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T* x, T* t, T* d, bool zero_init,
-             const T* val, const T* dinv, int prof_id, const LatticeOp* lat, const Grid& G) {
+             const T* val, const T* dinv, int prof_id, const LatticeOp* lat, const CellPiOp* cpi, const Grid& G) {
   const double lo = prm.cheb_lower * L.lmax, hi = prm.cheb_upper * L.lmax;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
   const double sigma = theta / delta;
@@ -950,6 +950,10 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
       k_cheb_step_csr<BS, T, GL><<<blocks_for((int64_t)n * GL), kBlock, 0, s>>>(
           n, L.A.rowptr, L.A.col, val, dinv, b, cur, nxt, d, (T)c1, (T)c2);
       g_prof.end(s, prof_id, 0.0);
+    } else if (BS == 1 && cpi) {
+      cellpi_cheb_step<T>(s, G, *cpi, dinv, b, cur, nxt, d, (T)c1, (T)c2);
+      // algorithmic bytes: 21 packed values per cell; x/b/d read, x/d written, D^-1 per face
+      g_prof.end(s, prof_id, (double)G.nc * 21 * sizeof(T) + (double)n * sizeof(T) * 6);
     } else if (BS == 3 && lat) {
       lattice_cheb_step<T>(s, G, *lat, dinv, b, cur, nxt, d, (T)c1, (T)c2);
       // algorithmic bytes: x/b/d read, x/d written, D^-1 blocks, cell moduli
@@ -1016,10 +1020,13 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   // pre-smoothing from zero
   const int prof_id = l == 0 ? (BS == 3 ? kProfChebU0 : kProfChebPi0) : 0;
   const LatticeOp* lat = (l == 0 && BS == 3) ? H.lat : nullptr;
-  T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI, prof_id, lat, H.grid);
+  const CellPiOp* cpi = (l == 0 && BS == 1) ? H.cpi : nullptr;
+  T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI, prof_id, lat, cpi, H.grid);
   // residual, restriction
   if (lat) {
     lattice_residual<T>(s, H.grid, *lat, b, cur, r);
+  } else if (cpi) {
+    cellpi_residual<T>(s, H.grid, *cpi, b, cur, r);
   } else if (L.csr_cycle) {
     constexpr int GL = CsrLanes<BS>::value;
     k_residual_csr<BS, T, GL, true><<<blocks_for((int64_t)n * GL), kBlock, 0, s>>>(n, L.A.rowptr, L.A.col, AV, b,
@@ -1040,18 +1047,19 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   PM_CHECK_LAUNCH();
   // post-smoothing from the corrected iterate
   T* other = (cur == x) ? t : x;
-  T* res = chebyshev<BS, T>(s, L, prm, b, cur, other, d, false, AV, DI, prof_id, lat, H.grid);
+  T* res = chebyshev<BS, T>(s, L, prm, b, cur, other, d, false, AV, DI, prof_id, lat, cpi, H.grid);
   if (res != x) PM_HIP(hipMemcpyAsync(x, res, sizeof(T) * (size_t)n * BS, hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace
 
 void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H, const LatticeOp* lat,
-               const Grid* G) {
+               const Grid* G, const CellPiOp* cpi) {
   H.free_all();
   H.bs = A0.bs;
   H.lat = (lat && lat->on && G && A0.bs == 3) ? lat : nullptr;
-  if (H.lat) H.grid = *G;
+  H.cpi = (cpi && cpi->on && G && A0.bs == 1) ? cpi : nullptr;
+  if (H.lat || H.cpi) H.grid = *G;
   H.fp32 = prm.fp32;
   H.prm = prm;
   double nnz_total = 0.0, nnz0 = (double)A0.nnzb;
@@ -1079,7 +1087,7 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
     nnz_total += (double)L.A.nnzb;
     const bool last = (L.n <= prm.coarse_max) || (l + 1 >= prm.max_levels);
     alloc_level_vectors(L, prm.fp32);
-    const bool on_lattice = (l == 0 && H.lat);
+    const bool on_lattice = (l == 0 && (H.lat || H.cpi));
     L.csr_cycle = !last && l > 0 && (double)L.A.nnzb >= 16.0 * L.n;
     if (L.csr_cycle) {
       if (prm.fp32) {
@@ -1104,8 +1112,12 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
       PM_CHECK_LAUNCH();
     }
     if (on_lattice) {
-      L.lmax = power_lmax(s, L.n, 3, L.dinv, prm.power_its,
-                          [&](const double* v, double* w) { lattice_apply(s, H.grid, *H.lat, v, w); });
+      L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](const double* v, double* w) {
+        if (H.lat)
+          lattice_apply(s, H.grid, *H.lat, v, w);
+        else
+          cellpi_apply(s, H.grid, *H.cpi, v, w);
+      });
     } else if (L.csr_cycle) {
       const Csr& A = L.A;
       L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](const double* v, double* w) {
@@ -1178,6 +1190,8 @@ void iterated_cycles(hipStream_t s, Hierarchy& H, const T* b, T* x, T* r0, T* c0
   for (int c = 1; c < H.prm.cycles; ++c) {
     if (BS == 3 && H.lat) {
       lattice_residual<T>(s, H.grid, *H.lat, b, x, r0);
+    } else if (BS == 1 && H.cpi) {
+      cellpi_residual<T>(s, H.grid, *H.cpi, b, x, r0);
     } else {
       const int nth = L.As.nslices * kSlice;
       k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(L.n, L.As.sptr, L.As.col, LP::AV(L.As), b, x, r0);

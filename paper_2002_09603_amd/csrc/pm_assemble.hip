@@ -219,12 +219,7 @@ __global__ void k_masks(Grid G, int kind, uint8_t* __restrict__ ufix, uint8_t* _
     for (int d = 0; d < 3; ++d) ufix[3 * t + d] = u_fixed(G, kind, i, j, k, d);
   }
   if (t < G.nf) {
-    bool top = false;
-    if (t >= G.nfx + G.nfy) {
-      const int64_t g = t - G.nfx - G.nfy;
-      top = (g / ((int64_t)G.nx * G.ny)) == G.nz;
-    }
-    pifix[t] = top;
+    pifix[t] = pi_fixed(G, t);
   }
 }
 

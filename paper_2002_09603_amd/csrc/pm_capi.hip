@@ -52,6 +52,7 @@ void free_ctx_buffers(pm_ctx* c) {
   c->Hu.free_all();
   c->Hpi.free_all();
   c->lat.free_all();
+  c->cpi.free_all();
 }
 
 void copy_in(pm_ctx* c, double* dst, const double* src, int64_t n) {
@@ -97,7 +98,9 @@ void setup_hierarchies(pm_ctx* c, bool with_u) {
     pm::amg_setup(c->s, c->Auu, params_u(c), c->Hu, c->lattice ? &c->lat : nullptr, &G);
     c->hier_u_ok = true;
   }
-  pm::amg_setup(c->s, c->Cpi, params_pi(c), c->Hpi);
+  const pm::Grid Gp = pm::grid_of(c);
+  if (c->opts.cell_pi) pm::cellpi_build(c);
+  pm::amg_setup(c->s, c->Cpi, params_pi(c), c->Hpi, nullptr, &Gp, c->opts.cell_pi ? &c->cpi : nullptr);
   c->info.levels_u = (int)c->Hu.L.size();
   c->info.levels_pi = (int)c->Hpi.L.size();
   c->info.opcx_u = c->Hu.opcx;
@@ -155,6 +158,7 @@ void pm_default_opts(pm_opts* o) {
   o->orth_passes_transpose = 2;
   o->lattice_uu = 1;
   o->p_trunc_pi = 0.02;
+  o->cell_pi = 1;
   o->theta_pi = 0.08;
 }
 

@@ -98,6 +98,24 @@ __host__ __device__ inline bool u_fixed(const Grid& G, int kind, int i, int j, i
   return false;
 }
 
+// Dirichlet face pressures: the faces of the top plane (drained boundary).
+__host__ __device__ inline bool pi_fixed(const Grid& G, int64_t f) {
+  if (f < G.nfx + G.nfy) return false;
+  return (f - G.nfx - G.nfy) / ((int64_t)G.nx * G.ny) == G.nz;
+}
+// the same for local face e of cell (., ., k): only the +z face of a top cell
+__host__ __device__ inline bool pi_fixed_local(const Grid& G, int k, int e) { return e == 5 && k == G.nz - 1; }
+
+// Workgroups are dispatched to the 8 XCDs round-robin; this maps workgroup b
+// of nb so that each XCD runs one contiguous range of logical workgroups
+// (neighbour rows and planes gathered by a workgroup then sit in the L2 of
+// the same XCD).
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8;
+  const int64_t id = b % 8, idx = b / 8;
+  return id < r ? id * (q + 1) + idx : r * (q + 1) + (id - r) * q + idx;
+}
+
 constexpr double kGauss = 0.57735026918962576451;  // 1/sqrt(3)
 
 __host__ __device__ inline void gauss_point(int q, double xi[3]) {

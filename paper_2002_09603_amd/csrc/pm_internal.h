@@ -167,9 +167,26 @@ void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const doubl
 // vectors at node 0, and min |a|,|b|,|c| (synchronizes)
 void lattice_deviation(hipStream_t s, const Grid& G, const double* coords, double* dev, double* hmin);
 
+// C~_pi applied cell by cell from packed symmetric 6x6 element matrices
+// (pm_cellpi.hip): C[pk(a,b)*n_c + cell], a <= b, 21 per cell, FP64 and an
+// optional FP32 copy.
+struct CellPiOp {
+  bool on = false;
+  double* C = nullptr;
+  float* C32 = nullptr;
+  void free_all();
+};
+template <class T>
+void cellpi_cheb_step(hipStream_t s, const Grid& G, const CellPiOp& op, const T* dinv, const T* b, const T* xin,
+                      T* xout, T* d, T c1, T c2);
+template <class T>
+void cellpi_residual(hipStream_t s, const Grid& G, const CellPiOp& op, const T* b, const T* x, T* r);
+void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const double* x, double* y);
+
 struct Hierarchy {
   int bs = 1;
   const LatticeOp* lat = nullptr;  // finest level applied on the lattice (A_uu only)
+  const CellPiOp* cpi = nullptr;   // finest level applied cell by cell (C~_pi only)
   Grid grid{};                     // mesh of the lattice operator
   std::vector<Level> L;
   double* coarse_inv = nullptr;  // dense inverse of the coarsest operator (FP64)
@@ -205,6 +222,7 @@ struct pm_ctx {
   double* Ke = nullptr;      // 576*nc element stiffness (assembly scratch; unused on lattices)
   bool lattice = false;      // cells are translates of one parallelepiped
   pm::LatticeOp lat;         // finest-level A_uu operator on lattices
+  pm::CellPiOp cpi;          // finest-level C~_pi operator from element matrices
   double* ae = nullptr;      // 24*nc coupling column of A_up
   double* vol = nullptr;     // nc
   double* Minv = nullptr;    // 36*nc inverse RT0 mass
@@ -248,6 +266,7 @@ inline int64_t node_id(const pm_ctx* c, int i, int j, int k) {
 Grid grid_of(const pm_ctx* c);
 void assemble_all(pm_ctx* c);          // element kernels, A_uu, B~p, C~pi (no AMG)
 void lattice_finish(pm_ctx* c);        // lattice operator tables after assembly (pm_lattice.hip)
+void cellpi_build(pm_ctx* c);          // packed C~_pi element matrices (pm_cellpi.hip)
 void rebuild_dt(pm_ctx* c);            // B~p, C~pi for the current dt
 void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
 void check_status(pm_ctx* c, const char* where);
@@ -272,10 +291,11 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C);
 void block_diag_inverse(hipStream_t s, const Csr& A, double* dinv);
 
 // AMG (pm_amg.hip)
-// lat (may be null): apply the finest level of a block-3 hierarchy with the
-// lattice operator on grid G instead of an assembled sliced-ELL matrix
+// lat / cpi (may be null): apply the finest level of a block-3 / scalar
+// hierarchy with the lattice / cell operator on grid G instead of an
+// assembled sliced-ELL matrix
 void amg_setup(hipStream_t s, const Csr& A, const AmgParams& prm, Hierarchy& H, const LatticeOp* lat = nullptr,
-               const Grid* G = nullptr);
+               const Grid* G = nullptr, const CellPiOp* cpi = nullptr);
 void amg_vcycle(hipStream_t s, Hierarchy& H, const double* b, double* x);       // FP64
 void amg_vcycle32(hipStream_t s, Hierarchy& H, const float* b, float* x);       // FP32 levels
 

@@ -35,15 +35,6 @@ void LatticeOp::free_all() {
 
 namespace {
 
-// Workgroups are dispatched to the 8 XCDs round-robin; give each XCD one
-// contiguous range of nodes so that the neighbour rows and planes a
-// workgroup gathers sit in the L2 of the same XCD.
-__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
-  const int64_t q = nb / 8, r = nb % 8;
-  const int64_t id = b % 8, idx = b / 8;
-  return id < r ? id * (q + 1) + idx : r * (q + 1) + (id - r) * q + idx;
-}
-
 __device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j, int& k) {
   n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (n >= G.nn) return false;

@@ -56,6 +56,7 @@ class Options:
     orth_passes_transpose: int = 2
     lattice_uu: bool = True
     p_trunc_pi: float = 0.02
+    cell_pi: bool = True
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -81,6 +82,7 @@ class Options:
         o.orth_passes_transpose = self.orth_passes_transpose
         o.lattice_uu = int(self.lattice_uu)
         o.p_trunc_pi = self.p_trunc_pi
+        o.cell_pi = int(self.cell_pi)
         return o
 
 

@@ -178,3 +178,22 @@ def test_error_codes():
     with pytest.raises(_capi.PMError) as e:
         from_problem(prob.with_(coords=X)).assemble()
     assert e.value.code == _capi.PM_EINVAL
+
+
+@pytest.mark.parametrize("name", ["box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop"])
+def test_matrix_free_finest_levels_match_assembled(name):
+    """The V-cycles with the matrix-free finest levels (A_uu on lattices, C~_pi
+    cell by cell) equal those on the assembled finest matrices to FP64
+    rounding (same hierarchies below), and so does one M^-1 application."""
+    prob = _case(name)
+    rng = np.random.default_rng(11)
+    out = {}
+    for mf in (True, False):
+        s = from_problem(prob, Options(lattice_uu=mf, cell_pi=mf)).assemble()
+        xs = [_t(rng.standard_normal(n)) for n in (s.n_u, s.n_pi, s.N)]
+        rng = np.random.default_rng(11)
+        out[mf] = [_np(s.apply(op, x)) for op, x in zip(
+            (_capi.PM_OP_VCYCLE_U, _capi.PM_OP_VCYCLE_PI, _capi.PM_OP_MINV), xs)]
+        s.close()
+    for a, b in zip(out[True], out[False]):
+        assert rel(a, b) <= 1e-12
