@@ -869,9 +869,9 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
     block_diag_inverse(s, AF, dinvF);
     lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
     // smoothed prolongator P = (I - 4/(3 lmax) D_F^-1 A_F) P_tent on the pattern of A_F P_tent
-    spgemm(s, AF, Pt, P);
+    spgemm(s, AF, Pt, P, agg);
   } else {
-    spgemm(s, A, Pt, P);
+    spgemm(s, A, Pt, P, agg);
   }
   dfree(strong);
   Pt.free_all();
@@ -1088,7 +1088,8 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
     const bool last = (L.n <= prm.coarse_max) || (l + 1 >= prm.max_levels);
     alloc_level_vectors(L, prm.fp32);
     const bool on_lattice = (l == 0 && (H.lat || H.cpi));
-    L.csr_cycle = !last && l > 0 && (double)L.A.nnzb >= 16.0 * L.n;
+    // long rows on a small level: latency-bound with one thread per row
+    L.csr_cycle = !last && l > 0 && L.n <= 262144 && (double)L.A.nnzb >= 16.0 * L.n;
     if (L.csr_cycle) {
       if (prm.fp32) {
         const int64_t nv = L.A.nnzb * L.bs * L.bs;

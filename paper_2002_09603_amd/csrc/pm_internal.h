@@ -287,7 +287,9 @@ void csr_to_sell(hipStream_t s, const Csr& A, Sell& S, bool with_fp32);
 void sell_spmv(hipStream_t s, const Sell& A, const double* x, double* y);
 void sell_spmv32(hipStream_t s, const Sell& A, const float* x, float* y);
 void csr_transpose(hipStream_t s, const Csr& A, Csr& T);
-void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C);
+// C = A B; ptent_agg (optional): B is the tentative prolongator of that
+// aggregation (identity block in column agg[j] of row j), numeric phase by sums
+void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_agg = nullptr);
 void block_diag_inverse(hipStream_t s, const Csr& A, double* dinv);
 
 // AMG (pm_amg.hip)

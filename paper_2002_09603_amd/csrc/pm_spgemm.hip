@@ -199,6 +199,31 @@ void numeric_launch(hipStream_t s, const int* counts, const int* lists, int n, c
   PM_CHECK_LAUNCH();
 }
 
+// Numeric phase when B is a tentative prolongator (row j: one identity block
+// in column agg[j], none if agg[j] < 0): C[i, K] = sum of A[i, j] over the
+// entries with agg[j] == K, in entry order.  G lanes per row, each owning
+// every G-th output column of the row.
+template <int BS, int G>
+__global__ void __launch_bounds__(256) k_num_ptent(int n, const int* __restrict__ arp, const int* __restrict__ acol,
+                                                   const double* __restrict__ aval, const int* __restrict__ agg,
+                                                   const int* __restrict__ crp, const int* __restrict__ ccol,
+                                                   double* __restrict__ cval) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(t / G), lane = (int)(t % G);
+  if (row >= n) return;
+  const int c0 = crp[row], u = crp[row + 1] - c0;
+  const int e0 = arp[row], e1 = arp[row + 1];
+  for (int q = lane; q < u; q += G) {
+    const int key = ccol[c0 + q];
+    double acc[BS * BS];
+    for (int k = 0; k < BS * BS; ++k) acc[k] = 0.0;
+    for (int e = e0; e < e1; ++e)
+      if (agg[acol[e]] == key)
+        for (int k = 0; k < BS * BS; ++k) acc[k] += aval[(size_t)e * BS * BS + k];
+    for (int k = 0; k < BS * BS; ++k) cval[(size_t)(c0 + q) * BS * BS + k] = acc[k];
+  }
+}
+
 __global__ void k_i64_from_i32(int n, const int* __restrict__ a, int64_t* __restrict__ b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
@@ -206,7 +231,7 @@ __global__ void k_i64_from_i32(int n, const int* __restrict__ a, int64_t* __rest
 
 }  // namespace
 
-void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C) {
+void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_agg) {
   if (A.bs != B.bs || A.m != B.n) throw Error(PM_EINTERNAL, "spgemm: shape mismatch");
   C.free_all();
   C.bs = A.bs;
@@ -262,6 +287,19 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C) {
   C.col = dalloc<int>(total);
   C.val = dalloc<double>((int64_t)total * A.bs * A.bs);
   k_compact<<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, ubofs, tmp, C.rowptr, C.col);
+  if (ptent_agg) {
+    if (A.bs == 3)
+      k_num_ptent<3, 8><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, ptent_agg,
+                                                                      C.rowptr, C.col, C.val);
+    else
+      k_num_ptent<1, 8><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, ptent_agg,
+                                                                      C.rowptr, C.col, C.val);
+    PM_CHECK_LAUNCH();
+    PM_HIP(hipStreamSynchronize(s));
+    for (void* p : {(void*)ub, (void*)counters, (void*)lists, (void*)ub64, (void*)ubofs, (void*)cnt, (void*)tmp})
+      dfree(p);
+    return;
+  }
   // numeric phase binned by the exact number of distinct columns
   PM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(int), s));
   k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, cnt, 64, 512, counters, lists);
