@@ -160,8 +160,10 @@ void lattice_cheb_step(hipStream_t s, const Grid& G, const LatticeOp& op, const 
 template <class T>
 void lattice_residual(hipStream_t s, const Grid& G, const LatticeOp& op, const T* b, const T* x, T* r);
 void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y);
-// u-rows of A_H: y_u = A_uu u + sgn A_up p (free rows), y_u = u (Dirichlet rows)
-void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const double* u, const double* p, double sgn,
+// u-rows of A_H: y_u = A_uu u + sgn A_up p (free rows), y_u = u (Dirichlet rows);
+// FP64 arithmetic, FP64 or FP32 inputs
+template <class TX>
+void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const TX* u, const TX* p, double sgn,
                   double* y);
 // max over nodes of |X(i,j,k) - X(0) - i a - j b - k c| with a, b, c the edge
 // vectors at node 0, and min |a|,|b|,|c| (synchronizes)
@@ -242,7 +244,9 @@ struct pm_ctx {
   // Krylov workspace
   int m_alloc = 0;
   double* V = nullptr;       // (m+1)*N
-  double* Z = nullptr;       // m*N
+  double* Z = nullptr;       // m*N preconditioned vectors (FP64 preconditioner, or two-pass Gram-Schmidt)
+  float* Zf = nullptr;       // m*N preconditioned vectors from the FP32 preconditioner
+  int mz_alloc = 0, mzf_alloc = 0;
   double* wvec = nullptr;    // N
   double* rvec = nullptr;    // N
   double* xvec = nullptr;    // N
@@ -273,7 +277,9 @@ void check_status(pm_ctx* c, const char* where);
 
 // operators (pm_ops.hip)
 void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose);
+void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose);    // FP32 input, FP64 arithmetic
 void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose);
+void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose);   // FP32 hierarchies only
 void apply_csr(pm_ctx* c, const Csr& A, const double* x, double* y);
 void reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w);
 void grad(pm_ctx* c, const double* lam, const double* x, const double* p_prev, double* dk,

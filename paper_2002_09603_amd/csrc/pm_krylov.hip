@@ -64,8 +64,10 @@ __global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ pa
 }
 
 // w += sign * sum_{i<cnt} coef[i] V_i (coef on the device); with norm_row >= 0
-// also part[norm_row*kDotBlocks + block] = sum_chunk w_new . w_new
-__global__ void __launch_bounds__(256) k_multiaxpy(const double* __restrict__ V, int64_t N, int cnt,
+// also part[norm_row*kDotBlocks + block] = sum_chunk w_new . w_new.  V in
+// FP64, or FP32 for the preconditioned vectors of the mixed-precision solve.
+template <class TV>
+__global__ void __launch_bounds__(256) k_multiaxpy(const TV* __restrict__ V, int64_t N, int cnt,
                                                    const double* __restrict__ coef, double* __restrict__ w,
                                                    double sign, double* __restrict__ part, int norm_row) {
   __shared__ double c[512];
@@ -77,10 +79,10 @@ __global__ void __launch_bounds__(256) k_multiaxpy(const double* __restrict__ V,
     double s0 = 0.0, s1 = 0.0;
     int i = 0;
     for (; i + 1 < cnt; i += 2) {
-      s0 += c[i] * V[(size_t)i * N + k];
-      s1 += c[i + 1] * V[(size_t)(i + 1) * N + k];
+      s0 += c[i] * (double)V[(size_t)i * N + k];
+      s1 += c[i + 1] * (double)V[(size_t)(i + 1) * N + k];
     }
-    if (i < cnt) s0 += c[i] * V[(size_t)i * N + k];
+    if (i < cnt) s0 += c[i] * (double)V[(size_t)i * N + k];
     const double wn = w[k] + sign * (s0 + s1);
     w[k] = wn;
     nn += wn * wn;
@@ -98,6 +100,64 @@ __global__ void __launch_bounds__(256) k_multiaxpy(const double* __restrict__ V,
 __global__ void k_scale_const(int64_t N, const double* __restrict__ w, double s, double* __restrict__ v) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < N) v[k] = w[k] * s;
+}
+
+// v = w * s and its FP32 copy vf (the next preconditioner input)
+__global__ void k_scale2(int64_t N, const double* __restrict__ w, double s, double* __restrict__ v,
+                         float* __restrict__ vf) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const double x = w[k] * s;
+  v[k] = x;
+  if (vf) vf[k] = (float)x;
+}
+
+// scale = 1/sqrt(||w||^2 - ||h||^2) from the projections h[0..nv) and
+// h[nv] = ||w||^2 (Pythagoras for the orthogonalised vector); 1 when the
+// difference has cancelled below 1e-6 ||w||^2 (the exact norm then rescales)
+__global__ void k_pyth_scale(const double* __restrict__ h, int nv, double* __restrict__ scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double hh = 0.0;
+  for (int i = 0; i < nv; ++i) hh += h[i] * h[i];
+  const double b2 = h[nv] - hh;
+  scale[0] = (b2 > 1e-6 * h[nv] && b2 > 0.0) ? 1.0 / sqrt(b2) : 1.0;
+}
+
+// v = (w - sum_i coef[i] V_i) * scale[0], optional FP32 copy vf;
+// part[norm_row*kDotBlocks + block] = sum_chunk of (w - V coef)^2 (unscaled)
+__global__ void __launch_bounds__(256) k_orth_normalize(const double* __restrict__ V, int64_t N, int cnt,
+                                                        const double* __restrict__ coef,
+                                                        const double* __restrict__ scale,
+                                                        const double* __restrict__ w, double* __restrict__ v,
+                                                        float* __restrict__ vf, double* __restrict__ part,
+                                                        int norm_row) {
+  __shared__ double c[512];
+  __shared__ double sh[256];
+  for (int i = threadIdx.x; i < cnt; i += 256) c[i] = coef[i];
+  __syncthreads();
+  const double sc = scale[0];
+  double nn = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
+    double s0 = 0.0, s1 = 0.0;
+    int i = 0;
+    for (; i + 1 < cnt; i += 2) {
+      s0 += c[i] * V[(size_t)i * N + k];
+      s1 += c[i + 1] * V[(size_t)(i + 1) * N + k];
+    }
+    if (i < cnt) s0 += c[i] * V[(size_t)i * N + k];
+    const double wn = w[k] - (s0 + s1);
+    nn += wn * wn;
+    const double x = wn * sc;
+    v[k] = x;
+    if (vf) vf[k] = (float)x;
+  }
+  sh[threadIdx.x] = nn;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)norm_row * kDotBlocks + blockIdx.x] = sh[0];
 }
 
 __global__ void k_sub(int64_t N, const double* __restrict__ b, const double* __restrict__ a, double* __restrict__ r) {
@@ -138,12 +198,23 @@ int grid_for(int64_t N) { return (int)std::min<int64_t>(kDotBlocks, (N + 255) / 
 
 }  // namespace
 
-static void ensure_krylov(pm_ctx* c, int m) {
+// basis V (m+1 FP64 vectors) and the preconditioned vectors: FP64 Z, or FP32
+// Zf when they come from the FP32 preconditioner (exactly representable)
+static void ensure_krylov(pm_ctx* c, int m, bool z32) {
+  if (z32 ? (c->mzf_alloc < m || !c->Zf) : (c->mz_alloc < m || !c->Z)) {
+    if (z32) {
+      dfree(c->Zf);
+      c->Zf = dalloc<float>((int64_t)m * c->N);
+      c->mzf_alloc = m;
+    } else {
+      dfree(c->Z);
+      c->Z = dalloc<double>((int64_t)m * c->N);
+      c->mz_alloc = m;
+    }
+  }
   if (c->m_alloc >= m && c->V) return;
   dfree(c->V);
-  dfree(c->Z);
   c->V = dalloc<double>((int64_t)(m + 1) * c->N);
-  c->Z = dalloc<double>((int64_t)m * c->N);
   if (!c->red) c->red = dalloc<double>((int64_t)kDotBlocks * kPartRows);
   dfree(c->hcol);
   c->hcol = dalloc<double>(3 * (m + 2) + 8);
@@ -191,7 +262,7 @@ static void cgs_pass(pm_ctx* c, int nv, double* hpass, bool self_norm) {
   }
   k_dot_final<<<nv + (self_norm ? 1 : 0), 256, 0, c->s>>>(c->red, 0, nv + (self_norm ? 1 : 0), gb, hpass);
   g_prof.begin(c->s, kProfMultiaxpy);
-  k_multiaxpy<<<gb, 256, 0, c->s>>>(c->V, N, nv, hpass, c->wvec, -1.0, c->red, nv + 1);
+  k_multiaxpy<double><<<gb, 256, 0, c->s>>>(c->V, N, nv, hpass, c->wvec, -1.0, c->red, nv + 1);
   g_prof.end(c->s, kProfMultiaxpy, (double)(nv + 2) * N * 8.0);
   PM_CHECK_LAUNCH();
 }
@@ -206,13 +277,21 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
   const int max_it = std::max(1, c->opts.max_it);
   const double rtol = c->opts.rtol;
   if (m > 500) throw Error(PM_EINVAL, "restart length too large (max 500)");
-  ensure_krylov(c, m);
+  // one Gram-Schmidt pass: the norm of the new basis vector comes from the
+  // projections (Pythagoras) so one pass orthogonalises, normalises and
+  // writes the FP32 preconditioner input; the exact norm from the same pass
+  // corrects the scale when they differ
+  const bool fused = c->opts.orth_passes == 1;
+  const bool z32 = fused && c->opts.precond_fp32;
+  ensure_krylov(c, m, z32);
   const int64_t N = c->N;
   hipStream_t s = c->s;
   const int gN = blocks_for(N);
   double* h1 = c->hcol;               // pass-1 coefficients + norm (m+2)
   double* h2 = c->hcol + (m + 2);     // pass-2 coefficients, then y (m+2)
   double* dev_nrm = c->hcol + 2 * (m + 2);
+  double* dev_scale = dev_nrm + 1;
+  float* vf = z32 ? c->pw32 : nullptr;  // FP32 copy of the current basis vector
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
   PM_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, s));
   const double bnorm = std::sqrt(norm_sq(c, b, dev_nrm, true));
@@ -228,26 +307,70 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
   bool converged = false;
   PM_HIP(hipMemcpyAsync(c->rvec, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   while (true) {
-    k_scale_const<<<gN, kBlock, 0, s>>>(N, c->rvec, 1.0 / beta, c->V);
+    k_scale2<<<gN, kBlock, 0, s>>>(N, c->rvec, 1.0 / beta, c->V, vf);
     PM_CHECK_LAUNCH();
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jdone = 0;
     for (int j = 0; j < m && its < max_it; ++j) {
       double* vj = c->V + (size_t)j * N;
-      double* zj = c->Z + (size_t)j * N;
-      apply_Minv(c, vj, zj, transpose);
-      apply_AH(c, zj, c->wvec, transpose);
+      if (z32) {
+        float* zj = c->Zf + (size_t)j * N;
+        apply_Minv32(c, vf, zj, transpose);
+        apply_AH32(c, zj, c->wvec, transpose);
+      } else {
+        double* zj = c->Z + (size_t)j * N;
+        apply_Minv(c, vj, zj, transpose);
+        apply_AH(c, zj, c->wvec, transpose);
+      }
       const int nv = j + 1;
-      // classical Gram-Schmidt, one or two passes; h1[nv+1] = ||w||^2 after them
-      cgs_pass(c, nv, h1, false);
-      if (c->opts.orth_passes > 1) cgs_pass(c, nv, h2, false);
-      k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, grid_for(N), h1);
-      if (c->opts.orth_passes > 1) k_add_vec<<<blocks_for(nv), kBlock, 0, s>>>(nv, h2, h1);
-      PM_CHECK_LAUNCH();
-      PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
-      PM_HIP(hipStreamSynchronize(s));
-      const double hn = std::sqrt(c->hhost[nv + 1]);
+      double hn;
+      if (fused) {
+        // h = V^T w and ||w||^2, then v_{j+1} = (w - V h) / ||w - V h|| in one pass
+        const int gb = grid_for(N);
+        for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
+          const int cnt = std::min(kDotGroup, nv - i0);
+          g_prof.begin(s, kProfMultidot);
+          k_multidot<<<gb, 256, 0, s>>>(c->V, N, i0, cnt, c->wvec, c->red, i0 == 0 ? nv : -1);
+          g_prof.end(s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
+        }
+        k_dot_final<<<nv + 1, 256, 0, s>>>(c->red, 0, nv + 1, gb, h1);
+        k_pyth_scale<<<1, 64, 0, s>>>(h1, nv, dev_scale);
+        g_prof.begin(s, kProfMultiaxpy);
+        k_orth_normalize<<<gb, 256, 0, s>>>(c->V, N, nv, h1, dev_scale, c->wvec, c->V + (size_t)(j + 1) * N, vf,
+                                            c->red, nv + 1);
+        g_prof.end(s, kProfMultiaxpy, (double)(nv + 2) * N * 8.0 + (vf ? (double)N * 4.0 : 0.0));
+        k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, gb, h1);
+        PM_CHECK_LAUNCH();
+        PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipMemcpyAsync(c->hhost + nv + 2, dev_scale, sizeof(double), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipStreamSynchronize(s));
+        hn = std::sqrt(c->hhost[nv + 1]);
+        const double sc = c->hhost[nv + 2];
+        if (hn > 0.0 && std::isfinite(hn)) {
+          const double prod = hn * sc;  // norm of the written vector
+          if (std::fabs(prod - 1.0) > 1e-12) {
+            k_scale2<<<gN, kBlock, 0, s>>>(N, c->V + (size_t)(j + 1) * N, 1.0 / prod, c->V + (size_t)(j + 1) * N, vf);
+            PM_CHECK_LAUNCH();
+          } else {
+            hn = 1.0 / sc;  // keeps A z_j = V h + hn v_{j+1} exact
+          }
+        }
+      } else {
+        // classical Gram-Schmidt, one or two passes; h1[nv+1] = ||w||^2 after them
+        cgs_pass(c, nv, h1, false);
+        if (c->opts.orth_passes > 1) cgs_pass(c, nv, h2, false);
+        k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, grid_for(N), h1);
+        if (c->opts.orth_passes > 1) k_add_vec<<<blocks_for(nv), kBlock, 0, s>>>(nv, h2, h1);
+        PM_CHECK_LAUNCH();
+        PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipStreamSynchronize(s));
+        hn = std::sqrt(c->hhost[nv + 1]);
+        if (hn > 0.0 && std::isfinite(hn)) {
+          k_scale_const<<<gN, kBlock, 0, s>>>(N, c->wvec, 1.0 / hn, c->V + (size_t)(j + 1) * N);
+          PM_CHECK_LAUNCH();
+        }
+      }
       bool bad = !std::isfinite(hn);
       for (int i = 0; i < nv; ++i) {
         H[(size_t)i * m + j] = c->hhost[i];
@@ -255,10 +378,6 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
       }
       if (bad) throw Error(PM_EBREAKDOWN, "fgmres: non-finite value in the Arnoldi process");
       H[(size_t)nv * m + j] = hn;
-      if (hn > 0.0) {
-        k_scale_const<<<gN, kBlock, 0, s>>>(N, c->wvec, 1.0 / hn, c->V + (size_t)(j + 1) * N);
-        PM_CHECK_LAUNCH();
-      }
       for (int i = 0; i < j; ++i) {
         const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
         H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
@@ -287,7 +406,10 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
     }
     if (jdone > 0) {
       PM_HIP(hipMemcpyAsync(h2, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
-      k_multiaxpy<<<grid_for(N), 256, 0, s>>>(c->Z, N, jdone, h2, x, 1.0, c->red, -1);
+      if (z32)
+        k_multiaxpy<float><<<grid_for(N), 256, 0, s>>>(c->Zf, N, jdone, h2, x, 1.0, c->red, -1);
+      else
+        k_multiaxpy<double><<<grid_for(N), 256, 0, s>>>(c->Z, N, jdone, h2, x, 1.0, c->red, -1);
       PM_CHECK_LAUNCH();
     }
     // true residual in FP64; restart from it if needed

@@ -51,8 +51,8 @@ __device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j,
 // Indices are clamped into the mesh: a neighbour outside it only belongs to
 // cells outside the mesh, whose modulus is taken as zero below.  MASK zeroes
 // Dirichlet components (zero columns of A_uu).
-template <class T, bool MASK>
-__device__ __forceinline__ void load_plane(const Grid& G, int kind, const T* __restrict__ x, int i, int j, int nk,
+template <class T, class TX, bool MASK>
+__device__ __forceinline__ void load_plane(const Grid& G, int kind, const TX* __restrict__ x, int i, int j, int nk,
                                            T u[9][3]) {
   const int kc = min(max(nk, 0), G.nz);
 #pragma unroll
@@ -63,7 +63,7 @@ __device__ __forceinline__ void load_plane(const Grid& G, int kind, const T* __r
       const int64_t nb = G.node(min(max(ni, 0), G.nx), min(max(nj, 0), G.ny), kc);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T v = x[3 * nb + c];
+        const T v = (T)x[3 * nb + c];
         u[dx + 3 * dy][c] = (MASK && u_fixed(G, kind, ni, nj, nk, c)) ? (T)0 : v;
       }
     }
@@ -106,16 +106,16 @@ __device__ __forceinline__ void cell_layer(const Grid& G, const T* __restrict__ 
 
 // acc = sum over the cells T around node (i,j,k) of E_T Khat[3a..3a+2, :] u_T,
 // the neighbour planes loaded one at a time
-template <class T, bool MASK>
+template <class T, class TX, bool MASK>
 __device__ __forceinline__ void lattice_rows(const Grid& G, int kind, const T* __restrict__ Kh,
-                                             const T* __restrict__ E, const T* __restrict__ x, int i, int j, int k,
+                                             const T* __restrict__ E, const TX* __restrict__ x, int i, int j, int k,
                                              T acc[3]) {
   acc[0] = acc[1] = acc[2] = (T)0;
   T pa[9][3], pb[9][3];
-  load_plane<T, MASK>(G, kind, x, i, j, k - 1, pa);
-  load_plane<T, MASK>(G, kind, x, i, j, k, pb);
+  load_plane<T, TX, MASK>(G, kind, x, i, j, k - 1, pa);
+  load_plane<T, TX, MASK>(G, kind, x, i, j, k, pb);
   cell_layer<T>(G, Kh, E, pa, pb, 0, i, j, k, acc);
-  load_plane<T, MASK>(G, kind, x, i, j, k + 1, pa);
+  load_plane<T, TX, MASK>(G, kind, x, i, j, k + 1, pa);
   cell_layer<T>(G, Kh, E, pb, pa, 1, i, j, k, acc);
 }
 
@@ -132,9 +132,9 @@ __device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const T* __r
                                            const T* __restrict__ E, const T* __restrict__ x, int64_t n, int i, int j,
                                            int k, T ax[3]) {
   if (free_neighbourhood(G, kind, i, j, k))
-    lattice_rows<T, false>(G, kind, Kh, E, x, i, j, k, ax);
+    lattice_rows<T, T, false>(G, kind, Kh, E, x, i, j, k, ax);
   else
-    lattice_rows<T, true>(G, kind, Kh, E, x, i, j, k, ax);
+    lattice_rows<T, T, true>(G, kind, Kh, E, x, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
     if (u_fixed(G, kind, i, j, k, a)) ax[a] = x[3 * n + a];
@@ -189,19 +189,21 @@ __global__ void __launch_bounds__(256) k_lat_apply(Grid G, int kind, const doubl
   for (int a = 0; a < 3; ++a) y[3 * n + a] = ax[a];
 }
 
-// u-rows of A_H (sgn = +1) or A_H^T (sgn = -1): A_uu u + sgn A_up p on free rows
+// u-rows of A_H (sgn = +1) or A_H^T (sgn = -1): A_uu u + sgn A_up p on free
+// rows, in FP64 from FP64 or FP32 inputs
+template <class TX>
 __global__ void __launch_bounds__(256) k_lat_ah_u(Grid G, int kind, const double* __restrict__ Kh,
                                                   const double* __restrict__ ah, const double* __restrict__ E,
-                                                  const double* __restrict__ u, const double* __restrict__ p,
-                                                  double sgn, double* __restrict__ y) {
+                                                  const TX* __restrict__ u, const TX* __restrict__ p, double sgn,
+                                                  double* __restrict__ y) {
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   double acc[3];
   if (free_neighbourhood(G, kind, i, j, k))
-    lattice_rows<double, false>(G, kind, Kh, E, u, i, j, k, acc);
+    lattice_rows<double, TX, false>(G, kind, Kh, E, u, i, j, k, acc);
   else
-    lattice_rows<double, true>(G, kind, Kh, E, u, i, j, k, acc);
+    lattice_rows<double, TX, true>(G, kind, Kh, E, u, i, j, k, acc);
   double cp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int oz = 0; oz < 2; ++oz)
@@ -211,7 +213,7 @@ __global__ void __launch_bounds__(256) k_lat_ah_u(Grid G, int kind, const double
       for (int ox = 0; ox < 2; ++ox) {
         const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
         if (ci < 0 || ci >= G.nx || cj < 0 || cj >= G.ny || ck < 0 || ck >= G.nz) continue;
-        const double pc = p[G.cell(ci, cj, ck)];
+        const double pc = (double)p[G.cell(ci, cj, ck)];
         const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
 #pragma unroll
         for (int d = 0; d < 3; ++d) cp[d] += ah[3 * a + d] * pc;
@@ -219,7 +221,7 @@ __global__ void __launch_bounds__(256) k_lat_ah_u(Grid G, int kind, const double
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int64_t q = 3 * n + d;
-    y[q] = u_fixed(G, kind, i, j, k, d) ? u[q] : acc[d] + sgn * cp[d];
+    y[q] = u_fixed(G, kind, i, j, k, d) ? (double)u[q] : acc[d] + sgn * cp[d];
   }
 }
 
@@ -296,11 +298,16 @@ void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const doub
   PM_CHECK_LAUNCH();
 }
 
-void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const double* u, const double* p, double sgn,
+template <class TX>
+void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const TX* u, const TX* p, double sgn,
                   double* y) {
-  k_lat_ah_u<<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, op.Kh, op.ah, op.E, u, p, sgn, y);
+  k_lat_ah_u<TX><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, op.Kh, op.ah, op.E, u, p, sgn, y);
   PM_CHECK_LAUNCH();
 }
+template void lattice_ah_u<double>(hipStream_t, const Grid&, const LatticeOp&, const double*, const double*, double,
+                                   double*);
+template void lattice_ah_u<float>(hipStream_t, const Grid&, const LatticeOp&, const float*, const float*, double,
+                                  double*);
 
 void lattice_deviation(hipStream_t s, const Grid& G, const double* coords, double* dev, double* hmin) {
   unsigned long long* out = dalloc<unsigned long long>(1);

@@ -65,7 +65,7 @@ __global__ void k_ah_p(Grid G, AE ae, const double* __restrict__ vol,
                        const double* __restrict__ stabw, const uint8_t* __restrict__ ufix,
                        const uint8_t* __restrict__ pifix, const T* __restrict__ u, const T* __restrict__ p,
                        const T* __restrict__ pi, double S, double dt, int stabilize, double su, double spi,
-                       T* __restrict__ y) {
+                       double* __restrict__ y) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= G.nc) return;
   int i, j, k;
@@ -91,7 +91,7 @@ __global__ void k_ah_p(Grid G, AE ae, const double* __restrict__ vol,
   double t = 0.0;
   for (int e = 0; e < 6; ++e)
     if (!pifix[F[e]]) t -= gv[(size_t)e * G.nc + c] * (double)pi[F[e]];
-  y[c] = (T)(v + spi * t);
+  y[c] = v + spi * t;
 }
 
 // pi-rows: y_pi = sp * sum_T (-g_T[lf]) p_T + sum_T M_T^-1 pi_T (free faces);  fixed: y = pi
@@ -99,11 +99,11 @@ __global__ void k_ah_p(Grid G, AE ae, const double* __restrict__ vol,
 template <class T>
 __global__ void k_ah_pi(Grid G, const double* __restrict__ Minv, const double* __restrict__ gv,
                         const uint8_t* __restrict__ pifix, const T* __restrict__ p, const T* __restrict__ pi,
-                        double sp, T* __restrict__ y) {
+                        double sp, double* __restrict__ y) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= G.nf) return;
   if (pifix[f]) {
-    y[f] = pi[f];
+    y[f] = (double)pi[f];
     return;
   }
   int64_t cc[2];
@@ -121,7 +121,7 @@ __global__ void k_ah_pi(Grid G, const double* __restrict__ Minv, const double* _
     for (int e = 0; e < 6; ++e)
       if (!pifix[F[e]]) v += Minv[(size_t)(lf[s] * 6 + e) * G.nc + c] * (double)pi[F[e]];
   }
-  y[f] = (T)v;
+  y[f] = v;
 }
 
 // preconditioner pieces -------------------------------------------------------
@@ -361,31 +361,32 @@ __global__ void k_rhs_adj_p(Grid G, const double* __restrict__ vol, const double
 }
 
 template <class T>
-void ah_launch(pm_ctx* c, const T* x, T* y, bool transpose, const Sell& Auu, const T* auu_val) {
+void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
   const Grid G = grid_of(c);
   const T* u = x;
   const T* p = x + c->n_u;
   const T* pi = x + c->n_u + c->n_p;
-  T* yu = y;
-  T* yp = y + c->n_u;
-  T* ypi = y + c->n_u + c->n_p;
+  double* yu = y;
+  double* yp = y + c->n_u;
+  double* ypi = y + c->n_u + c->n_p;
   g_prof.begin(c->s, kProfAHu);
-  if constexpr (sizeof(T) == 8) {
-    if (c->lat.on) {
-      lattice_ah_u(c->s, G, c->lat, u, p, transpose ? -1.0 : 1.0, yu);
-      // algorithmic bytes: u read, y_u written, p and E read
-      g_prof.end(c->s, kProfAHu, (double)c->n_u * 2 * sizeof(T) + (double)c->nc * (sizeof(T) + 8));
+  if (c->lat.on) {
+    lattice_ah_u<T>(c->s, G, c->lat, u, p, transpose ? -1.0 : 1.0, yu);
+    // algorithmic bytes: u read, y_u written, p and E read
+    g_prof.end(c->s, kProfAHu, (double)c->n_u * (sizeof(T) + 8) + (double)c->nc * (sizeof(T) + 8));
+  } else {
+    if constexpr (sizeof(T) == 8) {
+      const Sell& Auu = c->Hu.L[0].As;
+      const int nth = Auu.nslices * kSlice;
+      k_ah_u<double><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.col, Auu.val, c->ae, c->ufix, u,
+                                                           p, transpose ? -1.0 : 1.0, yu);
+      // algorithmic bytes: A_uu blocks and column ids, u read, y_u written, coupling
+      // columns a_T, p read, Dirichlet mask
+      g_prof.end(c->s, kProfAHu,
+                 (double)Auu.nnzb * (9 * 8 + 4) + (double)c->n_u * (2 * 8 + 1) + (double)c->nc * (24 * 8 + 8));
+    } else {
+      throw Error(PM_EINTERNAL, "A_H with FP32 input needs the lattice operator");
     }
-  }
-  if (!c->lat.on || sizeof(T) != 8) {
-    const int nth = Auu.nslices * kSlice;
-    k_ah_u<T><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.col, auu_val, c->ae, c->ufix, u, p,
-                                                    transpose ? -1.0 : 1.0, yu);
-    // algorithmic bytes: A_uu blocks and column ids, u read, y_u written, coupling
-    // columns a_T, p read, Dirichlet mask
-    g_prof.end(c->s, kProfAHu,
-               (double)Auu.nnzb * (9 * sizeof(T) + 4) + (double)c->n_u * (2 * sizeof(T) + 1) +
-                   (double)c->nc * (24 * 8 + sizeof(T)));
   }
   const double su = transpose ? 1.0 : -1.0, spi = transpose ? 1.0 : c->dt;
   if (c->lat.on)
@@ -403,9 +404,16 @@ void ah_launch(pm_ctx* c, const T* x, T* y, bool transpose, const Sell& Auu, con
 
 }  // namespace
 
-void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose) {
-  const Sell& A = c->Hu.L[0].As;
-  ah_launch<double>(c, x, y, transpose, A, A.val);
+void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose) { ah_launch<double>(c, x, y, transpose); }
+
+void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose) {
+  if (c->lat.on) {
+    ah_launch<float>(c, x, y, transpose);
+    return;
+  }
+  k_f2d<<<blocks_for(c->N), kBlock, 0, c->s>>>(c->N, x, c->pw64);
+  PM_CHECK_LAUNCH();
+  ah_launch<double>(c, c->pw64, y, transpose);
 }
 
 template <class T>
@@ -459,6 +467,11 @@ void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose) {
   prec_apply_t<float>(c, rf, zf, tf, transpose);
   k_f2d<<<blocks_for(N), kBlock, 0, c->s>>>(N, zf, z);
   PM_CHECK_LAUNCH();
+}
+
+void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose) {
+  if (!c->opts.precond_fp32) throw Error(PM_EINTERNAL, "FP32 preconditioner requested without FP32 hierarchies");
+  prec_apply_t<float>(c, r, z, c->pw32 + 2 * c->N, transpose);
 }
 
 void reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w) {

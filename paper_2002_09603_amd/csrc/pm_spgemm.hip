@@ -61,8 +61,10 @@ __device__ inline int hslot(int key) {
 }
 
 // Symbolic phase for one class.  G lanes per row, GPB groups per block,
-// hash of H slots, at most KM distinct keys per row.
-template <int G, int GPB, int H, int KM>
+// hash of H slots, at most KM distinct keys per row.  A row with more keys
+// sets cnt[row] = -1 (MARK: to be retried with a larger hash) or the status
+// flag.
+template <int G, int GPB, int H, int KM, bool MARK = false>
 __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict__ list, const int* __restrict__ arp,
                                                  const int* __restrict__ acol, const int* __restrict__ brp,
                                                  const int* __restrict__ bcol, const int64_t* __restrict__ ubofs,
@@ -107,7 +109,12 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
   if (!valid) return;
   const int u = nk[grp];
   if (u > KM) {
-    if (lane == 0) atomicOr(status, kStatusCapacity);
+    if (lane == 0) {
+      if (MARK)
+        cnt[row] = -1;
+      else
+        atomicOr(status, kStatusCapacity);
+    }
     return;
   }
   int* dst = tmp + ubofs[row];
@@ -118,6 +125,15 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
     dst[rank] = key;
   }
   if (lane == 0) cnt[row] = u;
+}
+
+// rows of a list whose symbolic pass overflowed (cnt = -1)
+__global__ void k_retry_list(int nlist, const int* __restrict__ list, const int* __restrict__ cnt,
+                             int* __restrict__ counter, int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlist) return;
+  const int row = list[i];
+  if (cnt[row] < 0) out[atomicAdd(counter, 1)] = row;
 }
 
 // copy the sorted keys of each row from the scratch (ub offsets) into C
@@ -269,9 +285,27 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
   if (h[1] > 0)
     k_sym<64, 4, 1024, 512><<<(h[1] + 3) / 4, 256, 0, s>>>(h[1], lists + (size_t)n, A.rowptr, A.col, B.rowptr,
                                                            B.col, ubofs, tmp, cnt, status);
-  if (h[2] > 0)
-    k_sym<64, 1, 8192, 6144><<<h[2], 64, 0, s>>>(h[2], lists + 2 * (size_t)n, A.rowptr, A.col, B.rowptr, B.col,
-                                                 ubofs, tmp, cnt, status);
+  if (h[2] > 0) {
+    // rows with a large bound: most have few distinct columns (Galerkin rows
+    // of coarse operators); try the 1024-slot hash, retry the rest with 8192
+    int* rl = lists + 2 * (size_t)n;
+    k_sym<64, 4, 1024, 512, true><<<(h[2] + 3) / 4, 256, 0, s>>>(h[2], rl, A.rowptr, A.col, B.rowptr, B.col, ubofs,
+                                                                 tmp, cnt, status);
+    int* rc = dalloc<int>(1);
+    int* retry = dalloc<int>(h[2]);
+    PM_HIP(hipMemsetAsync(rc, 0, sizeof(int), s));
+    k_retry_list<<<blocks_for(h[2]), kBlock, 0, s>>>(h[2], rl, cnt, rc, retry);
+    PM_CHECK_LAUNCH();
+    int nr = 0;
+    PM_HIP(hipMemcpyAsync(&nr, rc, sizeof(int), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (nr > 0)
+      k_sym<64, 1, 8192, 6144><<<nr, 64, 0, s>>>(nr, retry, A.rowptr, A.col, B.rowptr, B.col, ubofs, tmp, cnt,
+                                                 status);
+    PM_CHECK_LAUNCH();
+    dfree(rc);
+    dfree(retry);
+  }
   PM_CHECK_LAUNCH();
   int st = 0;
   PM_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));

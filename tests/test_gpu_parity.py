@@ -81,20 +81,24 @@ def test_operator_and_block_parity(name, lattice):
     s.close()
 
 
-SOLVE_CASES = [(n, fp32, True) for n in ("unit8", "box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop")
-               for fp32 in (False, True)] + [("box10x6x4", fp32, False) for fp32 in (False, True)]
+# (case, FP32 preconditioner, lattice operator, Gram-Schmidt passes); one pass
+# takes the fused orthogonalise-and-normalise path (FP32 preconditioned
+# vectors with the FP32 preconditioner)
+SOLVE_CASES = ([(n, fp32, True, 2) for n in ("unit8", "box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop")
+                for fp32 in (False, True)] + [("box10x6x4", fp32, False, 2) for fp32 in (False, True)]
+               + [(n, fp32, True, 1) for n in ("box10x6x4", "perturbed6x8x6") for fp32 in (False, True)])
 
 
-@pytest.mark.parametrize("name,fp32,lattice", SOLVE_CASES,
-                         ids=[f"{n}-fp32={f}-lattice={l}" for n, f, l in SOLVE_CASES])
-def test_solve_parity(name, fp32, lattice):
+@pytest.mark.parametrize("name,fp32,lattice,orth", SOLVE_CASES,
+                         ids=[f"{n}-fp32={f}-lattice={l}-cgs{o}" for n, f, l, o in SOLVE_CASES])
+def test_solve_parity(name, fp32, lattice, orth):
     prob = make_config("unit8") if name == "unit8" else _case(name)
-    print(f"[solve parity] {name} fp32={fp32} lattice={lattice}", flush=True)
+    print(f"[solve parity] {name} fp32={fp32} lattice={lattice} orth={orth}", flush=True)
     A, b, B = build_system(prob)
     x = direct_solve(A, b)
     u0, p0, pi0 = split(B, x)
     s = from_problem(prob, Options(rtol=1e-13, precond_fp32=fp32, restart=100, max_it=600,
-                                   lattice_uu=lattice)).assemble()
+                                   lattice_uu=lattice, orth_passes=orth)).assemble()
     u, pi, p, info = s.solve(s.build_rhs())
     print("   info", info, flush=True)
     assert info["converged"] and info["relres_true"] <= 1e-13
