@@ -168,14 +168,19 @@ __global__ void k_mis_update(int n, const uint64_t* __restrict__ T0, const uint6
                              uint8_t* __restrict__ state, int* __restrict__ und) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (state[i] != kUnd) return;
-  if (T2[i] == T0[i]) {
-    state[i] = kIn;
-  } else if ((T2[i] >> 62) == 2) {
-    state[i] = kOut;
-  } else {
-    atomicAdd(und, 1);
+  bool left = false;
+  if (state[i] == kUnd) {
+    if (T2[i] == T0[i]) {
+      state[i] = kIn;
+    } else if ((T2[i] >> 62) == 2) {
+      state[i] = kOut;
+    } else {
+      left = true;
+    }
   }
+  // one flag store per wavefront with undecided rows
+  const unsigned long long m = __ballot(left);
+  if (m != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1)) *und = 1;
 }
 
 __global__ void k_root_flags(int n, const uint8_t* __restrict__ state, int* __restrict__ f) {
@@ -405,11 +410,14 @@ __global__ void k_rand_vec(int64_t n, double* __restrict__ x, uint32_t salt) {
   if (i < n) x[i] = (double)(mix32((uint32_t)i ^ salt) & 0xFFFFFF) / 16777216.0 + 0.5;
 }
 
+// out = D^-1 y / sqrt(nsq[0]) (nsq: squared norm of the previous iterate, on the device)
 template <int BS>
 __global__ void k_dinv_apply_scaled(int n, const double* __restrict__ dinv, const double* __restrict__ y,
-                                    double scale, double* __restrict__ out) {
+                                    const double* __restrict__ nsq, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const double q = nsq[0];
+  const double scale = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
   const double* D = dinv + (size_t)i * BS * BS;
   for (int a = 0; a < BS; ++a) {
     double s = 0.0;
@@ -705,26 +713,29 @@ double power_lmax(hipStream_t s, int64_t nb, int bs, const double* dinv, int its
   double* v = dalloc<double>(n);
   double* w = dalloc<double>(n);
   double* part = dalloc<double>(kRedBlocks);
-  double* out = dalloc<double>(1);
+  double* nsq = dalloc<double>(1);
   k_rand_vec<<<blocks_for(n), kBlock, 0, s>>>(n, v, 0x9e3779b9u);
-  double nv = std::sqrt(sum_squares(s, v, n, part, out));
-  double lam = 0.0;
+  // ||v|| stays on the device: lambda ~ ||D^-1 A v|| / ||v|| with v normalised
+  k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(v, n, part);
+  k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, nsq);
   for (int k = 0; k < its; ++k) {
     spmv(v, w);
     if (bs == 3)
-      k_dinv_apply_scaled<3><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, 1.0 / nv, v);
+      k_dinv_apply_scaled<3><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, nsq, v);
     else
-      k_dinv_apply_scaled<1><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, 1.0 / nv, v);
-    const double nn = std::sqrt(sum_squares(s, v, n, part, out));
-    lam = nn;  // ||D^-1 A v|| / ||v|| with ||v|| normalised
-    nv = nn;
-    if (!(nn > 0.0)) break;
+      k_dinv_apply_scaled<1><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, nsq, v);
+    k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(v, n, part);
+    k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, nsq);
   }
+  PM_CHECK_LAUNCH();
+  double h = 0.0;
+  PM_HIP(hipMemcpyAsync(&h, nsq, sizeof(double), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
   dfree(v);
   dfree(w);
   dfree(part);
-  dfree(out);
-  return lam;
+  dfree(nsq);
+  return std::sqrt(h);
 }
 
 double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) {
@@ -929,6 +940,8 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
   T* cur = x;
   T* nxt = t;
   int k0 = 0;
+  // from zero the result lands in x after cheb_degree kernels: start in t when even
+  if (zero_init && prm.cheb_degree % 2 == 0) std::swap(cur, nxt);
   if (zero_init) {
     k_cheb_first<BS, T><<<blocks_for(n), kBlock, 0, s>>>(n, dinv, b, (T)(1.0 / theta), cur, d);
     k0 = 1;

@@ -233,8 +233,10 @@ __global__ void k_auu_count(Grid G, int* __restrict__ cnt) {
   cnt[n] = cx * cy * cz;
 }
 
-// A_uu row gather: block (n,m) = sum over the cells containing both nodes of
-// K_T[a(n), b(m)], then the Dirichlet identity rows/columns.
+// A_uu row gather, one thread per (node n, neighbour offset): block (n, m) =
+// sum over the cells containing both nodes of K_T[a(n), b(m)], then the
+// Dirichlet identity rows / zero columns.  Blocks are placed in the row in
+// (dk, dj, di) order, so consecutive threads write consecutive blocks.
 // element stiffness sources: per-cell array, or E_T times the lattice matrix
 struct KeCells {
   const double* Ke;
@@ -251,49 +253,42 @@ template <class KS>
 __global__ void __launch_bounds__(256) k_auu_fill(Grid G, KS Ke, const uint8_t* __restrict__ ufix,
                                                   const int* __restrict__ rowptr, int* __restrict__ col,
                                                   double* __restrict__ val, double* __restrict__ diag) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= G.nn) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 27 * G.nn) return;
+  const int64_t n = t / 27;
+  const int q = (int)(t - n * 27);
+  const int di = q % 3 - 1, dj = (q / 3) % 3 - 1, dk = q / 9 - 1;
   int i, j, k;
   G.node_ijk(n, i, j, k);
-  int64_t pos = rowptr[n];
-  bool fr[3];
-  for (int r = 0; r < 3; ++r) fr[r] = ufix[3 * n + r];
-  for (int dk = -1; dk <= 1; ++dk) {
-    const int k2 = k + dk;
-    if (k2 < 0 || k2 > G.nz) continue;
-    for (int dj = -1; dj <= 1; ++dj) {
-      const int j2 = j + dj;
-      if (j2 < 0 || j2 > G.ny) continue;
-      for (int di = -1; di <= 1; ++di) {
-        const int i2 = i + di;
-        if (i2 < 0 || i2 > G.nx) continue;
-        const int64_t m = G.node(i2, j2, k2);
-        double B[9];
-        for (int e = 0; e < 9; ++e) B[e] = 0.0;
-        // cells containing both nodes: ci in {i-1,i} and {i2-1,i2}, inside the grid
-        for (int ck = max(max(k, k2) - 1, 0); ck <= min(min(k, k2), G.nz - 1); ++ck)
-          for (int cj = max(max(j, j2) - 1, 0); cj <= min(min(j, j2), G.ny - 1); ++cj)
-            for (int ci = max(max(i, i2) - 1, 0); ci <= min(min(i, i2), G.nx - 1); ++ci) {
-              const int64_t c = G.cell(ci, cj, ck);
-              const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
-              const int b = (i2 - ci) + 2 * (j2 - cj) + 4 * (k2 - ck);
-              for (int r = 0; r < 3; ++r)
-                for (int s = 0; s < 3; ++s)
-                  B[r * 3 + s] += Ke(3 * a + r, 3 * b + s, c);
-            }
+  const int i2 = i + di, j2 = j + dj, k2 = k + dk;
+  if (i2 < 0 || i2 > G.nx || j2 < 0 || j2 > G.ny || k2 < 0 || k2 > G.nz) return;
+  const int xlo = i > 0 ? -1 : 0, ylo = j > 0 ? -1 : 0, zlo = k > 0 ? -1 : 0;
+  const int nxc = (i < G.nx ? 1 : 0) - xlo + 1, nyc = (j < G.ny ? 1 : 0) - ylo + 1;
+  const int64_t pos = rowptr[n] + ((dk - zlo) * nyc + (dj - ylo)) * nxc + (di - xlo);
+  const int64_t m = G.node(i2, j2, k2);
+  double B[9];
+  for (int e = 0; e < 9; ++e) B[e] = 0.0;
+  // cells containing both nodes: ci in {i-1,i} and {i2-1,i2}, inside the grid
+  for (int ck = max(max(k, k2) - 1, 0); ck <= min(min(k, k2), G.nz - 1); ++ck)
+    for (int cj = max(max(j, j2) - 1, 0); cj <= min(min(j, j2), G.ny - 1); ++cj)
+      for (int ci = max(max(i, i2) - 1, 0); ci <= min(min(i, i2), G.nx - 1); ++ci) {
+        const int64_t c = G.cell(ci, cj, ck);
+        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
+        const int b = (i2 - ci) + 2 * (j2 - cj) + 4 * (k2 - ck);
         for (int r = 0; r < 3; ++r)
-          for (int s = 0; s < 3; ++s) {
-            const bool fixed = fr[r] || ufix[3 * m + s];
-            double v = fixed ? 0.0 : B[r * 3 + s];
-            if (m == n && r == s && fr[r]) v = 1.0;
-            val[(size_t)pos * 9 + r * 3 + s] = v;
-            if (m == n && r == s) diag[3 * n + r] = v;
-          }
-        col[pos] = (int)m;
-        ++pos;
+          for (int s = 0; s < 3; ++s) B[r * 3 + s] += Ke(3 * a + r, 3 * b + s, c);
       }
+  for (int r = 0; r < 3; ++r) {
+    const bool fr = ufix[3 * n + r];
+    for (int s = 0; s < 3; ++s) {
+      const bool fixed = fr || ufix[3 * m + s];
+      double v = fixed ? 0.0 : B[r * 3 + s];
+      if (m == n && r == s && fr) v = 1.0;
+      val[(size_t)pos * 9 + r * 3 + s] = v;
+      if (m == n && r == s) diag[3 * n + r] = v;
     }
   }
+  col[pos] = (int)m;
 }
 
 // B~_p = S|T| + dt alpha_T + (A_stab)_TT + sum_{free i} (A_up)_{iT}^2 / (A_uu)_ii
@@ -592,10 +587,10 @@ void assemble_all(pm_ctx* c) {
     c->Auu.val = dalloc<double>((int64_t)total * 9);
   }
   if (c->lattice)
-    k_auu_fill<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->Auu.rowptr,
+    k_auu_fill<<<blocks_for(27 * G.nn), kBlock, 0, s>>>(G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->Auu.rowptr,
                                                    c->Auu.col, c->Auu.val, c->auu_diag);
   else
-    k_auu_fill<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->Auu.rowptr, c->Auu.col,
+    k_auu_fill<<<blocks_for(27 * G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->Auu.rowptr, c->Auu.col,
                                                    c->Auu.val, c->auu_diag);
   PM_CHECK_LAUNCH();
   if (c->lattice) lattice_finish(c);

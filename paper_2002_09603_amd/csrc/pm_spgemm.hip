@@ -31,27 +31,38 @@ __global__ void k_ub(int n, const int* __restrict__ arp, const int* __restrict__
   ub[i] = s;
 }
 
-// Row lists per class: class 0 if v <= t0, 1 if v <= t1, else 2.  One atomic
-// per wavefront and class (ballot + prefix popcount); the order of rows within
-// a list does not affect any result.
+// Row lists per class: class 0 if v <= t0, 1 if v <= t1, else 2.  Counts are
+// aggregated per workgroup (ballots, LDS), one atomic per class and
+// workgroup; the order of rows within a list does not affect any result.
 __global__ void __launch_bounds__(256) k_classify(int n, const int* __restrict__ v, int t0, int t1,
                                                   int* __restrict__ counters, int* __restrict__ lists) {
+  __shared__ int wcnt[3][4];
+  __shared__ int base[3];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int c = 3;  // out of range
   if (i < n) {
     const int u = v[i];
     c = u <= t0 ? 0 : (u <= t1 ? 1 : 2);
   }
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long m[3];
   for (int k = 0; k < 3; ++k) {
-    const unsigned long long m = __ballot(c == k);
-    if (m == 0ull) continue;
-    int base = 0;
-    const int leader = __ffsll((long long)m) - 1;
-    if (lane == leader) base = atomicAdd(&counters[k], __popcll(m));
-    base = __shfl(base, leader, 64);
-    if (c == k) lists[(size_t)k * n + base + __popcll(m & below)] = i;
+    m[k] = __ballot(c == k);
+    if (lane == 0) wcnt[k][wave] = __popcll(m[k]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    int tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wcnt[k][w];
+    base[k] = tot ? atomicAdd(&counters[k], tot) : 0;
+  }
+  __syncthreads();
+  if (c < 3) {
+    int off = base[c];
+    for (int w = 0; w < wave; ++w) off += wcnt[c][w];
+    lists[(size_t)c * n + off + __popcll(m[c] & below)] = i;
   }
 }
 
