@@ -221,11 +221,12 @@ int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
  * synchronizes the recorded events and returns, for kernel id, the number of
  * launches, their summed duration (ms) and summed algorithmic bytes; it does
  * not stop the recording (call pm_profile_begin(ctx, 0) for that).  Ids:
- *   1 u-rows of A_H (assembled A_uu, FP64, fused coupling gather)
+ *   1 u-rows of A_H (FP64; lattice operator or assembled A_uu, with the coupling)
  *   2 fused Chebyshev smoothing step on the finest A_uu level
  *   3 fused Chebyshev smoothing step on the finest C~_pi level
  *   4 FGMRES multi-dot (Gram-Schmidt projections)
- *   5 FGMRES multi-AXPY
+ *   5 FGMRES Gram-Schmidt update of the new basis vector (orthogonalise and
+ *     normalise in one pass, or the multi-AXPY of the two-pass variant)
  *   6 restriction from the finest A_uu level
  * The recorder is process-wide (one context at a time). */
 enum { PM_PROF_AH_U = 1, PM_PROF_CHEB_U0 = 2, PM_PROF_CHEB_PI0 = 3, PM_PROF_MULTIDOT = 4,

@@ -594,6 +594,7 @@ void assemble_all(pm_ctx* c) {
                                                    c->Auu.val, c->auu_diag);
   PM_CHECK_LAUNCH();
   if (c->lattice) lattice_finish(c);
+  pack_minv(c);
   build_cpi(c);
 }
 

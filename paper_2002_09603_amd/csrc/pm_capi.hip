@@ -42,7 +42,7 @@ int guarded(pm_ctx* c, F&& f) {
 void free_ctx_buffers(pm_ctx* c) {
   using pm::dfree;
   for (void* p : {(void*)c->coords, (void*)c->E, (void*)c->kappa, (void*)c->Ke, (void*)c->ae, (void*)c->vol,
-                  (void*)c->Minv, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
+                  (void*)c->Minv, (void*)c->Mp, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
                   (void*)c->ufix, (void*)c->pifix, (void*)c->status, (void*)c->V, (void*)c->Z, (void*)c->Zf, (void*)c->wvec,
                   (void*)c->rvec, (void*)c->xvec, (void*)c->red, (void*)c->hcol, (void*)c->pw64, (void*)c->pw32})
     dfree(p);

@@ -22,9 +22,6 @@ void CellPiOp::free_all() {
 
 namespace {
 
-// packed index of (a, b), a <= b, row-major upper triangle of a 6x6 matrix
-__host__ __device__ inline int pk6(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
-
 __global__ void k_cpi_cells(Grid G, const double* __restrict__ Minv, const double* __restrict__ gv,
                             const double* __restrict__ bp, double dt, double* __restrict__ C,
                             float* __restrict__ C32) {
@@ -36,7 +33,7 @@ __global__ void k_cpi_cells(Grid G, const double* __restrict__ Minv, const doubl
   for (int a = 0; a < 6; ++a)
     for (int b = a; b < 6; ++b) {
       const double v = Minv[(size_t)(a * 6 + b) * G.nc + c] - sc * g[a] * g[b];
-      const size_t q = (size_t)pk6(a, b) * G.nc + c;
+      const size_t q = (size_t)sym6(a, b) * G.nc + c;
       C[q] = v;
       if (C32) C32[q] = (float)v;
     }
@@ -68,7 +65,7 @@ __device__ __forceinline__ T cpi_cells_row(const Grid& G, int64_t f, const T* __
     for (int e = 0; e < 6; ++e) {
       if (pi_fixed_local(G, k, e)) continue;
       const int a = l < e ? l : e, b = l < e ? e : l;
-      acc += C[(size_t)pk6(a, b) * G.nc + c] * x[F[e]];
+      acc += C[(size_t)sym6(a, b) * G.nc + c] * x[F[e]];
     }
   }
   return acc;

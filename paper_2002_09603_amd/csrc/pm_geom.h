@@ -106,6 +106,10 @@ __host__ __device__ inline bool pi_fixed(const Grid& G, int64_t f) {
 // the same for local face e of cell (., ., k): only the +z face of a top cell
 __host__ __device__ inline bool pi_fixed_local(const Grid& G, int k, int e) { return e == 5 && k == G.nz - 1; }
 
+// packed index of (a, b), a <= b, in the row-major upper triangle of a
+// symmetric 6x6 matrix (21 entries)
+__host__ __device__ inline int sym6(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
+
 // Workgroups are dispatched to the 8 XCDs round-robin; this maps workgroup b
 // of nb so that each XCD runs one contiguous range of logical workgroups
 // (neighbour rows and planes gathered by a workgroup then sit in the L2 of

@@ -42,11 +42,11 @@ inline int blocks_for(int64_t n, int bs = kBlock) { return (int)((n + bs - 1) / 
 // kernel profiler: HIP events around the launches of selected kernels on
 // their own stream, with the algorithmic bytes each launch must move
 enum ProfKernel : int {
-  kProfAHu = 1,          // u-rows of A_H (assembled A_uu SELL, FP64, fused coupling)
+  kProfAHu = 1,          // u-rows of A_H (FP64, lattice or assembled A_uu, fused coupling)
   kProfChebU0 = 2,       // fused Chebyshev step on the finest A_uu level
   kProfChebPi0 = 3,      // fused Chebyshev step on the finest C~_pi level
   kProfMultidot = 4,     // FGMRES multi-dot (Gram-Schmidt projections)
-  kProfMultiaxpy = 5,    // FGMRES multi-AXPY
+  kProfMultiaxpy = 5,    // FGMRES Gram-Schmidt update (orthogonalise + normalise, or multi-AXPY)
   kProfRestrictU0 = 6,   // restriction from the finest A_uu level
   kProfCount = 7
 };
@@ -228,6 +228,7 @@ struct pm_ctx {
   double* ae = nullptr;      // 24*nc coupling column of A_up
   double* vol = nullptr;     // nc
   double* Minv = nullptr;    // 36*nc inverse RT0 mass
+  double* Mp = nullptr;      // 21*nc packed upper triangle of M^-1 (operator pi-rows)
   double* g = nullptr;       // 6*nc  M^-1 1
   double* alpha = nullptr;   // nc    1^T M^-1 1
   double* stabw = nullptr;   // nmacro: beta_M |M|
@@ -281,6 +282,7 @@ void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose);    // FP3
 void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose);
 void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose);   // FP32 hierarchies only
 void apply_csr(pm_ctx* c, const Csr& A, const double* x, double* y);
+void pack_minv(pm_ctx* c);             // c->Mp from c->Minv
 void reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w);
 void grad(pm_ctx* c, const double* lam, const double* x, const double* p_prev, double* dk,
           double* dE);

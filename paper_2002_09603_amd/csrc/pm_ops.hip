@@ -96,13 +96,14 @@ __global__ void k_ah_p(Grid G, AE ae, const double* __restrict__ vol,
 
 // pi-rows: y_pi = sp * sum_T (-g_T[lf]) p_T + sum_T M_T^-1 pi_T (free faces);  fixed: y = pi
 //   A_H: sp = 1    A_H^T: sp = dt
+// M_T^-1 is read from its packed upper triangle (21 values per cell).
 template <class T>
-__global__ void k_ah_pi(Grid G, const double* __restrict__ Minv, const double* __restrict__ gv,
-                        const uint8_t* __restrict__ pifix, const T* __restrict__ p, const T* __restrict__ pi,
-                        double sp, double* __restrict__ y) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_ah_pi(Grid G, const double* __restrict__ Mp,
+                                               const double* __restrict__ gv, const T* __restrict__ p,
+                                               const T* __restrict__ pi, double sp, double* __restrict__ y) {
+  const int64_t f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (f >= G.nf) return;
-  if (pifix[f]) {
+  if (pi_fixed(G, f)) {
     y[f] = (double)pi[f];
     return;
   }
@@ -117,11 +118,26 @@ __global__ void k_ah_pi(Grid G, const double* __restrict__ Minv, const double* _
     G.cell_ijk(c, i, j, k);
     int64_t F[6];
     G.cell_faces(i, j, k, F);
-    v -= sp * gv[(size_t)lf[s] * G.nc + c] * (double)p[c];
-    for (int e = 0; e < 6; ++e)
-      if (!pifix[F[e]]) v += Minv[(size_t)(lf[s] * 6 + e) * G.nc + c] * (double)pi[F[e]];
+    const int l = lf[s];
+    v -= sp * gv[(size_t)l * G.nc + c] * (double)p[c];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      if (pi_fixed_local(G, k, e)) continue;
+      const int a = l < e ? l : e, b = l < e ? e : l;
+      v += Mp[(size_t)sym6(a, b) * G.nc + c] * (double)pi[F[e]];
+    }
   }
   y[f] = v;
+}
+
+// packed upper triangle of the symmetrised M_T^-1
+__global__ void k_pack_minv(Grid G, const double* __restrict__ Minv, double* __restrict__ Mp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b)
+      Mp[(size_t)sym6(a, b) * G.nc + c] =
+          0.5 * (Minv[(size_t)(a * 6 + b) * G.nc + c] + Minv[(size_t)(b * 6 + a) * G.nc + c]);
 }
 
 // preconditioner pieces -------------------------------------------------------
@@ -397,8 +413,7 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
     k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, AeCells{c->ae, G.nc}, c->vol, c->alpha, c->g, c->stabw,
                                                      c->ufix, c->pifix, u, p, pi, c->S, c->dt, c->opts.stabilize,
                                                      su, spi, yp);
-  k_ah_pi<T><<<blocks_for(G.nf), kBlock, 0, c->s>>>(G, c->Minv, c->g, c->pifix, p, pi,
-                                                    transpose ? c->dt : 1.0, ypi);
+  k_ah_pi<T><<<blocks_for(G.nf), kBlock, 0, c->s>>>(G, c->Mp, c->g, p, pi, transpose ? c->dt : 1.0, ypi);
   PM_CHECK_LAUNCH();
 }
 
@@ -472,6 +487,13 @@ void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose) {
 void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose) {
   if (!c->opts.precond_fp32) throw Error(PM_EINTERNAL, "FP32 preconditioner requested without FP32 hierarchies");
   prec_apply_t<float>(c, r, z, c->pw32 + 2 * c->N, transpose);
+}
+
+void pack_minv(pm_ctx* c) {
+  const Grid G = grid_of(c);
+  if (!c->Mp) c->Mp = dalloc<double>(21 * G.nc);
+  k_pack_minv<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Minv, c->Mp);
+  PM_CHECK_LAUNCH();
 }
 
 void reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w) {
