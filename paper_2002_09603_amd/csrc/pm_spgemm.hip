@@ -210,11 +210,128 @@ __global__ void __launch_bounds__(G* GPB) k_num(int nlist, const int* __restrict
     for (int i = lane; i < u * BS * BS; i += G) cval[(size_t)c0 * BS * BS + i] = acc[i];
 }
 
+// Numeric phase for rows with at most 64 distinct columns, 16 lanes per row,
+// 4 rows per wavefront.  Same order of summation as k_num (entries of A in
+// order, lanes over the B row), with the latency of the dependent loads
+// hidden: a prologue stages the B-row extents of every entry of the A row in
+// LDS, and the B-row entries and A block of the next entry are loaded while
+// the current one is accumulated.
+template <int BS>
+__global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restrict__ list,
+                                                  const int* __restrict__ arp, const int* __restrict__ acol,
+                                                  const double* __restrict__ aval, const int* __restrict__ brp,
+                                                  const int* __restrict__ bcol, const double* __restrict__ bval,
+                                                  const int* __restrict__ crp, const int* __restrict__ ccol,
+                                                  double* __restrict__ cval) {
+  constexpr int G = 16, GPB = 4, CAP = 64, AMAX = 64, B2 = BS * BS;
+  __shared__ int cols_l[GPB][CAP];
+  __shared__ double acc_l[GPB][CAP * B2];
+  __shared__ int fb_l[GPB][AMAX];
+  __shared__ int fe_l[GPB][AMAX];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  const int li = blockIdx.x * GPB + grp;
+  if (li >= nlist) return;  // groups never synchronize across rows: per-wave ordering only
+  const int row = list[li];
+  const int c0 = crp[row], u = crp[row + 1] - c0;
+  const int e0 = arp[row], na = arp[row + 1] - e0;
+  int* cols = cols_l[grp];
+  double* acc = acc_l[grp];
+  for (int i = lane; i < u; i += G) cols[i] = ccol[c0 + i];
+  for (int i = lane; i < u * B2; i += G) acc[i] = 0.0;
+  const bool staged = na <= AMAX;
+  if (staged)
+    for (int q = lane; q < na; q += G) {
+      const int k = acol[e0 + q];
+      fb_l[grp][q] = brp[k];
+      fe_l[grp][q] = brp[k + 1];
+    }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  auto extent = [&](int e, int& fb, int& fe) {
+    if (staged) {
+      fb = fb_l[grp][e];
+      fe = fe_l[grp][e];
+    } else {
+      const int k = acol[e0 + e];
+      fb = brp[k];
+      fe = brp[k + 1];
+    }
+  };
+  auto slot_of = [&](int key) {
+    int lo = 0, hi = u - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cols[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  // current step's operands
+  int fb = 0, fe = 0;
+  if (na > 0) extent(0, fb, fe);
+  bool v = fb + lane < fe;
+  int key = v ? bcol[fb + lane] : 0;
+  double a[B2], b[B2];
+  for (int q = 0; q < B2; ++q) {
+    a[q] = na > 0 ? aval[(size_t)e0 * B2 + q] : 0.0;
+    b[q] = v ? bval[(size_t)(fb + lane) * B2 + q] : 0.0;
+  }
+  for (int e = 0; e < na; ++e) {
+    // operands of the next entry, loaded before the current one is used
+    int fbn = 0, fen = 0;
+    bool vn = false;
+    int keyn = 0;
+    double an[B2], bn[B2];
+    if (e + 1 < na) {
+      extent(e + 1, fbn, fen);
+      vn = fbn + lane < fen;
+      keyn = vn ? bcol[fbn + lane] : 0;
+      for (int q = 0; q < B2; ++q) {
+        an[q] = aval[(size_t)(e0 + e + 1) * B2 + q];
+        bn[q] = vn ? bval[(size_t)(fbn + lane) * B2 + q] : 0.0;
+      }
+    }
+    if (v) {
+      double* dst = acc + (size_t)slot_of(key) * B2;
+      for (int i = 0; i < BS; ++i)
+        for (int j = 0; j < BS; ++j) {
+          double sacc = dst[i * BS + j];
+          for (int t = 0; t < BS; ++t) sacc += a[i * BS + t] * b[t * BS + j];
+          dst[i * BS + j] = sacc;
+        }
+    }
+    // B rows longer than the group (rare): remaining entries, in order
+    for (int f = fb + lane + G; f < fe; f += G) {
+      double* dst = acc + (size_t)slot_of(bcol[f]) * B2;
+      const double* bb = bval + (size_t)f * B2;
+      for (int i = 0; i < BS; ++i)
+        for (int j = 0; j < BS; ++j) {
+          double sacc = dst[i * BS + j];
+          for (int t = 0; t < BS; ++t) sacc += a[i * BS + t] * bb[t * BS + j];
+          dst[i * BS + j] = sacc;
+        }
+    }
+    // the next entry of A may update the same slots from other lanes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (e + 1 < na) {
+      fb = fbn;
+      fe = fen;
+      v = vn;
+      key = keyn;
+      for (int q = 0; q < B2; ++q) {
+        a[q] = an[q];
+        b[q] = bn[q];
+      }
+    }
+  }
+  for (int i = lane; i < u * B2; i += G) cval[(size_t)c0 * B2 + i] = acc[i];
+}
+
 template <int BS>
 void numeric_launch(hipStream_t s, const int* counts, const int* lists, int n, const Csr& A, const Csr& B, Csr& C) {
   if (counts[0] > 0)
-    k_num<BS, 16, 4, 64><<<(counts[0] + 3) / 4, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr,
-                                                            B.col, B.val, C.rowptr, C.col, C.val);
+    k_num_small<BS><<<(counts[0] + 3) / 4, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr, B.col,
+                                                       B.val, C.rowptr, C.col, C.val);
   if (counts[1] > 0)
     k_num<BS, 64, 1, (BS == 3 ? 512 : 512)><<<counts[1], 64, 0, s>>>(counts[1], lists + (size_t)n, A.rowptr, A.col,
                                                                       A.val, B.rowptr, B.col, B.val, C.rowptr,
