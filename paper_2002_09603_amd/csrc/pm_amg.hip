@@ -615,10 +615,49 @@ __global__ void __launch_bounds__(256) k_residual_csr(int n, const int* __restri
   rr[(size_t)row * BS + lane] = RES ? b[(size_t)row * BS + lane] - v : v;
 }
 
-template <int BS>
-struct CsrLanes {
-  static constexpr int value = BS == 3 ? 8 : 16;
-};
+// launch the CSR-lane kernels with G in {4, 8, 16} lanes per row
+template <int BS, class T>
+void cheb_step_csr(hipStream_t s, const Level& L, const T* val, const T* dinv, const T* b, const T* xin, T* xout,
+                   T* d, T c1, T c2) {
+  const int n = L.n;
+  switch (L.csr_lanes) {
+    case 4:
+      k_cheb_step_csr<BS, T, 4><<<blocks_for((int64_t)n * 4), kBlock, 0, s>>>(n, L.A.rowptr, L.A.col, val, dinv, b,
+                                                                              xin, xout, d, c1, c2);
+      break;
+    case 8:
+      k_cheb_step_csr<BS, T, 8><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, L.A.rowptr, L.A.col, val, dinv, b,
+                                                                              xin, xout, d, c1, c2);
+      break;
+    default:
+      k_cheb_step_csr<BS, T, 16><<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, L.A.rowptr, L.A.col, val, dinv,
+                                                                                b, xin, xout, d, c1, c2);
+  }
+  PM_CHECK_LAUNCH();
+}
+
+template <int BS, class T, bool RES>
+void residual_csr(hipStream_t s, const Csr& A, int lanes, const T* val, const T* b, const T* x, T* r) {
+  const int n = A.n;
+  switch (lanes) {
+    case 4:
+      k_residual_csr<BS, T, 4, RES><<<blocks_for((int64_t)n * 4), kBlock, 0, s>>>(n, A.rowptr, A.col, val, b, x, r);
+      break;
+    case 8:
+      k_residual_csr<BS, T, 8, RES><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, val, b, x, r);
+      break;
+    default:
+      k_residual_csr<BS, T, 16, RES><<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, A.rowptr, A.col, val, b, x,
+                                                                                    r);
+  }
+  PM_CHECK_LAUNCH();
+}
+
+// lanes per row: about a quarter of the average row length, 4 to 16
+inline int csr_lanes_for(const Csr& A) {
+  const double avg = (double)A.nnzb / std::max(1, A.n);
+  return avg < 24.0 ? 4 : (avg < 48.0 ? 8 : 16);
+}
 
 // dense coarse level
 __global__ void k_dense_from_csr(int nb, int bs, const int* __restrict__ rp, const int* __restrict__ col,
@@ -959,9 +998,7 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
     }
     g_prof.begin(s, prof_id);
     if (L.csr_cycle) {
-      constexpr int GL = CsrLanes<BS>::value;
-      k_cheb_step_csr<BS, T, GL><<<blocks_for((int64_t)n * GL), kBlock, 0, s>>>(
-          n, L.A.rowptr, L.A.col, val, dinv, b, cur, nxt, d, (T)c1, (T)c2);
+      cheb_step_csr<BS, T>(s, L, val, dinv, b, cur, nxt, d, (T)c1, (T)c2);
       g_prof.end(s, prof_id, 0.0);
     } else if (BS == 1 && cpi) {
       cellpi_cheb_step<T>(s, G, *cpi, dinv, b, cur, nxt, d, (T)c1, (T)c2);
@@ -1041,9 +1078,7 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   } else if (cpi) {
     cellpi_residual<T>(s, H.grid, *cpi, b, cur, r);
   } else if (L.csr_cycle) {
-    constexpr int GL = CsrLanes<BS>::value;
-    k_residual_csr<BS, T, GL, true><<<blocks_for((int64_t)n * GL), kBlock, 0, s>>>(n, L.A.rowptr, L.A.col, AV, b,
-                                                                                   cur, r);
+    residual_csr<BS, T, true>(s, L.A, L.csr_lanes, AV, b, cur, r);
   } else {
     const int nth = L.As.nslices * kSlice;
     k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
@@ -1078,18 +1113,11 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
   double nnz_total = 0.0, nnz0 = (double)A0.nnzb;
   const char* env = getenv("PM_AMG_VERBOSE");
   const bool verbose = env && env[0] == '1';
-  Csr cur;
-  // copy of level-0 operator (the hierarchy owns its matrices)
-  cur.bs = A0.bs;
-  cur.n = A0.n;
-  cur.m = A0.m;
-  cur.nnzb = A0.nnzb;
-  cur.rowptr = dalloc<int>(A0.n + 1);
-  cur.col = dalloc<int>(A0.nnzb);
-  cur.val = dalloc<double>(A0.nnzb * A0.bs * A0.bs);
-  PM_HIP(hipMemcpyAsync(cur.rowptr, A0.rowptr, sizeof(int) * (A0.n + 1), hipMemcpyDeviceToDevice, s));
-  PM_HIP(hipMemcpyAsync(cur.col, A0.col, sizeof(int) * A0.nnzb, hipMemcpyDeviceToDevice, s));
-  PM_HIP(hipMemcpyAsync(cur.val, A0.val, sizeof(double) * A0.nnzb * A0.bs * A0.bs, hipMemcpyDeviceToDevice, s));
+  // level 0 refers to the caller's operator (which outlives the hierarchy:
+  // both are rebuilt together); coarser levels are owned
+  Csr cur = A0;
+  cur.val32 = nullptr;
+  cur.borrowed = true;
   for (int l = 0;; ++l) {
     H.L.emplace_back();
     Level& L = H.L.back();
@@ -1102,7 +1130,10 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
     alloc_level_vectors(L, prm.fp32);
     const bool on_lattice = (l == 0 && (H.lat || H.cpi));
     // long rows on a small level: latency-bound with one thread per row
-    L.csr_cycle = !last && l > 0 && L.n <= 262144 && (double)L.A.nnzb >= 16.0 * L.n;
+    // small coarse levels with long rows: CSR with lanes per row (one thread
+    // per sliced-ELL row is latency-bound there); large levels keep sliced ELL
+    L.csr_cycle = !last && l > 0 && L.n <= 262144 && (double)L.A.nnzb >= 12.0 * L.n;
+    L.csr_lanes = csr_lanes_for(L.A);
     if (L.csr_cycle) {
       if (prm.fp32) {
         const int64_t nv = L.A.nnzb * L.bs * L.bs;
@@ -1136,12 +1167,9 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
       const Csr& A = L.A;
       L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](const double* v, double* w) {
         if (L.bs == 3)
-          k_residual_csr<3, double, 8, false><<<blocks_for((int64_t)A.n * 8), kBlock, 0, s>>>(
-              A.n, A.rowptr, A.col, A.val, nullptr, v, w);
+          residual_csr<3, double, false>(s, A, L.csr_lanes, A.val, nullptr, v, w);
         else
-          k_residual_csr<1, double, 16, false><<<blocks_for((int64_t)A.n * 16), kBlock, 0, s>>>(
-              A.n, A.rowptr, A.col, A.val, nullptr, v, w);
-        PM_CHECK_LAUNCH();
+          residual_csr<1, double, false>(s, A, L.csr_lanes, A.val, nullptr, v, w);
       });
     } else
       L.lmax = estimate_lmax(s, L.As, L.dinv, prm.power_its);

@@ -86,6 +86,7 @@ struct Csr {
   int* col = nullptr;     // nnzb
   double* val = nullptr;  // nnzb*bs*bs
   float* val32 = nullptr; // optional FP32 copy of val
+  bool borrowed = false;  // arrays owned elsewhere: free_all only forgets them
   void free_all();
 };
 
@@ -110,7 +111,8 @@ struct Level {
   int bs = 1, n = 0;
   Csr A;                     // kept for the Galerkin products
   Sell As;                   // operator used by the cycle (sliced ELL) ...
-  bool csr_cycle = false;    // ... or A itself, G lanes per row (coarse levels with long rows)
+  bool csr_cycle = false;    // ... or A itself, csr_lanes lanes per row (coarse levels)
+  int csr_lanes = 16;
   double* dinv = nullptr;    // n*bs*bs inverse diagonal blocks
   float* dinv32 = nullptr;
   Sell P;                    // prolongation from level+1 (empty on the coarsest level)

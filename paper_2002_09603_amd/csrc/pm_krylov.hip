@@ -20,11 +20,13 @@ constexpr int kDotGroup = 8;      // basis vectors per multi-dot pass
 constexpr int kPartRows = 504;    // rows of the partial-sum buffer (basis vectors + 2 norms)
 
 // part[(i0+g)*kDotBlocks + block] = sum_chunk V_{i0+g} . w for g < cnt; with
-// self_row >= 0 also part[self_row*kDotBlocks + block] = sum_chunk w . w
+// self_row >= 0 also part[self_row*kDotBlocks + block] = sum_chunk w . w.
+// Workgroup sums: shuffles within each wavefront, then the 4 wavefronts in
+// order (deterministic).
 __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, int64_t N, int i0, int cnt,
                                                   const double* __restrict__ w, double* __restrict__ part,
                                                   int self_row) {
-  __shared__ double sh[kDotGroup + 1][256];
+  __shared__ double sh[4][kDotGroup + 1];
   double acc[kDotGroup + 1];
   for (int g = 0; g <= kDotGroup; ++g) acc[g] = 0.0;
   const double* Vi = V + (size_t)i0 * N;
@@ -35,15 +37,19 @@ __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, 
       if (g < cnt) acc[g] += Vi[(size_t)g * N + k] * wk;
     acc[kDotGroup] += wk * wk;
   }
-  for (int g = 0; g <= kDotGroup; ++g) sh[g][threadIdx.x] = acc[g];
+#pragma unroll
+  for (int g = 0; g <= kDotGroup; ++g)
+    for (int off = 32; off > 0; off >>= 1) acc[g] += __shfl_down(acc[g], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int g = 0; g <= kDotGroup; ++g) sh[wave][g] = acc[g];
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off)
-      for (int g = 0; g <= kDotGroup; ++g) sh[g][threadIdx.x] += sh[g][threadIdx.x + off];
-    __syncthreads();
+  if ((int)threadIdx.x <= kDotGroup) {
+    const int g = threadIdx.x;
+    const double v = ((sh[0][g] + sh[1][g]) + sh[2][g]) + sh[3][g];
+    if (g < cnt) part[(size_t)(i0 + g) * kDotBlocks + blockIdx.x] = v;
+    if (g == kDotGroup && self_row >= 0) part[(size_t)self_row * kDotBlocks + blockIdx.x] = v;
   }
-  if (threadIdx.x < cnt) part[(size_t)(i0 + threadIdx.x) * kDotBlocks + blockIdx.x] = sh[threadIdx.x][0];
-  if (self_row >= 0 && threadIdx.x == 0) part[(size_t)self_row * kDotBlocks + blockIdx.x] = sh[kDotGroup][0];
 }
 
 // h[row0 + i] = sum_{b < np} part[(row0 + i)*kDotBlocks + b], one workgroup per i
@@ -349,7 +355,7 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
         const double sc = c->hhost[nv + 2];
         if (hn > 0.0 && std::isfinite(hn)) {
           const double prod = hn * sc;  // norm of the written vector
-          if (std::fabs(prod - 1.0) > 1e-12) {
+          if (std::fabs(prod - 1.0) > 1e-10) {
             k_scale2<<<gN, kBlock, 0, s>>>(N, c->V + (size_t)(j + 1) * N, 1.0 / prod, c->V + (size_t)(j + 1) * N, vf);
             PM_CHECK_LAUNCH();
           } else {

@@ -136,10 +136,13 @@ void Profiler::collect(int k, int64_t* n, double* ms, double* bytes) {
 }
 
 void Csr::free_all() {
-  dfree(rowptr);
-  dfree(col);
-  dfree(val);
-  dfree(val32);
+  if (!borrowed) {
+    dfree(rowptr);
+    dfree(col);
+    dfree(val);
+    dfree(val32);
+  }
+  borrowed = false;
   rowptr = nullptr;
   col = nullptr;
   val = nullptr;

@@ -81,39 +81,64 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
                                                  const int* __restrict__ bcol, const int64_t* __restrict__ ubofs,
                                                  int* __restrict__ tmp, int* __restrict__ cnt,
                                                  int* __restrict__ status) {
+  constexpr int AMAX = 64;  // rows of A up to this long have their pairs spread over the lanes
   __shared__ int tab[GPB][H];
   __shared__ int keys[GPB][KM];
   __shared__ int nk[GPB];
+  __shared__ int pre_l[GPB][AMAX + 1];
+  __shared__ int fb_l[GPB][AMAX];
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int li = blockIdx.x * GPB + grp;
   const bool valid = li < nlist;
   const int row = valid ? list[li] : 0;
   for (int q = lane; q < H; q += G) tab[grp][q] = -1;
   if (lane == 0) nk[grp] = 0;
+  const int e0 = valid ? arp[row] : 0;
+  const int na = valid ? arp[row + 1] - e0 : 0;
+  const bool staged = valid && na <= AMAX;
+  if (staged)
+    for (int q = lane; q < na; q += G) {
+      const int k = acol[e0 + q];
+      const int b0 = brp[k];
+      fb_l[grp][q] = b0;
+      pre_l[grp][q + 1] = brp[k + 1] - b0;
+    }
   __syncthreads();
-  if (valid) {
-    for (int e = arp[row]; e < arp[row + 1]; ++e) {
-      const int k = acol[e];
-      for (int f = brp[k] + lane; f < brp[k + 1]; f += G) {
-        const int key = bcol[f];
-        int h = hslot<H>(key);
-        bool placed = false;
-        for (int probe = 0; probe < H; ++probe) {
-          const int prev = atomicCAS(&tab[grp][h], -1, key);
-          if (prev == -1) {
-            const int pos = atomicAdd(&nk[grp], 1);
-            if (pos < KM) keys[grp][pos] = key;
-            placed = true;
-            break;
-          }
-          if (prev == key) {
-            placed = true;
-            break;
-          }
-          h = (h + 1) & (H - 1);
-        }
-        if (!placed) atomicAdd(&nk[grp], KM + 1);
+  if (staged && lane == 0) {
+    pre_l[grp][0] = 0;
+    for (int q = 1; q <= na; ++q) pre_l[grp][q] += pre_l[grp][q - 1];
+  }
+  __syncthreads();
+  auto insert = [&](int key) {
+    int h = hslot<H>(key);
+    for (int probe = 0; probe < H; ++probe) {
+      const int prev = atomicCAS(&tab[grp][h], -1, key);
+      if (prev == -1) {
+        const int pos = atomicAdd(&nk[grp], 1);
+        if (pos < KM) keys[grp][pos] = key;
+        return;
       }
+      if (prev == key) return;
+      h = (h + 1) & (H - 1);
+    }
+    atomicAdd(&nk[grp], KM + 1);
+  };
+  if (staged) {
+    // the (entry of A, entry of its B row) pairs of the row, spread over the lanes
+    const int* pre = pre_l[grp];
+    const int tot = pre[na];
+    for (int pq = lane; pq < tot; pq += G) {
+      int lo = 0, hi = na - 1;  // largest e with pre[e] <= pq
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= pq) lo = mid; else hi = mid - 1;
+      }
+      insert(bcol[fb_l[grp][lo] + (pq - pre[lo])]);
+    }
+  } else if (valid) {
+    for (int e = e0; e < e0 + na; ++e) {
+      const int k = acol[e];
+      for (int f = brp[k] + lane; f < brp[k + 1]; f += G) insert(bcol[f]);
     }
   }
   __syncthreads();
