@@ -117,6 +117,9 @@ typedef struct {
                                 their row's largest, rescaling to the row sum (0: keep all) */
   int32_t cell_pi;           /* 1: apply the finest C~_pi level cell by cell from packed symmetric
                                 6x6 element matrices; 0: assembled matrix */
+  double p_trunc_u;          /* A_uu hierarchy: drop prolongator blocks below this fraction of
+                                their row's largest (Frobenius norms), keeping the block row sum */
+  double cheb_lower_pi;      /* Chebyshev interval lower end for C~_pi (0: use cheb_lower) */
 } pm_opts;
 
 typedef struct {
@@ -133,11 +136,11 @@ typedef struct {
  * increment form, Chebyshev degree 2 (A_uu) / 2 (C~_pi), coarse_max 64, one
  * V-cycle per block, two Gram-Schmidt passes, strength thresholds theta
  * 0 (A_uu) / 0.08 (C~_pi), distance-2 aggregation roots, Chebyshev interval
- * from lambda_max/30; transposed solves: rtol, restart 100 and two
+ * from 0.3 lambda_max; transposed solves: rtol, restart 100 and two
  * Gram-Schmidt passes (restarted GMRES on the transposed preconditioned
  * operator stagnates with short restarts or one pass on strongly
  * heterogeneous permeability); lattice operator on; C~_pi prolongator
- * truncation 0.02; cell-by-cell finest C~_pi level. */
+ * truncation 0.02 (C~_pi) and 0.02 (A_uu); cell-by-cell finest C~_pi level. */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

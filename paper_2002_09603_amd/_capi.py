@@ -53,7 +53,8 @@ class pm_opts(C.Structure):
                 ("agg_dist_u", C.c_int32), ("agg_dist_pi", C.c_int32), ("cheb_lower", C.c_double),
                 ("rtol_transpose", C.c_double), ("restart_transpose", C.c_int32),
                 ("orth_passes_transpose", C.c_int32), ("lattice_uu", C.c_int32),
-                ("p_trunc_pi", C.c_double), ("cell_pi", C.c_int32)]
+                ("p_trunc_pi", C.c_double), ("cell_pi", C.c_int32), ("p_trunc_u", C.c_double),
+                ("cheb_lower_pi", C.c_double)]
 
 
 class pm_info(C.Structure):

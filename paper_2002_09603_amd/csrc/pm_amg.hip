@@ -275,47 +275,98 @@ __global__ void k_smooth_p(int n, const int* __restrict__ agg, const double* __r
   }
 }
 
-// Truncation of a scalar prolongator: entries below tau * (largest |entry| of
-// the row) are dropped and the kept ones rescaled to the row's former sum, so
-// that interpolation of the near-kernel (constants) is unchanged.
+// Truncation of a prolongator: blocks whose norm is below tau * (largest block
+// norm of the row) are dropped and the kept ones rescaled so that the row's
+// block sum is unchanged (scalar: by the ratio of sums; 3x3: right-multiplied
+// by (sum kept)^-1 (sum all)), so that interpolation of the near kernel
+// (constants, or rigid translations per component) is unchanged.
+template <int BS>
+__device__ inline double pblock_norm(const double* v) {
+  double s = 0.0;
+  for (int q = 0; q < BS * BS; ++q) s += v[q] * v[q];
+  return sqrt(s);
+}
+
+template <int BS>
 __global__ void k_trunc_count(int n, const int* __restrict__ rp, const double* __restrict__ val, double tau,
                               int* __restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double mx = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) mx = fmax(mx, fabs(val[e]));
+  for (int e = rp[i]; e < rp[i + 1]; ++e) mx = fmax(mx, pblock_norm<BS>(val + (size_t)e * BS * BS));
   int c = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) c += fabs(val[e]) >= tau * mx;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) c += pblock_norm<BS>(val + (size_t)e * BS * BS) >= tau * mx;
   cnt[i] = c;
 }
 
+template <int BS>
 __global__ void k_trunc_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
                              const double* __restrict__ val, double tau, const int* __restrict__ trp,
                              int* __restrict__ tcol, double* __restrict__ tval) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double mx = 0.0, all = 0.0, kept = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) mx = fmax(mx, fabs(val[e]));
+  double mx = 0.0, all[BS * BS], kept[BS * BS];
+  for (int q = 0; q < BS * BS; ++q) all[q] = kept[q] = 0.0;
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    all += val[e];
-    if (fabs(val[e]) >= tau * mx) kept += val[e];
+    const double* v = val + (size_t)e * BS * BS;
+    mx = fmax(mx, pblock_norm<BS>(v));
+    for (int q = 0; q < BS * BS; ++q) all[q] += v[q];
   }
-  const double scale = kept != 0.0 ? all / kept : 1.0;
-  int p = trp[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (fabs(val[e]) >= tau * mx) {
-      tcol[p] = col[e];
-      tval[p] = val[e] * scale;
-      ++p;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const double* v = val + (size_t)e * BS * BS;
+    if (pblock_norm<BS>(v) >= tau * mx)
+      for (int q = 0; q < BS * BS; ++q) kept[q] += v[q];
+  }
+  // S = kept^-1 all (identity if kept is singular)
+  double S[BS * BS];
+  for (int q = 0; q < BS * BS; ++q) S[q] = (q % (BS + 1) == 0) ? 1.0 : 0.0;
+  if (BS == 1) {
+    if (kept[0] != 0.0) S[0] = all[0] / kept[0];
+  } else {
+    const double* k = kept;
+    const double det = k[0] * (k[4] * k[8] - k[5] * k[7]) - k[1] * (k[3] * k[8] - k[5] * k[6]) +
+                       k[2] * (k[3] * k[7] - k[4] * k[6]);
+    if (det != 0.0 && isfinite(det)) {
+      double inv[9];
+      inv[0] = (k[4] * k[8] - k[5] * k[7]) / det;
+      inv[1] = (k[2] * k[7] - k[1] * k[8]) / det;
+      inv[2] = (k[1] * k[5] - k[2] * k[4]) / det;
+      inv[3] = (k[5] * k[6] - k[3] * k[8]) / det;
+      inv[4] = (k[0] * k[8] - k[2] * k[6]) / det;
+      inv[5] = (k[2] * k[3] - k[0] * k[5]) / det;
+      inv[6] = (k[3] * k[7] - k[4] * k[6]) / det;
+      inv[7] = (k[1] * k[6] - k[0] * k[7]) / det;
+      inv[8] = (k[0] * k[4] - k[1] * k[3]) / det;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double t = 0.0;
+          for (int c = 0; c < 3; ++c) t += inv[a * 3 + c] * all[c * 3 + b];
+          S[a * 3 + b] = t;
+        }
     }
+  }
+  int p = trp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const double* v = val + (size_t)e * BS * BS;
+    if (pblock_norm<BS>(v) < tau * mx) continue;
+    tcol[p] = col[e];
+    for (int a = 0; a < BS; ++a)
+      for (int b = 0; b < BS; ++b) {
+        double t = 0.0;
+        for (int c = 0; c < BS; ++c) t += v[a * BS + c] * S[c * BS + b];
+        tval[(size_t)p * BS * BS + a * BS + b] = t;
+      }
+    ++p;
+  }
 }
 
+template <int BS>
 void truncate_p(hipStream_t s, Csr& P, double tau) {
   int* cnt = dalloc<int>(P.n);
-  k_trunc_count<<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.val, tau, cnt);
+  k_trunc_count<BS><<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.val, tau, cnt);
   PM_CHECK_LAUNCH();
   Csr T;
-  T.bs = 1;
+  T.bs = BS;
   T.n = P.n;
   T.m = P.m;
   T.rowptr = dalloc<int>(P.n + 1);
@@ -324,8 +375,8 @@ void truncate_p(hipStream_t s, Csr& P, double tau) {
   dfree(cnt);
   T.nnzb = nnz;
   T.col = dalloc<int>(nnz);
-  T.val = dalloc<double>(nnz);
-  k_trunc_fill<<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.col, P.val, tau, T.rowptr, T.col, T.val);
+  T.val = dalloc<double>((int64_t)nnz * BS * BS);
+  k_trunc_fill<BS><<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.col, P.val, tau, T.rowptr, T.col, T.val);
   PM_CHECK_LAUNCH();
   P.free_all();
   P = T;
@@ -929,7 +980,7 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   const double omega = 4.0 / (3.0 * lF);
   k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, filtered ? dinvF : L.dinv, omega, P.rowptr, P.col, P.val);
   PM_CHECK_LAUNCH();
-  if (BS == 1 && prm.p_trunc > 0.0) truncate_p(s, P, prm.p_trunc);
+  if (prm.p_trunc > 0.0) truncate_p<BS>(s, P, prm.p_trunc);
   dfree(dinvF);
   dfree(agg);
   // Galerkin coarse operator
@@ -979,8 +1030,9 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
   T* cur = x;
   T* nxt = t;
   int k0 = 0;
-  // from zero the result lands in x after cheb_degree kernels: start in t when even
-  if (zero_init && prm.cheb_degree % 2 == 0) std::swap(cur, nxt);
+  // from zero, start in t: pre-smoothing then ends in x (even degree) or t
+  // (odd), and the post-smoothing steps that follow end in x either way
+  if (zero_init) std::swap(cur, nxt);
   if (zero_init) {
     k_cheb_first<BS, T><<<blocks_for(n), kBlock, 0, s>>>(n, dinv, b, (T)(1.0 / theta), cur, d);
     k0 = 1;

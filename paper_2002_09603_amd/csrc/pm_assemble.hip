@@ -510,6 +510,10 @@ Grid grid_of(const pm_ctx* c) {
   G.nfy = c->nfy;
   G.nfz = c->nfz;
   G.nf = c->nf;
+  G.dnx.init((uint32_t)c->nx);
+  G.dnx1.init((uint32_t)c->nx + 1);
+  G.dny.init((uint32_t)c->ny);
+  G.dny1.init((uint32_t)c->ny + 1);
   return G;
 }
 

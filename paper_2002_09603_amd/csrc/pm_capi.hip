@@ -78,6 +78,7 @@ pm::AmgParams params_u(const pm_ctx* c) {
   p.agg_dist = c->opts.agg_dist_u;
   p.cheb_lower = c->opts.cheb_lower;
   p.fp32 = c->opts.precond_fp32 != 0;
+  p.p_trunc = c->opts.p_trunc_u;
   return p;
 }
 
@@ -89,6 +90,7 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   p.cycles = c->opts.cycles_pi;
   p.agg_dist = c->opts.agg_dist_pi;
   p.p_trunc = c->opts.p_trunc_pi;
+  if (c->opts.cheb_lower_pi > 0.0) p.cheb_lower = c->opts.cheb_lower_pi;
   return p;
 }
 
@@ -152,12 +154,14 @@ void pm_default_opts(pm_opts* o) {
   o->theta_u = 0.0;
   o->agg_dist_u = 2;
   o->agg_dist_pi = 2;
-  o->cheb_lower = 1.0 / 30.0;
+  o->cheb_lower = 0.3;
   o->rtol_transpose = 0.0;
   o->restart_transpose = 100;
   o->orth_passes_transpose = 2;
   o->lattice_uu = 1;
   o->p_trunc_pi = 0.02;
+  o->p_trunc_u = 0.02;
+  o->cheb_lower_pi = 0.0;
   o->cell_pi = 1;
   o->theta_pi = 0.08;
 }
@@ -196,6 +200,8 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     c->nfy = nx * (ny + 1) * nz;
     c->nfz = nx * ny * (nz + 1);
     c->nf = c->nfx + c->nfy + c->nfz;
+    if (c->nf >= ((int64_t)1 << 31) || c->nn >= ((int64_t)1 << 31))
+      throw Error(PM_EINVAL, "pm_setup: meshes with 2^31 or more faces or nodes are not supported");
     c->nmacro = c->nc / 8;
     c->n_u = 3 * c->nn;
     c->n_p = c->nc;
@@ -218,7 +224,9 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
         !(c->opts.cheb_lower > 0.0 && c->opts.cheb_lower < 1.0) || c->opts.restart > 500 ||
         c->opts.restart_transpose < 0 || c->opts.restart_transpose > 500 || c->opts.orth_passes_transpose < 0 ||
         c->opts.orth_passes_transpose > 2 || !(c->opts.rtol_transpose >= 0.0) ||
-        !(c->opts.p_trunc_pi >= 0.0 && c->opts.p_trunc_pi < 1.0))
+        !(c->opts.p_trunc_pi >= 0.0 && c->opts.p_trunc_pi < 1.0) ||
+        !(c->opts.p_trunc_u >= 0.0 && c->opts.p_trunc_u < 1.0) ||
+        !(c->opts.cheb_lower_pi >= 0.0 && c->opts.cheb_lower_pi < 1.0))
       throw Error(PM_EINVAL, "pm_setup: invalid solver options");
     c->coords = pm::dalloc<double>(3 * c->nn);
     c->E = pm::dalloc<double>(c->nc);

@@ -9,10 +9,28 @@
 
 namespace pm {
 
-// Structured grid description passed by value to kernels.
+// Division by a run-time constant d for 0 <= n < 2^31: q = (n m) >> sh with
+// L = ceil(log2 d), sh = 31 + L, m = ceil(2^sh / d) < 2^32 (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994).
+struct FastDiv {
+  uint32_t d = 1, m = 0x80000000u;
+  int sh = 31;
+  __host__ void init(uint32_t dd) {
+    d = dd;
+    int L = 0;
+    while ((1ull << L) < dd) ++L;
+    sh = 31 + L;
+    m = (uint32_t)(((1ull << sh) + dd - 1) / dd);
+  }
+  __host__ __device__ uint32_t div(uint32_t n) const { return (uint32_t)(((uint64_t)n * m) >> sh); }
+};
+
+// Structured grid description passed by value to kernels.  Index arithmetic
+// assumes fewer than 2^31 nodes, cells and faces (checked at set-up).
 struct Grid {
   int nx, ny, nz;
   int64_t nn, nc, nfx, nfy, nfz, nf;
+  FastDiv dnx, dnx1, dny, dny1;  // division by nx, nx+1, ny, ny+1
   __host__ __device__ int64_t node(int i, int j, int k) const {
     return i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
   }
@@ -41,45 +59,43 @@ struct Grid {
     f[5] = fz(i, j, k + 1);
   }
   __host__ __device__ void cell_ijk(int64_t c, int& i, int& j, int& k) const {
-    i = (int)(c % nx);
-    int64_t r = c / nx;
-    j = (int)(r % ny);
-    k = (int)(r / ny);
+    const uint32_t u = (uint32_t)c, r = dnx.div(u), kk = dny.div(r);
+    i = (int)(u - r * (uint32_t)nx);
+    j = (int)(r - kk * (uint32_t)ny);
+    k = (int)kk;
   }
   __host__ __device__ void node_ijk(int64_t n, int& i, int& j, int& k) const {
-    i = (int)(n % (nx + 1));
-    int64_t r = n / (nx + 1);
-    j = (int)(r % (ny + 1));
-    k = (int)(r / (ny + 1));
+    const uint32_t u = (uint32_t)n, r = dnx1.div(u), kk = dny1.div(r);
+    i = (int)(u - r * (uint32_t)(nx + 1));
+    j = (int)(r - kk * (uint32_t)(ny + 1));
+    k = (int)kk;
   }
   // cells adjacent to face f: cell ids (or -1) and the local face index in each
   __host__ __device__ void face_cells(int64_t f, int64_t c[2], int lf[2]) const {
     int i, j, k;
     if (f < nfx) {
-      i = (int)(f % (nx + 1));
-      int64_t r = f / (nx + 1);
-      j = (int)(r % ny);
-      k = (int)(r / ny);
+      const uint32_t u = (uint32_t)f, r = dnx1.div(u), kk = dny.div(r);
+      i = (int)(u - r * (uint32_t)(nx + 1));
+      j = (int)(r - kk * (uint32_t)ny);
+      k = (int)kk;
       c[0] = i > 0 ? cell(i - 1, j, k) : -1;
       lf[0] = 1;
       c[1] = i < nx ? cell(i, j, k) : -1;
       lf[1] = 0;
     } else if (f < nfx + nfy) {
-      int64_t g = f - nfx;
-      i = (int)(g % nx);
-      int64_t r = g / nx;
-      j = (int)(r % (ny + 1));
-      k = (int)(r / (ny + 1));
+      const uint32_t u = (uint32_t)(f - nfx), r = dnx.div(u), kk = dny1.div(r);
+      i = (int)(u - r * (uint32_t)nx);
+      j = (int)(r - kk * (uint32_t)(ny + 1));
+      k = (int)kk;
       c[0] = j > 0 ? cell(i, j - 1, k) : -1;
       lf[0] = 3;
       c[1] = j < ny ? cell(i, j, k) : -1;
       lf[1] = 2;
     } else {
-      int64_t g = f - nfx - nfy;
-      i = (int)(g % nx);
-      int64_t r = g / nx;
-      j = (int)(r % ny);
-      k = (int)(r / ny);
+      const uint32_t u = (uint32_t)(f - nfx - nfy), r = dnx.div(u), kk = dny.div(r);
+      i = (int)(u - r * (uint32_t)nx);
+      j = (int)(r - kk * (uint32_t)ny);
+      k = (int)kk;
       c[0] = k > 0 ? cell(i, j, k - 1) : -1;
       lf[0] = 5;
       c[1] = k < nz ? cell(i, j, k) : -1;
@@ -100,8 +116,7 @@ __host__ __device__ inline bool u_fixed(const Grid& G, int kind, int i, int j, i
 
 // Dirichlet face pressures: the faces of the top plane (drained boundary).
 __host__ __device__ inline bool pi_fixed(const Grid& G, int64_t f) {
-  if (f < G.nfx + G.nfy) return false;
-  return (f - G.nfx - G.nfy) / ((int64_t)G.nx * G.ny) == G.nz;
+  return f >= G.nf - (int64_t)G.nx * G.ny;  // z-faces are numbered last, plane k = nz at the end
 }
 // the same for local face e of cell (., ., k): only the +z face of a top cell
 __host__ __device__ inline bool pi_fixed_local(const Grid& G, int k, int e) { return e == 5 && k == G.nz - 1; }

@@ -131,7 +131,7 @@ struct AmgParams {
   int cheb_degree = 2;
   int cycles = 1;                  // V-cycles per application
   int agg_dist = 2;                // aggregation roots: distance-1 or distance-2 independent set
-  double cheb_lower = 1.0 / 30.0;  // Chebyshev interval [lower*lmax, upper*lmax]
+  double cheb_lower = 0.3;         // Chebyshev interval [lower*lmax, upper*lmax]
   double cheb_upper = 1.1;
   int power_its = 15;
   double p_trunc = 0.0;            // scalar prolongator truncation threshold (0: none)

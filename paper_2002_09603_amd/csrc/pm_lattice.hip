@@ -38,8 +38,10 @@ namespace {
 __device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j, int& k) {
   n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (n >= G.nn) return false;
+  // plain 32-bit division here (fewer registers live across the stencil than
+  // the multiply-shift form)
   const uint32_t nx1 = (uint32_t)G.nx + 1, ny1 = (uint32_t)G.ny + 1;
-  const uint32_t m = (uint32_t)n;  // nn < 2^31 is checked at set-up
+  const uint32_t m = (uint32_t)n;
   const uint32_t r = m / nx1;
   i = (int)(m - r * nx1);
   k = (int)(r / ny1);

@@ -50,13 +50,15 @@ class Options:
     theta_pi: float = 0.08
     agg_dist_u: int = 2
     agg_dist_pi: int = 2
-    cheb_lower: float = 1.0 / 30.0
+    cheb_lower: float = 0.3
     rtol_transpose: float = 0.0
     restart_transpose: int = 100
     orth_passes_transpose: int = 2
     lattice_uu: bool = True
     p_trunc_pi: float = 0.02
     cell_pi: bool = True
+    p_trunc_u: float = 0.02
+    cheb_lower_pi: float = 0.0
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -83,6 +85,8 @@ class Options:
         o.lattice_uu = int(self.lattice_uu)
         o.p_trunc_pi = self.p_trunc_pi
         o.cell_pi = int(self.cell_pi)
+        o.p_trunc_u = self.p_trunc_u
+        o.cheb_lower_pi = self.cheb_lower_pi
         return o
 
 

@@ -20,7 +20,8 @@ from paper_2002_09603_amd import _capi  # noqa: E402
 from paper_2002_09603_amd.solver import Options, from_problem  # noqa: E402
 from synth import make_config  # noqa: E402
 
-BENCH_OPTS = dict(rtol=1e-8, precond_fp32=True, restart=24, max_it=1000, orth_passes=1)
+BENCH_OPTS = dict(rtol=1e-8, precond_fp32=True, restart=24, max_it=1000, orth_passes=1, cheb_degree_pi=1,
+                  cheb_lower_pi=0.1)
 
 CASES = [
     ("layered128", None, 0.0, BENCH_OPTS),
