@@ -191,13 +191,15 @@ __global__ void __launch_bounds__(G* GPB) k_num(int nlist, const int* __restrict
                                                  const int* __restrict__ acol, const double* __restrict__ aval,
                                                  const int* __restrict__ brp, const int* __restrict__ bcol,
                                                  const double* __restrict__ bval, const int* __restrict__ crp,
-                                                 const int* __restrict__ ccol, double* __restrict__ cval) {
+                                                 const int* __restrict__ ccol, double* __restrict__ cval,
+                                                 int min_na = 0) {
   __shared__ int cols_l[GPB][CAP];
   __shared__ double acc_l[GPB][CAP * BS * BS];
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int li = blockIdx.x * GPB + grp;
   if (li >= nlist) return;  // groups never synchronize across rows: per-wave ordering only
   const int row = list[li];
+  if (arp[row + 1] - arp[row] < min_na) return;  // rows handled by k_num_small
   const int c0 = crp[row], u = crp[row + 1] - c0;
   const bool in_lds = u <= CAP;
   const int* cols = in_lds ? (const int*)cols_l[grp] : ccol + c0;
@@ -242,6 +244,16 @@ __global__ void __launch_bounds__(G* GPB) k_num(int nlist, const int* __restrict
 // LDS, and the B-row entries and A block of the next entry are loaded while
 // the current one is accumulated.
 template <int BS>
+__device__ inline int slot_in(const int* __restrict__ cols, int u, int key) {
+  int lo = 0, hi = u - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cols[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <int BS>
 __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restrict__ list,
                                                   const int* __restrict__ arp, const int* __restrict__ acol,
                                                   const double* __restrict__ aval, const int* __restrict__ brp,
@@ -251,112 +263,98 @@ __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restri
   constexpr int G = 16, GPB = 4, CAP = 64, AMAX = 64, B2 = BS * BS;
   __shared__ int cols_l[GPB][CAP];
   __shared__ double acc_l[GPB][CAP * B2];
-  __shared__ int fb_l[GPB][AMAX];
-  __shared__ int fe_l[GPB][AMAX];
+  __shared__ int fb_l[GPB][AMAX + 1];
+  __shared__ int fe_l[GPB][AMAX + 1];
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int li = blockIdx.x * GPB + grp;
   if (li >= nlist) return;  // groups never synchronize across rows: per-wave ordering only
   const int row = list[li];
   const int c0 = crp[row], u = crp[row + 1] - c0;
   const int e0 = arp[row], na = arp[row + 1] - e0;
-  int* cols = cols_l[grp];
-  double* acc = acc_l[grp];
-  for (int i = lane; i < u; i += G) cols[i] = ccol[c0 + i];
-  for (int i = lane; i < u * B2; i += G) acc[i] = 0.0;
-  const bool staged = na <= AMAX;
-  if (staged)
-    for (int q = lane; q < na; q += G) {
-      const int k = acol[e0 + q];
-      fb_l[grp][q] = brp[k];
-      fe_l[grp][q] = brp[k + 1];
-    }
+  for (int i = lane; i < u; i += G) cols_l[grp][i] = ccol[c0 + i];
+  for (int i = lane; i < u * B2; i += G) acc_l[grp][i] = 0.0;
+  // rows with more than AMAX entries in A are left to k_num (rare)
+  if (na > AMAX) return;
+  // B-row extents of the row's A entries
+  for (int q = lane; q < na; q += G) {
+    const int k = acol[e0 + q];
+    fb_l[grp][q] = brp[k];
+    fe_l[grp][q] = brp[k + 1];
+  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
-  auto extent = [&](int e, int& fb, int& fe) {
-    if (staged) {
-      fb = fb_l[grp][e];
-      fe = fe_l[grp][e];
-    } else {
-      const int k = acol[e0 + e];
-      fb = brp[k];
-      fe = brp[k + 1];
-    }
-  };
-  auto slot_of = [&](int key) {
-    int lo = 0, hi = u - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (cols[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-  };
-  // current step's operands
-  int fb = 0, fe = 0;
-  if (na > 0) extent(0, fb, fe);
-  bool v = fb + lane < fe;
-  int key = v ? bcol[fb + lane] : 0;
-  double a[B2], b[B2];
-  for (int q = 0; q < B2; ++q) {
-    a[q] = na > 0 ? aval[(size_t)e0 * B2 + q] : 0.0;
-    b[q] = v ? bval[(size_t)(fb + lane) * B2 + q] : 0.0;
+  if (na == 0) {
+    for (int i = lane; i < u * B2; i += G) cval[(size_t)c0 * B2 + i] = 0.0;
+    return;
   }
-  for (int e = 0; e < na; ++e) {
-    // operands of the next entry, loaded before the current one is used
-    int fbn = 0, fen = 0;
-    bool vn = false;
-    int keyn = 0;
-    double an[B2], bn[B2];
-    if (e + 1 < na) {
-      extent(e + 1, fbn, fen);
-      vn = fbn + lane < fen;
-      keyn = vn ? bcol[fbn + lane] : 0;
-      for (int q = 0; q < B2; ++q) {
-        an[q] = aval[(size_t)(e0 + e + 1) * B2 + q];
-        bn[q] = vn ? bval[(size_t)(fbn + lane) * B2 + q] : 0.0;
-      }
+  // Two register sets alternate (loop unrolled by two): the operands of entry
+  // e+1 are loaded, with clamped always-valid indices, before entry e is
+  // accumulated, and no register copies tie the loads to the loop back edge.
+  struct Ops {
+    int fb, fe, key;
+    bool v;
+    double a[B2], b[B2];
+  };
+  auto load = [&](int e, Ops& o) {
+    const int ec = min(e, na - 1);
+    o.fb = fb_l[grp][ec];
+    o.fe = fe_l[grp][ec];
+    o.v = (e < na) && (o.fb + lane < o.fe);
+    const int fs = o.v ? o.fb + lane : 0;
+    o.key = bcol[fs];
+    for (int q = 0; q < B2; ++q) {
+      o.a[q] = aval[(size_t)(e0 + ec) * B2 + q];
+      o.b[q] = bval[(size_t)fs * B2 + q];
     }
-    if (v) {
-      double* dst = acc + (size_t)slot_of(key) * B2;
+  };
+  auto accumulate = [&](const Ops& o) {
+    if (o.v) {
+      double* dst = &acc_l[grp][slot_in<BS>(cols_l[grp], u, o.key) * B2];
       for (int i = 0; i < BS; ++i)
         for (int j = 0; j < BS; ++j) {
           double sacc = dst[i * BS + j];
-          for (int t = 0; t < BS; ++t) sacc += a[i * BS + t] * b[t * BS + j];
+          for (int t = 0; t < BS; ++t) sacc += o.a[i * BS + t] * o.b[t * BS + j];
           dst[i * BS + j] = sacc;
         }
     }
     // B rows longer than the group (rare): remaining entries, in order
-    for (int f = fb + lane + G; f < fe; f += G) {
-      double* dst = acc + (size_t)slot_of(bcol[f]) * B2;
+    for (int f = o.fb + lane + G; f < o.fe; f += G) {
+      double* dst = &acc_l[grp][slot_in<BS>(cols_l[grp], u, bcol[f]) * B2];
       const double* bb = bval + (size_t)f * B2;
       for (int i = 0; i < BS; ++i)
         for (int j = 0; j < BS; ++j) {
           double sacc = dst[i * BS + j];
-          for (int t = 0; t < BS; ++t) sacc += a[i * BS + t] * bb[t * BS + j];
+          for (int t = 0; t < BS; ++t) sacc += o.a[i * BS + t] * bb[t * BS + j];
           dst[i * BS + j] = sacc;
         }
     }
-    // the next entry of A may update the same slots from other lanes
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // the next entry of A may update the same slots from other lanes of this
+    // wavefront: LDS accesses of one wavefront complete in order, so only the
+    // compiler must not move them across this point
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (e + 1 < na) {
-      fb = fbn;
-      fe = fen;
-      v = vn;
-      key = keyn;
-      for (int q = 0; q < B2; ++q) {
-        a[q] = an[q];
-        b[q] = bn[q];
-      }
-    }
+  };
+  Ops p0, p1;
+  load(0, p0);
+  for (int e = 0; e < na; e += 2) {
+    load(e + 1, p1);
+    accumulate(p0);
+    if (e + 1 >= na) break;
+    load(e + 2, p0);
+    accumulate(p1);
   }
-  for (int i = lane; i < u * B2; i += G) cval[(size_t)c0 * B2 + i] = acc[i];
+  for (int i = lane; i < u * B2; i += G) cval[(size_t)c0 * B2 + i] = acc_l[grp][i];
 }
 
 template <int BS>
 void numeric_launch(hipStream_t s, const int* counts, const int* lists, int n, const Csr& A, const Csr& B, Csr& C) {
-  if (counts[0] > 0)
+  if (counts[0] > 0) {
     k_num_small<BS><<<(counts[0] + 3) / 4, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr, B.col,
                                                        B.val, C.rowptr, C.col, C.val);
+    // the few rows with more than 64 entries in A
+    k_num<BS, 16, 4, 64><<<(counts[0] + 3) / 4, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr,
+                                                            B.col, B.val, C.rowptr, C.col, C.val, 65);
+  }
   if (counts[1] > 0)
     k_num<BS, 64, 1, (BS == 3 ? 512 : 512)><<<counts[1], 64, 0, s>>>(counts[1], lists + (size_t)n, A.rowptr, A.col,
                                                                       A.val, B.rowptr, B.col, B.val, C.rowptr,
