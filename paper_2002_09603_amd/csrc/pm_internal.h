@@ -246,7 +246,8 @@ struct pm_ctx {
   bool hier_u_ok = false;
   // Krylov workspace
   int m_alloc = 0;
-  double* V = nullptr;       // (m+1)*N
+  int64_t ld = 0;            // distance between consecutive Krylov vectors (N rounded up to 32)
+  double* V = nullptr;       // (m+1)*ld
   double* Z = nullptr;       // m*N preconditioned vectors (FP64 preconditioner, or two-pass Gram-Schmidt)
   float* Zf = nullptr;       // m*N preconditioned vectors from the FP32 preconditioner
   int mz_alloc = 0, mzf_alloc = 0;

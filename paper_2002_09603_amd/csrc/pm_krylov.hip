@@ -22,19 +22,33 @@ constexpr int kPartRows = 504;    // rows of the partial-sum buffer (basis vecto
 // part[(i0+g)*kDotBlocks + block] = sum_chunk V_{i0+g} . w for g < cnt; with
 // self_row >= 0 also part[self_row*kDotBlocks + block] = sum_chunk w . w.
 // Workgroup sums: shuffles within each wavefront, then the 4 wavefronts in
-// order (deterministic).
-__global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, int64_t N, int i0, int cnt,
-                                                  const double* __restrict__ w, double* __restrict__ part,
+// order (deterministic).  Eight waves per SIMD so that all kDotBlocks
+// workgroups are resident at once (no second, mostly idle, round).
+__global__ void __launch_bounds__(256, 8) k_multidot(const double* __restrict__ V, int64_t N, int64_t ld, int i0,
+                                                  int cnt, const double* __restrict__ w, double* __restrict__ part,
                                                   int self_row) {
   __shared__ double sh[4][kDotGroup + 1];
   double acc[kDotGroup + 1];
   for (int g = 0; g <= kDotGroup; ++g) acc[g] = 0.0;
-  const double* Vi = V + (size_t)i0 * N;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
-    const double wk = w[k];
+  const double* Vi = V + (size_t)i0 * ld;
+  // element pairs (16-byte loads; vectors start at multiples of ld), then the odd tail
+  const int64_t np = N >> 1;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < np; q += (int64_t)gridDim.x * 256) {
+    const int64_t k = 2 * q;
+    const double2 wk = *reinterpret_cast<const double2*>(w + k);
 #pragma unroll
     for (int g = 0; g < kDotGroup; ++g)
-      if (g < cnt) acc[g] += Vi[(size_t)g * N + k] * wk;
+      if (g < cnt) {
+        const double2 v = *reinterpret_cast<const double2*>(Vi + (size_t)g * ld + k);
+        acc[g] += v.x * wk.x + v.y * wk.y;
+      }
+    acc[kDotGroup] += wk.x * wk.x + wk.y * wk.y;
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t k = N - 1;
+    const double wk = w[k];
+    for (int g = 0; g < kDotGroup; ++g)
+      if (g < cnt) acc[g] += Vi[(size_t)g * ld + k] * wk;
     acc[kDotGroup] += wk * wk;
   }
 #pragma unroll
@@ -73,23 +87,46 @@ __global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ pa
 // also part[norm_row*kDotBlocks + block] = sum_chunk w_new . w_new.  V in
 // FP64, or FP32 for the preconditioned vectors of the mixed-precision solve.
 template <class TV>
-__global__ void __launch_bounds__(256) k_multiaxpy(const TV* __restrict__ V, int64_t N, int cnt,
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
+template <class TV>
+__global__ void __launch_bounds__(256) k_multiaxpy(const TV* __restrict__ V, int64_t N, int64_t ld, int cnt,
                                                    const double* __restrict__ coef, double* __restrict__ w,
                                                    double sign, double* __restrict__ part, int norm_row) {
+  using V2 = typename Vec2<TV>::type;
   __shared__ double c[512];
   __shared__ double sh[256];
   for (int i = threadIdx.x; i < cnt; i += 256) c[i] = coef[i];
   __syncthreads();
   double nn = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
-    double s0 = 0.0, s1 = 0.0;
-    int i = 0;
-    for (; i + 1 < cnt; i += 2) {
-      s0 += c[i] * (double)V[(size_t)i * N + k];
-      s1 += c[i + 1] * (double)V[(size_t)(i + 1) * N + k];
+  const int64_t np = N >> 1;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < np; q += (int64_t)gridDim.x * 256) {
+    const int64_t k = 2 * q;
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+      const V2 v = *reinterpret_cast<const V2*>(V + (size_t)i * ld + k);
+      sx += c[i] * (double)v.x;
+      sy += c[i] * (double)v.y;
     }
-    if (i < cnt) s0 += c[i] * (double)V[(size_t)i * N + k];
-    const double wn = w[k] + sign * (s0 + s1);
+    double2 wk = *reinterpret_cast<const double2*>(w + k);
+    wk.x += sign * sx;
+    wk.y += sign * sy;
+    *reinterpret_cast<double2*>(w + k) = wk;
+    nn += wk.x * wk.x + wk.y * wk.y;
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t k = N - 1;
+    double s0 = 0.0;
+    for (int i = 0; i < cnt; ++i) s0 += c[i] * (double)V[(size_t)i * ld + k];
+    const double wn = w[k] + sign * s0;
     w[k] = wn;
     nn += wn * wn;
   }
@@ -131,8 +168,8 @@ __global__ void k_pyth_scale(const double* __restrict__ h, int nv, double* __res
 
 // v = (w - sum_i coef[i] V_i) * scale[0], optional FP32 copy vf;
 // part[norm_row*kDotBlocks + block] = sum_chunk of (w - V coef)^2 (unscaled)
-__global__ void __launch_bounds__(256) k_orth_normalize(const double* __restrict__ V, int64_t N, int cnt,
-                                                        const double* __restrict__ coef,
+__global__ void __launch_bounds__(256) k_orth_normalize(const double* __restrict__ V, int64_t N, int64_t ld,
+                                                        int cnt, const double* __restrict__ coef,
                                                         const double* __restrict__ scale,
                                                         const double* __restrict__ w, double* __restrict__ v,
                                                         float* __restrict__ vf, double* __restrict__ part,
@@ -143,19 +180,30 @@ __global__ void __launch_bounds__(256) k_orth_normalize(const double* __restrict
   __syncthreads();
   const double sc = scale[0];
   double nn = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
-    double s0 = 0.0, s1 = 0.0;
-    int i = 0;
-    for (; i + 1 < cnt; i += 2) {
-      s0 += c[i] * V[(size_t)i * N + k];
-      s1 += c[i + 1] * V[(size_t)(i + 1) * N + k];
+  const int64_t np = N >> 1;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < np; q += (int64_t)gridDim.x * 256) {
+    const int64_t k = 2 * q;
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+      const double2 x = *reinterpret_cast<const double2*>(V + (size_t)i * ld + k);
+      sx += c[i] * x.x;
+      sy += c[i] * x.y;
     }
-    if (i < cnt) s0 += c[i] * V[(size_t)i * N + k];
-    const double wn = w[k] - (s0 + s1);
+    const double2 wk = *reinterpret_cast<const double2*>(w + k);
+    const double wx = wk.x - sx, wy = wk.y - sy;
+    nn += wx * wx + wy * wy;
+    const double2 out = make_double2(wx * sc, wy * sc);
+    *reinterpret_cast<double2*>(v + k) = out;
+    if (vf) *reinterpret_cast<float2*>(vf + k) = make_float2((float)out.x, (float)out.y);
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t k = N - 1;
+    double s0 = 0.0;
+    for (int i = 0; i < cnt; ++i) s0 += c[i] * V[(size_t)i * ld + k];
+    const double wn = w[k] - s0;
     nn += wn * wn;
-    const double x = wn * sc;
-    v[k] = x;
-    if (vf) vf[k] = (float)x;
+    v[k] = wn * sc;
+    if (vf) vf[k] = (float)(wn * sc);
   }
   sh[threadIdx.x] = nn;
   __syncthreads();
@@ -207,20 +255,21 @@ int grid_for(int64_t N) { return (int)std::min<int64_t>(kDotBlocks, (N + 255) / 
 // basis V (m+1 FP64 vectors) and the preconditioned vectors: FP64 Z, or FP32
 // Zf when they come from the FP32 preconditioner (exactly representable)
 static void ensure_krylov(pm_ctx* c, int m, bool z32) {
+  c->ld = (c->N + 31) / 32 * 32;  // vectors start 256-byte aligned
   if (z32 ? (c->mzf_alloc < m || !c->Zf) : (c->mz_alloc < m || !c->Z)) {
     if (z32) {
       dfree(c->Zf);
-      c->Zf = dalloc<float>((int64_t)m * c->N);
+      c->Zf = dalloc<float>((int64_t)m * c->ld);
       c->mzf_alloc = m;
     } else {
       dfree(c->Z);
-      c->Z = dalloc<double>((int64_t)m * c->N);
+      c->Z = dalloc<double>((int64_t)m * c->ld);
       c->mz_alloc = m;
     }
   }
   if (c->m_alloc >= m && c->V) return;
   dfree(c->V);
-  c->V = dalloc<double>((int64_t)(m + 1) * c->N);
+  c->V = dalloc<double>((int64_t)(m + 1) * c->ld);
   if (!c->red) c->red = dalloc<double>((int64_t)kDotBlocks * kPartRows);
   dfree(c->hcol);
   c->hcol = dalloc<double>(3 * (m + 2) + 8);
@@ -263,12 +312,12 @@ static void cgs_pass(pm_ctx* c, int nv, double* hpass, bool self_norm) {
   for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
     const int cnt = std::min(kDotGroup, nv - i0);
     g_prof.begin(c->s, kProfMultidot);
-    k_multidot<<<gb, 256, 0, c->s>>>(c->V, N, i0, cnt, c->wvec, c->red, (self_norm && i0 == 0) ? nv : -1);
+    k_multidot<<<gb, 256, 0, c->s>>>(c->V, N, c->ld, i0, cnt, c->wvec, c->red, (self_norm && i0 == 0) ? nv : -1);
     g_prof.end(c->s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
   }
   k_dot_final<<<nv + (self_norm ? 1 : 0), 256, 0, c->s>>>(c->red, 0, nv + (self_norm ? 1 : 0), gb, hpass);
   g_prof.begin(c->s, kProfMultiaxpy);
-  k_multiaxpy<double><<<gb, 256, 0, c->s>>>(c->V, N, nv, hpass, c->wvec, -1.0, c->red, nv + 1);
+  k_multiaxpy<double><<<gb, 256, 0, c->s>>>(c->V, N, c->ld, nv, hpass, c->wvec, -1.0, c->red, nv + 1);
   g_prof.end(c->s, kProfMultiaxpy, (double)(nv + 2) * N * 8.0);
   PM_CHECK_LAUNCH();
 }
@@ -319,13 +368,14 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
     g[0] = beta;
     int jdone = 0;
     for (int j = 0; j < m && its < max_it; ++j) {
-      double* vj = c->V + (size_t)j * N;
+      const int64_t ld = c->ld;
+      double* vj = c->V + (size_t)j * ld;
       if (z32) {
-        float* zj = c->Zf + (size_t)j * N;
+        float* zj = c->Zf + (size_t)j * ld;
         apply_Minv32(c, vf, zj, transpose);
         apply_AH32(c, zj, c->wvec, transpose);
       } else {
-        double* zj = c->Z + (size_t)j * N;
+        double* zj = c->Z + (size_t)j * ld;
         apply_Minv(c, vj, zj, transpose);
         apply_AH(c, zj, c->wvec, transpose);
       }
@@ -337,14 +387,14 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
         for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
           const int cnt = std::min(kDotGroup, nv - i0);
           g_prof.begin(s, kProfMultidot);
-          k_multidot<<<gb, 256, 0, s>>>(c->V, N, i0, cnt, c->wvec, c->red, i0 == 0 ? nv : -1);
+          k_multidot<<<gb, 256, 0, s>>>(c->V, N, ld, i0, cnt, c->wvec, c->red, i0 == 0 ? nv : -1);
           g_prof.end(s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
         }
         k_dot_final<<<nv + 1, 256, 0, s>>>(c->red, 0, nv + 1, gb, h1);
         k_pyth_scale<<<1, 64, 0, s>>>(h1, nv, dev_scale);
         g_prof.begin(s, kProfMultiaxpy);
-        k_orth_normalize<<<gb, 256, 0, s>>>(c->V, N, nv, h1, dev_scale, c->wvec, c->V + (size_t)(j + 1) * N, vf,
-                                            c->red, nv + 1);
+        k_orth_normalize<<<gb, 256, 0, s>>>(c->V, N, ld, nv, h1, dev_scale, c->wvec, c->V + (size_t)(j + 1) * ld,
+                                            vf, c->red, nv + 1);
         g_prof.end(s, kProfMultiaxpy, (double)(nv + 2) * N * 8.0 + (vf ? (double)N * 4.0 : 0.0));
         k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, gb, h1);
         PM_CHECK_LAUNCH();
@@ -356,7 +406,8 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
         if (hn > 0.0 && std::isfinite(hn)) {
           const double prod = hn * sc;  // norm of the written vector
           if (std::fabs(prod - 1.0) > 1e-10) {
-            k_scale2<<<gN, kBlock, 0, s>>>(N, c->V + (size_t)(j + 1) * N, 1.0 / prod, c->V + (size_t)(j + 1) * N, vf);
+            k_scale2<<<gN, kBlock, 0, s>>>(N, c->V + (size_t)(j + 1) * ld, 1.0 / prod, c->V + (size_t)(j + 1) * ld,
+                                           vf);
             PM_CHECK_LAUNCH();
           } else {
             hn = 1.0 / sc;  // keeps A z_j = V h + hn v_{j+1} exact
@@ -373,7 +424,7 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
         PM_HIP(hipStreamSynchronize(s));
         hn = std::sqrt(c->hhost[nv + 1]);
         if (hn > 0.0 && std::isfinite(hn)) {
-          k_scale_const<<<gN, kBlock, 0, s>>>(N, c->wvec, 1.0 / hn, c->V + (size_t)(j + 1) * N);
+          k_scale_const<<<gN, kBlock, 0, s>>>(N, c->wvec, 1.0 / hn, c->V + (size_t)(j + 1) * ld);
           PM_CHECK_LAUNCH();
         }
       }
@@ -413,9 +464,9 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
     if (jdone > 0) {
       PM_HIP(hipMemcpyAsync(h2, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
       if (z32)
-        k_multiaxpy<float><<<grid_for(N), 256, 0, s>>>(c->Zf, N, jdone, h2, x, 1.0, c->red, -1);
+        k_multiaxpy<float><<<grid_for(N), 256, 0, s>>>(c->Zf, N, c->ld, jdone, h2, x, 1.0, c->red, -1);
       else
-        k_multiaxpy<double><<<grid_for(N), 256, 0, s>>>(c->Z, N, jdone, h2, x, 1.0, c->red, -1);
+        k_multiaxpy<double><<<grid_for(N), 256, 0, s>>>(c->Z, N, c->ld, jdone, h2, x, 1.0, c->red, -1);
       PM_CHECK_LAUNCH();
     }
     // true residual in FP64; restart from it if needed

@@ -49,44 +49,75 @@ __device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j,
   return true;
 }
 
-// One plane (fixed nk) of the 3x3 neighbour displacements of node (i,j,k).
-// Indices are clamped into the mesh: a neighbour outside it only belongs to
-// cells outside the mesh, whose modulus is taken as zero below.  MASK zeroes
-// Dirichlet components (zero columns of A_uu).
+// The clamped 3x3x3 node box and 2x2x2 cell box around node (i,j,k), as one
+// 64-bit base (the lower corner) plus non-negative 32-bit offsets per axis.
+// A neighbour outside the mesh is clamped onto the node itself; it only
+// belongs to cells outside the mesh, whose modulus is taken as zero.
+struct Box {
+  uint32_t nxo[3], nyo[3], nzo[3];  // node offsets (in nodes) of the lower/middle/upper neighbour
+  uint32_t cxo, cyo, czo;           // cell offset of the upper cell along each axis
+  bool inx[2], iny[2], inz[2];      // lower/upper cell inside the mesh
+  int64_t n0, c0;                   // lower-corner node and cell
+};
+
+__device__ __forceinline__ Box box_of(const Grid& G, int64_t n, int i, int j, int k) {
+  Box B;
+  const uint32_t sy = (uint32_t)G.nx + 1, sz = sy * ((uint32_t)G.ny + 1);
+  const uint32_t lx = i > 0, ly = j > 0, lz = k > 0;
+  const uint32_t hx = i < G.nx, hy = j < G.ny, hz = k < G.nz;
+  B.nxo[0] = 0;
+  B.nxo[1] = lx;
+  B.nxo[2] = lx + hx;
+  B.nyo[0] = 0;
+  B.nyo[1] = ly * sy;
+  B.nyo[2] = (ly + hy) * sy;
+  B.nzo[0] = 0;
+  B.nzo[1] = lz * sz;
+  B.nzo[2] = (lz + hz) * sz;
+  B.n0 = n - (int64_t)(B.nxo[1] + B.nyo[1] + B.nzo[1]);
+  // cells i-1 and i along x, clamped into [0, nx-1] (nx >= 1)
+  B.cxo = lx + hx - 1;
+  B.cyo = (ly + hy - 1) * (uint32_t)G.nx;
+  B.czo = (lz + hz - 1) * (uint32_t)G.nx * (uint32_t)G.ny;
+  B.c0 = G.cell(i - (int)lx, j - (int)ly, k - (int)lz);
+  B.inx[0] = lx;
+  B.inx[1] = hx;
+  B.iny[0] = ly;
+  B.iny[1] = hy;
+  B.inz[0] = lz;
+  B.inz[1] = hz;
+  return B;
+}
+
+// One plane dz of the 3x3 neighbour displacements of node (i,j,k).  MASK
+// zeroes Dirichlet components (zero columns of A_uu).
 template <class T, class TX, bool MASK>
-__device__ __forceinline__ void load_plane(const Grid& G, int kind, const TX* __restrict__ x, int i, int j, int nk,
-                                           T u[9][3]) {
-  const int kc = min(max(nk, 0), G.nz);
+__device__ __forceinline__ void load_plane(const Grid& G, int kind, const TX* __restrict__ xb, const Box& B, int dz,
+                                           int i, int j, int k, T u[9][3]) {
 #pragma unroll
   for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      const int ni = i + dx - 1, nj = j + dy - 1;
-      const int64_t nb = G.node(min(max(ni, 0), G.nx), min(max(nj, 0), G.ny), kc);
+      const TX* q = xb + 3 * (B.nxo[dx] + B.nyo[dy] + B.nzo[dz]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T v = (T)x[3 * nb + c];
-        u[dx + 3 * dy][c] = (MASK && u_fixed(G, kind, ni, nj, nk, c)) ? (T)0 : v;
+        const T v = (T)q[c];
+        u[dx + 3 * dy][c] = (MASK && u_fixed(G, kind, i + dx - 1, j + dy - 1, k + dz - 1, c)) ? (T)0 : v;
       }
     }
 }
 
-// acc += contributions of the 4 cells of layer oz around node (i,j,k); lo and
-// hi are the neighbour planes below and above that cell layer
+// acc += contributions of the 4 cells of layer oz around the node; lo and hi
+// are the neighbour planes below and above that cell layer
 template <class T>
-__device__ __forceinline__ void cell_layer(const Grid& G, const T* __restrict__ Kh, const T* __restrict__ E,
-                                           const T lo[9][3], const T hi[9][3], int oz, int i, int j, int k,
-                                           T acc[3]) {
-  const int ck = k - 1 + oz;
-  const bool kin = ck >= 0 && ck < G.nz;
-  const int ckc = min(max(ck, 0), G.nz - 1);
+__device__ __forceinline__ void cell_layer(const T* __restrict__ Kh, const T* __restrict__ Eb, const Box& B,
+                                           const T lo[9][3], const T hi[9][3], int oz, T acc[3]) {
 #pragma unroll
   for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
     for (int ox = 0; ox < 2; ++ox) {
-      const int ci = i - 1 + ox, cj = j - 1 + oy;
-      const bool in = kin && ci >= 0 && ci < G.nx && cj >= 0 && cj < G.ny;
-      const T ev = E[G.cell(min(max(ci, 0), G.nx - 1), min(max(cj, 0), G.ny - 1), ckc)];
+      const bool in = B.inz[oz] && B.iny[oy] && B.inx[ox];
+      const T ev = Eb[(ox ? B.cxo : 0u) + (oy ? B.cyo : 0u) + (oz ? B.czo : 0u)];
       const T e = in ? ev : (T)0;
       const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
 #pragma unroll
@@ -110,15 +141,17 @@ __device__ __forceinline__ void cell_layer(const Grid& G, const T* __restrict__ 
 // the neighbour planes loaded one at a time
 template <class T, class TX, bool MASK>
 __device__ __forceinline__ void lattice_rows(const Grid& G, int kind, const T* __restrict__ Kh,
-                                             const T* __restrict__ E, const TX* __restrict__ x, int i, int j, int k,
-                                             T acc[3]) {
+                                             const T* __restrict__ E, const TX* __restrict__ x, const Box& B, int i,
+                                             int j, int k, T acc[3]) {
   acc[0] = acc[1] = acc[2] = (T)0;
+  const TX* xb = x + 3 * B.n0;
+  const T* Eb = E + B.c0;
   T pa[9][3], pb[9][3];
-  load_plane<T, TX, MASK>(G, kind, x, i, j, k - 1, pa);
-  load_plane<T, TX, MASK>(G, kind, x, i, j, k, pb);
-  cell_layer<T>(G, Kh, E, pa, pb, 0, i, j, k, acc);
-  load_plane<T, TX, MASK>(G, kind, x, i, j, k + 1, pa);
-  cell_layer<T>(G, Kh, E, pb, pa, 1, i, j, k, acc);
+  load_plane<T, TX, MASK>(G, kind, xb, B, 0, i, j, k, pa);
+  load_plane<T, TX, MASK>(G, kind, xb, B, 1, i, j, k, pb);
+  cell_layer<T>(Kh, Eb, B, pa, pb, 0, acc);
+  load_plane<T, TX, MASK>(G, kind, xb, B, 2, i, j, k, pa);
+  cell_layer<T>(Kh, Eb, B, pb, pa, 1, acc);
 }
 
 // no Dirichlet component among the 27 neighbours of node (i,j,k)
@@ -133,17 +166,25 @@ template <class T>
 __device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const T* __restrict__ Kh,
                                            const T* __restrict__ E, const T* __restrict__ x, int64_t n, int i, int j,
                                            int k, T ax[3]) {
+  const Box B = box_of(G, n, i, j, k);
   if (free_neighbourhood(G, kind, i, j, k))
-    lattice_rows<T, T, false>(G, kind, Kh, E, x, i, j, k, ax);
+    lattice_rows<T, T, false>(G, kind, Kh, E, x, B, i, j, k, ax);
   else
-    lattice_rows<T, T, true>(G, kind, Kh, E, x, i, j, k, ax);
+    lattice_rows<T, T, true>(G, kind, Kh, E, x, B, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
     if (u_fixed(G, kind, i, j, k, a)) ax[a] = x[3 * n + a];
 }
 
+// Minimum waves per SIMD for the stencil kernels.  In FP64 the neighbour
+// planes in flight take about 170 vector registers, one over the limit for
+// three resident waves; capping the allocation there costs a few spilled
+// values and runs faster than two waves.
 template <class T>
-__global__ void __launch_bounds__(256) k_lat_cheb(Grid G, int kind, const T* __restrict__ Kh,
+constexpr int kLatWaves = sizeof(T) == 8 ? 3 : 1;
+
+template <class T>
+__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, int kind, const T* __restrict__ Kh,
                                                   const T* __restrict__ E, const T* __restrict__ dinv,
                                                   const T* __restrict__ b, const T* __restrict__ xin,
                                                   T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
@@ -167,7 +208,7 @@ __global__ void __launch_bounds__(256) k_lat_cheb(Grid G, int kind, const T* __r
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_lat_residual(Grid G, int kind, const T* __restrict__ Kh,
+__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_residual(Grid G, int kind, const T* __restrict__ Kh,
                                                       const T* __restrict__ E, const T* __restrict__ b,
                                                       const T* __restrict__ x, T* __restrict__ r) {
   int64_t n;
@@ -179,7 +220,7 @@ __global__ void __launch_bounds__(256) k_lat_residual(Grid G, int kind, const T*
   for (int a = 0; a < 3; ++a) r[3 * n + a] = b[3 * n + a] - ax[a];
 }
 
-__global__ void __launch_bounds__(256) k_lat_apply(Grid G, int kind, const double* __restrict__ Kh,
+__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_apply(Grid G, int kind, const double* __restrict__ Kh,
                                                    const double* __restrict__ E, const double* __restrict__ x,
                                                    double* __restrict__ y) {
   int64_t n;
@@ -194,7 +235,7 @@ __global__ void __launch_bounds__(256) k_lat_apply(Grid G, int kind, const doubl
 // u-rows of A_H (sgn = +1) or A_H^T (sgn = -1): A_uu u + sgn A_up p on free
 // rows, in FP64 from FP64 or FP32 inputs
 template <class TX>
-__global__ void __launch_bounds__(256) k_lat_ah_u(Grid G, int kind, const double* __restrict__ Kh,
+__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_ah_u(Grid G, int kind, const double* __restrict__ Kh,
                                                   const double* __restrict__ ah, const double* __restrict__ E,
                                                   const TX* __restrict__ u, const TX* __restrict__ p, double sgn,
                                                   double* __restrict__ y) {
@@ -202,20 +243,22 @@ __global__ void __launch_bounds__(256) k_lat_ah_u(Grid G, int kind, const double
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   double acc[3];
+  const Box B = box_of(G, n, i, j, k);
   if (free_neighbourhood(G, kind, i, j, k))
-    lattice_rows<double, TX, false>(G, kind, Kh, E, u, i, j, k, acc);
+    lattice_rows<double, TX, false>(G, kind, Kh, E, u, B, i, j, k, acc);
   else
-    lattice_rows<double, TX, true>(G, kind, Kh, E, u, i, j, k, acc);
+    lattice_rows<double, TX, true>(G, kind, Kh, E, u, B, i, j, k, acc);
   double cp[3] = {0.0, 0.0, 0.0};
+  const TX* pb = p + B.c0;
 #pragma unroll
   for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
     for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
       for (int ox = 0; ox < 2; ++ox) {
-        const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
-        if (ci < 0 || ci >= G.nx || cj < 0 || cj >= G.ny || ck < 0 || ck >= G.nz) continue;
-        const double pc = (double)p[G.cell(ci, cj, ck)];
+        const bool in = B.inz[oz] && B.iny[oy] && B.inx[ox];
+        const double pv = (double)pb[(ox ? B.cxo : 0u) + (oy ? B.cyo : 0u) + (oz ? B.czo : 0u)];
+        const double pc = in ? pv : 0.0;
         const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
 #pragma unroll
         for (int d = 0; d < 3; ++d) cp[d] += ah[3 * a + d] * pc;
