@@ -44,31 +44,33 @@ __device__ inline bool face_of_thread(const Grid& G, int64_t& f) {
   return f < G.nf;
 }
 
-// (C~_pi x)_f over the free columns of the free row f
+// (C~_pi x)_f over the free columns of the free row f, f at (i,j,k) of
+// orientation O.  The packed-matrix entry of each term is a compile-time
+// row of C, so every load is a wave-uniform base plus a 32-bit offset.
+template <int O, class T>
+__device__ __forceinline__ T cpi_row_o(const Grid& G, uint32_t i, uint32_t j, uint32_t k, const T* __restrict__ C,
+                                       const T* __restrict__ x) {
+  T acc = (T)0;
+  const uint32_t top = (uint32_t)G.nz - 1;
+  visit_face_cells<O>(G, i, j, k, [&](auto lc, uint32_t c, const uint32_t F[6], uint32_t ck) {
+    constexpr int l = decltype(lc)::value;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const T v = ld32(C + (size_t)sym6(l < e ? l : e, l < e ? e : l) * G.nc, c) * ld32(x, F[e]);
+      if (e != 5 || ck != top) acc += v;  // the top face of the top layer is a zero column
+    }
+  });
+  return acc;
+}
+
 template <class T>
 __device__ __forceinline__ T cpi_cells_row(const Grid& G, int64_t f, const T* __restrict__ C,
                                            const T* __restrict__ x) {
-  int64_t cc[2];
-  int lf[2];
-  G.face_cells(f, cc, lf);
-  T acc = (T)0;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int64_t c = cc[s];
-    if (c < 0) continue;
-    int i, j, k;
-    G.cell_ijk(c, i, j, k);
-    int64_t F[6];
-    G.cell_faces(i, j, k, F);
-    const int l = lf[s];
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      if (pi_fixed_local(G, k, e)) continue;
-      const int a = l < e ? l : e, b = l < e ? e : l;
-      acc += C[(size_t)sym6(a, b) * G.nc + c] * x[F[e]];
-    }
-  }
-  return acc;
+  uint32_t i, j, k;
+  const int o = face_pos(G, (uint32_t)f, i, j, k);
+  if (o == 0) return cpi_row_o<0, T>(G, i, j, k, C, x);
+  if (o == 1) return cpi_row_o<1, T>(G, i, j, k, C, x);
+  return cpi_row_o<2, T>(G, i, j, k, C, x);
 }
 
 template <class T>

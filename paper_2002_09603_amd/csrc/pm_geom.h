@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "poromech.h"
 
@@ -124,6 +125,73 @@ __host__ __device__ inline bool pi_fixed_local(const Grid& G, int k, int e) { re
 // packed index of (a, b), a <= b, in the row-major upper triangle of a
 // symmetric 6x6 matrix (21 entries)
 __host__ __device__ inline int sym6(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
+
+// base[idx] through a 32-bit byte offset from a (typically wave-uniform)
+// base; valid for arrays of fewer than 2^32 bytes, which the set-up size
+// limits guarantee for every per-node, per-cell and per-face array.
+template <class T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+
+// Faces of cell (ci,cj,ck) in 32-bit arithmetic, local order (-x,+x,-y,+y,-z,+z).
+__device__ __forceinline__ void cell_faces32(const Grid& G, uint32_t ci, uint32_t cj, uint32_t ck, uint32_t F[6]) {
+  const uint32_t nx = (uint32_t)G.nx, ny = (uint32_t)G.ny;
+  F[0] = ci + (nx + 1) * (cj + ny * ck);
+  F[1] = F[0] + 1;
+  F[2] = (uint32_t)G.nfx + ci + nx * (cj + (ny + 1) * ck);
+  F[3] = F[2] + nx;
+  F[4] = (uint32_t)(G.nfx + G.nfy) + ci + nx * (cj + ny * ck);
+  F[5] = F[4] + nx * ny;
+}
+
+// Position (i,j,k) of face f within its orientation (0: x, 1: y, 2: z).
+__device__ __forceinline__ int face_pos(const Grid& G, uint32_t f, uint32_t& i, uint32_t& j, uint32_t& k) {
+  const uint32_t nx = (uint32_t)G.nx, ny = (uint32_t)G.ny;
+  if (f < (uint32_t)G.nfx) {
+    const uint32_t r = G.dnx1.div(f);
+    i = f - r * (nx + 1);
+    k = G.dny.div(r);
+    j = r - k * ny;
+    return 0;
+  }
+  if (f < (uint32_t)(G.nfx + G.nfy)) {
+    const uint32_t u = f - (uint32_t)G.nfx, r = G.dnx.div(u);
+    i = u - r * nx;
+    k = G.dny1.div(r);
+    j = r - k * (ny + 1);
+    return 1;
+  }
+  const uint32_t u = f - (uint32_t)(G.nfx + G.nfy), r = G.dnx.div(u);
+  i = u - r * nx;
+  k = G.dny.div(r);
+  j = r - k * ny;
+  return 2;
+}
+
+template <int L>
+using LocalFace = std::integral_constant<int, L>;
+
+// Calls fn(LocalFace<l>{}, c, F, ck) for each cell c adjacent to the face at
+// (i,j,k) of orientation O, where l is the face's local index in c (a
+// compile-time constant), F the six faces of c and ck its layer.
+template <int O, class Fn>
+__device__ __forceinline__ void visit_face_cells(const Grid& G, uint32_t i, uint32_t j, uint32_t k, Fn&& fn) {
+  const uint32_t pos = O == 0 ? i : (O == 1 ? j : k);
+  const uint32_t lim = (uint32_t)(O == 0 ? G.nx : (O == 1 ? G.ny : G.nz));
+  const uint32_t nx = (uint32_t)G.nx, ny = (uint32_t)G.ny;
+  if (pos > 0) {
+    const uint32_t ci = i - (O == 0), cj = j - (O == 1), ck = k - (O == 2);
+    uint32_t F[6];
+    cell_faces32(G, ci, cj, ck, F);
+    fn(LocalFace<2 * O + 1>{}, ci + nx * (cj + ny * ck), F, ck);
+  }
+  if (pos < lim) {
+    uint32_t F[6];
+    cell_faces32(G, i, j, k, F);
+    fn(LocalFace<2 * O>{}, i + nx * (j + ny * k), F, k);
+  }
+}
 
 // Workgroups are dispatched to the 8 XCDs round-robin; this maps workgroup b
 // of nb so that each XCD runs one contiguous range of logical workgroups

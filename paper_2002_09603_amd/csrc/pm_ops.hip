@@ -19,7 +19,7 @@ namespace {
 struct AeCells {
   const double* ae;
   int64_t nc;
-  __device__ double operator()(int q, int64_t c) const { return ae[(size_t)q * nc + c]; }
+  __device__ double operator()(int q, int64_t c) const { return ld32(ae + (size_t)q * nc, (uint32_t)c); }
 };
 struct AeLattice {
   const double* ah;
@@ -59,44 +59,76 @@ __global__ void __launch_bounds__(256) k_ah_u(Grid G, int n, const int* __restri
 
 // p-rows: y_p = su * sum a_T u + (S|T| + dt alpha) p + A_stab p + spi * sum_e (-g_e) pi_e
 //   A_H:   su = -1, spi = dt      A_H^T: su = +1, spi = 1
+// Dirichlet columns follow u_fixed / pi_fixed_local (the rule the masks are
+// built from); all indices are 32-bit offsets from wave-uniform bases.
 template <class T, class AE>
-__global__ void k_ah_p(Grid G, AE ae, const double* __restrict__ vol,
-                       const double* __restrict__ alpha, const double* __restrict__ gv,
-                       const double* __restrict__ stabw, const uint8_t* __restrict__ ufix,
-                       const uint8_t* __restrict__ pifix, const T* __restrict__ u, const T* __restrict__ p,
-                       const T* __restrict__ pi, double S, double dt, int stabilize, double su, double spi,
-                       double* __restrict__ y) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= G.nc) return;
+__global__ void __launch_bounds__(256) k_ah_p(Grid G, int kind, AE ae, const double* __restrict__ vol,
+                                              const double* __restrict__ alpha, const double* __restrict__ gv,
+                                              const double* __restrict__ stabw, const T* __restrict__ u,
+                                              const T* __restrict__ p, const T* __restrict__ pi, double S,
+                                              double dt, int stabilize, double su, double spi,
+                                              double* __restrict__ y) {
+  const int64_t c64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c64 >= G.nc) return;
+  const uint32_t c = (uint32_t)c64;
   int i, j, k;
-  G.cell_ijk(c, i, j, k);
+  G.cell_ijk(c64, i, j, k);
+  const uint32_t sy = (uint32_t)G.nx + 1, sz = sy * ((uint32_t)G.ny + 1);
+  const uint32_t n0 = (uint32_t)i + sy * (uint32_t)j + sz * (uint32_t)k;
   double v = 0.0;
+#pragma unroll
   for (int a = 0; a < 8; ++a) {
-    const int64_t n = G.node(i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    const uint32_t n = n0 + (uint32_t)ax + (ay ? sy : 0u) + (az ? sz : 0u);
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const size_t q = 3 * (size_t)n + d;
-      if (!ufix[q]) v += ae(3 * a + d, c) * (double)u[q];
+      const double t = ae(3 * a + d, c) * (double)ld32(u, 3 * n + d);
+      if (!u_fixed(G, kind, i + ax, j + ay, k + az, d)) v += t;
     }
   }
   v *= su;
-  const double pc = (double)p[c];
-  v += (S * vol[c] + dt * alpha[c]) * pc;
+  const double pc = (double)ld32(p, c);
+  v += (S * ld32(vol, c) + dt * ld32(alpha, c)) * pc;
   if (stabilize) {
-    const double w = stabw[G.macro(i, j, k)];
-    v += w * ((pc - (double)p[G.cell(i ^ 1, j, k)]) + (pc - (double)p[G.cell(i, j ^ 1, k)]) +
-              (pc - (double)p[G.cell(i, j, k ^ 1)]));
+    const uint32_t nx = (uint32_t)G.nx, nxy = nx * (uint32_t)G.ny;
+    const uint32_t mx = nx >> 1, my = (uint32_t)G.ny >> 1;
+    const double w = ld32(stabw, ((uint32_t)i >> 1) + mx * (((uint32_t)j >> 1) + my * ((uint32_t)k >> 1)));
+    // partners in the 2x2x2 macro-element: cells (i^1,j,k), (i,j^1,k), (i,j,k^1)
+    const uint32_t cx = (i & 1) ? c - 1 : c + 1, cy = (j & 1) ? c - nx : c + nx, cz = (k & 1) ? c - nxy : c + nxy;
+    v += w * ((pc - (double)ld32(p, cx)) + (pc - (double)ld32(p, cy)) + (pc - (double)ld32(p, cz)));
   }
-  int64_t F[6];
-  G.cell_faces(i, j, k, F);
+  uint32_t F[6];
+  cell_faces32(G, (uint32_t)i, (uint32_t)j, (uint32_t)k, F);
   double t = 0.0;
-  for (int e = 0; e < 6; ++e)
-    if (!pifix[F[e]]) t -= gv[(size_t)e * G.nc + c] * (double)pi[F[e]];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const double q = ld32(gv + (size_t)e * G.nc, c) * (double)ld32(pi, F[e]);
+    if (!pi_fixed_local(G, k, e)) t -= q;
+  }
   y[c] = v + spi * t;
 }
 
 // pi-rows: y_pi = sp * sum_T (-g_T[lf]) p_T + sum_T M_T^-1 pi_T (free faces);  fixed: y = pi
 //   A_H: sp = 1    A_H^T: sp = dt
 // M_T^-1 is read from its packed upper triangle (21 values per cell).
+template <int O, class T>
+__device__ __forceinline__ double ah_pi_row(const Grid& G, uint32_t i, uint32_t j, uint32_t k,
+                                            const double* __restrict__ Mp, const double* __restrict__ gv,
+                                            const T* __restrict__ p, const T* __restrict__ pi, double sp) {
+  double v = 0.0;
+  const uint32_t top = (uint32_t)G.nz - 1;
+  visit_face_cells<O>(G, i, j, k, [&](auto lc, uint32_t c, const uint32_t F[6], uint32_t ck) {
+    constexpr int l = decltype(lc)::value;
+    v -= sp * ld32(gv + (size_t)l * G.nc, c) * (double)ld32(p, c);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const double t = ld32(Mp + (size_t)sym6(l < e ? l : e, l < e ? e : l) * G.nc, c) * (double)ld32(pi, F[e]);
+      if (e != 5 || ck != top) v += t;  // the top face of the top layer is a zero column
+    }
+  });
+  return v;
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_ah_pi(Grid G, const double* __restrict__ Mp,
                                                const double* __restrict__ gv, const T* __restrict__ p,
@@ -107,26 +139,15 @@ __global__ void __launch_bounds__(256) k_ah_pi(Grid G, const double* __restrict_
     y[f] = (double)pi[f];
     return;
   }
-  int64_t cc[2];
-  int lf[2];
-  G.face_cells(f, cc, lf);
-  double v = 0.0;
-  for (int s = 0; s < 2; ++s) {
-    const int64_t c = cc[s];
-    if (c < 0) continue;
-    int i, j, k;
-    G.cell_ijk(c, i, j, k);
-    int64_t F[6];
-    G.cell_faces(i, j, k, F);
-    const int l = lf[s];
-    v -= sp * gv[(size_t)l * G.nc + c] * (double)p[c];
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      if (pi_fixed_local(G, k, e)) continue;
-      const int a = l < e ? l : e, b = l < e ? e : l;
-      v += Mp[(size_t)sym6(a, b) * G.nc + c] * (double)pi[F[e]];
-    }
-  }
+  uint32_t i, j, k;
+  const int o = face_pos(G, (uint32_t)f, i, j, k);
+  double v;
+  if (o == 0)
+    v = ah_pi_row<0, T>(G, i, j, k, Mp, gv, p, pi, sp);
+  else if (o == 1)
+    v = ah_pi_row<1, T>(G, i, j, k, Mp, gv, p, pi, sp);
+  else
+    v = ah_pi_row<2, T>(G, i, j, k, Mp, gv, p, pi, sp);
   y[f] = v;
 }
 
@@ -143,41 +164,60 @@ __global__ void k_pack_minv(Grid G, const double* __restrict__ Minv, double* __r
 // preconditioner pieces -------------------------------------------------------
 // z_p = (r_p - dt A_ppi z_pi) / B~_p
 template <class T>
-__global__ void k_prec_p(Grid G, const double* __restrict__ gv, const double* __restrict__ bp,
-                         const uint8_t* __restrict__ pifix, const T* __restrict__ rp, const T* __restrict__ zpi,
-                         double dt, T* __restrict__ zp) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= G.nc) return;
+__global__ void __launch_bounds__(256) k_prec_p(Grid G, const double* __restrict__ gv, const double* __restrict__ bp,
+                                                const T* __restrict__ rp, const T* __restrict__ zpi, double dt,
+                                                T* __restrict__ zp) {
+  const int64_t c64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c64 >= G.nc) return;
+  const uint32_t c = (uint32_t)c64;
   int i, j, k;
-  G.cell_ijk(c, i, j, k);
-  int64_t F[6];
-  G.cell_faces(i, j, k, F);
+  G.cell_ijk(c64, i, j, k);
+  uint32_t F[6];
+  cell_faces32(G, (uint32_t)i, (uint32_t)j, (uint32_t)k, F);
   double t = 0.0;
-  for (int e = 0; e < 6; ++e)
-    if (!pifix[F[e]]) t -= gv[(size_t)e * G.nc + c] * (double)zpi[F[e]];
-  zp[c] = (T)(((double)rp[c] - dt * t) / bp[c]);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const double q = ld32(gv + (size_t)e * G.nc, c) * (double)ld32(zpi, F[e]);
+    if (!pi_fixed_local(G, k, e)) t -= q;
+  }
+  zp[c] = (T)(((double)ld32(rp, c) - dt * t) / ld32(bp, c));
 }
 
 // t_u = r_u - A_up z_p
 template <class T, class AE>
-__global__ void k_prec_u(Grid G, AE ae, const uint8_t* __restrict__ ufix,
-                         const T* __restrict__ ru, const T* __restrict__ zp, T* __restrict__ tu) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= G.nn) return;
+__global__ void __launch_bounds__(256) k_prec_u(Grid G, int kind, AE ae, const T* __restrict__ ru,
+                                                const T* __restrict__ zp, T* __restrict__ tu) {
+  const int64_t n64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n64 >= G.nn) return;
+  const uint32_t n = (uint32_t)n64;
   int i, j, k;
-  G.node_ijk(n, i, j, k);
+  G.node_ijk(n64, i, j, k);
+  // the (up to 8) cells around the node, clamped into the mesh; cells
+  // outside it take p = 0
+  const uint32_t nx = (uint32_t)G.nx, nxy = nx * (uint32_t)G.ny;
+  const bool lx = i > 0, ly = j > 0, lz = k > 0, hx = i < G.nx, hy = j < G.ny, hz = k < G.nz;
+  const uint32_t c0 = (uint32_t)(i - lx) + nx * (uint32_t)(j - ly) + nxy * (uint32_t)(k - lz);
+  const uint32_t cxo = (uint32_t)(lx + hx - 1), cyo = (uint32_t)(ly + hy - 1) * nx,
+                 czo = (uint32_t)(lz + hz - 1) * nxy;
   double cp[3] = {0.0, 0.0, 0.0};
-  for (int ck = max(k - 1, 0); ck <= min(k, G.nz - 1); ++ck)
-    for (int cj = max(j - 1, 0); cj <= min(j, G.ny - 1); ++cj)
-      for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
-        const int64_t c = G.cell(ci, cj, ck);
-        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
-        const double pc = (double)zp[c];
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const bool in = (oz ? hz : lz) && (oy ? hy : ly) && (ox ? hx : lx);
+        const uint32_t c = c0 + (ox ? cxo : 0u) + (oy ? cyo : 0u) + (oz ? czo : 0u);
+        const double pv = (double)ld32(zp, c);
+        const double pc = in ? pv : 0.0;
+        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+#pragma unroll
         for (int d = 0; d < 3; ++d) cp[d] += ae(3 * a + d, c) * pc;
       }
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const size_t q = 3 * (size_t)n + d;
-    tu[q] = (T)((double)ru[q] - (ufix[q] ? 0.0 : cp[d]));
+    const uint32_t q = 3 * n + d;
+    tu[q] = (T)((double)ld32(ru, q) - (u_fixed(G, kind, i, j, k, d) ? 0.0 : cp[d]));
   }
 }
 
@@ -406,13 +446,13 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
   }
   const double su = transpose ? 1.0 : -1.0, spi = transpose ? 1.0 : c->dt;
   if (c->lat.on)
-    k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, AeLattice{c->lat.ah}, c->vol, c->alpha, c->g, c->stabw,
-                                                     c->ufix, c->pifix, u, p, pi, c->S, c->dt, c->opts.stabilize,
-                                                     su, spi, yp);
+    k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->bc_kind, AeLattice{c->lat.ah}, c->vol, c->alpha, c->g,
+                                                     c->stabw, u, p, pi, c->S, c->dt, c->opts.stabilize, su, spi,
+                                                     yp);
   else
-    k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, AeCells{c->ae, G.nc}, c->vol, c->alpha, c->g, c->stabw,
-                                                     c->ufix, c->pifix, u, p, pi, c->S, c->dt, c->opts.stabilize,
-                                                     su, spi, yp);
+    k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->bc_kind, AeCells{c->ae, G.nc}, c->vol, c->alpha, c->g,
+                                                     c->stabw, u, p, pi, c->S, c->dt, c->opts.stabilize, su, spi,
+                                                     yp);
   k_ah_pi<T><<<blocks_for(G.nf), kBlock, 0, c->s>>>(G, c->Mp, c->g, p, pi, transpose ? c->dt : 1.0, ypi);
   PM_CHECK_LAUNCH();
 }
@@ -449,11 +489,11 @@ static void prec_apply_t(pm_ctx* c, const T* r, T* z, T* tmp, bool transpose) {
   };
   if (!transpose) {
     vc(c->Hpi, rpi, zpi);
-    k_prec_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->g, c->bp, c->pifix, rp, zpi, c->dt, zp);
+    k_prec_p<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->g, c->bp, rp, zpi, c->dt, zp);
     if (c->lat.on)
-      k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, AeLattice{c->lat.ah}, c->ufix, ru, zp, tmp);
+      k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, c->bc_kind, AeLattice{c->lat.ah}, ru, zp, tmp);
     else
-      k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, AeCells{c->ae, G.nc}, c->ufix, ru, zp, tmp);
+      k_prec_u<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, c->bc_kind, AeCells{c->ae, G.nc}, ru, zp, tmp);
     PM_CHECK_LAUNCH();
     vc(c->Hu, tmp, zu);
   } else {
