@@ -164,6 +164,113 @@ void launch_mis_max(hipStream_t s, const Csr& A, const uint8_t* strong, const ui
   PM_CHECK_LAUNCH();
 }
 
+// Finest levels on the structured mesh: the strong neighbours of a row as a
+// bit mask over its stencil slots, so that each independent-set pass reads 4
+// bytes per row (plus the neighbours' tuples, mostly from cache) instead of
+// the CSR columns and strength flags.  The strong graph, and so the result
+// of the rounds, is the same as on the CSR.
+//   A_uu (node graph): slot (dk+1)*9 + (dj+1)*3 + (di+1) of neighbour (di,dj,dk).
+//   C~_pi (face graph): slot 6*s + e = local face e of the cell on side s of
+//   the face (s = 0: the cell below/left of it, 1: above/right).
+__global__ void k_mask_nodes(Grid G, const int* __restrict__ rp, const int* __restrict__ col,
+                             const uint8_t* __restrict__ strong, uint32_t* __restrict__ mask, int* __restrict__ bad) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return;
+  int i, j, k;
+  G.node_ijk(n, i, j, k);
+  uint32_t m = 0;
+  for (int e = rp[n]; e < rp[n + 1]; ++e) {
+    if (strong[e] != 1) continue;
+    int a, b, c;
+    G.node_ijk(col[e], a, b, c);
+    const int di = a - i, dj = b - j, dk = c - k;
+    if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1) {
+      *bad = 1;
+      continue;
+    }
+    m |= 1u << ((dk + 1) * 9 + (dj + 1) * 3 + (di + 1));
+  }
+  mask[n] = m;
+}
+
+__global__ void __launch_bounds__(256) k_mis_max_nodes(Grid G, const uint32_t* __restrict__ mask,
+                                                       const uint64_t* __restrict__ Tin,
+                                                       uint64_t* __restrict__ Tout) {
+  const int64_t n64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n64 >= G.nn) return;
+  const uint32_t n = (uint32_t)n64;
+  const int sy = G.nx + 1, sz = (G.nx + 1) * (G.ny + 1);
+  const uint32_t bits = mask[n];
+  uint64_t m = Tin[n];
+#pragma unroll
+  for (int b = 0; b < 27; ++b) {
+    if (b == 13 || !((bits >> b) & 1u)) continue;
+    const int off = (b % 3 - 1) + (b / 3 % 3 - 1) * sy + (b / 9 - 1) * sz;
+    const uint64_t v = ld32(Tin, (uint32_t)((int)n + off));
+    m = v > m ? v : m;
+  }
+  Tout[n] = m;
+}
+
+// the (up to 12) faces of the two cells on either side of face f; absent
+// cells give UINT32_MAX
+__device__ inline void face_slots(const Grid& G, uint32_t f, uint32_t S[12]) {
+  uint32_t i, j, k;
+  const int o = face_pos(G, f, i, j, k);
+#pragma unroll
+  for (int q = 0; q < 12; ++q) S[q] = 0xFFFFFFFFu;
+  auto fill = [&](auto lc, uint32_t, const uint32_t F[6], uint32_t) {
+    constexpr int side = (decltype(lc)::value & 1) ? 0 : 1;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) S[6 * side + e] = F[e];
+  };
+  if (o == 0)
+    visit_face_cells<0>(G, i, j, k, fill);
+  else if (o == 1)
+    visit_face_cells<1>(G, i, j, k, fill);
+  else
+    visit_face_cells<2>(G, i, j, k, fill);
+}
+
+__global__ void k_mask_faces(Grid G, const int* __restrict__ rp, const int* __restrict__ col,
+                             const uint8_t* __restrict__ strong, uint32_t* __restrict__ mask, int* __restrict__ bad) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  uint32_t S[12];
+  face_slots(G, (uint32_t)f, S);
+  uint32_t m = 0;
+  for (int e = rp[f]; e < rp[f + 1]; ++e) {
+    if (strong[e] != 1) continue;
+    const uint32_t g = (uint32_t)col[e];
+    uint32_t hit = 0;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) hit |= (S[q] == g ? 1u : 0u) << q;
+    if (!hit) *bad = 1;
+    m |= hit;
+  }
+  mask[f] = m;
+}
+
+__global__ void __launch_bounds__(256) k_mis_max_faces(Grid G, const uint32_t* __restrict__ mask,
+                                                       const uint64_t* __restrict__ Tin,
+                                                       uint64_t* __restrict__ Tout) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  const uint32_t bits = mask[f];
+  uint64_t m = Tin[f];
+  if (bits) {
+    uint32_t S[12];
+    face_slots(G, (uint32_t)f, S);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      if (!((bits >> q) & 1u)) continue;
+      const uint64_t v = ld32(Tin, S[q]);
+      m = v > m ? v : m;
+    }
+  }
+  Tout[f] = m;
+}
+
 __global__ void k_mis_update(int n, const uint64_t* __restrict__ T0, const uint64_t* __restrict__ T2,
                              uint8_t* __restrict__ state, int* __restrict__ und) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -872,8 +979,11 @@ void dense_inverse(hipStream_t s, const Csr& A, Hierarchy& H) {
   if (st) throw Error(PM_EBREAKDOWN, "AMG: coarsest operator is not positive definite");
 }
 
+// SG: the structured mesh when A is the finest level of the A_uu (nodes) or
+// C~_pi (faces) hierarchy, else nullptr
 template <int BS>
-void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, int* nagg_out, uint8_t* strong) {
+void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, int* nagg_out, uint8_t* strong,
+               const Grid* SG) {
   const int n = A.n;
   double* dn = dalloc<double>(n);
   uint8_t* state = dalloc<uint8_t>(n);
@@ -884,11 +994,36 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
   k_diag_norm<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, dn);
   k_strength<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, dn, theta, strong, state);
   PM_CHECK_LAUNCH();
+  uint32_t* mask = nullptr;
+  if (SG) {
+    mask = dalloc<uint32_t>(n);
+    PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
+    if (BS == 3)
+      k_mask_nodes<<<blocks_for(n), kBlock, 0, s>>>(*SG, A.rowptr, A.col, strong, mask, und);
+    else
+      k_mask_faces<<<blocks_for(n), kBlock, 0, s>>>(*SG, A.rowptr, A.col, strong, mask, und);
+    PM_CHECK_LAUNCH();
+    int bad = 0;
+    PM_HIP(hipMemcpyAsync(&bad, und, sizeof(int), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (bad) {  // a strong column outside the stencil: use the CSR rounds
+      dfree(mask);
+      mask = nullptr;
+    }
+  }
+  auto mis_pass = [&](const uint64_t* Tin, uint64_t* Tout) {
+    if (!mask)
+      launch_mis_max(s, A, strong, Tin, Tout);
+    else if (BS == 3)
+      k_mis_max_nodes<<<blocks_for(n), kBlock, 0, s>>>(*SG, mask, Tin, Tout);
+    else
+      k_mis_max_faces<<<blocks_for(n), kBlock, 0, s>>>(*SG, mask, Tin, Tout);
+  };
   for (int round = 0; round < 1000; ++round) {
     PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
     k_mis_init<<<blocks_for(n), kBlock, 0, s>>>(n, state, 0x12345u, T0);
-    launch_mis_max(s, A, strong, T0, T1);
-    if (dist == 2) launch_mis_max(s, A, strong, T1, T2);
+    mis_pass(T0, T1);
+    if (dist == 2) mis_pass(T1, T2);
     k_mis_update<<<blocks_for(n), kBlock, 0, s>>>(n, T0, dist == 2 ? T2 : T1, state, und);
     PM_CHECK_LAUNCH();
     int h = 0;
@@ -911,20 +1046,20 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
   PM_HIP(hipMemcpyAsync(&st, und, sizeof(int), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
   for (void* p : {(void*)dn, (void*)state, (void*)T0, (void*)T1, (void*)T2, (void*)und,
-                  (void*)flags, (void*)root_id, (void*)agg1})
+                  (void*)flags, (void*)root_id, (void*)agg1, (void*)mask})
     dfree(p);
   if (st) throw Error(PM_EINTERNAL, "AMG: aggregation left a connected node unassigned");
   *nagg_out = nagg;
 }
 
 template <int BS>
-void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Acoarse) {
+void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Acoarse, const Grid* SG) {
   const Csr& A = L.A;
   const int n = A.n;
   int* agg = dalloc<int>(n);
   uint8_t* strong = dalloc<uint8_t>(A.nnzb);
   int nagg = 0;
-  aggregate<BS>(s, A, prm.theta, prm.agg_dist, agg, &nagg, strong);
+  aggregate<BS>(s, A, prm.theta, prm.agg_dist, agg, &nagg, strong, SG);
   // tentative prolongator
   Csr Pt;
   Pt.bs = BS;
@@ -1230,10 +1365,13 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
               (long long)L.A.nnzb, (double)L.A.nnzb / std::max(1, L.n), L.lmax);
     Csr Ac;
     const auto tl0 = std::chrono::steady_clock::now();
+    // the finest level of either hierarchy is the structured node or face graph
+    const Grid* sg =
+        (l == 0 && G && ((L.bs == 3 && L.n == G->nn) || (L.bs == 1 && L.n == G->nf))) ? G : nullptr;
     if (L.bs == 3)
-      build_level_transfer<3>(s, L, prm, Ac);
+      build_level_transfer<3>(s, L, prm, Ac, sg);
     else
-      build_level_transfer<1>(s, L, prm, Ac);
+      build_level_transfer<1>(s, L, prm, Ac, sg);
     if (verbose) {
       PM_HIP(hipStreamSynchronize(s));
       fprintf(stderr, "[amg bs=%d] level %d transfer + Galerkin product: %.3f s\n", L.bs, l,
