@@ -14,6 +14,7 @@
 //  cycle: V(k,k) with Chebyshev(D^-1 A) smoothing (same polynomial before and
 //  after, so the cycle is a symmetric operator and serves M^T as well).
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 
@@ -80,39 +81,97 @@ __device__ inline double block_norm(const double* v) {
   return sqrt(s);
 }
 
+// Norms of the stored blocks for strength and aggregation.  3x3 blocks:
+// computed once per entry into an array (one thread per block, coalesced),
+// since three passes over the rows need them; scalars: |a| on the fly.
+template <int BS>
+struct BlockNorms {
+  const double* p;  // BS == 3: per-entry norms; BS == 1: the values
+  __device__ double operator()(int64_t e) const {
+    if constexpr (BS == 1)
+      return block_norm<1>(p + e);
+    else
+      return p[e];
+  }
+};
+
+template <int BS>
+__global__ void k_block_norms(int64_t nnzb, const double* __restrict__ val, double* __restrict__ nrm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnzb) nrm[e] = block_norm<BS>(val + (size_t)e * BS * BS);
+}
+
 // strength: strong[e] = 1 for off-diagonal |A_ij| >= theta sqrt(|A_ii||A_jj|), |A_ij| > 0;
 // kZeroBlock for a stored block that is exactly zero (weak, but dropping it
 // does not change the operator); 0 for the other weak couplings
 constexpr uint8_t kZeroBlock = 2;
-template <int BS>
-__global__ void k_diag_norm(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                            const double* __restrict__ val, double* __restrict__ dn) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// The row kernels of strength and aggregation run G lanes per row (entries
+// strided over the lanes, contiguous loads) and combine the lanes with
+// shuffles; the results equal those of a sequential pass over each row.
+template <int BS, int G>
+__global__ void __launch_bounds__(256) k_diag_norm(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                   BlockNorms<BS> nv, double* __restrict__ dn) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
   double v = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (col[e] == i) v = block_norm<BS>(val + (size_t)e * BS * BS);
-  dn[i] = v;
+  if (i < n)
+    for (int e = rp[i] + l; e < rp[i + 1]; e += G)
+      if (col[e] == i) v = nv(e);
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));  // one lane holds the (>= 0) norm
+  if (i < n && l == 0) dn[i] = v;
 }
 
-template <int BS>
-__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                           const double* __restrict__ val, const double* __restrict__ dn, double theta,
-                           uint8_t* __restrict__ strong, uint8_t* __restrict__ state) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+template <int BS, int G>
+__global__ void __launch_bounds__(256) k_strength(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                  BlockNorms<BS> nv, const double* __restrict__ dn, double theta,
+                                                  uint8_t* __restrict__ strong, uint8_t* __restrict__ state) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
   int ns = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const int j = col[e];
-    uint8_t s = 0;
-    if (j != i) {
-      const double a = block_norm<BS>(val + (size_t)e * BS * BS);
-      s = a == 0.0 ? kZeroBlock : (a >= theta * sqrt(dn[i] * dn[j]) ? 1 : 0);
+  if (i < n) {
+    const double di = dn[i];
+    for (int e = rp[i] + l; e < rp[i + 1]; e += G) {
+      const int j = col[e];
+      uint8_t sv = 0;
+      if (j != i) {
+        const double a = nv(e);
+        sv = a == 0.0 ? kZeroBlock : (a >= theta * sqrt(di * dn[j]) ? 1 : 0);
+      }
+      strong[e] = sv;
+      ns += sv == 1;
     }
-    strong[e] = s;
-    ns += s == 1;
   }
-  state[i] = ns > 0 ? kUnd : kOut;  // isolated rows (e.g. Dirichlet) are never aggregated
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) ns += __shfl_xor(ns, o, G);
+  if (i < n && l == 0) state[i] = ns > 0 ? kUnd : kOut;  // isolated rows (e.g. Dirichlet) are never aggregated
+}
+
+// lanes' (best value, entry, target): the largest value, the first entry among ties
+template <int G>
+__device__ inline void argmax_lanes(double& best, int& eb, int& a) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, G);
+    const int oe = __shfl_xor(eb, o, G), oa = __shfl_xor(a, o, G);
+    if (ob > best || (ob == best && oe < eb)) {
+      best = ob;
+      eb = oe;
+      a = oa;
+    }
+  }
+}
+
+// lanes per row for the row kernels: as for the independent-set passes
+template <class F>
+void with_row_lanes(const Csr& A, F&& f) {
+  const double avg = (double)A.nnzb / std::max(1, A.n);
+  if (avg <= 12.0)
+    f(std::integral_constant<int, 4>{});
+  else if (avg <= 40.0)
+    f(std::integral_constant<int, 8>{});
+  else
+    f(std::integral_constant<int, 16>{});
 }
 
 __device__ inline uint64_t pack_tuple(uint8_t st, int i, uint32_t salt) {
@@ -172,25 +231,39 @@ void launch_mis_max(hipStream_t s, const Csr& A, const uint8_t* strong, const ui
 //   A_uu (node graph): slot (dk+1)*9 + (dj+1)*3 + (di+1) of neighbour (di,dj,dk).
 //   C~_pi (face graph): slot 6*s + e = local face e of the cell on side s of
 //   the face (s = 0: the cell below/left of it, 1: above/right).
-__global__ void k_mask_nodes(Grid G, const int* __restrict__ rp, const int* __restrict__ col,
-                             const uint8_t* __restrict__ strong, uint32_t* __restrict__ mask, int* __restrict__ bad) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= G.nn) return;
-  int i, j, k;
-  G.node_ijk(n, i, j, k);
+// 32 lanes per row (a node has at most 27 blocks), OR-reduced with shuffles
+__global__ void __launch_bounds__(256) k_mask_nodes(Grid G, const int* __restrict__ rp,
+                                                    const int* __restrict__ col,
+                                                    const uint8_t* __restrict__ strong, uint32_t* __restrict__ mask,
+                                                    int* __restrict__ bad) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = t >> 5;
+  const int l = (int)(t & 31);
   uint32_t m = 0;
-  for (int e = rp[n]; e < rp[n + 1]; ++e) {
-    if (strong[e] != 1) continue;
-    int a, b, c;
-    G.node_ijk(col[e], a, b, c);
-    const int di = a - i, dj = b - j, dk = c - k;
-    if (di < -1 || di > 1 || dj < -1 || dj > 1 || dk < -1 || dk > 1) {
-      *bad = 1;
-      continue;
+  if (n < G.nn) {
+    int i, j, k;
+    G.node_ijk(n, i, j, k);
+    const int sy = G.nx + 1, sz = sy * (G.ny + 1);
+    for (int e = rp[n] + l; e < rp[n + 1]; e += 32) {
+      if (strong[e] != 1) continue;
+      // offset col - n = di + dj*sy + dk*sz with |di|, |dj|, |dk| <= 1, checked below
+      const int d = col[e] - (int)n;
+      const int dk = d > sz / 2 ? 1 : (d < -(sz / 2) ? -1 : 0);
+      const int r = d - dk * sz;
+      const int dj = r > sy / 2 ? 1 : (r < -(sy / 2) ? -1 : 0);
+      const int di = r - dj * sy;
+      const bool ok = di >= -1 && di <= 1 && i + di >= 0 && i + di <= G.nx && j + dj >= 0 && j + dj <= G.ny &&
+                      k + dk >= 0 && k + dk <= G.nz;
+      if (!ok) {
+        *bad = 1;
+        continue;
+      }
+      m |= 1u << ((dk + 1) * 9 + (dj + 1) * 3 + (di + 1));
     }
-    m |= 1u << ((dk + 1) * 9 + (dj + 1) * 3 + (di + 1));
   }
-  mask[n] = m;
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) m |= __shfl_xor(m, o, 32);
+  if (n < G.nn && l == 0) mask[n] = m;
 }
 
 __global__ void __launch_bounds__(256) k_mis_max_nodes(Grid G, const uint32_t* __restrict__ mask,
@@ -296,54 +369,64 @@ __global__ void k_root_flags(int n, const uint8_t* __restrict__ state, int* __re
 }
 
 // distance-1 attachment: a node joins its most strongly coupled root
-template <int BS>
-__global__ void k_agg_phase1(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                             const double* __restrict__ val, const uint8_t* __restrict__ strong,
-                             const uint8_t* __restrict__ state, const int* __restrict__ root_id,
-                             int* __restrict__ agg1) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int a = -1;
-  if (state[i] == kIn) {
-    a = root_id[i];
-  } else {
-    double best = -1.0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e)
+template <int BS, int G>
+__global__ void __launch_bounds__(256) k_agg_phase1(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                    BlockNorms<BS> nv, const uint8_t* __restrict__ strong,
+                                                    const uint8_t* __restrict__ state,
+                                                    const int* __restrict__ root_id, int* __restrict__ agg1) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
+  int a = -1, eb = INT_MAX;
+  double best = -1.0;
+  const bool root = i < n && state[i] == kIn;
+  if (i < n && !root)
+    for (int e = rp[i] + l; e < rp[i + 1]; e += G)
       if (strong[e] == 1 && state[col[e]] == kIn) {
-        const double sv = block_norm<BS>(val + (size_t)e * BS * BS);
+        const double sv = nv(e);
         if (sv > best) {
           best = sv;
+          eb = e;
           a = root_id[col[e]];
         }
       }
-  }
-  agg1[i] = a;
+  argmax_lanes<G>(best, eb, a);
+  if (i < n && l == 0) agg1[i] = root ? root_id[i] : a;
 }
 
-template <int BS>
-__global__ void k_agg_phase2(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                             const double* __restrict__ val, const uint8_t* __restrict__ strong,
-                             const int* __restrict__ agg1, int* __restrict__ agg, int* __restrict__ status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int a = agg1[i];
-  if (a < 0) {
-    bool has_strong = false;
-    double best = -1.0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+template <int BS, int G>
+__global__ void __launch_bounds__(256) k_agg_phase2(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                    BlockNorms<BS> nv, const uint8_t* __restrict__ strong,
+                                                    const int* __restrict__ agg1, int* __restrict__ agg,
+                                                    int* __restrict__ status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
+  const int a1 = i < n ? agg1[i] : 0;
+  int a = -1, eb = INT_MAX, has_strong = 0;
+  double best = -1.0;
+  if (i < n && a1 < 0)
+    for (int e = rp[i] + l; e < rp[i + 1]; e += G) {
       if (strong[e] != 1) continue;
-      has_strong = true;
+      has_strong = 1;
       const int j = col[e];
       if (agg1[j] < 0) continue;
-      const double s = block_norm<BS>(val + (size_t)e * BS * BS);
-      if (s > best) {
-        best = s;
+      const double sv = nv(e);
+      if (sv > best) {
+        best = sv;
+        eb = e;
         a = agg1[j];
       }
     }
-    if (has_strong && a < 0) atomicOr(status, kStatusCapacity);
+  argmax_lanes<G>(best, eb, a);
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) has_strong |= __shfl_xor(has_strong, o, G);
+  if (i < n && l == 0) {
+    if (a1 >= 0) {
+      agg[i] = a1;
+    } else {
+      if (has_strong && a < 0) atomicOr(status, kStatusCapacity);
+      agg[i] = a;
+    }
   }
-  agg[i] = a;
 }
 
 __global__ void k_count_aggregated(int n, const int* __restrict__ agg, int* __restrict__ f) {
@@ -491,41 +574,70 @@ void truncate_p(hipStream_t s, Csr& P, double tau) {
 
 // filtered operator for prolongator smoothing: strong off-diagonal blocks
 // kept, weak ones lumped into the diagonal block (row sums preserved)
-// entries kept in A_F (diagonal and strong); weak_rows counts the rows that
-// drop a nonzero block
-__global__ void k_filter_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                               const uint8_t* __restrict__ strong, int* __restrict__ cnt,
-                               int* __restrict__ weak_rows) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// entries kept in A_F (diagonal and strong); *any_weak is set when some row
+// drops a nonzero block.  G lanes per row as in the strength kernels.
+template <int G>
+__global__ void __launch_bounds__(256) k_filter_count(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ col,
+                                                      const uint8_t* __restrict__ strong, int* __restrict__ cnt,
+                                                      int* __restrict__ any_weak) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
   int c = 0, w = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const bool diag = col[e] == i;
-    c += diag || strong[e] == 1;
-    w += !diag && strong[e] == 0;
-  }
-  cnt[i] = c;
-  if (w) atomicAdd(weak_rows, 1);
+  if (i < n)
+    for (int e = rp[i] + l; e < rp[i + 1]; e += G) {
+      const bool diag = col[e] == i;
+      c += diag || strong[e] == 1;
+      w |= !diag && strong[e] == 0;
+    }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, G);
+  if (i < n && l == 0) cnt[i] = c;
+  // one flag store per wavefront that has a weak coupling (all store 1)
+  const unsigned long long m = __ballot(w != 0);
+  if (m != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1)) *any_weak = 1;
 }
 
-template <int BS>
-__global__ void k_filter_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                              const double* __restrict__ val, const uint8_t* __restrict__ strong,
-                              const int* __restrict__ frp, int* __restrict__ fcol, double* __restrict__ fval) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// A_F rows: the kept entries in their order, the weak blocks summed (lane
+// partial sums, then a shuffle tree) onto the diagonal block
+template <int BS, int G>
+__global__ void __launch_bounds__(256) k_filter_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const uint8_t* __restrict__ strong,
+                                                     const int* __restrict__ frp, int* __restrict__ fcol,
+                                                     double* __restrict__ fval) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
   double lump[BS * BS];
+#pragma unroll
   for (int q = 0; q < BS * BS; ++q) lump[q] = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
+  const int e0 = i < n ? rp[i] : 0, e1 = i < n ? rp[i + 1] : 0;
+  for (int e = e0 + l; e < e1; e += G)
     if (col[e] != i && strong[e] == 0)
+#pragma unroll
       for (int q = 0; q < BS * BS; ++q) lump[q] += val[(size_t)e * BS * BS + q];
-  int p = frp[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const bool diag = col[e] == i;
-    if (!diag && strong[e] != 1) continue;
-    fcol[p] = col[e];
-    for (int q = 0; q < BS * BS; ++q) fval[(size_t)p * BS * BS + q] = val[(size_t)e * BS * BS + q] + (diag ? lump[q] : 0.0);
-    ++p;
+#pragma unroll
+  for (int q = 0; q < BS * BS; ++q)
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) lump[q] += __shfl_xor(lump[q], o, G);
+  // compaction: each pass over G entries places the kept ones after those of
+  // the lower lanes (ballot of the row's lane group)
+  const int lane = threadIdx.x & 63, base = lane & ~(G - 1);
+  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  int p = i < n ? frp[i] : 0;
+  for (int e00 = e0; e00 < e1; e00 += G) {  // same trip count on every lane of the row
+    const int e = e00 + l;
+    const bool diag = e < e1 && col[e] == i;
+    const bool keep = e < e1 && (diag || strong[e] == 1);
+    const unsigned long long grp = (__ballot(keep) >> base) & gmask;
+    if (keep) {
+      const int q0 = p + __popcll(grp & ((1ull << l) - 1ull));
+      fcol[q0] = col[e];
+#pragma unroll
+      for (int q = 0; q < BS * BS; ++q)
+        fval[(size_t)q0 * BS * BS + q] = val[(size_t)e * BS * BS + q] + (diag ? lump[q] : 0.0);
+    }
+    p += __popcll(grp);
   }
 }
 
@@ -991,15 +1103,26 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
   uint64_t* T1 = dalloc<uint64_t>(n);
   uint64_t* T2 = dalloc<uint64_t>(n);
   int* und = dalloc<int>(1);
-  k_diag_norm<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, dn);
-  k_strength<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, dn, theta, strong, state);
+  double* nrm = nullptr;
+  BlockNorms<BS> nv{A.val};
+  if (BS > 1) {
+    nrm = dalloc<double>(A.nnzb);
+    k_block_norms<BS><<<blocks_for(A.nnzb), kBlock, 0, s>>>(A.nnzb, A.val, nrm);
+    nv.p = nrm;
+  }
+  with_row_lanes(A, [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    k_diag_norm<BS, G><<<blocks_for((int64_t)n * G), kBlock, 0, s>>>(n, A.rowptr, A.col, nv, dn);
+    k_strength<BS, G><<<blocks_for((int64_t)n * G), kBlock, 0, s>>>(n, A.rowptr, A.col, nv, dn, theta, strong,
+                                                                   state);
+  });
   PM_CHECK_LAUNCH();
   uint32_t* mask = nullptr;
   if (SG) {
     mask = dalloc<uint32_t>(n);
     PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
     if (BS == 3)
-      k_mask_nodes<<<blocks_for(n), kBlock, 0, s>>>(*SG, A.rowptr, A.col, strong, mask, und);
+      k_mask_nodes<<<blocks_for((int64_t)n * 32), kBlock, 0, s>>>(*SG, A.rowptr, A.col, strong, mask, und);
     else
       k_mask_faces<<<blocks_for(n), kBlock, 0, s>>>(*SG, A.rowptr, A.col, strong, mask, und);
     PM_CHECK_LAUNCH();
@@ -1038,15 +1161,20 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
   int nagg = 0;
   exclusive_scan(s, flags, root_id, n, &nagg);
   int* agg1 = dalloc<int>(n);
-  k_agg_phase1<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, state, root_id, agg1);
   PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
-  k_agg_phase2<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, agg1, agg, und);
+  with_row_lanes(A, [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    k_agg_phase1<BS, G><<<blocks_for((int64_t)n * G), kBlock, 0, s>>>(n, A.rowptr, A.col, nv, strong, state,
+                                                                     root_id, agg1);
+    k_agg_phase2<BS, G><<<blocks_for((int64_t)n * G), kBlock, 0, s>>>(n, A.rowptr, A.col, nv, strong, agg1, agg,
+                                                                     und);
+  });
   PM_CHECK_LAUNCH();
   int st = 0;
   PM_HIP(hipMemcpyAsync(&st, und, sizeof(int), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
   for (void* p : {(void*)dn, (void*)state, (void*)T0, (void*)T1, (void*)T2, (void*)und,
-                  (void*)flags, (void*)root_id, (void*)agg1, (void*)mask})
+                  (void*)flags, (void*)root_id, (void*)agg1, (void*)mask, (void*)nrm})
     dfree(p);
   if (st) throw Error(PM_EINTERNAL, "AMG: aggregation left a connected node unassigned");
   *nagg_out = nagg;
@@ -1082,7 +1210,10 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   AF.n = AF.m = n;
   int* weak_rows = dalloc<int>(1);
   PM_HIP(hipMemsetAsync(weak_rows, 0, sizeof(int), s));
-  k_filter_count<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, f, weak_rows);
+  with_row_lanes(A, [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    k_filter_count<G><<<blocks_for((int64_t)n * G), kBlock, 0, s>>>(n, A.rowptr, A.col, strong, f, weak_rows);
+  });
   AF.rowptr = dalloc<int>(n + 1);
   int fnnz = 0;
   exclusive_scan(s, f, AF.rowptr, n, &fnnz);
@@ -1099,7 +1230,11 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
     AF.nnzb = fnnz;
     AF.col = dalloc<int>(fnnz);
     AF.val = dalloc<double>((int64_t)fnnz * BS * BS);
-    k_filter_fill<BS><<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong, AF.rowptr, AF.col, AF.val);
+    with_row_lanes(A, [&](auto g) {
+      constexpr int G = decltype(g)::value;
+      k_filter_fill<BS, G><<<blocks_for((int64_t)n * G), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, strong,
+                                                                         AF.rowptr, AF.col, AF.val);
+    });
     PM_CHECK_LAUNCH();
     dinvF = dalloc<double>((int64_t)n * BS * BS);
     block_diag_inverse(s, AF, dinvF);
