@@ -1,6 +1,8 @@
 // C ABI entry points (include/poromech.h): argument validation, context
 // lifetime, timing, and conversion of internal errors to return codes.
 #include <chrono>
+#include <exception>
+#include <thread>
 #include <cmath>
 #include <cstring>
 
@@ -53,6 +55,11 @@ void free_ctx_buffers(pm_ctx* c) {
   c->Hpi.free_all();
   c->lat.free_all();
   c->cpi.free_all();
+  if (c->s_aux) {
+    (void)hipStreamSynchronize(c->s_aux);
+    (void)hipStreamDestroy(c->s_aux);
+    c->s_aux = nullptr;
+  }
 }
 
 void copy_in(pm_ctx* c, double* dst, const double* src, int64_t n) {
@@ -94,15 +101,51 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   return p;
 }
 
+// C~_pi's packed element matrices and AMG hierarchy, on stream s (the
+// caller's thread must have made s its allocation stream)
+void setup_pi(pm_ctx* c, hipStream_t s) {
+  const pm::Grid G = pm::grid_of(c);
+  if (c->opts.cell_pi) pm::cellpi_build(c, s);
+  pm::amg_setup(s, c->Cpi, params_pi(c), c->Hpi, nullptr, &G, c->opts.cell_pi ? &c->cpi : nullptr);
+}
+
+// The two hierarchies are independent: A_uu's is built on the caller's
+// stream by this thread while C~_pi's is built on the library's second
+// stream by a helper thread (the set-up is dominated by small kernels and
+// host round trips for sizes, which the two overlap).  Both start after the
+// assembly has completed on the caller's stream and both streams are
+// synchronized before this returns; each hierarchy's result does not depend
+// on the interleaving.
 void setup_hierarchies(pm_ctx* c, bool with_u) {
   if (with_u) {
-    const pm::Grid G = pm::grid_of(c);
-    pm::amg_setup(c->s, c->Auu, params_u(c), c->Hu, c->lattice ? &c->lat : nullptr, &G);
+    PM_HIP(hipStreamSynchronize(c->s));
+    if (!c->s_aux) PM_HIP(hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking));
+    int dev = 0;
+    PM_HIP(hipGetDevice(&dev));
+    std::exception_ptr pi_err;
+    std::thread th([c, dev, &pi_err] {
+      try {
+        PM_HIP(hipSetDevice(dev));
+        pm::set_alloc_stream(c->s_aux);
+        setup_pi(c, c->s_aux);
+        PM_HIP(hipStreamSynchronize(c->s_aux));
+      } catch (...) {
+        pi_err = std::current_exception();
+      }
+    });
+    try {
+      const pm::Grid G = pm::grid_of(c);
+      pm::amg_setup(c->s, c->Auu, params_u(c), c->Hu, c->lattice ? &c->lat : nullptr, &G);
+    } catch (...) {
+      th.join();
+      throw;
+    }
+    th.join();
+    if (pi_err) std::rethrow_exception(pi_err);
     c->hier_u_ok = true;
+  } else {
+    setup_pi(c, c->s);
   }
-  const pm::Grid Gp = pm::grid_of(c);
-  if (c->opts.cell_pi) pm::cellpi_build(c);
-  pm::amg_setup(c->s, c->Cpi, params_pi(c), c->Hpi, nullptr, &Gp, c->opts.cell_pi ? &c->cpi : nullptr);
   c->info.levels_u = (int)c->Hu.L.size();
   c->info.levels_pi = (int)c->Hpi.L.size();
   c->info.opcx_u = c->Hu.opcx;

@@ -111,12 +111,12 @@ const float* cp_C<float>(const CellPiOp& op) { return op.C32; }
 
 }  // namespace
 
-void cellpi_build(pm_ctx* c) {
+void cellpi_build(pm_ctx* c, hipStream_t s) {
   CellPiOp& op = c->cpi;
   const Grid G = grid_of(c);
   if (!op.C) op.C = dalloc<double>(21 * G.nc);
   if (c->opts.precond_fp32 && !op.C32) op.C32 = dalloc<float>(21 * G.nc);
-  k_cpi_cells<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Minv, c->g, c->bp, c->dt, op.C,
+  k_cpi_cells<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->Minv, c->g, c->bp, c->dt, op.C,
                                                      c->opts.precond_fp32 ? op.C32 : nullptr);
   PM_CHECK_LAUNCH();
   op.on = true;

@@ -210,6 +210,7 @@ struct Hierarchy {
 // the context (opaque in the C ABI)
 struct pm_ctx {
   hipStream_t s = nullptr;
+  hipStream_t s_aux = nullptr;  // library-owned second stream (C~_pi hierarchy set-up)
   int nx = 0, ny = 0, nz = 0;
   int64_t nn = 0, nc = 0, nfx = 0, nfy = 0, nfz = 0, nf = 0, nmacro = 0;
   int64_t n_u = 0, n_p = 0, n_pi = 0, N = 0;
@@ -274,7 +275,7 @@ inline int64_t node_id(const pm_ctx* c, int i, int j, int k) {
 Grid grid_of(const pm_ctx* c);
 void assemble_all(pm_ctx* c);          // element kernels, A_uu, B~p, C~pi (no AMG)
 void lattice_finish(pm_ctx* c);        // lattice operator tables after assembly (pm_lattice.hip)
-void cellpi_build(pm_ctx* c);          // packed C~_pi element matrices (pm_cellpi.hip)
+void cellpi_build(pm_ctx* c, hipStream_t s);          // packed C~_pi element matrices (pm_cellpi.hip)
 void rebuild_dt(pm_ctx* c);            // B~p, C~pi for the current dt
 void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
 void check_status(pm_ctx* c, const char* where);

@@ -22,13 +22,19 @@ namespace {
 
 enum { kSmallUb = 64, kMediumUb = 512 };
 
-__global__ void k_ub(int n, const int* __restrict__ arp, const int* __restrict__ acol, const int* __restrict__ brp,
-                     int* __restrict__ ub) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// ub[i] = sum over the entries (i, j) of A of the length of row j of B; G
+// lanes per row, summed with shuffles
+template <int G>
+__global__ void __launch_bounds__(256) k_ub(int n, const int* __restrict__ arp, const int* __restrict__ acol,
+                                            const int* __restrict__ brp, int* __restrict__ ub) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / G), l = (int)(t % G);
   int s = 0;
-  for (int e = arp[i]; e < arp[i + 1]; ++e) s += brp[acol[e] + 1] - brp[acol[e]];
-  ub[i] = s;
+  if (i < n)
+    for (int e = arp[i] + l; e < arp[i + 1]; e += G) s += brp[acol[e] + 1] - brp[acol[e]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  if (i < n && l == 0) ub[i] = s;
 }
 
 // Row lists per class: class 0 if v <= t0, 1 if v <= t1, else 2.  Counts are
@@ -420,7 +426,10 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
   int64_t* ubofs = dalloc<int64_t>(n + 1);
   int* cnt = dalloc<int>(n);
   PM_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(int), s));
-  k_ub<<<blocks_for(n), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
+  if ((double)A.nnzb <= 12.0 * n)
+    k_ub<4><<<blocks_for((int64_t)n * 4), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
+  else
+    k_ub<16><<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
   k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, ub, kSmallUb, kMediumUb, counters, lists);
   k_i64_from_i32<<<blocks_for(n), kBlock, 0, s>>>(n, ub, ub64);
   PM_CHECK_LAUNCH();
