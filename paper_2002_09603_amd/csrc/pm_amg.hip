@@ -680,20 +680,45 @@ __global__ void k_rand_vec(int64_t n, double* __restrict__ x, uint32_t salt) {
   if (i < n) x[i] = (double)(mix32((uint32_t)i ^ salt) & 0xFFFFFF) / 16777216.0 + 0.5;
 }
 
-// out = D^-1 y / sqrt(nsq[0]) (nsq: squared norm of the previous iterate, on the device)
+// One power-iteration step after the operator product w = A v: nsq = the sum
+// of the previous step's partial sums (in k_sum_final's order), v = D^-1 w /
+// sqrt(nsq), and this step's partial sums of v^2 (in k_sumsq_part's order,
+// so with kRedBlocks workgroups the iterates equal those of the separate
+// kernels bit for bit).
 template <int BS>
-__global__ void k_dinv_apply_scaled(int n, const double* __restrict__ dinv, const double* __restrict__ y,
-                                    const double* __restrict__ nsq, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double q = nsq[0];
-  const double scale = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
-  const double* D = dinv + (size_t)i * BS * BS;
-  for (int a = 0; a < BS; ++a) {
-    double s = 0.0;
-    for (int b = 0; b < BS; ++b) s += D[a * BS + b] * y[(size_t)i * BS + b];
-    out[(size_t)i * BS + a] = s * scale;
+__global__ void __launch_bounds__(256) k_power_step(int64_t n, const double* __restrict__ dinv,
+                                                    const double* __restrict__ w, const double* __restrict__ part_in,
+                                                    double* __restrict__ v, double* __restrict__ part_out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += 256) s += part_in[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
   }
+  const double q = sh[0];
+  __syncthreads();
+  const double scale = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t node = i / BS;
+    const int a = (int)(i - node * BS);
+    const double* D = dinv + (size_t)node * BS * BS + a * BS;
+    double t = 0.0;
+    for (int b = 0; b < BS; ++b) t += D[b] * w[(size_t)node * BS + b];
+    const double x = t * scale;
+    v[i] = x;
+    acc += x * x;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part_out[blockIdx.x] = sh[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1021,28 +1046,28 @@ double power_lmax(hipStream_t s, int64_t nb, int bs, const double* dinv, int its
   const int64_t n = nb * bs;
   double* v = dalloc<double>(n);
   double* w = dalloc<double>(n);
-  double* part = dalloc<double>(kRedBlocks);
+  double* pbuf = dalloc<double>(2 * kRedBlocks);
+  double *part = pbuf, *part2 = pbuf + kRedBlocks;
   double* nsq = dalloc<double>(1);
   k_rand_vec<<<blocks_for(n), kBlock, 0, s>>>(n, v, 0x9e3779b9u);
   // ||v|| stays on the device: lambda ~ ||D^-1 A v|| / ||v|| with v normalised
   k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(v, n, part);
-  k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, nsq);
   for (int k = 0; k < its; ++k) {
     spmv(v, w);
     if (bs == 3)
-      k_dinv_apply_scaled<3><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, nsq, v);
+      k_power_step<3><<<kRedBlocks, 256, 0, s>>>(n, dinv, w, part, v, part2);
     else
-      k_dinv_apply_scaled<1><<<blocks_for(nb), kBlock, 0, s>>>((int)nb, dinv, w, nsq, v);
-    k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(v, n, part);
-    k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, nsq);
+      k_power_step<1><<<kRedBlocks, 256, 0, s>>>(n, dinv, w, part, v, part2);
+    std::swap(part, part2);
   }
+  k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, nsq);
   PM_CHECK_LAUNCH();
   double h = 0.0;
   PM_HIP(hipMemcpyAsync(&h, nsq, sizeof(double), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
   dfree(v);
   dfree(w);
-  dfree(part);
+  dfree(pbuf);
   dfree(nsq);
   return std::sqrt(h);
 }

@@ -529,9 +529,8 @@ void check_status(pm_ctx* c, const char* where) {
   if (st & kStatusCapacity) throw Error(PM_EINTERNAL, std::string(where) + ": internal capacity exceeded");
 }
 
-static void build_cpi(pm_ctx* c) {
+void build_cpi(pm_ctx* c, hipStream_t s) {
   const Grid G = grid_of(c);
-  hipStream_t s = c->s;
   k_bp<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->ae, c->vol, c->alpha, c->stabw, c->auu_diag, c->ufix,
                                            c->S, c->dt, c->opts.stabilize, c->bp);
   PM_CHECK_LAUNCH();
@@ -599,10 +598,8 @@ void assemble_all(pm_ctx* c) {
   PM_CHECK_LAUNCH();
   if (c->lattice) lattice_finish(c);
   pack_minv(c);
-  build_cpi(c);
 }
 
-void rebuild_dt(pm_ctx* c) { build_cpi(c); }
 
 void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b) {
   const Grid G = grid_of(c);

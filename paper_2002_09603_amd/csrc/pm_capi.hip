@@ -101,10 +101,11 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   return p;
 }
 
-// C~_pi's packed element matrices and AMG hierarchy, on stream s (the
-// caller's thread must have made s its allocation stream)
+// B~_p, C~_pi (assembled and packed per cell) and C~_pi's AMG hierarchy, on
+// stream s (the caller's thread must have made s its allocation stream)
 void setup_pi(pm_ctx* c, hipStream_t s) {
   const pm::Grid G = pm::grid_of(c);
+  pm::build_cpi(c, s);
   if (c->opts.cell_pi) pm::cellpi_build(c, s);
   pm::amg_setup(s, c->Cpi, params_pi(c), c->Hpi, nullptr, &G, c->opts.cell_pi ? &c->cpi : nullptr);
 }
@@ -344,7 +345,6 @@ int pm_set_dt(pm_ctx* c, double dt) {
     if (!c->assembled) return PM_OK;
     PM_HIP(hipStreamSynchronize(c->s));
     const double t0 = now_s();
-    pm::rebuild_dt(c);
     setup_hierarchies(c, false);
     PM_HIP(hipStreamSynchronize(c->s));
     c->info.t_setup = now_s() - t0;

@@ -273,10 +273,10 @@ inline int64_t node_id(const pm_ctx* c, int i, int j, int k) {
 
 // assembly (pm_assemble.hip)
 Grid grid_of(const pm_ctx* c);
-void assemble_all(pm_ctx* c);          // element kernels, A_uu, B~p, C~pi (no AMG)
+void assemble_all(pm_ctx* c);          // element kernels, A_uu (no AMG)
 void lattice_finish(pm_ctx* c);        // lattice operator tables after assembly (pm_lattice.hip)
 void cellpi_build(pm_ctx* c, hipStream_t s);          // packed C~_pi element matrices (pm_cellpi.hip)
-void rebuild_dt(pm_ctx* c);            // B~p, C~pi for the current dt
+void build_cpi(pm_ctx* c, hipStream_t s);  // B~p, assembled C~pi for the current dt (after assemble_all)
 void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
 void check_status(pm_ctx* c, const char* where);
 
