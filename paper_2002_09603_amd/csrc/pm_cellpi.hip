@@ -39,67 +39,66 @@ __global__ void k_cpi_cells(Grid G, const double* __restrict__ Minv, const doubl
     }
 }
 
-__device__ inline bool face_of_thread(const Grid& G, int64_t& f) {
-  f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  return f < G.nf;
+__device__ inline bool cell_of_thread(const Grid& G, uint32_t& i, uint32_t& j, uint32_t& k) {
+  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return false;
+  int a, b, e;
+  G.cell_ijk(c, a, b, e);
+  i = (uint32_t)a;
+  j = (uint32_t)b;
+  k = (uint32_t)e;
+  return true;
 }
 
-// (C~_pi x)_f over the free columns of the free row f, f at (i,j,k) of
-// orientation O.  The packed-matrix entry of each term is a compile-time
-// row of C, so every load is a wave-uniform base plus a 32-bit offset.
-template <int O, class T>
-__device__ __forceinline__ T cpi_row_o(const Grid& G, uint32_t i, uint32_t j, uint32_t k, const T* __restrict__ C,
-                                       const T* __restrict__ x) {
-  T acc = (T)0;
-  const uint32_t top = (uint32_t)G.nz - 1;
-  visit_face_cells<O>(G, i, j, k, [&](auto lc, uint32_t c, const uint32_t F[6], uint32_t ck) {
-    constexpr int l = decltype(lc)::value;
+// sum_e C_T[l, e] x[F_T[e]] over the free columns, l a compile-time local face
+template <class T>
+struct CpiTerm {
+  const Grid& G;
+  const T* __restrict__ C;
+  const T* __restrict__ x;
+  template <int L>
+  __device__ __forceinline__ T operator()(LocalFace<L>, uint32_t c, const uint32_t F[6], uint32_t ck) const {
+    T acc = (T)0;
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-      const T v = ld32(C + (size_t)sym6(l < e ? l : e, l < e ? e : l) * G.nc, c) * ld32(x, F[e]);
-      if (e != 5 || ck != top) acc += v;  // the top face of the top layer is a zero column
+      const T v = ld32(C + (size_t)sym6(L < e ? L : e, L < e ? e : L) * G.nc, c) * ld32(x, F[e]);
+      if (e != 5 || ck != (uint32_t)G.nz - 1) acc += v;  // the top face of the top layer is a zero column
     }
-  });
-  return acc;
-}
+    return acc;
+  }
+};
 
-template <class T>
-__device__ __forceinline__ T cpi_cells_row(const Grid& G, int64_t f, const T* __restrict__ C,
-                                           const T* __restrict__ x) {
-  uint32_t i, j, k;
-  const int o = face_pos(G, (uint32_t)f, i, j, k);
-  if (o == 0) return cpi_row_o<0, T>(G, i, j, k, C, x);
-  if (o == 1) return cpi_row_o<1, T>(G, i, j, k, C, x);
-  return cpi_row_o<2, T>(G, i, j, k, C, x);
-}
-
+// Chebyshev step on the finest C~_pi level, one thread per cell (its owned faces)
 template <class T>
 __global__ void __launch_bounds__(256) k_cp_cheb(Grid G, const T* __restrict__ C, const T* __restrict__ dinv,
                                                  const T* __restrict__ b, const T* __restrict__ xin,
                                                  T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
-  int64_t f;
-  if (!face_of_thread(G, f)) return;
-  const T ax = pi_fixed(G, f) ? xin[f] : cpi_cells_row<T>(G, f, C, xin);
-  const T z = dinv[f] * (b[f] - ax);
-  const T dn = c1 * d[f] + c2 * z;
-  d[f] = dn;
-  xout[f] = xin[f] + dn;
+  uint32_t i, j, k;
+  if (!cell_of_thread(G, i, j, k)) return;
+  owned_face_rows<T>(G, i, j, k, CpiTerm<T>{G, C, xin}, [&](uint32_t f, bool fixed, T acc) {
+    const T ax = fixed ? xin[f] : acc;
+    const T z = dinv[f] * (b[f] - ax);
+    const T dn = c1 * d[f] + c2 * z;
+    d[f] = dn;
+    xout[f] = xin[f] + dn;
+  });
 }
 
 template <class T>
 __global__ void __launch_bounds__(256) k_cp_residual(Grid G, const T* __restrict__ C, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r) {
-  int64_t f;
-  if (!face_of_thread(G, f)) return;
-  const T ax = pi_fixed(G, f) ? x[f] : cpi_cells_row<T>(G, f, C, x);
-  r[f] = b[f] - ax;
+  uint32_t i, j, k;
+  if (!cell_of_thread(G, i, j, k)) return;
+  owned_face_rows<T>(G, i, j, k, CpiTerm<T>{G, C, x},
+                     [&](uint32_t f, bool fixed, T acc) { r[f] = b[f] - (fixed ? x[f] : acc); });
 }
 
 __global__ void __launch_bounds__(256) k_cp_apply(Grid G, const double* __restrict__ C,
                                                   const double* __restrict__ x, double* __restrict__ y) {
-  int64_t f;
-  if (!face_of_thread(G, f)) return;
-  y[f] = pi_fixed(G, f) ? x[f] : cpi_cells_row<double>(G, f, C, x);
+  uint32_t i, j, k;
+  if (!cell_of_thread(G, i, j, k)) return;
+  owned_face_rows<double>(G, i, j, k, CpiTerm<double>{G, C, x},
+                          [&](uint32_t f, bool fixed, double acc) { y[f] = fixed ? x[f] : acc; });
 }
 
 template <class T>
@@ -125,7 +124,7 @@ void cellpi_build(pm_ctx* c, hipStream_t s) {
 template <class T>
 void cellpi_cheb_step(hipStream_t s, const Grid& G, const CellPiOp& op, const T* dinv, const T* b, const T* xin,
                       T* xout, T* d, T c1, T c2) {
-  k_cp_cheb<T><<<blocks_for(G.nf), kBlock, 0, s>>>(G, cp_C<T>(op), dinv, b, xin, xout, d, c1, c2);
+  k_cp_cheb<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), dinv, b, xin, xout, d, c1, c2);
   PM_CHECK_LAUNCH();
 }
 template void cellpi_cheb_step<double>(hipStream_t, const Grid&, const CellPiOp&, const double*, const double*,
@@ -135,7 +134,7 @@ template void cellpi_cheb_step<float>(hipStream_t, const Grid&, const CellPiOp&,
 
 template <class T>
 void cellpi_residual(hipStream_t s, const Grid& G, const CellPiOp& op, const T* b, const T* x, T* r) {
-  k_cp_residual<T><<<blocks_for(G.nf), kBlock, 0, s>>>(G, cp_C<T>(op), b, x, r);
+  k_cp_residual<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), b, x, r);
   PM_CHECK_LAUNCH();
 }
 template void cellpi_residual<double>(hipStream_t, const Grid&, const CellPiOp&, const double*, const double*,
@@ -144,7 +143,7 @@ template void cellpi_residual<float>(hipStream_t, const Grid&, const CellPiOp&, 
                                      float*);
 
 void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const double* x, double* y) {
-  k_cp_apply<<<blocks_for(G.nf), kBlock, 0, s>>>(G, op.C, x, y);
+  k_cp_apply<<<blocks_for(G.nc), kBlock, 0, s>>>(G, op.C, x, y);
   PM_CHECK_LAUNCH();
 }
 

@@ -193,6 +193,51 @@ __device__ __forceinline__ void visit_face_cells(const Grid& G, uint32_t i, uint
   }
 }
 
+// Face rows by owning cell: cell (i,j,k) owns its -x, -y and -z faces, and
+// also its +x, +y, +z faces on the last layer of each direction, so every
+// face has one owner.  For each owned face f, out(f, fixed, acc) receives the
+// sum over the (one or two) cells T adjacent to f of
+// term(LocalFace<l>{}, c_T, F_T, k_T), l the local index of f in T, F_T the
+// six faces of T and k_T its layer; fixed marks the Dirichlet faces (the top
+// plane), whose acc is not formed.  A thread per cell reads each cell's data
+// for its own faces and its -x/-y/-z neighbours' data for the shared faces
+// (neighbouring threads, so mostly from cache): the per-cell arrays cross HBM
+// about once, where a thread per face re-reads them once per orientation.
+template <int D, class T, class Term, class Out>
+__device__ __forceinline__ void owned_face_dir(const Grid& G, uint32_t i, uint32_t j, uint32_t k, uint32_t c,
+                                               const uint32_t F[6], Term& term, Out& out) {
+  const uint32_t nx = (uint32_t)G.nx, ny = (uint32_t)G.ny;
+  const uint32_t pos = D == 0 ? i : (D == 1 ? j : k);
+  const uint32_t lim = (uint32_t)(D == 0 ? G.nx : (D == 1 ? G.ny : G.nz));
+  // face F[2D]: this cell (local 2D) and the cell before it (local 2D+1)
+  T acc = term(LocalFace<2 * D>{}, c, F, k);
+  if (pos > 0) {
+    const uint32_t bi = i - (D == 0), bj = j - (D == 1), bk = k - (D == 2);
+    uint32_t Fb[6];
+    cell_faces32(G, bi, bj, bk, Fb);
+    acc += term(LocalFace<2 * D + 1>{}, bi + nx * (bj + ny * bk), Fb, bk);
+  }
+  out(F[2 * D], false, acc);
+  // face F[2D+1] on the last layer: this cell only; the top plane is Dirichlet
+  if (pos == lim - 1) {
+    if (D == 2)
+      out(F[5], true, (T)0);
+    else
+      out(F[2 * D + 1], false, term(LocalFace<2 * D + 1>{}, c, F, k));
+  }
+}
+
+template <class T, class Term, class Out>
+__device__ __forceinline__ void owned_face_rows(const Grid& G, uint32_t i, uint32_t j, uint32_t k, Term&& term,
+                                                Out&& out) {
+  const uint32_t c = i + (uint32_t)G.nx * (j + (uint32_t)G.ny * k);
+  uint32_t F[6];
+  cell_faces32(G, i, j, k, F);
+  owned_face_dir<0, T>(G, i, j, k, c, F, term, out);
+  owned_face_dir<1, T>(G, i, j, k, c, F, term, out);
+  owned_face_dir<2, T>(G, i, j, k, c, F, term, out);
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin; this maps workgroup b
 // of nb so that each XCD runs one contiguous range of logical workgroups
 // (neighbour rows and planes gathered by a workgroup then sit in the L2 of

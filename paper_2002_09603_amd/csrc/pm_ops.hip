@@ -111,44 +111,37 @@ __global__ void __launch_bounds__(256) k_ah_p(Grid G, int kind, AE ae, const dou
 // pi-rows: y_pi = sp * sum_T (-g_T[lf]) p_T + sum_T M_T^-1 pi_T (free faces);  fixed: y = pi
 //   A_H: sp = 1    A_H^T: sp = dt
 // M_T^-1 is read from its packed upper triangle (21 values per cell).
-template <int O, class T>
-__device__ __forceinline__ double ah_pi_row(const Grid& G, uint32_t i, uint32_t j, uint32_t k,
-                                            const double* __restrict__ Mp, const double* __restrict__ gv,
-                                            const T* __restrict__ p, const T* __restrict__ pi, double sp) {
-  double v = 0.0;
-  const uint32_t top = (uint32_t)G.nz - 1;
-  visit_face_cells<O>(G, i, j, k, [&](auto lc, uint32_t c, const uint32_t F[6], uint32_t ck) {
-    constexpr int l = decltype(lc)::value;
-    v -= sp * ld32(gv + (size_t)l * G.nc, c) * (double)ld32(p, c);
+template <class T>
+struct AhPiTerm {
+  const Grid& G;
+  const double* __restrict__ Mp;
+  const double* __restrict__ gv;
+  const T* __restrict__ p;
+  const T* __restrict__ pi;
+  double sp;
+  template <int L>
+  __device__ __forceinline__ double operator()(LocalFace<L>, uint32_t c, const uint32_t F[6], uint32_t ck) const {
+    double v = -sp * ld32(gv + (size_t)L * G.nc, c) * (double)ld32(p, c);
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-      const double t = ld32(Mp + (size_t)sym6(l < e ? l : e, l < e ? e : l) * G.nc, c) * (double)ld32(pi, F[e]);
-      if (e != 5 || ck != top) v += t;  // the top face of the top layer is a zero column
+      const double t = ld32(Mp + (size_t)sym6(L < e ? L : e, L < e ? e : L) * G.nc, c) * (double)ld32(pi, F[e]);
+      if (e != 5 || ck != (uint32_t)G.nz - 1) v += t;  // the top face of the top layer is a zero column
     }
-  });
-  return v;
-}
+    return v;
+  }
+};
 
+// one thread per cell, writing the rows of the faces it owns
 template <class T>
 __global__ void __launch_bounds__(256) k_ah_pi(Grid G, const double* __restrict__ Mp,
                                                const double* __restrict__ gv, const T* __restrict__ p,
                                                const T* __restrict__ pi, double sp, double* __restrict__ y) {
-  const int64_t f = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (f >= G.nf) return;
-  if (pi_fixed(G, f)) {
-    y[f] = (double)pi[f];
-    return;
-  }
-  uint32_t i, j, k;
-  const int o = face_pos(G, (uint32_t)f, i, j, k);
-  double v;
-  if (o == 0)
-    v = ah_pi_row<0, T>(G, i, j, k, Mp, gv, p, pi, sp);
-  else if (o == 1)
-    v = ah_pi_row<1, T>(G, i, j, k, Mp, gv, p, pi, sp);
-  else
-    v = ah_pi_row<2, T>(G, i, j, k, Mp, gv, p, pi, sp);
-  y[f] = v;
+  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  owned_face_rows<double>(G, (uint32_t)i, (uint32_t)j, (uint32_t)k, AhPiTerm<T>{G, Mp, gv, p, pi, sp},
+                          [&](uint32_t f, bool fixed, double acc) { y[f] = fixed ? (double)pi[f] : acc; });
 }
 
 // packed upper triangle of the symmetrised M_T^-1
@@ -453,7 +446,7 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
     k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->bc_kind, AeCells{c->ae, G.nc}, c->vol, c->alpha, c->g,
                                                      c->stabw, u, p, pi, c->S, c->dt, c->opts.stabilize, su, spi,
                                                      yp);
-  k_ah_pi<T><<<blocks_for(G.nf), kBlock, 0, c->s>>>(G, c->Mp, c->g, p, pi, transpose ? c->dt : 1.0, ypi);
+  k_ah_pi<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Mp, c->g, p, pi, transpose ? c->dt : 1.0, ypi);
   PM_CHECK_LAUNCH();
 }
 
