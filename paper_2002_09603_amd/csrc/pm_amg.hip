@@ -810,36 +810,6 @@ __global__ void __launch_bounds__(256) k_sell_apply(int n, const int* __restrict
   }
 }
 
-// y = A x for a block CSR matrix with long rows (the restriction P^T):
-// 16 lanes per row stride over its entries, then reduce with shuffles
-template <int BS, class T>
-__global__ void __launch_bounds__(256) k_csr16(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                                               const T* __restrict__ val, const T* __restrict__ x,
-                                               T* __restrict__ y) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = (int)(t >> 4), lane = threadIdx.x & 15;
-  T acc[BS];
-  for (int a = 0; a < BS; ++a) acc[a] = 0;
-  if (row < n) {
-    for (int e = rp[row] + lane; e < rp[row + 1]; e += 16) {
-      const int j = col[e];
-      const T* v = val + (size_t)e * BS * BS;
-      T xj[BS];
-      for (int q = 0; q < BS; ++q) xj[q] = x[(size_t)j * BS + q];
-      for (int a = 0; a < BS; ++a)
-        for (int q = 0; q < BS; ++q) acc[a] += v[a * BS + q] * xj[q];
-    }
-  }
-  for (int off = 8; off > 0; off >>= 1)
-    for (int a = 0; a < BS; ++a) acc[a] += __shfl_xor(acc[a], off, 16);
-  if (row < n && lane < BS) {
-    T r = acc[0];
-    for (int a = 1; a < BS; ++a)
-      if (lane == a) r = acc[a];
-    y[(size_t)row * BS + lane] = r;
-  }
-}
-
 // Levels with long rows (coarse Galerkin operators): G lanes per block row
 // stride over its CSR entries, the partial sums are combined with a fixed
 // xor tree (deterministic), and lane a < BS finishes component a.
@@ -941,6 +911,10 @@ void residual_csr(hipStream_t s, const Csr& A, int lanes, const T* val, const T*
     case 8:
       k_residual_csr<BS, T, 8, RES><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, val, b, x, r);
       break;
+    case 64:
+      k_residual_csr<BS, T, 64, RES><<<blocks_for((int64_t)n * 64), kBlock, 0, s>>>(n, A.rowptr, A.col, val, b, x,
+                                                                                    r);
+      break;
     default:
       k_residual_csr<BS, T, 16, RES><<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, A.rowptr, A.col, val, b, x,
                                                                                     r);
@@ -952,6 +926,12 @@ void residual_csr(hipStream_t s, const Csr& A, int lanes, const T* val, const T*
 inline int csr_lanes_for(const Csr& A) {
   const double avg = (double)A.nnzb / std::max(1, A.n);
   return avg < 24.0 ? 4 : (avg < 48.0 ? 8 : 16);
+}
+// restrictions P^T have few, long rows on the coarse levels: a wavefront per
+// row once rows average 128 blocks or more
+inline int restrict_lanes_for(const Csr& R) {
+  const double avg = (double)R.nnzb / std::max(1, R.n);
+  return avg >= 128.0 ? 64 : csr_lanes_for(R);
 }
 
 // dense coarse level
@@ -1433,8 +1413,7 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   Level& C = H.L[l + 1];
   const int rprof = (l == 0 && BS == 3) ? kProfRestrictU0 : 0;
   g_prof.begin(s, rprof);
-  k_csr16<BS, T><<<blocks_for((int64_t)L.R.n * 16), kBlock, 0, s>>>(L.R.n, L.R.rowptr, L.R.col, LP::CV(L.R), r,
-                                                                    LP::B(C));
+  residual_csr<BS, T, false>(s, L.R, restrict_lanes_for(L.R), LP::CV(L.R), nullptr, r, LP::B(C));
   g_prof.end(s, rprof, (double)L.R.nnzb * (BS * BS * sizeof(T) + 4) + (double)(n + C.n) * BS * sizeof(T));
   vcycle_level<BS, T>(s, H, prm, l + 1, LP::B(C), LP::X(C));
   const int pth = L.P.nslices * kSlice;

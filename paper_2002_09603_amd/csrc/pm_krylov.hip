@@ -16,20 +16,25 @@ namespace pm {
 namespace {
 
 constexpr int kDotBlocks = 2048;  // partial sums per dot product (8 workgroups per CU)
-constexpr int kDotGroup = 8;      // basis vectors per multi-dot pass
+constexpr int kDotGroup = 8;      // basis vectors per multi-dot pass (CGS passes)
+constexpr int kDotGroupWide = 24; // basis vectors per multi-dot pass (one-pass Gram-Schmidt)
 constexpr int kPartRows = 504;    // rows of the partial-sum buffer (basis vectors + 2 norms)
 
-// part[(i0+g)*kDotBlocks + block] = sum_chunk V_{i0+g} . w for g < cnt; with
-// self_row >= 0 also part[self_row*kDotBlocks + block] = sum_chunk w . w.
+// part[(i0+g)*kDotBlocks + block] = sum_chunk V_{i0+g} . w for g < cnt <= NG;
+// with self_row >= 0 also part[self_row*kDotBlocks + block] = sum_chunk w . w.
 // Workgroup sums: shuffles within each wavefront, then the 4 wavefronts in
-// order (deterministic).  Eight waves per SIMD so that all kDotBlocks
-// workgroups are resident at once (no second, mostly idle, round).
-__global__ void __launch_bounds__(256, 8) k_multidot(const double* __restrict__ V, int64_t N, int64_t ld, int i0,
-                                                  int cnt, const double* __restrict__ w, double* __restrict__ part,
-                                                  int self_row) {
-  __shared__ double sh[4][kDotGroup + 1];
-  double acc[kDotGroup + 1];
-  for (int g = 0; g <= kDotGroup; ++g) acc[g] = 0.0;
+// order (deterministic).  WAVES waves per SIMD bound the registers so that
+// the whole grid is resident at once: NG = 8 with 8 waves and kDotBlocks
+// workgroups (the CGS passes); NG = 24 with 4 waves and kDotBlocks / 2
+// workgroups reads w once for up to 24 basis vectors (one-pass Gram-Schmidt).
+template <int NG, int WAVES>
+__global__ void __launch_bounds__(256, WAVES) k_multidot(const double* __restrict__ V, int64_t N, int64_t ld,
+                                                         int i0, int cnt, const double* __restrict__ w,
+                                                         double* __restrict__ part, int self_row) {
+  __shared__ double sh[4][NG + 1];
+  double acc[NG + 1];
+#pragma unroll
+  for (int g = 0; g <= NG; ++g) acc[g] = 0.0;
   const double* Vi = V + (size_t)i0 * ld;
   // element pairs (16-byte loads; vectors start at multiples of ld), then the odd tail
   const int64_t np = N >> 1;
@@ -37,32 +42,33 @@ __global__ void __launch_bounds__(256, 8) k_multidot(const double* __restrict__ 
     const int64_t k = 2 * q;
     const double2 wk = *reinterpret_cast<const double2*>(w + k);
 #pragma unroll
-    for (int g = 0; g < kDotGroup; ++g)
+    for (int g = 0; g < NG; ++g)
       if (g < cnt) {
         const double2 v = *reinterpret_cast<const double2*>(Vi + (size_t)g * ld + k);
         acc[g] += v.x * wk.x + v.y * wk.y;
       }
-    acc[kDotGroup] += wk.x * wk.x + wk.y * wk.y;
+    acc[NG] += wk.x * wk.x + wk.y * wk.y;
   }
   if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
     const int64_t k = N - 1;
     const double wk = w[k];
-    for (int g = 0; g < kDotGroup; ++g)
+    for (int g = 0; g < NG; ++g)
       if (g < cnt) acc[g] += Vi[(size_t)g * ld + k] * wk;
-    acc[kDotGroup] += wk * wk;
+    acc[NG] += wk * wk;
   }
 #pragma unroll
-  for (int g = 0; g <= kDotGroup; ++g)
+  for (int g = 0; g <= NG; ++g)
     for (int off = 32; off > 0; off >>= 1) acc[g] += __shfl_down(acc[g], off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0)
-    for (int g = 0; g <= kDotGroup; ++g) sh[wave][g] = acc[g];
+#pragma unroll
+    for (int g = 0; g <= NG; ++g) sh[wave][g] = acc[g];
   __syncthreads();
-  if ((int)threadIdx.x <= kDotGroup) {
+  if ((int)threadIdx.x <= NG) {
     const int g = threadIdx.x;
     const double v = ((sh[0][g] + sh[1][g]) + sh[2][g]) + sh[3][g];
     if (g < cnt) part[(size_t)(i0 + g) * kDotBlocks + blockIdx.x] = v;
-    if (g == kDotGroup && self_row >= 0) part[(size_t)self_row * kDotBlocks + blockIdx.x] = v;
+    if (g == NG && self_row >= 0) part[(size_t)self_row * kDotBlocks + blockIdx.x] = v;
   }
 }
 
@@ -312,7 +318,8 @@ static void cgs_pass(pm_ctx* c, int nv, double* hpass, bool self_norm) {
   for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
     const int cnt = std::min(kDotGroup, nv - i0);
     g_prof.begin(c->s, kProfMultidot);
-    k_multidot<<<gb, 256, 0, c->s>>>(c->V, N, c->ld, i0, cnt, c->wvec, c->red, (self_norm && i0 == 0) ? nv : -1);
+    k_multidot<kDotGroup, 8><<<gb, 256, 0, c->s>>>(c->V, N, c->ld, i0, cnt, c->wvec, c->red,
+                                                   (self_norm && i0 == 0) ? nv : -1);
     g_prof.end(c->s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
   }
   k_dot_final<<<nv + (self_norm ? 1 : 0), 256, 0, c->s>>>(c->red, 0, nv + (self_norm ? 1 : 0), gb, hpass);
@@ -384,13 +391,14 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
       if (fused) {
         // h = V^T w and ||w||^2, then v_{j+1} = (w - V h) / ||w - V h|| in one pass
         const int gb = grid_for(N);
-        for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
-          const int cnt = std::min(kDotGroup, nv - i0);
+        const int gd = std::max(1, std::min(gb, kDotBlocks / 2));
+        for (int i0 = 0; i0 < nv; i0 += kDotGroupWide) {
+          const int cnt = std::min(kDotGroupWide, nv - i0);
           g_prof.begin(s, kProfMultidot);
-          k_multidot<<<gb, 256, 0, s>>>(c->V, N, ld, i0, cnt, c->wvec, c->red, i0 == 0 ? nv : -1);
+          k_multidot<kDotGroupWide, 4><<<gd, 256, 0, s>>>(c->V, N, ld, i0, cnt, c->wvec, c->red, i0 == 0 ? nv : -1);
           g_prof.end(s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
         }
-        k_dot_final<<<nv + 1, 256, 0, s>>>(c->red, 0, nv + 1, gb, h1);
+        k_dot_final<<<nv + 1, 256, 0, s>>>(c->red, 0, nv + 1, gd, h1);
         k_pyth_scale<<<1, 64, 0, s>>>(h1, nv, dev_scale);
         g_prof.begin(s, kProfMultiaxpy);
         k_orth_normalize<<<gb, 256, 0, s>>>(c->V, N, ld, nv, h1, dev_scale, c->wvec, c->V + (size_t)(j + 1) * ld,
