@@ -21,7 +21,7 @@ PM_OP_AH, PM_OP_AHT, PM_OP_MINV, PM_OP_MINVT, PM_OP_CPI, PM_OP_BP, PM_OP_AUU, \
 PROF_KERNELS = {1: "k_lat_ah_u|k_ah_u (u-rows of A_H, FP64)",
                 2: "k_lat_cheb|k_cheb_step<3> (Chebyshev step, finest A_uu level)",
                 3: "k_cp_cheb|k_cheb_step<1> (Chebyshev step, finest C~pi level)", 4: "k_multidot",
-                5: "k_orth_normalize|k_multiaxpy (Gram-Schmidt update of the new basis vector)",
+                5: "k_orth_normalize_n<NG>|k_orth_normalize|k_multiaxpy (Gram-Schmidt update of the new basis vector)",
                 6: "k_residual_csr<3,float|double,16,false> (restriction from the finest A_uu level)"}
 
 ERROR_NAMES = {PM_EINVAL: "PM_EINVAL", PM_ENOMEM: "PM_ENOMEM", PM_EHIP: "PM_EHIP",
