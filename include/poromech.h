@@ -39,9 +39,14 @@
  *     error is returned by pm_last_error(ctx).  No C++ exception crosses it.
  *   - "device" pointers are HIP device (or managed) memory owned by the
  *     caller; "host or device" inputs are copied (hipMemcpyDefault).
- *   - every kernel is enqueued on the stream passed to pm_setup; calls that
- *     return results to the host (pm_solve, pm_solve_transpose) synchronize
- *     that stream; the others are asynchronous.
+ *   - kernels are enqueued on the stream passed to pm_setup, except that
+ *     pm_setup, pm_assemble and pm_update_material build B~_p, C~_pi and the
+ *     C~_pi hierarchy on a second, library-owned stream (non-blocking,
+ *     default priority) from a helper thread, concurrently with the A_uu
+ *     hierarchy on the caller's stream.  These calls, pm_set_dt, pm_solve
+ *     and pm_solve_transpose synchronize the caller's stream on entry and
+ *     return after all their work has completed; the others are
+ *     asynchronous.
  *   - a context is not thread-safe; use one context per host thread.
  */
 #ifndef POROMECH_H
