@@ -252,7 +252,7 @@ struct KeLattice {
 template <class KS>
 __global__ void __launch_bounds__(256) k_auu_fill(Grid G, KS Ke, const uint8_t* __restrict__ ufix,
                                                   const int* __restrict__ rowptr, int* __restrict__ col,
-                                                  double* __restrict__ val, double* __restrict__ diag) {
+                                                  double* __restrict__ val) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 27 * G.nn) return;
   const int64_t n = t / 27;
@@ -285,10 +285,30 @@ __global__ void __launch_bounds__(256) k_auu_fill(Grid G, KS Ke, const uint8_t* 
       double v = fixed ? 0.0 : B[r * 3 + s];
       if (m == n && r == s && fr) v = 1.0;
       val[(size_t)pos * 9 + r * 3 + s] = v;
-      if (m == n && r == s) diag[3 * n + r] = v;
     }
   }
   col[pos] = (int)m;
+}
+
+// Diagonal entries of A_uu (what k_auu_fill stores on the diagonal, with the
+// same cell order, so the same values): B~_p needs only these, which lets the
+// C~_pi set-up start before the full fill.
+template <class KS>
+__global__ void __launch_bounds__(256) k_auu_diag(Grid G, KS Ke, const uint8_t* __restrict__ ufix,
+                                                  double* __restrict__ diag) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= G.nn) return;
+  int i, j, k;
+  G.node_ijk(n, i, j, k);
+  double d[3] = {0.0, 0.0, 0.0};
+  for (int ck = max(k - 1, 0); ck <= min(k, G.nz - 1); ++ck)
+    for (int cj = max(j - 1, 0); cj <= min(j, G.ny - 1); ++cj)
+      for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
+        const int64_t c = G.cell(ci, cj, ck);
+        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
+        for (int r = 0; r < 3; ++r) d[r] += Ke(3 * a + r, 3 * a + r, c);
+      }
+  for (int r = 0; r < 3; ++r) diag[3 * n + r] = ufix[3 * n + r] ? 1.0 : d[r];
 }
 
 // B~_p = S|T| + dt alpha_T + (A_stab)_TT + sum_{free i} (A_up)_{iT}^2 / (A_uu)_ii
@@ -315,85 +335,101 @@ __global__ void k_bp(Grid G, const double* __restrict__ ae, const double* __rest
 }
 
 // C~_pi rows: count, then fill (sorted columns)
-__device__ inline int cpi_row_entries(const Grid& G, int64_t f, const uint8_t* __restrict__ pifix,
-                                      const double* __restrict__ Minv, const double* __restrict__ gv,
-                                      const double* __restrict__ bp, double dt, int64_t cols[12],
-                                      double vals[12], bool want_vals) {
-  if (pifix[f]) {
-    cols[0] = f;
-    vals[0] = 1.0;
-    return 1;
+
+// Row f of the assembled C~_pi in ascending column order without sorting:
+// for a face of orientation O between the cell before it (side 0, local face
+// 2O+1) and the cell after it (side 1, local face 2O), the 11 candidate
+// columns (side, local face) follow a fixed order, the face itself (both
+// sides' diagonal terms, side 0 first) at its place.  Absent cells and the
+// Dirichlet columns (top face of the top layer) are skipped.  emit(col, v).
+template <int O, bool VALS, class Emit>
+__device__ __forceinline__ void cpi_row_sorted(const Grid& G, uint32_t i, uint32_t j, uint32_t k, uint32_t f,
+                                               const double* __restrict__ Minv, const double* __restrict__ gv,
+                                               const double* __restrict__ bp, double dt, Emit&& emit) {
+  // slot order per orientation: (side, local face); -1 marks the diagonal
+  constexpr int kSide[3][11] = {{0, -1, 1, 0, 1, 0, 1, 0, 1, 0, 1},
+                                {0, 0, 1, 1, 0, -1, 1, 0, 1, 0, 1},
+                                {0, 0, 1, 1, 0, 0, 1, 1, 0, -1, 1}};
+  constexpr int kFace[3][11] = {{0, -1, 1, 2, 2, 3, 3, 4, 4, 5, 5},
+                                {0, 1, 0, 1, 2, -1, 3, 4, 4, 5, 5},
+                                {0, 1, 0, 1, 2, 3, 2, 3, 4, -1, 5}};
+  constexpr int L0 = 2 * O + 1, L1 = 2 * O;
+  const uint32_t pos = O == 0 ? i : (O == 1 ? j : k);
+  const uint32_t lim = (uint32_t)(O == 0 ? G.nx : (O == 1 ? G.ny : G.nz));
+  const bool has[2] = {pos > 0, pos < lim};
+  uint32_t c[2], ck[2], F[2][6];
+  c[0] = c[1] = 0;
+  ck[0] = ck[1] = 0;
+  const uint32_t nx = (uint32_t)G.nx, ny = (uint32_t)G.ny;
+  if (has[0]) {
+    const uint32_t bi = i - (O == 0), bj = j - (O == 1), bk = k - (O == 2);
+    c[0] = bi + nx * (bj + ny * bk);
+    ck[0] = bk;
+    cell_faces32(G, bi, bj, bk, F[0]);
   }
-  int64_t cc[2];
-  int lf[2];
-  G.face_cells(f, cc, lf);
-  int cnt = 0;
-  for (int s = 0; s < 2; ++s) {
-    const int64_t c = cc[s];
-    if (c < 0) continue;
-    int i, j, k;
-    G.cell_ijk(c, i, j, k);
-    int64_t F[6];
-    G.cell_faces(i, j, k, F);
-    double gl = 0.0, sc = 0.0;
-    if (want_vals) {
-      gl = gv[(size_t)lf[s] * G.nc + c];
-      sc = dt / bp[c];
-    }
-    for (int e = 0; e < 6; ++e) {
-      if (pifix[F[e]]) continue;
+  if (has[1]) {
+    c[1] = i + nx * (j + ny * k);
+    ck[1] = k;
+    cell_faces32(G, i, j, k, F[1]);
+  }
+  auto val = [&](int sd, int l, int e) -> double {
+    if (!VALS) return 0.0;
+    const double sc = dt / bp[c[sd]];
+    const double gl = gv[(size_t)l * G.nc + c[sd]];
+    return Minv[(size_t)(l * 6 + e) * G.nc + c[sd]] - sc * gl * gv[(size_t)e * G.nc + c[sd]];
+  };
+#pragma unroll
+  for (int q = 0; q < 11; ++q) {
+    const int sd = kSide[O][q], e = kFace[O][q];
+    if (sd < 0) {  // the face itself
       double v = 0.0;
-      if (want_vals)
-        v = Minv[(size_t)(lf[s] * 6 + e) * G.nc + c] - sc * gl * gv[(size_t)e * G.nc + c];
-      int p = 0;
-      while (p < cnt && cols[p] != F[e]) ++p;
-      if (p == cnt) {
-        cols[cnt] = F[e];
-        vals[cnt] = v;
-        ++cnt;
-      } else {
-        vals[p] += v;
-      }
+      if (has[0]) v = val(0, L0, L0);
+      if (has[1]) v = has[0] ? v + val(1, L1, L1) : val(1, L1, L1);
+      emit(f, v);
+    } else if (has[sd] && !(e == 5 && ck[sd] == (uint32_t)G.nz - 1)) {
+      emit(F[sd][e], val(sd, sd == 0 ? L0 : L1, e));
     }
   }
-  // insertion sort by column
-  for (int a = 1; a < cnt; ++a) {
-    const int64_t kc = cols[a];
-    const double kv = vals[a];
-    int b = a - 1;
-    while (b >= 0 && cols[b] > kc) {
-      cols[b + 1] = cols[b];
-      vals[b + 1] = vals[b];
-      --b;
-    }
-    cols[b + 1] = kc;
-    vals[b + 1] = kv;
-  }
-  return cnt;
 }
 
-__global__ void k_cpi_count(Grid G, const uint8_t* __restrict__ pifix, int* __restrict__ cnt) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= G.nf) return;
-  int64_t cols[12];
-  double vals[12];
-  cnt[f] = cpi_row_entries(G, f, pifix, nullptr, nullptr, nullptr, 0.0, cols, vals, false);
+template <bool VALS, class Emit>
+__device__ __forceinline__ void cpi_row_entries(const Grid& G, int64_t f, const double* __restrict__ Minv,
+                                                const double* __restrict__ gv, const double* __restrict__ bp,
+                                                double dt, Emit&& emit) {
+  if (pi_fixed(G, f)) {
+    emit((uint32_t)f, 1.0);
+    return;
+  }
+  uint32_t i, j, k;
+  const int o = face_pos(G, (uint32_t)f, i, j, k);
+  if (o == 0)
+    cpi_row_sorted<0, VALS>(G, i, j, k, (uint32_t)f, Minv, gv, bp, dt, emit);
+  else if (o == 1)
+    cpi_row_sorted<1, VALS>(G, i, j, k, (uint32_t)f, Minv, gv, bp, dt, emit);
+  else
+    cpi_row_sorted<2, VALS>(G, i, j, k, (uint32_t)f, Minv, gv, bp, dt, emit);
 }
 
-__global__ void k_cpi_fill(Grid G, const uint8_t* __restrict__ pifix, const double* __restrict__ Minv,
-                           const double* __restrict__ gv, const double* __restrict__ bp, double dt,
-                           const int* __restrict__ rowptr, int* __restrict__ col,
-                           double* __restrict__ val) {
+__global__ void k_cpi_count(Grid G, int* __restrict__ cnt) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= G.nf) return;
-  int64_t cols[12];
-  double vals[12];
-  const int cnt = cpi_row_entries(G, f, pifix, Minv, gv, bp, dt, cols, vals, true);
-  const int64_t p0 = rowptr[f];
-  for (int e = 0; e < cnt; ++e) {
-    col[p0 + e] = (int)cols[e];
-    val[p0 + e] = vals[e];
-  }
+  int n = 0;
+  cpi_row_entries<false>(G, f, nullptr, nullptr, nullptr, 0.0, [&](uint32_t, double) { ++n; });
+  cnt[f] = n;
+}
+
+__global__ void __launch_bounds__(256) k_cpi_fill(Grid G, const double* __restrict__ Minv,
+                                                  const double* __restrict__ gv, const double* __restrict__ bp,
+                                                  double dt, const int* __restrict__ rowptr, int* __restrict__ col,
+                                                  double* __restrict__ val) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= G.nf) return;
+  int p = rowptr[f];
+  cpi_row_entries<true>(G, f, Minv, gv, bp, dt, [&](uint32_t cl, double v) {
+    col[p] = (int)cl;
+    val[p] = v;
+    ++p;
+  });
 }
 
 // right-hand side (eq. MHFE_vector, f~_n of Sec. 2.1; no fluid source)
@@ -539,7 +575,7 @@ void build_cpi(pm_ctx* c, hipStream_t s) {
     c->Cpi.n = c->Cpi.m = (int)G.nf;
     c->Cpi.rowptr = dalloc<int>(G.nf + 1);
     int* cnt = dalloc<int>(G.nf);
-    k_cpi_count<<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->pifix, cnt);
+    k_cpi_count<<<blocks_for(G.nf), kBlock, 0, s>>>(G, cnt);
     PM_CHECK_LAUNCH();
     int total = 0;
     exclusive_scan(s, cnt, c->Cpi.rowptr, (int)G.nf, &total);
@@ -548,8 +584,8 @@ void build_cpi(pm_ctx* c, hipStream_t s) {
     c->Cpi.col = dalloc<int>(total);
     c->Cpi.val = dalloc<double>(total);
   }
-  k_cpi_fill<<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->pifix, c->Minv, c->g, c->bp, c->dt, c->Cpi.rowptr,
-                                                 c->Cpi.col, c->Cpi.val);
+  k_cpi_fill<<<blocks_for(G.nf), kBlock, 0, s>>>(G, c->Minv, c->g, c->bp, c->dt, c->Cpi.rowptr, c->Cpi.col,
+                                                 c->Cpi.val);
   PM_CHECK_LAUNCH();
 }
 
@@ -590,11 +626,23 @@ void assemble_all(pm_ctx* c) {
     c->Auu.val = dalloc<double>((int64_t)total * 9);
   }
   if (c->lattice)
+    k_auu_diag<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->auu_diag);
+  else
+    k_auu_diag<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->auu_diag);
+  PM_CHECK_LAUNCH();
+}
+
+// Values of A_uu, the FP32 lattice data and the packed M_T^-1 (after
+// assemble_all; the A_uu hierarchy and the solve need them, C~_pi does not).
+void assemble_auu(pm_ctx* c) {
+  const Grid G = grid_of(c);
+  hipStream_t s = c->s;
+  if (c->lattice)
     k_auu_fill<<<blocks_for(27 * G.nn), kBlock, 0, s>>>(G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->Auu.rowptr,
-                                                   c->Auu.col, c->Auu.val, c->auu_diag);
+                                                   c->Auu.col, c->Auu.val);
   else
     k_auu_fill<<<blocks_for(27 * G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->Auu.rowptr, c->Auu.col,
-                                                   c->Auu.val, c->auu_diag);
+                                                   c->Auu.val);
   PM_CHECK_LAUNCH();
   if (c->lattice) lattice_finish(c);
   pack_minv(c);

@@ -118,6 +118,9 @@ void setup_pi(pm_ctx* c, hipStream_t s) {
 // synchronized before this returns; each hierarchy's result does not depend
 // on the interleaving.
 void setup_hierarchies(pm_ctx* c, bool with_u) {
+  // with_u: after assemble_all; the A_uu values are filled on this thread
+  // (assemble_auu) while the helper thread builds C~_pi, which needs only
+  // the A_uu diagonal
   if (with_u) {
     PM_HIP(hipStreamSynchronize(c->s));
     if (!c->s_aux) PM_HIP(hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking));
@@ -136,6 +139,7 @@ void setup_hierarchies(pm_ctx* c, bool with_u) {
     });
     try {
       const pm::Grid G = pm::grid_of(c);
+      pm::assemble_auu(c);
       pm::amg_setup(c->s, c->Auu, params_u(c), c->Hu, c->lattice ? &c->lat : nullptr, &G);
     } catch (...) {
       th.join();
@@ -166,11 +170,17 @@ void assemble_and_setup(pm_ctx* c) {
     throw;
   }
   PM_HIP(hipStreamSynchronize(c->s));
+  const double t1 = now_s();
+  try {
+    setup_hierarchies(c, true);
+  } catch (...) {
+    pm::dfree(c->Ke);
+    c->Ke = nullptr;
+    throw;
+  }
+  PM_HIP(hipStreamSynchronize(c->s));
   pm::dfree(c->Ke);
   c->Ke = nullptr;
-  const double t1 = now_s();
-  setup_hierarchies(c, true);
-  PM_HIP(hipStreamSynchronize(c->s));
   const double t2 = now_s();
   c->info.t_asm = t1 - t0;
   c->info.t_setup = t2 - t1;

@@ -273,7 +273,8 @@ inline int64_t node_id(const pm_ctx* c, int i, int j, int k) {
 
 // assembly (pm_assemble.hip)
 Grid grid_of(const pm_ctx* c);
-void assemble_all(pm_ctx* c);          // element kernels, A_uu (no AMG)
+void assemble_all(pm_ctx* c);          // element kernels, masks, A_uu pattern and diagonal
+void assemble_auu(pm_ctx* c);          // A_uu values, FP32 lattice data, packed M^-1 (after assemble_all)
 void lattice_finish(pm_ctx* c);        // lattice operator tables after assembly (pm_lattice.hip)
 void cellpi_build(pm_ctx* c, hipStream_t s);          // packed C~_pi element matrices (pm_cellpi.hip)
 void build_cpi(pm_ctx* c, hipStream_t s);  // B~p, assembled C~pi for the current dt (after assemble_all)

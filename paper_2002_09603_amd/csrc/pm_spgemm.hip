@@ -14,6 +14,8 @@
 // so each accumulator slot has one writer per step and the summation order is
 // fixed (bitwise reproducible).  Accumulators live in LDS (large rows fall
 // back to the output array when they do not fit).
+#include <climits>
+
 #include "pm_internal.h"
 
 namespace pm {
@@ -397,6 +399,79 @@ __global__ void __launch_bounds__(256) k_num_ptent(int n, const int* __restrict_
   }
 }
 
+// Products with the tentative prolongator (one entry per aggregated row,
+// column = aggregate): the pattern of row i of A P_tent is the sorted set of
+// distinct agg[j] >= 0 over the entries (i, j) of A.  G lanes per row, rows of
+// at most G entries: a bitonic sort of the row's keys across the lanes, then
+// the first of each run is kept.  The keys go to tmp at A's row offsets.
+// longest row: per-workgroup maxima (grid-stride, 256 threads), then one workgroup
+__global__ void __launch_bounds__(256) k_row_len_part(int n, const int* __restrict__ rp, int* __restrict__ part) {
+  __shared__ int sh[4];
+  int v = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) v = max(v, rp[i + 1] - rp[i]);
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+}
+
+__global__ void __launch_bounds__(256) k_max_final(int np, const int* __restrict__ part, int* __restrict__ out) {
+  __shared__ int sh[4];
+  int v = 0;
+  for (int i = threadIdx.x; i < np; i += 256) v = max(v, part[i]);
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_sym_ptent(int n, const int* __restrict__ arp, const int* __restrict__ acol,
+                                                   const int* __restrict__ agg, int* __restrict__ tmp,
+                                                   int* __restrict__ cnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(t / G), l = (int)(t % G);
+  int key = INT_MAX;
+  int e0 = 0;
+  if (row < n) {
+    e0 = arp[row];
+    if (l < arp[row + 1] - e0) {
+      const int a = agg[acol[e0 + l]];
+      if (a >= 0) key = a;
+    }
+  }
+  // bitonic sort (ascending) over the G lanes of the row
+#pragma unroll
+  for (int k = 2; k <= G; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int other = __shfl_xor(key, j, G);
+      const bool up = (l & k) == 0;
+      const bool lower = (l & j) == 0;
+      key = (lower == up) ? min(key, other) : max(key, other);
+    }
+  const int prev = __shfl_up(key, 1, G);
+  const bool first = key != INT_MAX && (l == 0 || prev != key);
+  const int lane = threadIdx.x & 63, base = lane & ~(G - 1);
+  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  const unsigned long long grp = (__ballot(first) >> base) & gmask;
+  if (row < n) {
+    if (first) tmp[e0 + __popcll(grp & ((1ull << l) - 1ull))] = key;
+    if (l == 0) cnt[row] = __popcll(grp);
+  }
+}
+
+// copy the sorted keys of each row from the scratch (int offsets) into C
+__global__ void k_compact32(int n, const int* __restrict__ ofs, const int* __restrict__ tmp,
+                            const int* __restrict__ crp, int* __restrict__ ccol) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = (int)(t >> 4), lane = (int)(t & 15);
+  if (row >= n) return;
+  const int c0 = crp[row], u = crp[row + 1] - c0;
+  const int* src = tmp + ofs[row];
+  for (int a = lane; a < u; a += 16) ccol[c0 + a] = src[a];
+}
+
 __global__ void k_i64_from_i32(int n, const int* __restrict__ a, int64_t* __restrict__ b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
@@ -418,6 +493,50 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
     C.col = dalloc<int>(0);
     C.val = dalloc<double>(0);
     return;
+  }
+  if (ptent_agg) {
+    // rows of at most 64 entries: the sort-based pattern of A P_tent
+    const int np = (int)std::min<int64_t>(1024, blocks_for(n));
+    int* mx = dalloc<int>(np + 1);
+    k_row_len_part<<<np, 256, 0, s>>>(n, A.rowptr, mx + 1);
+    k_max_final<<<1, 256, 0, s>>>(np, mx + 1, mx);
+    PM_CHECK_LAUNCH();
+    int maxna = 0;
+    PM_HIP(hipMemcpyAsync(&maxna, mx, sizeof(int), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    dfree(mx);
+    if (maxna <= 64) {
+      int* tmp = dalloc<int>(std::max<int64_t>(A.nnzb, 1));
+      int* cnt = dalloc<int>(n);
+      auto sym = [&](auto g) {
+        constexpr int G = decltype(g)::value;
+        k_sym_ptent<G><<<blocks_for((int64_t)n * G), kBlock, 0, s>>>(n, A.rowptr, A.col, ptent_agg, tmp, cnt);
+      };
+      if (maxna <= 16)
+        sym(std::integral_constant<int, 16>{});
+      else if (maxna <= 32)
+        sym(std::integral_constant<int, 32>{});
+      else
+        sym(std::integral_constant<int, 64>{});
+      PM_CHECK_LAUNCH();
+      int total = 0;
+      exclusive_scan(s, cnt, C.rowptr, n, &total);
+      C.nnzb = total;
+      C.col = dalloc<int>(total);
+      C.val = dalloc<double>((int64_t)total * A.bs * A.bs);
+      k_compact32<<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, A.rowptr, tmp, C.rowptr, C.col);
+      if (A.bs == 3)
+        k_num_ptent<3, 8><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, ptent_agg,
+                                                                        C.rowptr, C.col, C.val);
+      else
+        k_num_ptent<1, 8><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, ptent_agg,
+                                                                        C.rowptr, C.col, C.val);
+      PM_CHECK_LAUNCH();
+      PM_HIP(hipStreamSynchronize(s));
+      dfree(tmp);
+      dfree(cnt);
+      return;
+    }
   }
   int* ub = dalloc<int>(n);
   int* counters = dalloc<int>(4);
