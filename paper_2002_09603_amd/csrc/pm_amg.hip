@@ -180,7 +180,11 @@ __device__ inline uint64_t pack_tuple(uint8_t st, int i, uint32_t salt) {
   return (rank << 62) | (pr << 32) | (uint32_t)i;
 }
 
-__global__ void k_mis_init(int n, const uint8_t* __restrict__ state, uint32_t salt, uint64_t* __restrict__ T0) {
+// The round kernels take go: a round whose predecessor left no undecided row
+// is skipped on the device (*go == 0), so the host checks only every few rounds.
+__global__ void k_mis_init(int n, const uint8_t* __restrict__ state, uint32_t salt, uint64_t* __restrict__ T0,
+                           const int* __restrict__ go) {
+  if (!*go) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) T0[i] = pack_tuple(state[i], i, salt);
 }
@@ -190,7 +194,9 @@ __global__ void k_mis_init(int n, const uint8_t* __restrict__ state, uint32_t sa
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_max(int n, const int* __restrict__ rp, const int* __restrict__ col,
                                                  const uint8_t* __restrict__ strong,
-                                                 const uint64_t* __restrict__ Tin, uint64_t* __restrict__ Tout) {
+                                                 const uint64_t* __restrict__ Tin, uint64_t* __restrict__ Tout,
+                                                 const int* __restrict__ go) {
+  if (!*go) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / G), l = (int)(t % G);
   uint64_t m = 0;
@@ -212,14 +218,15 @@ __global__ void __launch_bounds__(256) k_mis_max(int n, const int* __restrict__ 
   if (i < n && l == 0) Tout[i] = m;
 }
 
-void launch_mis_max(hipStream_t s, const Csr& A, const uint8_t* strong, const uint64_t* Tin, uint64_t* Tout) {
+void launch_mis_max(hipStream_t s, const Csr& A, const uint8_t* strong, const uint64_t* Tin, uint64_t* Tout,
+                    const int* go) {
   const double avg = (double)A.nnzb / std::max(1, A.n);
   if (avg <= 12.0)
-    k_mis_max<4><<<blocks_for((int64_t)A.n * 4), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout);
+    k_mis_max<4><<<blocks_for((int64_t)A.n * 4), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout, go);
   else if (avg <= 40.0)
-    k_mis_max<8><<<blocks_for((int64_t)A.n * 8), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout);
+    k_mis_max<8><<<blocks_for((int64_t)A.n * 8), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout, go);
   else
-    k_mis_max<16><<<blocks_for((int64_t)A.n * 16), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout);
+    k_mis_max<16><<<blocks_for((int64_t)A.n * 16), kBlock, 0, s>>>(A.n, A.rowptr, A.col, strong, Tin, Tout, go);
   PM_CHECK_LAUNCH();
 }
 
@@ -268,7 +275,8 @@ __global__ void __launch_bounds__(256) k_mask_nodes(Grid G, const int* __restric
 
 __global__ void __launch_bounds__(256) k_mis_max_nodes(Grid G, const uint32_t* __restrict__ mask,
                                                        const uint64_t* __restrict__ Tin,
-                                                       uint64_t* __restrict__ Tout) {
+                                                       uint64_t* __restrict__ Tout, const int* __restrict__ go) {
+  if (!*go) return;
   const int64_t n64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n64 >= G.nn) return;
   const uint32_t n = (uint32_t)n64;
@@ -326,7 +334,8 @@ __global__ void k_mask_faces(Grid G, const int* __restrict__ rp, const int* __re
 
 __global__ void __launch_bounds__(256) k_mis_max_faces(Grid G, const uint32_t* __restrict__ mask,
                                                        const uint64_t* __restrict__ Tin,
-                                                       uint64_t* __restrict__ Tout) {
+                                                       uint64_t* __restrict__ Tout, const int* __restrict__ go) {
+  if (!*go) return;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= G.nf) return;
   const uint32_t bits = mask[f];
@@ -345,7 +354,8 @@ __global__ void __launch_bounds__(256) k_mis_max_faces(Grid G, const uint32_t* _
 }
 
 __global__ void k_mis_update(int n, const uint64_t* __restrict__ T0, const uint64_t* __restrict__ T2,
-                             uint8_t* __restrict__ state, int* __restrict__ und) {
+                             uint8_t* __restrict__ state, int* __restrict__ und, const int* __restrict__ go) {
+  if (!*go) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   bool left = false;
@@ -975,6 +985,54 @@ __global__ void k_gj_elim(int n, int k, double* __restrict__ M, const double* __
   M[t] -= colk[i] * M[(size_t)k * w + j];
 }
 
+// All n Gauss-Jordan steps in one workgroup, inverting in place in LDS (n^2
+// doubles; no pivoting, the coarsest operators are SPD): one launch instead
+// of 2n.  Reads the left half of the augmented matrix and writes the inverse
+// into its right half, where k_extract_inverse expects it.
+constexpr int kGjLdsBytes = 160 * 1024;
+constexpr int kGjMaxN = 256;
+__global__ void __launch_bounds__(1024) k_gj_lds(int n, double* __restrict__ M, int* __restrict__ status) {
+  extern __shared__ double S[];
+  __shared__ double rowk[kGjMaxN], colk[kGjMaxN];
+  __shared__ double piv;
+  const int nn = n * n;
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) S[t] = M[(size_t)(t / n) * 2 * n + (t % n)];
+  const int i0 = (int)threadIdx.x / n, j0 = (int)threadIdx.x % n;
+  const int di = (int)blockDim.x / n, dj = (int)blockDim.x % n;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      piv = S[k * n + k];
+      if (!(piv > 0.0)) atomicOr(status, kStatusBadPivot);
+    }
+    __syncthreads();
+    const double p = 1.0 / piv;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      rowk[j] = (j == k) ? p : S[k * n + j] * p;
+      colk[j] = (j == k) ? 0.0 : S[j * n + k];
+    }
+    __syncthreads();
+    // (i, j) of t advanced without division: t grows by blockDim.x each pass
+    int i = i0, j = j0;
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+      if (i == k)
+        S[t] = rowk[j];
+      else if (j == k)
+        S[t] = -colk[i] * p;
+      else
+        S[t] -= colk[i] * rowk[j];
+      i += di;
+      j += dj;
+      if (j >= n) {
+        j -= n;
+        ++i;
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) M[(size_t)(t / n) * 2 * n + n + (t % n)] = S[t];
+}
+
 __global__ void k_extract_inverse(int n, const double* __restrict__ M, double* __restrict__ inv) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * n) return;
@@ -1078,9 +1136,22 @@ void dense_inverse(hipStream_t s, const Csr& A, Hierarchy& H) {
   k_set_identity_right<<<blocks_for(n), kBlock, 0, s>>>(n, M);
   PM_CHECK_LAUNCH();
   const int64_t tot = (int64_t)n * 2 * n;
-  for (int k = 0; k < n; ++k) {
-    k_gj_pivot<<<1, 256, 0, s>>>(n, k, M, colk, status);
-    k_gj_elim<<<blocks_for(tot), kBlock, 0, s>>>(n, k, M, colk);
+  const size_t lds = sizeof(double) * (size_t)n * n;
+  const size_t lds_static = sizeof(double) * (2 * kGjMaxN + 1);
+  if (n <= kGjMaxN && lds + lds_static <= (size_t)kGjLdsBytes) {
+    // once per process (thread-safe static initialisation)
+    static const bool attr_set = [] {
+      PM_HIP(hipFuncSetAttribute((const void*)k_gj_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(kGjLdsBytes - lds_static)));
+      return true;
+    }();
+    (void)attr_set;
+    k_gj_lds<<<1, 1024, lds, s>>>(n, M, status);
+  } else {
+    for (int k = 0; k < n; ++k) {
+      k_gj_pivot<<<1, 256, 0, s>>>(n, k, M, colk, status);
+      k_gj_elim<<<blocks_for(tot), kBlock, 0, s>>>(n, k, M, colk);
+    }
   }
   PM_CHECK_LAUNCH();
   H.coarse_inv = dalloc<double>((int64_t)n * n);
@@ -1139,27 +1210,40 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
       mask = nullptr;
     }
   }
-  auto mis_pass = [&](const uint64_t* Tin, uint64_t* Tout) {
+  auto mis_pass = [&](const uint64_t* Tin, uint64_t* Tout, const int* go) {
     if (!mask)
-      launch_mis_max(s, A, strong, Tin, Tout);
+      launch_mis_max(s, A, strong, Tin, Tout, go);
     else if (BS == 3)
-      k_mis_max_nodes<<<blocks_for(n), kBlock, 0, s>>>(*SG, mask, Tin, Tout);
+      k_mis_max_nodes<<<blocks_for(n), kBlock, 0, s>>>(*SG, mask, Tin, Tout, go);
     else
-      k_mis_max_faces<<<blocks_for(n), kBlock, 0, s>>>(*SG, mask, Tin, Tout);
+      k_mis_max_faces<<<blocks_for(n), kBlock, 0, s>>>(*SG, mask, Tin, Tout, go);
   };
-  for (int round = 0; round < 1000; ++round) {
-    PM_HIP(hipMemsetAsync(und, 0, sizeof(int), s));
-    k_mis_init<<<blocks_for(n), kBlock, 0, s>>>(n, state, 0x12345u, T0);
-    mis_pass(T0, T1);
-    if (dist == 2) mis_pass(T1, T2);
-    k_mis_update<<<blocks_for(n), kBlock, 0, s>>>(n, T0, dist == 2 ? T2 : T1, state, und);
+  // round r runs if round r-1 left undecided rows (flag[(r+1)&1]) and sets
+  // flag[r&1]; the host looks every kRoundsPerCheck rounds
+  constexpr int kRoundsPerCheck = 5;
+  int* flag = dalloc<int>(2);
+  PM_HIP(hipMemsetD32Async((hipDeviceptr_t)flag, 1, 2, s));
+  for (int round = 0;; ++round) {
+    int* cur = flag + (round & 1);
+    const int* prev = flag + ((round + 1) & 1);
+    PM_HIP(hipMemsetAsync(cur, 0, sizeof(int), s));
+    k_mis_init<<<blocks_for(n), kBlock, 0, s>>>(n, state, 0x12345u, T0, prev);
+    mis_pass(T0, T1, prev);
+    if (dist == 2) mis_pass(T1, T2, prev);
+    k_mis_update<<<blocks_for(n), kBlock, 0, s>>>(n, T0, dist == 2 ? T2 : T1, state, cur, prev);
     PM_CHECK_LAUNCH();
-    int h = 0;
-    PM_HIP(hipMemcpyAsync(&h, und, sizeof(int), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipStreamSynchronize(s));
-    if (h == 0) break;
-    if (round == 999) throw Error(PM_EINTERNAL, "AMG: independent-set rounds did not terminate");
+    if ((round + 1) % kRoundsPerCheck == 0) {
+      int h = 0;
+      PM_HIP(hipMemcpyAsync(&h, cur, sizeof(int), hipMemcpyDeviceToHost, s));
+      PM_HIP(hipStreamSynchronize(s));
+      if (h == 0) break;
+      if (round >= 999) {
+        dfree(flag);
+        throw Error(PM_EINTERNAL, "AMG: independent-set rounds did not terminate");
+      }
+    }
   }
+  dfree(flag);
   int* flags = dalloc<int>(n);
   int* root_id = dalloc<int>(n + 1);
   k_root_flags<<<blocks_for(n), kBlock, 0, s>>>(n, state, flags);
