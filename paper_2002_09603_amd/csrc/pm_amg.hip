@@ -760,18 +760,20 @@ __global__ void k_cheb_first(int n, const T* __restrict__ dinv, const T* __restr
 
 // fused step: r = D^-1 (b - A x_in); d = c1 d + c2 r; x_out = x_in + d
 template <int BS, class T>
-__global__ void __launch_bounds__(256) k_cheb_step(int n, const int* __restrict__ sptr, const int* __restrict__ col,
+__global__ void __launch_bounds__(256) k_cheb_step(int n, const int* __restrict__ sptr,
+                                                   const int* __restrict__ perm, const int* __restrict__ col,
                                                    const T* __restrict__ val, const T* __restrict__ dinv,
                                                    const T* __restrict__ b, const T* __restrict__ xin,
                                                    T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = r / kSlice, lane = r % kSlice;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = t / kSlice, lane = t % kSlice;
   if (s * kSlice >= n) return;
   const int e0 = sptr[s], e1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
   sell_row<BS, SellUnroll<BS>::value, T, T>(e0, e1, col, val, xin, lane, acc);
-  if (r >= n) return;
+  const int r = sell_row_of(perm, t, n);
+  if (r < 0) return;
   T res[BS], z[BS];
   for (int a = 0; a < BS; ++a) res[a] = b[(size_t)r * BS + a] - acc[a];
   dinv_mul<BS, T>(dinv + (size_t)r * BS * BS, res, z);
@@ -785,33 +787,37 @@ __global__ void __launch_bounds__(256) k_cheb_step(int n, const int* __restrict_
 
 // residual r = b - A x
 template <int BS, class T>
-__global__ void __launch_bounds__(256) k_residual(int n, const int* __restrict__ sptr, const int* __restrict__ col,
+__global__ void __launch_bounds__(256) k_residual(int n, const int* __restrict__ sptr,
+                                                  const int* __restrict__ perm, const int* __restrict__ col,
                                                   const T* __restrict__ val, const T* __restrict__ b,
                                                   const T* __restrict__ x, T* __restrict__ rr) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = r / kSlice, lane = r % kSlice;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = t / kSlice, lane = t % kSlice;
   if (s * kSlice >= n) return;
   const int e0 = sptr[s], e1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
   sell_row<BS, SellUnroll<BS>::value, T, T>(e0, e1, col, val, x, lane, acc);
-  if (r >= n) return;
+  const int r = sell_row_of(perm, t, n);
+  if (r < 0) return;
   for (int a = 0; a < BS; ++a) rr[(size_t)r * BS + a] = b[(size_t)r * BS + a] - acc[a];
 }
 
 // y = A x (ADD = false) or y += A x (ADD = true): restriction and prolongation
 template <int BS, class T, bool ADD>
-__global__ void __launch_bounds__(256) k_sell_apply(int n, const int* __restrict__ sptr, const int* __restrict__ col,
+__global__ void __launch_bounds__(256) k_sell_apply(int n, const int* __restrict__ sptr,
+                                                    const int* __restrict__ perm, const int* __restrict__ col,
                                                     const T* __restrict__ val, const T* __restrict__ xc,
                                                     T* __restrict__ x) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = r / kSlice, lane = r % kSlice;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = t / kSlice, lane = t % kSlice;
   if (s * kSlice >= n) return;
   const int e0 = sptr[s], e1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
   sell_row<BS, SellUnroll<BS>::value, T, T>(e0, e1, col, val, xc, lane, acc);
-  if (r >= n) return;
+  const int r = sell_row_of(perm, t, n);
+  if (r < 0) return;
   for (int a = 0; a < BS; ++a) {
     if (ADD)
       x[(size_t)r * BS + a] += acc[a];
@@ -1421,7 +1427,7 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
       g_prof.end(s, prof_id, (double)n * BS * sizeof(T) * 5 + (double)n * BS * BS * sizeof(T) +
                                  (double)G.nc * sizeof(T));
     } else {
-      k_cheb_step<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, val, dinv, b, cur, nxt, d,
+      k_cheb_step<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.perm, L.As.col, val, dinv, b, cur, nxt, d,
                                                             (T)c1, (T)c2);
       // algorithmic bytes: blocks + column ids, x/b/d read, x/d written, D^-1 blocks
       g_prof.end(s, prof_id,
@@ -1492,7 +1498,7 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
     residual_csr<BS, T, true>(s, L.A, L.csr_lanes, AV, b, cur, r);
   } else {
     const int nth = L.As.nslices * kSlice;
-    k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.col, AV, b, cur, r);
+    k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.perm, L.As.col, AV, b, cur, r);
   }
   Level& C = H.L[l + 1];
   const int rprof = (l == 0 && BS == 3) ? kProfRestrictU0 : 0;
@@ -1501,7 +1507,8 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   g_prof.end(s, rprof, (double)L.R.nnzb * (BS * BS * sizeof(T) + 4) + (double)(n + C.n) * BS * sizeof(T));
   vcycle_level<BS, T>(s, H, prm, l + 1, LP::B(C), LP::X(C));
   const int pth = L.P.nslices * kSlice;
-  k_sell_apply<BS, T, true><<<blocks_for(pth), kBlock, 0, s>>>(L.P.n, L.P.sptr, L.P.col, LP::AV(L.P), LP::X(C), cur);
+  k_sell_apply<BS, T, true><<<blocks_for(pth), kBlock, 0, s>>>(L.P.n, L.P.sptr, L.P.perm, L.P.col, LP::AV(L.P),
+                                                                LP::X(C), cur);
   PM_CHECK_LAUNCH();
   // post-smoothing from the corrected iterate
   T* other = (cur == x) ? t : x;
@@ -1584,8 +1591,9 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
     } else
       L.lmax = estimate_lmax(s, L.As, L.dinv, prm.power_its);
     if (verbose)
-      fprintf(stderr, "[amg bs=%d] level %d: rows %d, blocks %lld (%.1f/row), lmax(D^-1 A) %.4f\n", L.bs, l, L.n,
-              (long long)L.A.nnzb, (double)L.A.nnzb / std::max(1, L.n), L.lmax);
+      fprintf(stderr, "[amg bs=%d] level %d: rows %d, blocks %lld (%.1f/row), lmax(D^-1 A) %.4f, sliced-ELL fill %.3f\n",
+              L.bs, l, L.n, (long long)L.A.nnzb, (double)L.A.nnzb / std::max(1, L.n), L.lmax,
+              L.As.nslices ? (double)L.As.ncols * kSlice / std::max<int64_t>(1, L.A.nnzb) : 0.0);
     Csr Ac;
     const auto tl0 = std::chrono::steady_clock::now();
     // the finest level of either hierarchy is the structured node or face graph
@@ -1649,7 +1657,8 @@ void iterated_cycles(hipStream_t s, Hierarchy& H, const T* b, T* x, T* r0, T* c0
       cellpi_residual<T>(s, H.grid, *H.cpi, b, x, r0);
     } else {
       const int nth = L.As.nslices * kSlice;
-      k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(L.n, L.As.sptr, L.As.col, LP::AV(L.As), b, x, r0);
+      k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(L.n, L.As.sptr, L.As.perm, L.As.col, LP::AV(L.As), b, x,
+                                                         r0);
     }
     vcycle_level<BS, T>(s, H, H.prm, 0, r0, c0);
     k_axpy_inplace<T><<<blocks_for(m), kBlock, 0, s>>>(m, c0, x);

@@ -34,6 +34,7 @@ struct Error : std::runtime_error {
 #define PM_CHECK_LAUNCH() PM_HIP(hipGetLastError())
 
 constexpr int kSlice = 64;   // SELL slice height = one wavefront of rows
+constexpr int kSellWindow = 8;  // slices per window within which rows are sorted by length
 constexpr int kBlock = 256;  // default threads per workgroup for streaming kernels
 
 inline int blocks_for(int64_t n, int bs = kBlock) { return (int)((n + bs - 1) / bs); }
@@ -100,6 +101,8 @@ struct Sell {
   int64_t ncols = 0;        // total entry columns over all slices
   int64_t nnzb = 0;         // stored blocks of the source matrix (no padding)
   int* sptr = nullptr;      // nslices+1 (entry-column offsets)
+  int* perm = nullptr;      // 3x3 blocks: row held by each slot (rows sorted by length within
+                            // windows of kSellWindow slices, -1 empty); null: slot t holds row t
   int* col = nullptr;       // ncols*64
   double* val = nullptr;    // ncols*64*bs*bs
   float* val32 = nullptr;   // FP32 copy (mixed precision) or null
@@ -362,6 +365,11 @@ __device__ inline void sell_row(int e0, int e1, const int* __restrict__ col, con
       for (int q = 0; q < BS; ++q)
         acc[a] += (TA)val[((size_t)c * BS * BS + a * BS + q) * kSlice + lane] * (TA)xj[q];
   }
+}
+
+// row held by SELL slot t (perm null: slot t holds row t), -1 for an empty slot
+__device__ __forceinline__ int sell_row_of(const int* __restrict__ perm, int t, int n) {
+  return perm ? perm[t] : (t < n ? t : -1);
 }
 
 template <int BS>

@@ -29,17 +29,19 @@ struct AeLattice {
 // u-rows: y_u = A_uu u + sgn * A_up p     (sgn = +1: A_H; -1: A_H^T, since A_pu = -A_up^T)
 template <class T>
 __global__ void __launch_bounds__(256) k_ah_u(Grid G, int n, const int* __restrict__ sptr,
-                                              const int* __restrict__ col, const T* __restrict__ val,
+                                              const int* __restrict__ perm, const int* __restrict__ col,
+                                              const T* __restrict__ val,
                                               const double* __restrict__ ae, const uint8_t* __restrict__ ufix,
                                               const T* __restrict__ u, const T* __restrict__ p, double sgn,
                                               T* __restrict__ y) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = r / kSlice, lane = r % kSlice;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = t / kSlice, lane = t % kSlice;
   if (s * kSlice >= n) return;
   const int e0 = sptr[s], e1 = sptr[s + 1];
   double acc[3] = {0.0, 0.0, 0.0};
   sell_row<3, 3, T, double>(e0, e1, col, val, u, lane, acc);
-  if (r >= n) return;
+  const int r = sell_row_of(perm, t, n);
+  if (r < 0) return;
   int i, j, k;
   G.node_ijk(r, i, j, k);
   double cp[3] = {0.0, 0.0, 0.0};
@@ -427,7 +429,7 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
     if constexpr (sizeof(T) == 8) {
       const Sell& Auu = c->Hu.L[0].As;
       const int nth = Auu.nslices * kSlice;
-      k_ah_u<double><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.col, Auu.val, c->ae, c->ufix, u,
+      k_ah_u<double><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.perm, Auu.col, Auu.val, c->ae, c->ufix, u,
                                                            p, transpose ? -1.0 : 1.0, yu);
       // algorithmic bytes: A_uu blocks and column ids, u read, y_u written, coupling
       // columns a_T, p read, Dirichlet mask

@@ -3,6 +3,8 @@
 // row-wise Gustavson SpGEMM with per-wavefront LDS hashing, and inverses of
 // the diagonal blocks.  Every result is bitwise reproducible: no
 // floating-point atomics; summation orders are fixed.
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 #include <unordered_map>
 
@@ -153,10 +155,12 @@ void Csr::free_all() {
 
 void Sell::free_all() {
   dfree(sptr);
+  dfree(perm);
   dfree(col);
   dfree(val);
   dfree(val32);
   sptr = nullptr;
+  perm = nullptr;
   col = nullptr;
   val = nullptr;
   val32 = nullptr;
@@ -254,14 +258,44 @@ void scan_impl(hipStream_t s, const T* in, T* out, int64_t n, T* total_host) {
 }
 
 // ---------------------------------------------------------------------------
-// CSR -> SELL
-__global__ void k_slice_width(const int* __restrict__ rowptr, int n, int nslices, int* __restrict__ w) {
+// CSR -> SELL-C-sigma: within each window of kSellWindow slices the rows are
+// sorted by decreasing length (ties by row id), so the rows sharing a slice
+// have similar lengths and the padding to the slice width stays small.  The
+// kernels find each slot's row in perm; row results are unchanged.
+constexpr int kWinRows = kSellWindow * kSlice;  // 512
+
+__global__ void __launch_bounds__(kWinRows) k_sell_perm(const int* __restrict__ rowptr, int n, int* __restrict__ perm) {
+  __shared__ uint64_t key[kWinRows];
+  const int t = threadIdx.x;
+  const int r = blockIdx.x * kWinRows + t;
+  // ascending keys = decreasing length, then increasing row; empty slots last
+  key[t] = r < n ? ((uint64_t)(0x7FFFFFFF - (rowptr[r + 1] - rowptr[r])) << 32) | (uint32_t)r : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= kWinRows; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int o = t ^ j;
+      if (o > t) {
+        const uint64_t a = key[t], b = key[o];
+        const bool up = (t & k) == 0;
+        if ((a > b) == up) {
+          key[t] = b;
+          key[o] = a;
+        }
+      }
+      __syncthreads();
+    }
+  const uint64_t v = key[t];
+  perm[blockIdx.x * kWinRows + t] = v == ~0ull ? -1 : (int)(uint32_t)v;
+}
+
+__global__ void k_slice_width(const int* __restrict__ rowptr, const int* __restrict__ perm, int n, int nslices,
+                              int* __restrict__ w) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslices) return;
   int mx = 0;
   for (int l = 0; l < kSlice; ++l) {
-    const int r = s * kSlice + l;
-    if (r < n) mx = max(mx, rowptr[r + 1] - rowptr[r]);
+    const int r = sell_row_of(perm, s * kSlice + l, n);
+    if (r >= 0) mx = max(mx, rowptr[r + 1] - rowptr[r]);
   }
   w[s] = mx;
 }
@@ -269,13 +303,15 @@ __global__ void k_slice_width(const int* __restrict__ rowptr, int n, int nslices
 template <int BS>
 __global__ void k_sell_fill(const int* __restrict__ rowptr, const int* __restrict__ col,
                             const double* __restrict__ val, int n, int m, const int* __restrict__ sptr,
-                            int* __restrict__ scol, double* __restrict__ sval, float* __restrict__ sval32) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = r / kSlice, lane = r % kSlice;
+                            const int* __restrict__ perm, int* __restrict__ scol, double* __restrict__ sval,
+                            float* __restrict__ sval32) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = t / kSlice, lane = t % kSlice;
   if (s * kSlice >= n) return;
+  const int r = sell_row_of(perm, t, n);
   const int c0 = sptr[s], c1 = sptr[s + 1];
-  const int b0 = r < n ? rowptr[r] : 0, len = r < n ? rowptr[r + 1] - b0 : 0;
-  const int dummy = min(r, m - 1);
+  const int b0 = r >= 0 ? rowptr[r] : 0, len = r >= 0 ? rowptr[r + 1] - b0 : 0;
+  const int dummy = min(max(r, 0), m - 1);
   for (int c = c0; c < c1; ++c) {
     const int e = c - c0;
     const size_t slot = (size_t)c * kSlice + lane;
@@ -293,16 +329,18 @@ __global__ void k_sell_fill(const int* __restrict__ rowptr, const int* __restric
 // SELL SpMV: one thread per block row.
 template <int BS, class T>
 __global__ void __launch_bounds__(256) k_sell_spmv(int n, const int* __restrict__ sptr,
-                                                   const int* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ x, T* __restrict__ y) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = r / kSlice, lane = r % kSlice;
+                                                   const int* __restrict__ perm, const int* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ x,
+                                                   T* __restrict__ y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = t / kSlice, lane = t % kSlice;
   if (s * kSlice >= n) return;
   const int c0 = sptr[s], c1 = sptr[s + 1];
   T acc[BS];
   for (int q = 0; q < BS; ++q) acc[q] = 0;
   sell_row<BS, SellUnroll<BS>::value, T, T>(c0, c1, col, val, x, lane, acc);
-  if (r < n)
+  const int r = sell_row_of(perm, t, n);
+  if (r >= 0)
     for (int q = 0; q < BS; ++q) y[(size_t)r * BS + q] = acc[q];
 }
 
@@ -409,43 +447,55 @@ void csr_to_sell(hipStream_t s, const Csr& A, Sell& S, bool with_fp32) {
   S.m = A.m;
   S.nslices = (A.n + kSlice - 1) / kSlice;
   S.nnzb = A.nnzb;
+  // Sorting pays for 3x3 blocks (rows of 36-72 B per block against a 12-24 B
+  // vector entry); for scalar rows the gathers and scatters of the row
+  // vectors through perm cost more than the padding saved (measured)
+  if (A.bs == 3) {
+    const int nwin = (S.nslices + kSellWindow - 1) / kSellWindow;
+    S.perm = dalloc<int>((int64_t)nwin * kWinRows);
+    if (nwin > 0) k_sell_perm<<<nwin, kWinRows, 0, s>>>(A.rowptr, A.n, S.perm);
+  }
   int* w = dalloc<int>(S.nslices);
-  k_slice_width<<<blocks_for(S.nslices), kBlock, 0, s>>>(A.rowptr, A.n, S.nslices, w);
+  k_slice_width<<<blocks_for(S.nslices), kBlock, 0, s>>>(A.rowptr, S.perm, A.n, S.nslices, w);
   PM_CHECK_LAUNCH();
   S.sptr = dalloc<int>(S.nslices + 1);
   int total = 0;
   exclusive_scan(s, w, S.sptr, S.nslices, &total);
   dfree(w);
   S.ncols = total;
+  if (const char* v = getenv("PM_AMG_VERBOSE"))
+    if (v[0] == '1')
+      fprintf(stderr, "[sell] rows %d bs %d: stored %lld of %lld slots (fill %.3f)\n", A.n, A.bs, (long long)A.nnzb,
+              (long long)S.ncols * kSlice, (double)S.ncols * kSlice / std::max<int64_t>(1, A.nnzb));
   const int64_t bb = (int64_t)A.bs * A.bs;
   S.col = dalloc<int>(S.ncols * kSlice);
   S.val = dalloc<double>(S.ncols * kSlice * bb);
   S.val32 = with_fp32 ? dalloc<float>(S.ncols * kSlice * bb) : nullptr;
   const int nthreads = S.nslices * kSlice;
   if (A.bs == 3)
-    k_sell_fill<3><<<blocks_for(nthreads), kBlock, 0, s>>>(A.rowptr, A.col, A.val, A.n, A.m, S.sptr, S.col,
-                                                           S.val, S.val32);
+    k_sell_fill<3><<<blocks_for(nthreads), kBlock, 0, s>>>(A.rowptr, A.col, A.val, A.n, A.m, S.sptr, S.perm,
+                                                           S.col, S.val, S.val32);
   else
-    k_sell_fill<1><<<blocks_for(nthreads), kBlock, 0, s>>>(A.rowptr, A.col, A.val, A.n, A.m, S.sptr, S.col,
-                                                           S.val, S.val32);
+    k_sell_fill<1><<<blocks_for(nthreads), kBlock, 0, s>>>(A.rowptr, A.col, A.val, A.n, A.m, S.sptr, S.perm,
+                                                           S.col, S.val, S.val32);
   PM_CHECK_LAUNCH();
 }
 
 void sell_spmv(hipStream_t s, const Sell& A, const double* x, double* y) {
   const int nthreads = A.nslices * kSlice;
   if (A.bs == 3)
-    k_sell_spmv<3, double><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.col, A.val, x, y);
+    k_sell_spmv<3, double><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.perm, A.col, A.val, x, y);
   else
-    k_sell_spmv<1, double><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.col, A.val, x, y);
+    k_sell_spmv<1, double><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.perm, A.col, A.val, x, y);
   PM_CHECK_LAUNCH();
 }
 
 void sell_spmv32(hipStream_t s, const Sell& A, const float* x, float* y) {
   const int nthreads = A.nslices * kSlice;
   if (A.bs == 3)
-    k_sell_spmv<3, float><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.col, A.val32, x, y);
+    k_sell_spmv<3, float><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.perm, A.col, A.val32, x, y);
   else
-    k_sell_spmv<1, float><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.col, A.val32, x, y);
+    k_sell_spmv<1, float><<<blocks_for(nthreads), kBlock, 0, s>>>(A.n, A.sptr, A.perm, A.col, A.val32, x, y);
   PM_CHECK_LAUNCH();
 }
 
