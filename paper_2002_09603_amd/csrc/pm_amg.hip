@@ -938,9 +938,11 @@ void residual_csr(hipStream_t s, const Csr& A, int lanes, const T* val, const T*
   PM_CHECK_LAUNCH();
 }
 
-// lanes per row: about a quarter of the average row length, 4 to 16
+// lanes per row, 4 to 16: about a quarter of the average row length for
+// scalar rows, about half of it for 3x3 blocks (nine values per entry)
 inline int csr_lanes_for(const Csr& A) {
   const double avg = (double)A.nnzb / std::max(1, A.n);
+  if (A.bs == 3) return avg < 12.0 ? 4 : (avg < 24.0 ? 8 : 16);
   return avg < 24.0 ? 4 : (avg < 48.0 ? 8 : 16);
 }
 // restrictions P^T have few, long rows on the coarse levels: a wavefront per
