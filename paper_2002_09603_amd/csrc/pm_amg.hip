@@ -1123,12 +1123,15 @@ double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) 
 }
 
 // lambda_max(D^-1 A) for a CSR operator (power iteration, fixed start)
+// on the CSR arrays directly (lanes per row), without a sliced-ELL copy
 double estimate_lmax_csr(hipStream_t s, const Csr& A, const double* dinv, int its) {
-  Sell S;
-  csr_to_sell(s, A, S, false);
-  const double l = estimate_lmax(s, S, dinv, its);
-  S.free_all();
-  return l;
+  const int lanes = csr_lanes_for(A);
+  return power_lmax(s, A.n, A.bs, dinv, its, [&](const double* v, double* w) {
+    if (A.bs == 3)
+      residual_csr<3, double, false>(s, A, lanes, A.val, nullptr, v, w);
+    else
+      residual_csr<1, double, false>(s, A, lanes, A.val, nullptr, v, w);
+  });
 }
 
 void dense_inverse(hipStream_t s, const Csr& A, Hierarchy& H) {

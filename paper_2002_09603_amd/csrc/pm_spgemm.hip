@@ -104,17 +104,39 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
   const int e0 = valid ? arp[row] : 0;
   const int na = valid ? arp[row + 1] - e0 : 0;
   const bool staged = valid && na <= AMAX;
-  if (staged)
-    for (int q = lane; q < na; q += G) {
-      const int k = acol[e0 + q];
-      const int b0 = brp[k];
-      fb_l[grp][q] = b0;
-      pre_l[grp][q + 1] = brp[k + 1] - b0;
+  // B-row extents and their prefix sums: each lane takes AMAX/G consecutive
+  // entries, sums them, and the lane sums are scanned with shuffles
+  {
+    constexpr int CH = AMAX / G;
+    int len[CH], run = 0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int q = lane * CH + u;
+      len[u] = 0;
+      if (staged && q < na) {
+        const int k = acol[e0 + q];
+        const int b0 = brp[k];
+        fb_l[grp][q] = b0;
+        len[u] = brp[k + 1] - b0;
+      }
+      run += len[u];
     }
-  __syncthreads();
-  if (staged && lane == 0) {
-    pre_l[grp][0] = 0;
-    for (int q = 1; q <= na; ++q) pre_l[grp][q] += pre_l[grp][q - 1];
+    int incl = run;  // inclusive scan of the lane sums within the group
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const int v = __shfl_up(incl, o, G);
+      if (lane >= o) incl += v;
+    }
+    int acc = incl - run;
+    if (staged) {
+      if (lane == 0) pre_l[grp][0] = 0;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int q = lane * CH + u;
+        acc += len[u];
+        if (q < na) pre_l[grp][q + 1] = acc;
+      }
+    }
   }
   __syncthreads();
   auto insert = [&](int key) {
