@@ -125,6 +125,11 @@ typedef struct {
   double p_trunc_u;          /* A_uu hierarchy: drop prolongator blocks below this fraction of
                                 their row's largest (Frobenius norms), keeping the block row sum */
   double cheb_lower_pi;      /* Chebyshev interval lower end for C~_pi (0: use cheb_lower) */
+  int32_t block_minv;        /* 1: if every cell's M_T^-1 couples only the two faces of each direction
+                                (off-block entries within 1e-12 of the geometric mean of the
+                                diagonals: axis-aligned boxes, diagonal permeability), apply
+                                M_T^-1 and C~_T in the solve from the 9 block entries, leaving
+                                the rounding-level rest out; 0: always the full 6x6 matrices */
 } pm_opts;
 
 typedef struct {
@@ -135,6 +140,7 @@ typedef struct {
   double t_asm, t_setup, t_solve;   /* seconds: assembly, AMG + B~/C~ setup, Krylov solve */
   double opcx_u, opcx_pi;    /* AMG operator complexities */
   int32_t lattice_uu;        /* 1 if the finest A_uu level runs on the lattice operator */
+  int32_t block_minv;        /* 1 if M_T^-1 is stored and applied by direction blocks */
 } pm_info;
 
 /* Default options: rtol 1e-8, restart 100, max_it 1000, FP64, stabilize,
@@ -145,7 +151,8 @@ typedef struct {
  * Gram-Schmidt passes (restarted GMRES on the transposed preconditioned
  * operator stagnates with short restarts or one pass on strongly
  * heterogeneous permeability); lattice operator on; C~_pi prolongator
- * truncation 0.02 (C~_pi) and 0.02 (A_uu); cell-by-cell finest C~_pi level. */
+ * truncation 0.02 (C~_pi) and 0.02 (A_uu); cell-by-cell finest C~_pi level;
+ * M_T^-1 by direction blocks where the cells allow it. */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

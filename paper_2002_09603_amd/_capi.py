@@ -54,14 +54,15 @@ class pm_opts(C.Structure):
                 ("rtol_transpose", C.c_double), ("restart_transpose", C.c_int32),
                 ("orth_passes_transpose", C.c_int32), ("lattice_uu", C.c_int32),
                 ("p_trunc_pi", C.c_double), ("cell_pi", C.c_int32), ("p_trunc_u", C.c_double),
-                ("cheb_lower_pi", C.c_double)]
+                ("cheb_lower_pi", C.c_double), ("block_minv", C.c_int32)]
 
 
 class pm_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("levels_u", C.c_int32), ("levels_pi", C.c_int32),
                 ("relres_est", C.c_double), ("relres_true", C.c_double),
                 ("t_asm", C.c_double), ("t_setup", C.c_double), ("t_solve", C.c_double),
-                ("opcx_u", C.c_double), ("opcx_pi", C.c_double), ("lattice_uu", C.c_int32)]
+                ("opcx_u", C.c_double), ("opcx_pi", C.c_double), ("lattice_uu", C.c_int32),
+                ("block_minv", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

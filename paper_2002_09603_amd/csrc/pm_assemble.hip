@@ -553,7 +553,7 @@ Grid grid_of(const pm_ctx* c) {
   return G;
 }
 
-void check_status(pm_ctx* c, const char* where) {
+int check_status(pm_ctx* c, const char* where) {
   int st = 0;
   PM_HIP(hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->s));
   PM_HIP(hipStreamSynchronize(c->s));
@@ -563,6 +563,33 @@ void check_status(pm_ctx* c, const char* where) {
     throw Error(PM_EINVAL, std::string(where) + ": RT0 mass matrix not positive definite");
   if (st & kStatusNonFinite) throw Error(PM_EBREAKDOWN, std::string(where) + ": non-finite value");
   if (st & kStatusCapacity) throw Error(PM_EINTERNAL, std::string(where) + ": internal capacity exceeded");
+  return st;
+}
+
+// On an axis-aligned box with a diagonal permeability the RT0 basis
+// functions of faces of different directions are orthogonal in the K^-1
+// weighted product, so M_T, and M_T^-1, couple only the two faces of each
+// direction.  The computed matrices carry rounding-level off-block entries
+// (from the Jacobian's off-diagonal rounding).  k_minv_pattern flags a cell
+// whose off-block entries exceed 1e-12 of the geometric mean of the two
+// diagonals (|m_ab| <= sqrt(m_aa m_bb) for an SPD matrix; NaN flags too).
+// Without a flag the operator applications use the direction blocks only;
+// M^-1 itself, g, alpha and the assembled C~_pi keep every entry (the AMG
+// set-up sees the same matrix either way).
+__global__ void k_minv_pattern(Grid G, const double* __restrict__ Minv, int* status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool full = false;
+  if (c < G.nc) {
+    double dg[6];
+    for (int a = 0; a < 6; ++a) dg[a] = Minv[(size_t)(a * 7) * G.nc + c];
+    for (int a = 0; a < 6; ++a)
+      for (int b = a + 1; b < 6; ++b)
+        if ((a >> 1) != (b >> 1)) {
+          const double m = fabs(Minv[(size_t)(a * 6 + b) * G.nc + c]);
+          full |= !(m <= 1e-12 * sqrt(dg[a] * dg[b]));
+        }
+  }
+  if (__ballot(full) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, kStatusFullMinv);
 }
 
 void build_cpi(pm_ctx* c, hipStream_t s) {
@@ -598,6 +625,10 @@ void assemble_all(pm_ctx* c) {
   k_cell_data<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->coords, c->kappa, c->mu, c->biot, c->ae, c->vol,
                                                   c->Minv, c->g, c->alpha, c->status);
   PM_CHECK_LAUNCH();
+  if (c->opts.block_minv) {
+    k_minv_pattern<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->Minv, c->status);
+    PM_CHECK_LAUNCH();
+  }
   if (c->lattice) {
     if (!c->lat.Kh) {
       c->lat.Kh = dalloc<double>(576);
@@ -608,7 +639,8 @@ void assemble_all(pm_ctx* c) {
     k_q1_stiffness<<<blocks_for(8 * G.nc), kBlock, 0, s>>>(G, c->coords, c->E, c->nu, c->Ke, c->status);
   }
   PM_CHECK_LAUNCH();
-  check_status(c, "element kernels");
+  const int st = check_status(c, "element kernels");
+  c->mblock = c->opts.block_minv && !(st & kStatusFullMinv);
   k_stab_weights<<<blocks_for(c->nmacro), kBlock, 0, s>>>(G, c->E, c->vol, c->nu, c->biot, c->stabw);
   PM_CHECK_LAUNCH();
   if (!c->Auu.rowptr) {

@@ -44,7 +44,7 @@ int guarded(pm_ctx* c, F&& f) {
 void free_ctx_buffers(pm_ctx* c) {
   using pm::dfree;
   for (void* p : {(void*)c->coords, (void*)c->E, (void*)c->kappa, (void*)c->Ke, (void*)c->ae, (void*)c->vol,
-                  (void*)c->Minv, (void*)c->Mp, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
+                  (void*)c->Minv, (void*)c->Mp, (void*)c->Mb, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
                   (void*)c->ufix, (void*)c->pifix, (void*)c->status, (void*)c->V, (void*)c->Z, (void*)c->Zf, (void*)c->wvec,
                   (void*)c->rvec, (void*)c->xvec, (void*)c->red, (void*)c->hcol, (void*)c->pw64, (void*)c->pw32})
     dfree(p);
@@ -156,6 +156,7 @@ void setup_hierarchies(pm_ctx* c, bool with_u) {
   c->info.opcx_u = c->Hu.opcx;
   c->info.opcx_pi = c->Hpi.opcx;
   c->info.lattice_uu = c->lattice ? 1 : 0;
+  c->info.block_minv = c->mblock ? 1 : 0;
 }
 
 void assemble_and_setup(pm_ctx* c) {
@@ -218,6 +219,7 @@ void pm_default_opts(pm_opts* o) {
   o->cheb_lower_pi = 0.0;
   o->cell_pi = 1;
   o->theta_pi = 0.08;
+  o->block_minv = 1;
 }
 
 int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, double dt, const pm_opts* opts,

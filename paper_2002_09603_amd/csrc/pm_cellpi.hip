@@ -5,9 +5,13 @@
 // structure of arrays), and a face row is formed from the (one or two) cells
 // that share the face: 21 values per cell instead of 11 stored entries and
 // column indices per face, about a third of the bytes of the assembled rows,
-// and no index arrays (structured face numbering).  Dirichlet faces (the
-// drained top) are identity rows with zero columns, as in the assembled
-// matrix.  Coarser levels and the Galerkin products use the assembled matrix.
+// and no index arrays (structured face numbering).  When M_T^-1 couples only
+// the two faces of each direction (axis-aligned boxes, diagonal
+// permeability) the element matrix is kept as its 9 block entries and
+// dt / B~_T, 10 values per cell, and the rank-one term is formed on the fly
+// (g = M^-1 1 from the blocks).  Dirichlet faces (the drained top) are
+// identity rows with zero columns, as in the assembled matrix.  Coarser
+// levels and the Galerkin products use the assembled matrix.
 #include "pm_internal.h"
 
 namespace pm {
@@ -18,6 +22,8 @@ void CellPiOp::free_all() {
   C = nullptr;
   C32 = nullptr;
   on = false;
+  block = false;
+  nvals = 0;
 }
 
 namespace {
@@ -37,6 +43,26 @@ __global__ void k_cpi_cells(Grid G, const double* __restrict__ Minv, const doubl
       C[q] = v;
       if (C32) C32[q] = (float)v;
     }
+}
+
+// block form: the direction blocks of M_T^-1 ([3d] (2d,2d), [3d+1] (2d,2d+1),
+// [3d+2] (2d+1,2d+1)) and dt / B~_T
+__global__ void k_cpi_cells_block_minv(Grid G, const double* __restrict__ Minv, const double* __restrict__ bp,
+                                       double dt, double* __restrict__ C, float* __restrict__ C32) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  double v[10];
+  for (int d = 0; d < 3; ++d) {
+    const int a = 2 * d, b = 2 * d + 1;
+    v[3 * d + 0] = Minv[(size_t)(a * 6 + a) * G.nc + c];
+    v[3 * d + 1] = 0.5 * (Minv[(size_t)(a * 6 + b) * G.nc + c] + Minv[(size_t)(b * 6 + a) * G.nc + c]);
+    v[3 * d + 2] = Minv[(size_t)(b * 6 + b) * G.nc + c];
+  }
+  v[9] = dt / bp[c];
+  for (int q = 0; q < 10; ++q) {
+    C[(size_t)q * G.nc + c] = v[q];
+    if (C32) C32[(size_t)q * G.nc + c] = (float)v[q];
+  }
 }
 
 __device__ inline bool cell_of_thread(const Grid& G, uint32_t& i, uint32_t& j, uint32_t& k) {
@@ -68,14 +94,44 @@ struct CpiTerm {
   }
 };
 
-// Chebyshev step on the finest C~_pi level, one thread per cell (its owned faces)
+// the same from the block form: row L = 2d + s of
+// M^-1 - sc g g^T is the block row [m_L,2d, m_L,2d+1] on faces 2d, 2d+1
+// minus sc g_L (g^T x), g^T x over the free faces of the cell
 template <class T>
+struct CpiBlockTerm {
+  const Grid& G;
+  const T* __restrict__ C;
+  const T* __restrict__ x;
+  template <int L>
+  __device__ __forceinline__ T operator()(LocalFace<L>, uint32_t c, const uint32_t F[6], uint32_t ck) const {
+    constexpr int d = L >> 1, sd = L & 1;
+    T m[9], xv[6];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) m[q] = ld32(C + (size_t)q * G.nc, c);
+    const T sc = ld32(C + (size_t)9 * G.nc, c);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) xv[e] = ld32(x, F[e]);
+    if (ck == (uint32_t)G.nz - 1) xv[5] = (T)0;  // the top face of the top layer is a zero column
+    T gx = (T)0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gx += (m[3 * a] + m[3 * a + 1]) * xv[2 * a] + (m[3 * a + 1] + m[3 * a + 2]) * xv[2 * a + 1];
+    const T md = m[3 * d + 2 * sd], mo = m[3 * d + 1];
+    const T gl = md + mo;
+    return (sd ? mo : md) * xv[2 * d] + (sd ? md : mo) * xv[2 * d + 1] - sc * gl * gx;
+  }
+};
+
+template <class T, bool BLOCK>
+using CpiTermOf = typename std::conditional<BLOCK, CpiBlockTerm<T>, CpiTerm<T>>::type;
+
+// Chebyshev step on the finest C~_pi level, one thread per cell (its owned faces)
+template <class T, bool BLOCK>
 __global__ void __launch_bounds__(256) k_cp_cheb(Grid G, const T* __restrict__ C, const T* __restrict__ dinv,
                                                  const T* __restrict__ b, const T* __restrict__ xin,
                                                  T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
   uint32_t i, j, k;
   if (!cell_of_thread(G, i, j, k)) return;
-  owned_face_rows<T>(G, i, j, k, CpiTerm<T>{G, C, xin}, [&](uint32_t f, bool fixed, T acc) {
+  owned_face_rows<T>(G, i, j, k, CpiTermOf<T, BLOCK>{G, C, xin}, [&](uint32_t f, bool fixed, T acc) {
     const T ax = fixed ? xin[f] : acc;
     const T z = dinv[f] * (b[f] - ax);
     const T dn = c1 * d[f] + c2 * z;
@@ -84,20 +140,21 @@ __global__ void __launch_bounds__(256) k_cp_cheb(Grid G, const T* __restrict__ C
   });
 }
 
-template <class T>
+template <class T, bool BLOCK>
 __global__ void __launch_bounds__(256) k_cp_residual(Grid G, const T* __restrict__ C, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r) {
   uint32_t i, j, k;
   if (!cell_of_thread(G, i, j, k)) return;
-  owned_face_rows<T>(G, i, j, k, CpiTerm<T>{G, C, x},
+  owned_face_rows<T>(G, i, j, k, CpiTermOf<T, BLOCK>{G, C, x},
                      [&](uint32_t f, bool fixed, T acc) { r[f] = b[f] - (fixed ? x[f] : acc); });
 }
 
+template <bool BLOCK>
 __global__ void __launch_bounds__(256) k_cp_apply(Grid G, const double* __restrict__ C,
                                                   const double* __restrict__ x, double* __restrict__ y) {
   uint32_t i, j, k;
   if (!cell_of_thread(G, i, j, k)) return;
-  owned_face_rows<double>(G, i, j, k, CpiTerm<double>{G, C, x},
+  owned_face_rows<double>(G, i, j, k, CpiTermOf<double, BLOCK>{G, C, x},
                           [&](uint32_t f, bool fixed, double acc) { y[f] = fixed ? x[f] : acc; });
 }
 
@@ -113,10 +170,25 @@ const float* cp_C<float>(const CellPiOp& op) { return op.C32; }
 void cellpi_build(pm_ctx* c, hipStream_t s) {
   CellPiOp& op = c->cpi;
   const Grid G = grid_of(c);
-  if (!op.C) op.C = dalloc<double>(21 * G.nc);
-  if (c->opts.precond_fp32 && !op.C32) op.C32 = dalloc<float>(21 * G.nc);
-  k_cpi_cells<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->Minv, c->g, c->bp, c->dt, op.C,
-                                                     c->opts.precond_fp32 ? op.C32 : nullptr);
+  const int nv = c->mblock ? 10 : 21;
+  if (op.nvals != nv) {
+    dfree(op.C);
+    dfree(op.C32);
+    op.C = nullptr;
+    op.C32 = nullptr;
+    op.nvals = nv;
+  }
+  if (!op.C) op.C = dalloc<double>((int64_t)nv * G.nc);
+  if (c->opts.precond_fp32 && !op.C32) op.C32 = dalloc<float>((int64_t)nv * G.nc);
+  op.block = c->mblock;
+  if (op.block) {
+    // the block entries straight from M^-1 (c->Mb is packed on the other stream)
+    k_cpi_cells_block_minv<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->Minv, c->bp, c->dt, op.C,
+                                                                  c->opts.precond_fp32 ? op.C32 : nullptr);
+  } else {
+    k_cpi_cells<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->Minv, c->g, c->bp, c->dt, op.C,
+                                                       c->opts.precond_fp32 ? op.C32 : nullptr);
+  }
   PM_CHECK_LAUNCH();
   op.on = true;
 }
@@ -124,7 +196,10 @@ void cellpi_build(pm_ctx* c, hipStream_t s) {
 template <class T>
 void cellpi_cheb_step(hipStream_t s, const Grid& G, const CellPiOp& op, const T* dinv, const T* b, const T* xin,
                       T* xout, T* d, T c1, T c2) {
-  k_cp_cheb<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), dinv, b, xin, xout, d, c1, c2);
+  if (op.block)
+    k_cp_cheb<T, true><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), dinv, b, xin, xout, d, c1, c2);
+  else
+    k_cp_cheb<T, false><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), dinv, b, xin, xout, d, c1, c2);
   PM_CHECK_LAUNCH();
 }
 template void cellpi_cheb_step<double>(hipStream_t, const Grid&, const CellPiOp&, const double*, const double*,
@@ -134,7 +209,10 @@ template void cellpi_cheb_step<float>(hipStream_t, const Grid&, const CellPiOp&,
 
 template <class T>
 void cellpi_residual(hipStream_t s, const Grid& G, const CellPiOp& op, const T* b, const T* x, T* r) {
-  k_cp_residual<T><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), b, x, r);
+  if (op.block)
+    k_cp_residual<T, true><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), b, x, r);
+  else
+    k_cp_residual<T, false><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), b, x, r);
   PM_CHECK_LAUNCH();
 }
 template void cellpi_residual<double>(hipStream_t, const Grid&, const CellPiOp&, const double*, const double*,
@@ -143,7 +221,10 @@ template void cellpi_residual<float>(hipStream_t, const Grid&, const CellPiOp&, 
                                      float*);
 
 void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const double* x, double* y) {
-  k_cp_apply<<<blocks_for(G.nc), kBlock, 0, s>>>(G, op.C, x, y);
+  if (op.block)
+    k_cp_apply<true><<<blocks_for(G.nc), kBlock, 0, s>>>(G, op.C, x, y);
+  else
+    k_cp_apply<false><<<blocks_for(G.nc), kBlock, 0, s>>>(G, op.C, x, y);
   PM_CHECK_LAUNCH();
 }
 

@@ -309,5 +309,8 @@ __device__ inline void load_cell_coords(const Grid& G, const double* __restrict_
 
 // status word bits written by kernels (read back by the host)
 enum : int { kStatusInverted = 1, kStatusNonFinite = 2, kStatusCapacity = 4, kStatusBadPivot = 8 };
+// informational bit (not an error): some cell's M_T^-1 couples faces of
+// different directions beyond rounding
+enum : int { kStatusFullMinv = 16 };
 
 }  // namespace pm

@@ -174,11 +174,16 @@ void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const TX* u
 // vectors at node 0, and min |a|,|b|,|c| (synchronizes)
 void lattice_deviation(hipStream_t s, const Grid& G, const double* coords, double* dev, double* hmin);
 
-// C~_pi applied cell by cell from packed symmetric 6x6 element matrices
-// (pm_cellpi.hip): C[pk(a,b)*n_c + cell], a <= b, 21 per cell, FP64 and an
-// optional FP32 copy.
+// C~_pi applied cell by cell from its element matrices (pm_cellpi.hip), FP64
+// and an optional FP32 copy, structure of arrays [q*n_c + cell]:
+//   full:  packed symmetric 6x6, q = pk(a,b) for a <= b (21 per cell);
+//   block: M_T^-1 by direction blocks (q < 9, the layout of pm_ctx::Mb) and
+//          q = 9: dt / B~_T, the element matrix being M^-1 - (dt/B~) g g^T
+//          with g = M^-1 1 (10 per cell).
 struct CellPiOp {
   bool on = false;
+  bool block = false;
+  int nvals = 0;  // values per cell of the allocated arrays
   double* C = nullptr;
   float* C32 = nullptr;
   void free_all();
@@ -235,6 +240,8 @@ struct pm_ctx {
   double* vol = nullptr;     // nc
   double* Minv = nullptr;    // 36*nc inverse RT0 mass
   double* Mp = nullptr;      // 21*nc packed upper triangle of M^-1 (operator pi-rows)
+  bool mblock = false;       // M^-1 couples only the two faces of each direction (beyond rounding)
+  double* Mb = nullptr;      // 9*nc its blocks: [3d] (2d,2d), [3d+1] (2d,2d+1), [3d+2] (2d+1,2d+1)
   double* g = nullptr;       // 6*nc  M^-1 1
   double* alpha = nullptr;   // nc    1^T M^-1 1
   double* stabw = nullptr;   // nmacro: beta_M |M|
@@ -282,7 +289,7 @@ void lattice_finish(pm_ctx* c);        // lattice operator tables after assembly
 void cellpi_build(pm_ctx* c, hipStream_t s);          // packed C~_pi element matrices (pm_cellpi.hip)
 void build_cpi(pm_ctx* c, hipStream_t s);  // B~p, assembled C~pi for the current dt (after assemble_all)
 void build_rhs(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
-void check_status(pm_ctx* c, const char* where);
+int check_status(pm_ctx* c, const char* where);  // throws on error bits, returns the word
 
 // operators (pm_ops.hip)
 void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose);
@@ -290,7 +297,7 @@ void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose);    // FP3
 void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose);
 void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose);   // FP32 hierarchies only
 void apply_csr(pm_ctx* c, const Csr& A, const double* x, double* y);
-void pack_minv(pm_ctx* c);             // c->Mp from c->Minv
+void pack_minv(pm_ctx* c);             // c->Mp (or c->Mb when c->mblock) from c->Minv
 void reconstruct_w(pm_ctx* c, const double* p, const double* pi, double* w);
 void grad(pm_ctx* c, const double* lam, const double* x, const double* p_prev, double* dk,
           double* dE);

@@ -146,6 +146,56 @@ __global__ void __launch_bounds__(256) k_ah_pi(Grid G, const double* __restrict_
                           [&](uint32_t f, bool fixed, double acc) { y[f] = fixed ? (double)pi[f] : acc; });
 }
 
+// The same rows when M_T^-1 couples only the two faces of each direction
+// (up to rounding-level entries, which are left out): local face L = 2d + s
+// meets faces 2d and 2d+1 through the block [[m0, m1], [m1, m2]] of
+// direction d (Mb[3d + q]), and g_L = M^-1 1 is the block's row sum.
+template <class T>
+struct AhPiBlockTerm {
+  const Grid& G;
+  const double* __restrict__ Mb;
+  const T* __restrict__ p;
+  const T* __restrict__ pi;
+  double sp;
+  template <int L>
+  __device__ __forceinline__ double operator()(LocalFace<L>, uint32_t c, const uint32_t F[6], uint32_t ck) const {
+    constexpr int d = L >> 1, sd = L & 1;
+    const double md = ld32(Mb + (size_t)(3 * d + 2 * sd) * G.nc, c);
+    const double mo = ld32(Mb + (size_t)(3 * d + 1) * G.nc, c);
+    const double gl = sd ? mo + md : md + mo;
+    double v = -sp * gl * (double)ld32(p, c);
+    v += (sd ? mo : md) * (double)ld32(pi, F[2 * d]);
+    // the top face of the top layer is a zero column
+    if (d != 2 || ck != (uint32_t)G.nz - 1) v += (sd ? md : mo) * (double)ld32(pi, F[2 * d + 1]);
+    return v;
+  }
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_ah_pi_block(Grid G, const double* __restrict__ Mb,
+                                                     const T* __restrict__ p, const T* __restrict__ pi, double sp,
+                                                     double* __restrict__ y) {
+  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  int i, j, k;
+  G.cell_ijk(c, i, j, k);
+  owned_face_rows<double>(G, (uint32_t)i, (uint32_t)j, (uint32_t)k, AhPiBlockTerm<T>{G, Mb, p, pi, sp},
+                          [&](uint32_t f, bool fixed, double acc) { y[f] = fixed ? (double)pi[f] : acc; });
+}
+
+// the direction blocks of M_T^-1 (its only entries beyond rounding)
+__global__ void k_pack_mblock(Grid G, const double* __restrict__ Minv, double* __restrict__ Mb) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= G.nc) return;
+  for (int d = 0; d < 3; ++d) {
+    const int a = 2 * d, b = 2 * d + 1;
+    Mb[(size_t)(3 * d + 0) * G.nc + c] = Minv[(size_t)(a * 6 + a) * G.nc + c];
+    Mb[(size_t)(3 * d + 1) * G.nc + c] =
+        0.5 * (Minv[(size_t)(a * 6 + b) * G.nc + c] + Minv[(size_t)(b * 6 + a) * G.nc + c]);
+    Mb[(size_t)(3 * d + 2) * G.nc + c] = Minv[(size_t)(b * 6 + b) * G.nc + c];
+  }
+}
+
 // packed upper triangle of the symmetrised M_T^-1
 __global__ void k_pack_minv(Grid G, const double* __restrict__ Minv, double* __restrict__ Mp) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -448,7 +498,10 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
     k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->bc_kind, AeCells{c->ae, G.nc}, c->vol, c->alpha, c->g,
                                                      c->stabw, u, p, pi, c->S, c->dt, c->opts.stabilize, su, spi,
                                                      yp);
-  k_ah_pi<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Mp, c->g, p, pi, transpose ? c->dt : 1.0, ypi);
+  if (c->mblock)
+    k_ah_pi_block<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Mb, p, pi, transpose ? c->dt : 1.0, ypi);
+  else
+    k_ah_pi<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Mp, c->g, p, pi, transpose ? c->dt : 1.0, ypi);
   PM_CHECK_LAUNCH();
 }
 
@@ -526,6 +579,12 @@ void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose) {
 
 void pack_minv(pm_ctx* c) {
   const Grid G = grid_of(c);
+  if (c->mblock) {
+    if (!c->Mb) c->Mb = dalloc<double>(9 * G.nc);
+    k_pack_mblock<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Minv, c->Mb);
+    PM_CHECK_LAUNCH();
+    return;
+  }
   if (!c->Mp) c->Mp = dalloc<double>(21 * G.nc);
   k_pack_minv<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Minv, c->Mp);
   PM_CHECK_LAUNCH();

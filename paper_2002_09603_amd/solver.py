@@ -59,6 +59,7 @@ class Options:
     cell_pi: bool = True
     p_trunc_u: float = 0.02
     cheb_lower_pi: float = 0.0
+    block_minv: bool = True
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -87,6 +88,7 @@ class Options:
         o.cell_pi = int(self.cell_pi)
         o.p_trunc_u = self.p_trunc_u
         o.cheb_lower_pi = self.cheb_lower_pi
+        o.block_minv = int(self.block_minv)
         return o
 
 

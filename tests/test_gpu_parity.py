@@ -58,6 +58,8 @@ def test_operator_and_block_parity(name, lattice):
     assert (s.n_u, s.n_p, s.n_pi) == (B.n_u, B.n_p, B.n_pi)
     # uniform boxes take the lattice operator when allowed, perturbed meshes never
     assert s.info()["lattice_uu"] == int(lattice and not CASES[name].get("perturb", False))
+    # axis-aligned boxes (diagonal permeability) store M_T^-1 by direction blocks
+    assert s.info()["block_minv"] == int(not CASES[name].get("perturb", False))
     rng = np.random.default_rng(7)
     x = rng.standard_normal(s.N)
     y = _np(s.apply(_capi.PM_OP_AH, _t(x)))
@@ -218,20 +220,60 @@ def test_error_codes():
     assert e.value.code == _capi.PM_EINVAL
 
 
+@pytest.mark.parametrize("fp32", [False, True])
 @pytest.mark.parametrize("name", ["box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop"])
-def test_matrix_free_finest_levels_match_assembled(name):
+def test_matrix_free_finest_levels_match_assembled(name, fp32):
     """The V-cycles with the matrix-free finest levels (A_uu on lattices, C~_pi
-    cell by cell) equal those on the assembled finest matrices to FP64
-    rounding (same hierarchies below), and so does one M^-1 application."""
+    cell by cell, from the full or, on boxes, the direction-block element
+    matrices) equal those on the assembled finest matrices to FP64 rounding
+    (same hierarchies below), and so does one M^-1 application; with the FP32
+    preconditioner to FP32 rounding."""
     prob = _case(name)
+    print(f"[matrix-free finest] {name} fp32={fp32}", flush=True)
     rng = np.random.default_rng(11)
     out = {}
     for mf in (True, False):
-        s = from_problem(prob, Options(lattice_uu=mf, cell_pi=mf)).assemble()
+        s = from_problem(prob, Options(lattice_uu=mf, cell_pi=mf, precond_fp32=fp32)).assemble()
         xs = [_t(rng.standard_normal(n)) for n in (s.n_u, s.n_pi, s.N)]
         rng = np.random.default_rng(11)
         out[mf] = [_np(s.apply(op, x)) for op, x in zip(
             (_capi.PM_OP_VCYCLE_U, _capi.PM_OP_VCYCLE_PI, _capi.PM_OP_MINV), xs)]
         s.close()
     for a, b in zip(out[True], out[False]):
-        assert rel(a, b) <= 1e-12
+        assert rel(a, b) <= (1e-5 if fp32 else 1e-12)
+
+
+@pytest.mark.parametrize("name", ["box10x6x4", "rollers4x4x8_ptop"])
+def test_block_minv_matches_full(name):
+    """On axis-aligned boxes the direction-block form of M_T^-1 (9 entries per
+    cell, the rounding-level rest left out of the operator applications)
+    gives the operators of the full 6x6 form to FP64 rounding, the same AMG
+    hierarchies (built from the full matrices either way), hence the same
+    V-cycles to rounding, and the solved fields to the solver tolerance."""
+    prob = _case(name)
+    print(f"[block M^-1] {name}", flush=True)
+    rng = np.random.default_rng(5)
+    out = {}
+    for blk in (True, False):
+        for fp32 in (False, True):
+            s = from_problem(prob, Options(block_minv=blk, precond_fp32=fp32, rtol=1e-12,
+                                           restart=100, max_it=600)).assemble()
+            assert s.info()["block_minv"] == int(blk)
+            rng = np.random.default_rng(5)
+            x, xpi = _t(rng.standard_normal(s.N)), _t(rng.standard_normal(s.n_pi))
+            ops = [_np(s.apply(op, x)) for op in (_capi.PM_OP_AH, _capi.PM_OP_AHT)]
+            ops.append(_np(s.apply(_capi.PM_OP_CPI, xpi)))
+            ops.append(_np(s.apply(_capi.PM_OP_VCYCLE_PI, xpi)))
+            ops.append(_np(s.apply(_capi.PM_OP_MINV, x)))
+            u, pi, p, info = s.solve(s.build_rhs())
+            assert info["converged"]
+            out[blk, fp32] = ops + [_np(u), _np(pi), _np(p)]
+            s.close()
+    for fp32 in (False, True):
+        a, b = out[True, fp32], out[False, fp32]
+        for k in range(3):
+            assert rel(a[k], b[k]) <= 1e-14
+        assert rel(a[3], b[3]) <= 1e-12
+        assert rel(a[4], b[4]) <= (1e-5 if fp32 else 1e-12)
+        for k in range(5, 8):
+            assert rel(a[k], b[k]) <= 1e-9
