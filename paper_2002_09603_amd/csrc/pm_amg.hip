@@ -1086,52 +1086,122 @@ double sum_squares(hipStream_t s, const double* x, int64_t n, double* part, doub
 }
 
 // lambda_max(D^-1 A) by power iteration from a fixed pseudo-random start;
-// spmv(v, w) launches w = A v
+// spmv(stream, v, w) launches w = A v on the stream.  The iteration can run
+// on a second stream while the caller's stream goes on (power_start /
+// power_finish): it reads only the operator and D^-1, which the caller keeps
+// unchanged until the result is taken, and the result does not depend on the
+// stream.
+struct PowerJob {
+  hipStream_t s2 = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+  double *v = nullptr, *w = nullptr, *pbuf = nullptr, *nsq = nullptr;
+  bool pending() const { return s2 != nullptr; }
+  PowerJob() = default;
+  PowerJob(const PowerJob&) = delete;
+  PowerJob& operator=(const PowerJob&) = delete;
+  PowerJob& operator=(PowerJob&& o) noexcept {
+    std::swap(s2, o.s2);
+    std::swap(ready, o.ready);
+    std::swap(done, o.done);
+    std::swap(v, o.v);
+    std::swap(w, o.w);
+    std::swap(pbuf, o.pbuf);
+    std::swap(nsq, o.nsq);
+    return *this;
+  }
+  void release() {
+    if (s2) (void)hipStreamSynchronize(s2);  // the buffers are in use until the stream drains
+    for (double* p : {v, w, pbuf, nsq}) dfree(p);
+    if (ready) (void)hipEventDestroy(ready);
+    if (done) (void)hipEventDestroy(done);
+    s2 = nullptr;
+    ready = done = nullptr;
+    v = w = pbuf = nsq = nullptr;
+  }
+  ~PowerJob() { release(); }
+};
+
 template <class F>
-double power_lmax(hipStream_t s, int64_t nb, int bs, const double* dinv, int its, F spmv) {
+void power_launch(hipStream_t s, const PowerJob& j, int64_t nb, int bs, const double* dinv, int its, F spmv) {
   const int64_t n = nb * bs;
-  double* v = dalloc<double>(n);
-  double* w = dalloc<double>(n);
-  double* pbuf = dalloc<double>(2 * kRedBlocks);
-  double *part = pbuf, *part2 = pbuf + kRedBlocks;
-  double* nsq = dalloc<double>(1);
-  k_rand_vec<<<blocks_for(n), kBlock, 0, s>>>(n, v, 0x9e3779b9u);
+  double *part = j.pbuf, *part2 = j.pbuf + kRedBlocks;
+  k_rand_vec<<<blocks_for(n), kBlock, 0, s>>>(n, j.v, 0x9e3779b9u);
   // ||v|| stays on the device: lambda ~ ||D^-1 A v|| / ||v|| with v normalised
-  k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(v, n, part);
+  k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(j.v, n, part);
   for (int k = 0; k < its; ++k) {
-    spmv(v, w);
+    spmv(s, j.v, j.w);
     if (bs == 3)
-      k_power_step<3><<<kRedBlocks, 256, 0, s>>>(n, dinv, w, part, v, part2);
+      k_power_step<3><<<kRedBlocks, 256, 0, s>>>(n, dinv, j.w, part, j.v, part2);
     else
-      k_power_step<1><<<kRedBlocks, 256, 0, s>>>(n, dinv, w, part, v, part2);
+      k_power_step<1><<<kRedBlocks, 256, 0, s>>>(n, dinv, j.w, part, j.v, part2);
     std::swap(part, part2);
   }
-  k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, nsq);
+  k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, j.nsq);
   PM_CHECK_LAUNCH();
+}
+
+void power_alloc(PowerJob& j, int64_t n) {
+  j.v = dalloc<double>(n);
+  j.w = dalloc<double>(n);
+  j.pbuf = dalloc<double>(2 * kRedBlocks);
+  j.nsq = dalloc<double>(1);
+}
+
+template <class F>
+double power_lmax(hipStream_t s, int64_t nb, int bs, const double* dinv, int its, F spmv) {
+  PowerJob j;
+  power_alloc(j, nb * bs);
+  power_launch(s, j, nb, bs, dinv, its, spmv);
   double h = 0.0;
-  PM_HIP(hipMemcpyAsync(&h, nsq, sizeof(double), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipMemcpyAsync(&h, j.nsq, sizeof(double), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
-  dfree(v);
-  dfree(w);
-  dfree(pbuf);
-  dfree(nsq);
+  return std::sqrt(h);
+}
+
+// the same on stream s2, after the work queued so far on s
+template <class F>
+void power_start(PowerJob& j, hipStream_t s, hipStream_t s2, int64_t nb, int bs, const double* dinv, int its,
+                 F spmv) {
+  j.release();
+  power_alloc(j, nb * bs);
+  j.s2 = s2;
+  PM_HIP(hipEventCreateWithFlags(&j.ready, hipEventDisableTiming));
+  PM_HIP(hipEventCreateWithFlags(&j.done, hipEventDisableTiming));
+  PM_HIP(hipEventRecord(j.ready, s));
+  PM_HIP(hipStreamWaitEvent(s2, j.ready, 0));
+  power_launch(s2, j, nb, bs, dinv, its, spmv);
+  PM_HIP(hipEventRecord(j.done, s2));
+}
+
+double power_finish(PowerJob& j) {
+  double h = 0.0;
+  PM_HIP(hipMemcpyAsync(&h, j.nsq, sizeof(double), hipMemcpyDeviceToHost, j.s2));
+  PM_HIP(hipStreamSynchronize(j.s2));
+  j.release();
   return std::sqrt(h);
 }
 
 double estimate_lmax(hipStream_t s, const Sell& A, const double* dinv, int its) {
-  return power_lmax(s, A.n, A.bs, dinv, its, [&](const double* v, double* w) { sell_spmv(s, A, v, w); });
+  return power_lmax(s, A.n, A.bs, dinv, its,
+                    [&](hipStream_t ss, const double* v, double* w) { sell_spmv(ss, A, v, w); });
 }
 
 // lambda_max(D^-1 A) for a CSR operator (power iteration, fixed start)
 // on the CSR arrays directly (lanes per row), without a sliced-ELL copy
-double estimate_lmax_csr(hipStream_t s, const Csr& A, const double* dinv, int its) {
-  const int lanes = csr_lanes_for(A);
-  return power_lmax(s, A.n, A.bs, dinv, its, [&](const double* v, double* w) {
+// w = A v on the CSR arrays with csr_lanes_for(A) lanes per row
+struct CsrSpmv {
+  const Csr& A;
+  int lanes;
+  void operator()(hipStream_t ss, const double* v, double* w) const {
     if (A.bs == 3)
-      residual_csr<3, double, false>(s, A, lanes, A.val, nullptr, v, w);
+      residual_csr<3, double, false>(ss, A, lanes, A.val, nullptr, v, w);
     else
-      residual_csr<1, double, false>(s, A, lanes, A.val, nullptr, v, w);
-  });
+      residual_csr<1, double, false>(ss, A, lanes, A.val, nullptr, v, w);
+  }
+};
+
+double estimate_lmax_csr(hipStream_t s, const Csr& A, const double* dinv, int its) {
+  return power_lmax(s, A.n, A.bs, dinv, its, CsrSpmv{A, csr_lanes_for(A)});
 }
 
 void dense_inverse(hipStream_t s, const Csr& A, Hierarchy& H) {
@@ -1280,8 +1350,11 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
   *nagg_out = nagg;
 }
 
+// lmax_job: the level's own power iteration when it is still running on the
+// side stream (taken here if the transfer needs it)
 template <int BS>
-void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Acoarse, const Grid* SG) {
+void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Acoarse, const Grid* SG,
+                          PowerJob* lmax_job) {
   const Csr& A = L.A;
   const int n = A.n;
   int* agg = dalloc<int>(n);
@@ -1324,7 +1397,7 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   dfree(weak_rows);
   const bool filtered = nweak > 0;
   double* dinvF = nullptr;
-  double lF = L.lmax;
+  double lF = 0.0;
   Csr P;
   if (filtered) {
     AF.nnzb = fnnz;
@@ -1338,11 +1411,21 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
     PM_CHECK_LAUNCH();
     dinvF = dalloc<double>((int64_t)n * BS * BS);
     block_diag_inverse(s, AF, dinvF);
-    lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
-    // smoothed prolongator P = (I - 4/(3 lmax) D_F^-1 A_F) P_tent on the pattern of A_F P_tent
-    spgemm(s, AF, Pt, P, agg);
+    // smoothed prolongator P = (I - 4/(3 lmax) D_F^-1 A_F) P_tent on the pattern of A_F P_tent;
+    // lambda_max(D_F^-1 A_F) on the side stream, if any, during the product
+    if (prm.side) {
+      PowerJob jf;
+      power_start(jf, s, prm.side, n, BS, dinvF, prm.power_its, CsrSpmv{AF, csr_lanes_for(AF)});
+      spgemm(s, AF, Pt, P, agg);
+      lF = power_finish(jf);
+    } else {
+      lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
+      spgemm(s, AF, Pt, P, agg);
+    }
   } else {
     spgemm(s, A, Pt, P, agg);
+    if (lmax_job && lmax_job->pending()) L.lmax = power_finish(*lmax_job);
+    lF = L.lmax;
   }
   dfree(strong);
   Pt.free_all();
@@ -1578,36 +1661,51 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
                                                                          L.dinv32);
       PM_CHECK_LAUNCH();
     }
+    // the finest level's lambda_max runs on the side stream, if any, during
+    // the aggregation (the transfer takes it when it needs it)
+    PowerJob job;
     if (on_lattice) {
-      L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](const double* v, double* w) {
+      auto op = [&](hipStream_t ss, const double* v, double* w) {
         if (H.lat)
-          lattice_apply(s, H.grid, *H.lat, v, w);
+          lattice_apply(ss, H.grid, *H.lat, v, w);
         else
-          cellpi_apply(s, H.grid, *H.cpi, v, w);
-      });
+          cellpi_apply(ss, H.grid, *H.cpi, v, w);
+      };
+      if (prm.side)
+        power_start(job, s, prm.side, L.n, L.bs, L.dinv, prm.power_its, op);
+      else
+        L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, op);
     } else if (L.csr_cycle) {
       const Csr& A = L.A;
-      L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](const double* v, double* w) {
+      L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](hipStream_t ss, const double* v, double* w) {
         if (L.bs == 3)
-          residual_csr<3, double, false>(s, A, L.csr_lanes, A.val, nullptr, v, w);
+          residual_csr<3, double, false>(ss, A, L.csr_lanes, A.val, nullptr, v, w);
         else
-          residual_csr<1, double, false>(s, A, L.csr_lanes, A.val, nullptr, v, w);
+          residual_csr<1, double, false>(ss, A, L.csr_lanes, A.val, nullptr, v, w);
       });
     } else
       L.lmax = estimate_lmax(s, L.As, L.dinv, prm.power_its);
-    if (verbose)
-      fprintf(stderr, "[amg bs=%d] level %d: rows %d, blocks %lld (%.1f/row), lmax(D^-1 A) %.4f, sliced-ELL fill %.3f\n",
-              L.bs, l, L.n, (long long)L.A.nnzb, (double)L.A.nnzb / std::max(1, L.n), L.lmax,
-              L.As.nslices ? (double)L.As.ncols * kSlice / std::max<int64_t>(1, L.A.nnzb) : 0.0);
+    auto report = [&] {
+      if (verbose)
+        fprintf(stderr,
+                "[amg bs=%d] level %d: rows %d, blocks %lld (%.1f/row), lmax(D^-1 A) %.4f, sliced-ELL fill %.3f\n",
+                L.bs, l, L.n, (long long)L.A.nnzb, (double)L.A.nnzb / std::max(1, L.n), L.lmax,
+                L.As.nslices ? (double)L.As.ncols * kSlice / std::max<int64_t>(1, L.A.nnzb) : 0.0);
+    };
+    if (!job.pending()) report();
     Csr Ac;
     const auto tl0 = std::chrono::steady_clock::now();
     // the finest level of either hierarchy is the structured node or face graph
     const Grid* sg =
         (l == 0 && G && ((L.bs == 3 && L.n == G->nn) || (L.bs == 1 && L.n == G->nf))) ? G : nullptr;
     if (L.bs == 3)
-      build_level_transfer<3>(s, L, prm, Ac, sg);
+      build_level_transfer<3>(s, L, prm, Ac, sg, &job);
     else
-      build_level_transfer<1>(s, L, prm, Ac, sg);
+      build_level_transfer<1>(s, L, prm, Ac, sg, &job);
+    if (job.pending()) {
+      L.lmax = power_finish(job);
+      report();
+    }
     if (verbose) {
       PM_HIP(hipStreamSynchronize(s));
       fprintf(stderr, "[amg bs=%d] level %d transfer + Galerkin product: %.3f s\n", L.bs, l,

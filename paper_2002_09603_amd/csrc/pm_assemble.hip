@@ -249,45 +249,73 @@ struct KeLattice {
   __device__ double operator()(int row, int col, int64_t c) const { return E[c] * Kh[row * 24 + col]; }
 };
 
+// A_uu blocks, one thread per (node, neighbour slot), a workgroup per
+// kFillNodes consecutive nodes (27 threads each).  The workgroup's blocks
+// are the contiguous rows rowptr[n0] .. rowptr[n0 + kFillNodes]: each thread
+// sums its 3x3 block over the cells the two nodes share and stages it in LDS,
+// and the workgroup then writes the whole range with consecutive 8-byte
+// stores (a thread's own 72-byte block would make every store instruction
+// touch 64 scattered words).  On lattices the unit-modulus element matrix is
+// read from LDS.
+constexpr int kFillNodes = 16, kFillThreads = 27 * kFillNodes;
+
 template <class KS>
-__global__ void __launch_bounds__(256) k_auu_fill(Grid G, KS Ke, const uint8_t* __restrict__ ufix,
-                                                  const int* __restrict__ rowptr, int* __restrict__ col,
-                                                  double* __restrict__ val) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 27 * G.nn) return;
-  const int64_t n = t / 27;
-  const int q = (int)(t - n * 27);
+__global__ void __launch_bounds__(kFillThreads) k_auu_fill(Grid G, KS Ke, const uint8_t* __restrict__ ufix,
+                                                           const int* __restrict__ rowptr, int* __restrict__ col,
+                                                           double* __restrict__ val) {
+  constexpr bool kLat = std::is_same<KS, KeLattice>::value;
+  __shared__ double kh[kLat ? 576 : 1];
+  __shared__ double stage[kFillThreads * 9];
+  const int n0 = blockIdx.x * kFillNodes;  // < nn (grid = ceil(nn / kFillNodes))
+  if constexpr (kLat)
+    for (int q = threadIdx.x; q < 576; q += kFillThreads) kh[q] = Ke.Kh[q];
+  const int base = rowptr[n0];
+  const int end = rowptr[min((int64_t)n0 + kFillNodes, G.nn)];
+  __syncthreads();
+  const KS K = [&] {
+    if constexpr (kLat)
+      return KeLattice{kh, Ke.E};
+    else
+      return Ke;
+  }();
+  const int ln = (int)threadIdx.x / 27, q = (int)threadIdx.x - 27 * ln;
+  const int64_t n = (int64_t)n0 + ln;
   const int di = q % 3 - 1, dj = (q / 3) % 3 - 1, dk = q / 9 - 1;
-  int i, j, k;
-  G.node_ijk(n, i, j, k);
+  int i = 0, j = 0, k = 0;
+  if (n < G.nn) G.node_ijk(n, i, j, k);
   const int i2 = i + di, j2 = j + dj, k2 = k + dk;
-  if (i2 < 0 || i2 > G.nx || j2 < 0 || j2 > G.ny || k2 < 0 || k2 > G.nz) return;
-  const int xlo = i > 0 ? -1 : 0, ylo = j > 0 ? -1 : 0, zlo = k > 0 ? -1 : 0;
-  const int nxc = (i < G.nx ? 1 : 0) - xlo + 1, nyc = (j < G.ny ? 1 : 0) - ylo + 1;
-  const int64_t pos = rowptr[n] + ((dk - zlo) * nyc + (dj - ylo)) * nxc + (di - xlo);
-  const int64_t m = G.node(i2, j2, k2);
-  double B[9];
-  for (int e = 0; e < 9; ++e) B[e] = 0.0;
-  // cells containing both nodes: ci in {i-1,i} and {i2-1,i2}, inside the grid
-  for (int ck = max(max(k, k2) - 1, 0); ck <= min(min(k, k2), G.nz - 1); ++ck)
-    for (int cj = max(max(j, j2) - 1, 0); cj <= min(min(j, j2), G.ny - 1); ++cj)
-      for (int ci = max(max(i, i2) - 1, 0); ci <= min(min(i, i2), G.nx - 1); ++ci) {
-        const int64_t c = G.cell(ci, cj, ck);
-        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
-        const int b = (i2 - ci) + 2 * (j2 - cj) + 4 * (k2 - ck);
-        for (int r = 0; r < 3; ++r)
-          for (int s = 0; s < 3; ++s) B[r * 3 + s] += Ke(3 * a + r, 3 * b + s, c);
+  if (n < G.nn && i2 >= 0 && i2 <= G.nx && j2 >= 0 && j2 <= G.ny && k2 >= 0 && k2 <= G.nz) {
+    const int xlo = i > 0 ? -1 : 0, ylo = j > 0 ? -1 : 0, zlo = k > 0 ? -1 : 0;
+    const int nxc = (i < G.nx ? 1 : 0) - xlo + 1, nyc = (j < G.ny ? 1 : 0) - ylo + 1;
+    const int pos = rowptr[n] + ((dk - zlo) * nyc + (dj - ylo)) * nxc + (di - xlo);
+    const int64_t m = G.node(i2, j2, k2);
+    double B[9];
+    for (int e = 0; e < 9; ++e) B[e] = 0.0;
+    // cells containing both nodes: ci in {i-1,i} and {i2-1,i2}, inside the grid
+    for (int ck = max(max(k, k2) - 1, 0); ck <= min(min(k, k2), G.nz - 1); ++ck)
+      for (int cj = max(max(j, j2) - 1, 0); cj <= min(min(j, j2), G.ny - 1); ++cj)
+        for (int ci = max(max(i, i2) - 1, 0); ci <= min(min(i, i2), G.nx - 1); ++ci) {
+          const int64_t c = G.cell(ci, cj, ck);
+          const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
+          const int b = (i2 - ci) + 2 * (j2 - cj) + 4 * (k2 - ck);
+          for (int r = 0; r < 3; ++r)
+            for (int s = 0; s < 3; ++s) B[r * 3 + s] += K(3 * a + r, 3 * b + s, c);
+        }
+    for (int r = 0; r < 3; ++r) {
+      const bool fr = ufix[3 * n + r];
+      for (int s = 0; s < 3; ++s) {
+        const bool fixed = fr || ufix[3 * m + s];
+        double v = fixed ? 0.0 : B[r * 3 + s];
+        if (m == n && r == s && fr) v = 1.0;
+        stage[(pos - base) * 9 + r * 3 + s] = v;
       }
-  for (int r = 0; r < 3; ++r) {
-    const bool fr = ufix[3 * n + r];
-    for (int s = 0; s < 3; ++s) {
-      const bool fixed = fr || ufix[3 * m + s];
-      double v = fixed ? 0.0 : B[r * 3 + s];
-      if (m == n && r == s && fr) v = 1.0;
-      val[(size_t)pos * 9 + r * 3 + s] = v;
     }
+    col[pos] = (int)m;
   }
-  col[pos] = (int)m;
+  __syncthreads();
+  const int cnt = (end - base) * 9;
+  double* dst = val + (size_t)base * 9;
+  for (int e = threadIdx.x; e < cnt; e += kFillThreads) dst[e] = stage[e];
 }
 
 // Diagonal entries of A_uu (what k_auu_fill stores on the diagonal, with the
@@ -670,11 +698,11 @@ void assemble_auu(pm_ctx* c) {
   const Grid G = grid_of(c);
   hipStream_t s = c->s;
   if (c->lattice)
-    k_auu_fill<<<blocks_for(27 * G.nn), kBlock, 0, s>>>(G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->Auu.rowptr,
-                                                   c->Auu.col, c->Auu.val);
+    k_auu_fill<<<(G.nn + kFillNodes - 1) / kFillNodes, kFillThreads, 0, s>>>(
+        G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->Auu.rowptr, c->Auu.col, c->Auu.val);
   else
-    k_auu_fill<<<blocks_for(27 * G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->Auu.rowptr, c->Auu.col,
-                                                   c->Auu.val);
+    k_auu_fill<<<(G.nn + kFillNodes - 1) / kFillNodes, kFillThreads, 0, s>>>(
+        G, KeCells{c->Ke, G.nc}, c->ufix, c->Auu.rowptr, c->Auu.col, c->Auu.val);
   PM_CHECK_LAUNCH();
   if (c->lattice) lattice_finish(c);
   pack_minv(c);

@@ -55,6 +55,12 @@ void free_ctx_buffers(pm_ctx* c) {
   c->Hpi.free_all();
   c->lat.free_all();
   c->cpi.free_all();
+  for (hipStream_t* ps : {&c->s_side_u, &c->s_side_pi})
+    if (*ps) {
+      (void)hipStreamSynchronize(*ps);
+      (void)hipStreamDestroy(*ps);
+      *ps = nullptr;
+    }
   if (c->s_aux) {
     (void)hipStreamSynchronize(c->s_aux);
     (void)hipStreamDestroy(c->s_aux);
@@ -86,6 +92,7 @@ pm::AmgParams params_u(const pm_ctx* c) {
   p.cheb_lower = c->opts.cheb_lower;
   p.fp32 = c->opts.precond_fp32 != 0;
   p.p_trunc = c->opts.p_trunc_u;
+  p.side = c->s_side_u;
   return p;
 }
 
@@ -98,6 +105,7 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   p.agg_dist = c->opts.agg_dist_pi;
   p.p_trunc = c->opts.p_trunc_pi;
   if (c->opts.cheb_lower_pi > 0.0) p.cheb_lower = c->opts.cheb_lower_pi;
+  p.side = c->s_side_pi;
   return p;
 }
 
@@ -124,6 +132,8 @@ void setup_hierarchies(pm_ctx* c, bool with_u) {
   if (with_u) {
     PM_HIP(hipStreamSynchronize(c->s));
     if (!c->s_aux) PM_HIP(hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking));
+    if (!c->s_side_u) PM_HIP(hipStreamCreateWithFlags(&c->s_side_u, hipStreamNonBlocking));
+    if (!c->s_side_pi) PM_HIP(hipStreamCreateWithFlags(&c->s_side_pi, hipStreamNonBlocking));
     int dev = 0;
     PM_HIP(hipGetDevice(&dev));
     std::exception_ptr pi_err;

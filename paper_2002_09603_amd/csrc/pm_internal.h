@@ -139,6 +139,7 @@ struct AmgParams {
   int power_its = 15;
   double p_trunc = 0.0;            // scalar prolongator truncation threshold (0: none)
   bool fp32 = false;
+  hipStream_t side = nullptr;      // optional second stream for set-up power iterations
 };
 
 // A_uu on a mesh whose cells are translates of one parallelepiped: every
@@ -219,6 +220,7 @@ struct Hierarchy {
 struct pm_ctx {
   hipStream_t s = nullptr;
   hipStream_t s_aux = nullptr;  // library-owned second stream (C~_pi hierarchy set-up)
+  hipStream_t s_side_u = nullptr, s_side_pi = nullptr;  // set-up power iterations of each hierarchy
   int nx = 0, ny = 0, nz = 0;
   int64_t nn = 0, nc = 0, nfx = 0, nfy = 0, nfz = 0, nf = 0, nmacro = 0;
   int64_t n_u = 0, n_p = 0, n_pi = 0, N = 0;
