@@ -1,19 +1,24 @@
 // Sparse matrix-matrix product C = A * B for the Galerkin products of the AMG
 // setup (block CSR, square blocks of size 1 or 3), row-wise (Gustavson).
 //
-// Rows are binned by ub = sum over the row of A of the lengths of the B rows
-// it touches (an upper bound on the row's distinct columns):
-//   small   ub <= 64   16 lanes per row (4 rows per wavefront)
-//   medium  ub <= 512  one wavefront per row
-//   large   otherwise  one wavefront per row, 8192-slot hash
-// Symbolic: one pass; each group hashes its row's column ids in LDS, ranks
-// the distinct ids (sorted order) and writes them to a scratch array at the
-// row's ub offset; a compaction copies them into C after a scan of the counts.
-// Numeric: the entries of A's row are taken in order; lanes of the group
-// cover the entries of the corresponding B row, whose columns are distinct,
-// so each accumulator slot has one writer per step and the summation order is
-// fixed (bitwise reproducible).  Accumulators live in LDS (large rows fall
-// back to the output array when they do not fit).
+// Symbolic: rows are binned by ub = sum over the row of A of the lengths of
+// the B rows it touches (an upper bound on the row's distinct columns):
+//   small   ub <= 64   16 lanes per row, 128-slot hash
+//   medium  ub <= 512  the small configuration first; rows with more than 64
+//                      distinct columns are redone with a wavefront per row
+//                      and a 1024-slot hash
+//   large   otherwise  a wavefront per row, 1024-slot hash first, the rest
+//                      with 8192 slots
+// Each group hashes its row's column ids in LDS, ranks the distinct ids
+// (sorted order) and writes them to a scratch array at the row's ub offset;
+// a compaction copies them into C after a scan of the counts.
+// Numeric: rows are binned by their exact number of distinct columns (<= 16,
+// <= 64: 16 lanes per row; <= 512, more: a wavefront per row).  The entries
+// of A's row are taken in order; lanes of the group cover the entries of the
+// corresponding B row, whose columns are distinct, so each accumulator slot
+// has one writer per step and the summation order is fixed (bitwise
+// reproducible).  Accumulators live in LDS (large rows fall back to the
+// output array when they do not fit).
 #include <climits>
 
 #include "pm_internal.h"
@@ -39,35 +44,37 @@ __global__ void __launch_bounds__(256) k_ub(int n, const int* __restrict__ arp, 
   if (i < n && l == 0) ub[i] = s;
 }
 
-// Row lists per class: class 0 if v <= t0, 1 if v <= t1, else 2.  Counts are
-// aggregated per workgroup (ballots, LDS), one atomic per class and
-// workgroup; the order of rows within a list does not affect any result.
-__global__ void __launch_bounds__(256) k_classify(int n, const int* __restrict__ v, int t0, int t1,
+// Row lists per class: class 0 if v <= t0, 1 if v <= t1, 2 if v <= t2,
+// else 3.  Counts are aggregated per workgroup (ballots, LDS), one atomic per
+// class and workgroup; the order of rows within a list does not affect any
+// result.
+__global__ void __launch_bounds__(256) k_classify(int n, const int* __restrict__ v, int t0, int t1, int t2,
                                                   int* __restrict__ counters, int* __restrict__ lists) {
-  __shared__ int wcnt[3][4];
-  __shared__ int base[3];
+  constexpr int NC = 4;
+  __shared__ int wcnt[NC][4];
+  __shared__ int base[NC];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int c = 3;  // out of range
+  int c = NC;  // out of range
   if (i < n) {
     const int u = v[i];
-    c = u <= t0 ? 0 : (u <= t1 ? 1 : 2);
+    c = u <= t0 ? 0 : (u <= t1 ? 1 : (u <= t2 ? 2 : 3));
   }
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  unsigned long long m[3];
-  for (int k = 0; k < 3; ++k) {
+  unsigned long long m[NC];
+  for (int k = 0; k < NC; ++k) {
     m[k] = __ballot(c == k);
     if (lane == 0) wcnt[k][wave] = __popcll(m[k]);
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < NC) {
     const int k = threadIdx.x;
     int tot = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wcnt[k][w];
     base[k] = tot ? atomicAdd(&counters[k], tot) : 0;
   }
   __syncthreads();
-  if (c < 3) {
+  if (c < NC) {
     int off = base[c];
     for (int w = 0; w < wave; ++w) off += wcnt[c][w];
     lists[(size_t)c * n + off + __popcll(m[c] & below)] = i;
@@ -267,8 +274,10 @@ __global__ void __launch_bounds__(G* GPB) k_num(int nlist, const int* __restrict
     for (int i = lane; i < u * BS * BS; i += G) cval[(size_t)c0 * BS * BS + i] = acc[i];
 }
 
-// Numeric phase for rows with at most 64 distinct columns, 16 lanes per row,
-// 4 rows per wavefront.  Same order of summation as k_num (entries of A in
+// Numeric phase for rows with at most CAP <= 64 distinct columns, 16 lanes
+// per row, 4 rows per wavefront (the LDS accumulators are sized by CAP: the
+// rows of the Galerkin products of the block operator mostly have <= 16, and
+// the smaller footprint keeps more wavefronts resident).  Same order of summation as k_num (entries of A in
 // order, lanes over the B row), with the latency of the dependent loads
 // hidden: a prologue stages the B-row extents of every entry of the A row in
 // LDS, and the B-row entries and A block of the next entry are loaded while
@@ -283,14 +292,14 @@ __device__ inline int slot_in(const int* __restrict__ cols, int u, int key) {
   return lo;
 }
 
-template <int BS>
+template <int BS, int CAP>
 __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restrict__ list,
                                                   const int* __restrict__ arp, const int* __restrict__ acol,
                                                   const double* __restrict__ aval, const int* __restrict__ brp,
                                                   const int* __restrict__ bcol, const double* __restrict__ bval,
                                                   const int* __restrict__ crp, const int* __restrict__ ccol,
                                                   double* __restrict__ cval) {
-  constexpr int G = 16, GPB = 4, CAP = 64, AMAX = 64, B2 = BS * BS;
+  constexpr int G = 16, GPB = 4, AMAX = 64, B2 = BS * BS;
   __shared__ int cols_l[GPB][CAP];
   __shared__ double acc_l[GPB][CAP * B2];
   __shared__ int fb_l[GPB][AMAX + 1];
@@ -376,21 +385,25 @@ __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restri
   for (int i = lane; i < u * B2; i += G) cval[(size_t)c0 * B2 + i] = acc_l[grp][i];
 }
 
+// classes by the exact number of distinct columns: <= 16, <= 64, <= 512, more
 template <int BS>
 void numeric_launch(hipStream_t s, const int* counts, const int* lists, int n, const Csr& A, const Csr& B, Csr& C) {
-  if (counts[0] > 0) {
-    k_num_small<BS><<<(counts[0] + 3) / 4, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr, B.col,
-                                                       B.val, C.rowptr, C.col, C.val);
+  auto small = [&](auto cap, int cnt, const int* list) {
+    constexpr int CAP = decltype(cap)::value;
+    if (cnt <= 0) return;
+    k_num_small<BS, CAP><<<(cnt + 3) / 4, 64, 0, s>>>(cnt, list, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
+                                                      C.rowptr, C.col, C.val);
     // the few rows with more than 64 entries in A
-    k_num<BS, 16, 4, 64><<<(counts[0] + 3) / 4, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr,
-                                                            B.col, B.val, C.rowptr, C.col, C.val, 65);
-  }
-  if (counts[1] > 0)
-    k_num<BS, 64, 1, (BS == 3 ? 512 : 512)><<<counts[1], 64, 0, s>>>(counts[1], lists + (size_t)n, A.rowptr, A.col,
-                                                                      A.val, B.rowptr, B.col, B.val, C.rowptr,
-                                                                      C.col, C.val);
+    k_num<BS, 16, 4, CAP><<<(cnt + 3) / 4, 64, 0, s>>>(cnt, list, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
+                                                       C.rowptr, C.col, C.val, 65);
+  };
+  small(std::integral_constant<int, 16>{}, counts[0], lists);
+  small(std::integral_constant<int, 64>{}, counts[1], lists + (size_t)n);
   if (counts[2] > 0)
-    k_num<BS, 64, 1, (BS == 3 ? 224 : 1536)><<<counts[2], 64, 0, s>>>(counts[2], lists + 2 * (size_t)n, A.rowptr,
+    k_num<BS, 64, 1, 512><<<counts[2], 64, 0, s>>>(counts[2], lists + 2 * (size_t)n, A.rowptr, A.col, A.val,
+                                                   B.rowptr, B.col, B.val, C.rowptr, C.col, C.val);
+  if (counts[3] > 0)
+    k_num<BS, 64, 1, (BS == 3 ? 224 : 1536)><<<counts[3], 64, 0, s>>>(counts[3], lists + 3 * (size_t)n, A.rowptr,
                                                                        A.col, A.val, B.rowptr, B.col, B.val,
                                                                        C.rowptr, C.col, C.val);
   PM_CHECK_LAUNCH();
@@ -561,17 +574,17 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
     }
   }
   int* ub = dalloc<int>(n);
-  int* counters = dalloc<int>(4);
-  int* lists = dalloc<int>(3 * (int64_t)n);
+  int* counters = dalloc<int>(5);
+  int* lists = dalloc<int>(4 * (int64_t)n);
   int64_t* ub64 = dalloc<int64_t>(n);
   int64_t* ubofs = dalloc<int64_t>(n + 1);
   int* cnt = dalloc<int>(n);
-  PM_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(int), s));
+  PM_HIP(hipMemsetAsync(counters, 0, 5 * sizeof(int), s));
   if ((double)A.nnzb <= 12.0 * n)
     k_ub<4><<<blocks_for((int64_t)n * 4), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
   else
     k_ub<16><<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
-  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, ub, kSmallUb, kMediumUb, counters, lists);
+  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, ub, kSmallUb, kMediumUb, INT_MAX, counters, lists);
   k_i64_from_i32<<<blocks_for(n), kBlock, 0, s>>>(n, ub, ub64);
   PM_CHECK_LAUNCH();
   int h[4] = {0, 0, 0, 0};
@@ -579,34 +592,47 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
   PM_HIP(hipMemcpyAsync(h, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   exclusive_scan64(s, ub64, ubofs, n, &tmp_total);
   int* tmp = dalloc<int>(std::max<int64_t>(tmp_total, 1));
-  int* status = counters + 3;  // cleared above
+  int* status = counters + 4;  // cleared above
   if (h[0] > 0)
     k_sym<16, 16, 128, 64><<<(h[0] + 15) / 16, 256, 0, s>>>(h[0], lists, A.rowptr, A.col, B.rowptr, B.col, ubofs,
                                                             tmp, cnt, status);
-  if (h[1] > 0)
-    k_sym<64, 4, 1024, 512><<<(h[1] + 3) / 4, 256, 0, s>>>(h[1], lists + (size_t)n, A.rowptr, A.col, B.rowptr,
-                                                           B.col, ubofs, tmp, cnt, status);
-  if (h[2] > 0) {
-    // rows with a large bound: most have few distinct columns (Galerkin rows
-    // of coarse operators); try the 1024-slot hash, retry the rest with 8192
-    int* rl = lists + 2 * (size_t)n;
-    k_sym<64, 4, 1024, 512, true><<<(h[2] + 3) / 4, 256, 0, s>>>(h[2], rl, A.rowptr, A.col, B.rowptr, B.col, ubofs,
-                                                                 tmp, cnt, status);
-    int* rc = dalloc<int>(1);
-    int* retry = dalloc<int>(h[2]);
-    PM_HIP(hipMemsetAsync(rc, 0, sizeof(int), s));
-    k_retry_list<<<blocks_for(h[2]), kBlock, 0, s>>>(h[2], rl, cnt, rc, retry);
+  // Rows with a larger bound mostly have few distinct columns (Galerkin rows):
+  // each class first tries the next smaller configuration, marking the rows
+  // that do not fit (cnt = -1), which are redone with its own.
+  int* rc = dalloc<int>(2);
+  int* retry = dalloc<int>(std::max(h[1], h[2]));
+  PM_HIP(hipMemsetAsync(rc, 0, 2 * sizeof(int), s));
+  auto retry_rows = [&](const int* rl, int nl, int* counter) {
+    k_retry_list<<<blocks_for(nl), kBlock, 0, s>>>(nl, rl, cnt, counter, retry);
     PM_CHECK_LAUNCH();
     int nr = 0;
-    PM_HIP(hipMemcpyAsync(&nr, rc, sizeof(int), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipMemcpyAsync(&nr, counter, sizeof(int), hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
+    return nr;
+  };
+  if (h[1] > 0) {
+    const int* rl = lists + (size_t)n;
+    k_sym<16, 16, 128, 64, true><<<(h[1] + 15) / 16, 256, 0, s>>>(h[1], rl, A.rowptr, A.col, B.rowptr, B.col,
+                                                                  ubofs, tmp, cnt, status);
+    const int nr = retry_rows(rl, h[1], rc);
+    if (nr > 0)
+      k_sym<64, 4, 1024, 512><<<(nr + 3) / 4, 256, 0, s>>>(nr, retry, A.rowptr, A.col, B.rowptr, B.col, ubofs, tmp,
+                                                           cnt, status);
+    PM_CHECK_LAUNCH();
+  }
+  if (h[2] > 0) {
+    // the 1024-slot hash first, the rest with 8192
+    const int* rl = lists + 2 * (size_t)n;
+    k_sym<64, 4, 1024, 512, true><<<(h[2] + 3) / 4, 256, 0, s>>>(h[2], rl, A.rowptr, A.col, B.rowptr, B.col, ubofs,
+                                                                 tmp, cnt, status);
+    const int nr = retry_rows(rl, h[2], rc + 1);
     if (nr > 0)
       k_sym<64, 1, 8192, 6144><<<nr, 64, 0, s>>>(nr, retry, A.rowptr, A.col, B.rowptr, B.col, ubofs, tmp, cnt,
                                                  status);
     PM_CHECK_LAUNCH();
-    dfree(rc);
-    dfree(retry);
   }
+  dfree(rc);
+  dfree(retry);
   PM_CHECK_LAUNCH();
   int st = 0;
   PM_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -636,10 +662,10 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
     return;
   }
   // numeric phase binned by the exact number of distinct columns
-  PM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(int), s));
-  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, cnt, 64, 512, counters, lists);
+  PM_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(int), s));
+  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, cnt, 16, 64, 512, counters, lists);
   PM_CHECK_LAUNCH();
-  PM_HIP(hipMemcpyAsync(h, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipMemcpyAsync(h, counters, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
   if (A.bs == 3)
     numeric_launch<3>(s, h, lists, n, A, B, C);
