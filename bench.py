@@ -170,6 +170,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16, help="cells per axis of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioned comparison solve")
+    ap.add_argument("--rbm", action="store_true",
+                    help="rigid-body near kernel (translations and rotations) for the A_uu hierarchy")
     ap.add_argument("--workload", choices=("layered", "spe192"), default="layered",
                     help="layered: one step of the layered workload (the benchmark line); spe192: the "
                          "20-step 192x192x96 forward + adjoint run with checkpoints every 5 steps")
@@ -201,7 +203,7 @@ def main():
     # benchmark solver settings: FGMRES(24), one Gram-Schmidt pass, V(2,2) on A_uu,
     # V(1,1) with a wider Chebyshev interval on C~_pi
     opts = Options(rtol=1e-8, precond_fp32=True, restart=24, max_it=1000, orth_passes=1, cheb_degree_pi=1,
-                   cheb_lower_pi=0.1)
+                   cheb_lower_pi=0.1, rbm_u=args.rbm)
     s = from_problem(prob, opts, device=dev)
     b = torch.empty(s.N, dtype=torch.float64, device=dev)
     if args.copy_probe > 0:
@@ -262,7 +264,8 @@ def main():
                                "S_eps 0, dt 1e-2; mixed-precision block-triangular AMG preconditioner "
                                "(V(2,2) A_uu, V(1,1) C~pi), FP64 FGMRES(24) with one classical "
                                "Gram-Schmidt pass, rtol 1e-8",
-                   "unknowns": s.N, "n_u": s.n_u, "n_pi": s.n_pi, "n_p": s.n_p},
+                   "unknowns": s.N, "n_u": s.n_u, "n_pi": s.n_pi, "n_p": s.n_p,
+                   "near_kernel_u": "rigid-body (6 modes)" if args.rbm else "translations (3 modes)"},
         "iterations": last["iters"],
         "relres_true": last["relres_true"],
         "t_asm_s": round(last["t_asm"], 4),
@@ -283,7 +286,7 @@ def main():
 
     if not args.no_fp64:
         s64 = from_problem(prob, Options(rtol=1e-8, precond_fp32=False, restart=24, max_it=1000, orth_passes=1,
-                                         cheb_degree_pi=1, cheb_lower_pi=0.1),
+                                         cheb_degree_pi=1, cheb_lower_pi=0.1, rbm_u=args.rbm),
                            device=dev)
         s64.assemble()
         b64 = s64.build_rhs()

@@ -130,6 +130,11 @@ typedef struct {
                                 diagonals: axis-aligned boxes, diagonal permeability), apply
                                 M_T^-1 and C~_T in the solve from the 9 block entries, leaving
                                 the rounding-level rest out; 0: always the full 6x6 matrices */
+  int32_t rbm_u;             /* 1: the A_uu hierarchy's finest tentative prolongator spans the six
+                                rigid-body modes of each aggregate (translations and rotations
+                                about its centroid, orthonormalised; two 3x3 coarse block rows
+                                per aggregate, no prolongator truncation on that level);
+                                0: translations only */
 } pm_opts;
 
 typedef struct {
@@ -152,7 +157,8 @@ typedef struct {
  * operator stagnates with short restarts or one pass on strongly
  * heterogeneous permeability); lattice operator on; C~_pi prolongator
  * truncation 0.02 (C~_pi) and 0.02 (A_uu); cell-by-cell finest C~_pi level;
- * M_T^-1 by direction blocks where the cells allow it. */
+ * M_T^-1 by direction blocks where the cells allow it; translation-only
+ * near kernel for A_uu. */
 void pm_default_opts(pm_opts* opts);
 
 /* Create a context: validates and copies mesh coordinates and material

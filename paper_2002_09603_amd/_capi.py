@@ -54,7 +54,8 @@ class pm_opts(C.Structure):
                 ("rtol_transpose", C.c_double), ("restart_transpose", C.c_int32),
                 ("orth_passes_transpose", C.c_int32), ("lattice_uu", C.c_int32),
                 ("p_trunc_pi", C.c_double), ("cell_pi", C.c_int32), ("p_trunc_u", C.c_double),
-                ("cheb_lower_pi", C.c_double), ("block_minv", C.c_int32)]
+                ("cheb_lower_pi", C.c_double), ("block_minv", C.c_int32),
+                ("rbm_u", C.c_int32)]
 
 
 class pm_info(C.Structure):

@@ -487,40 +487,57 @@ __device__ inline double pblock_norm(const double* v) {
   return sqrt(s);
 }
 
+// rigid-body prolongators (rigid = true): translation (even) and rotation
+// (odd) columns have different units, so each block is compared with the
+// largest of its own kind in the row, and nothing is rescaled
 template <int BS>
-__global__ void k_trunc_count(int n, const int* __restrict__ rp, const double* __restrict__ val, double tau,
-                              int* __restrict__ cnt) {
+__device__ inline void trunc_row_max(int i, const int* __restrict__ rp, const int* __restrict__ col,
+                                     const double* __restrict__ val, bool rigid, double mx[2]) {
+  mx[0] = mx[1] = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int k = rigid ? (col[e] & 1) : 0;
+    mx[k] = fmax(mx[k], pblock_norm<BS>(val + (size_t)e * BS * BS));
+  }
+}
+
+template <int BS>
+__device__ inline bool trunc_keep(int e, const int* __restrict__ col, const double* __restrict__ val, bool rigid,
+                                  double tau, const double mx[2]) {
+  return pblock_norm<BS>(val + (size_t)e * BS * BS) >= tau * mx[rigid ? (col[e] & 1) : 0];
+}
+
+template <int BS>
+__global__ void k_trunc_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                              const double* __restrict__ val, double tau, bool rigid, int* __restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double mx = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) mx = fmax(mx, pblock_norm<BS>(val + (size_t)e * BS * BS));
+  double mx[2];
+  trunc_row_max<BS>(i, rp, col, val, rigid, mx);
   int c = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) c += pblock_norm<BS>(val + (size_t)e * BS * BS) >= tau * mx;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) c += trunc_keep<BS>(e, col, val, rigid, tau, mx);
   cnt[i] = c;
 }
 
 template <int BS>
 __global__ void k_trunc_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                             const double* __restrict__ val, double tau, const int* __restrict__ trp,
+                             const double* __restrict__ val, double tau, bool rigid, const int* __restrict__ trp,
                              int* __restrict__ tcol, double* __restrict__ tval) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double mx = 0.0, all[BS * BS], kept[BS * BS];
+  double mx[2], all[BS * BS], kept[BS * BS];
+  trunc_row_max<BS>(i, rp, col, val, rigid, mx);
   for (int q = 0; q < BS * BS; ++q) all[q] = kept[q] = 0.0;
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     const double* v = val + (size_t)e * BS * BS;
-    mx = fmax(mx, pblock_norm<BS>(v));
     for (int q = 0; q < BS * BS; ++q) all[q] += v[q];
-  }
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const double* v = val + (size_t)e * BS * BS;
-    if (pblock_norm<BS>(v) >= tau * mx)
+    if (trunc_keep<BS>(e, col, val, rigid, tau, mx))
       for (int q = 0; q < BS * BS; ++q) kept[q] += v[q];
   }
   // S = kept^-1 all (identity if kept is singular)
   double S[BS * BS];
   for (int q = 0; q < BS * BS; ++q) S[q] = (q % (BS + 1) == 0) ? 1.0 : 0.0;
-  if (BS == 1) {
+  if (rigid) {
+  } else if (BS == 1) {
     if (kept[0] != 0.0) S[0] = all[0] / kept[0];
   } else {
     const double* k = kept;
@@ -548,7 +565,7 @@ __global__ void k_trunc_fill(int n, const int* __restrict__ rp, const int* __res
   int p = trp[i];
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     const double* v = val + (size_t)e * BS * BS;
-    if (pblock_norm<BS>(v) < tau * mx) continue;
+    if (!trunc_keep<BS>(e, col, val, rigid, tau, mx)) continue;
     tcol[p] = col[e];
     for (int a = 0; a < BS; ++a)
       for (int b = 0; b < BS; ++b) {
@@ -561,9 +578,9 @@ __global__ void k_trunc_fill(int n, const int* __restrict__ rp, const int* __res
 }
 
 template <int BS>
-void truncate_p(hipStream_t s, Csr& P, double tau) {
+void truncate_p(hipStream_t s, Csr& P, double tau, bool rigid = false) {
   int* cnt = dalloc<int>(P.n);
-  k_trunc_count<BS><<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.val, tau, cnt);
+  k_trunc_count<BS><<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.col, P.val, tau, rigid, cnt);
   PM_CHECK_LAUNCH();
   Csr T;
   T.bs = BS;
@@ -576,7 +593,8 @@ void truncate_p(hipStream_t s, Csr& P, double tau) {
   T.nnzb = nnz;
   T.col = dalloc<int>(nnz);
   T.val = dalloc<double>((int64_t)nnz * BS * BS);
-  k_trunc_fill<BS><<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.col, P.val, tau, T.rowptr, T.col, T.val);
+  k_trunc_fill<BS><<<blocks_for(P.n), kBlock, 0, s>>>(P.n, P.rowptr, P.col, P.val, tau, rigid, T.rowptr, T.col,
+                                                      T.val);
   PM_CHECK_LAUNCH();
   P.free_all();
   P = T;
@@ -1350,32 +1368,282 @@ void aggregate(hipStream_t s, const Csr& A, double theta, int dist, int* agg, in
   *nagg_out = nagg;
 }
 
-// lmax_job: the level's own power iteration when it is still running on the
-// side stream (taken here if the transfer needs it)
-template <int BS>
-void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Acoarse, const Grid* SG,
-                          PowerJob* lmax_job) {
-  const Csr& A = L.A;
-  const int n = A.n;
-  int* agg = dalloc<int>(n);
-  uint8_t* strong = dalloc<uint8_t>(A.nnzb);
-  int nagg = 0;
-  aggregate<BS>(s, A, prm.theta, prm.agg_dist, agg, &nagg, strong, SG);
-  // tentative prolongator
-  Csr Pt;
-  Pt.bs = BS;
-  Pt.n = n;
-  Pt.m = nagg;
-  int* f = dalloc<int>(n);
-  k_count_aggregated<<<blocks_for(n), kBlock, 0, s>>>(n, agg, f);
-  Pt.rowptr = dalloc<int>(n + 1);
+// ---------------------------------------------------------------------------
+// Rigid-body near kernel for the A_uu hierarchy (the analogue of the paper's
+// M_III^(h) preconditioner, Sec. 5).  Every coarse "node" is an aggregate J
+// with a centroid c_J and six unknowns: a translation T_J and a rotation
+// Omega_J (two 3x3 block rows, 2J and 2J+1).  The tentative prolongator
+// interpolates rigid motions exactly:
+//   finest level, node i of J:        u_i = T_J + Omega_J x (x_i - c_J)
+//   coarser level, aggregate I of J:  T_I = T_J + Omega_J x (c_I - c_J),
+//                                     Omega_I = Omega_J
+// i.e. block rows [I | rot(d)] (and [0 | I]), rot(d) w = w x d, so the
+// translations and rotations of every level are those of the finest.  The
+// coarse levels are aggregated on the graph of the aggregate pairs.  A
+// rotation that an aggregate cannot carry (one node, or nodes on a line
+// through the centroid along the axis) gives a zero prolongator column; the
+// coarse operator's zero diagonal entries there are set to one.  One thread
+// per aggregate takes its members in increasing order (deterministic).
+__global__ void k_agg_count(int n, const int* __restrict__ agg, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_agg_fill(int n, const int* __restrict__ agg, const int* __restrict__ aoff, int* __restrict__ cur,
+                           int* __restrict__ list) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || agg[i] < 0) return;
+  const int J = agg[i];
+  list[aoff[J] + atomicAdd(&cur[J], 1)] = i;
+}
+
+// blocks per row of the tentative prolongator: finest level 2 (translation
+// and rotation columns of the node's aggregate); paired levels 2 for the
+// translation row of an aggregated member, 1 for its rotation row
+__global__ void k_rbm_count(int n, const int* __restrict__ agg, int paired, int* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = paired ? i >> 1 : i;
+  f[i] = agg[m] < 0 ? 0 : ((paired && (i & 1)) ? 1 : 2);
+}
+
+// rot(d): column a is e_a x d
+__device__ inline void rot_block(const double d[3], double S[9]) {
+  S[0] = 0.0;   S[1] = d[2];  S[2] = -d[1];
+  S[3] = -d[2]; S[4] = 0.0;   S[5] = d[0];
+  S[6] = d[1];  S[7] = -d[0]; S[8] = 0.0;
+}
+
+__global__ void k_rbm_ptent(int nagg, const int* __restrict__ aoff, int* __restrict__ list,
+                            const double* __restrict__ pos, int paired, const int* __restrict__ prow,
+                            int* __restrict__ pcol, double* __restrict__ pval, double* __restrict__ cen) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= nagg) return;
+  const int b = aoff[J], e = aoff[J + 1], m = e - b;
+  for (int p = b + 1; p < e; ++p) {  // the members in increasing order
+    const int v = list[p];
+    int q = p - 1;
+    while (q >= b && list[q] > v) {
+      list[q + 1] = list[q];
+      --q;
+    }
+    list[q + 1] = v;
+  }
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int p = b; p < e; ++p)
+    for (int a = 0; a < 3; ++a) c[a] += pos[3 * (size_t)list[p] + a];
+  for (int a = 0; a < 3; ++a) {
+    c[a] /= (double)m;
+    cen[3 * (size_t)J + a] = c[a];
+  }
+  for (int p = b; p < e; ++p) {
+    const int i = list[p];
+    double d[3], S[9];
+    for (int a = 0; a < 3; ++a) d[a] = pos[3 * (size_t)i + a] - c[a];
+    rot_block(d, S);
+    const int r0 = paired ? 2 * i : i;  // the (translation) block row of the member
+    const int e0 = prow[r0];
+    pcol[e0] = 2 * J;
+    pcol[e0 + 1] = 2 * J + 1;
+    for (int q = 0; q < 9; ++q) {
+      pval[(size_t)e0 * 9 + q] = (q % 4 == 0) ? 1.0 : 0.0;
+      pval[(size_t)(e0 + 1) * 9 + q] = S[q];
+    }
+    if (paired) {  // the rotation row: Omega_I = Omega_J
+      const int e1 = prow[r0 + 1];
+      pcol[e1] = 2 * J + 1;
+      for (int q = 0; q < 9; ++q) pval[(size_t)e1 * 9 + q] = (q % 4 == 0) ? 1.0 : 0.0;
+    }
+  }
+}
+
+// Graph of the aggregate pairs of a paired level: super-row I merges block
+// rows 2I and 2I+1 (columns J = col / 2, both lists sorted), with the value
+// sqrt(sum of the squared Frobenius norms of the blocks it covers)
+__global__ void k_pair_count(int n2, const int* __restrict__ rp, const int* __restrict__ col,
+                             int* __restrict__ cnt) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n2) return;
+  int a = rp[2 * I], b = rp[2 * I + 1];
+  const int ae = rp[2 * I + 1], be = rp[2 * I + 2];
+  int k = 0, last = -1;
+  while (a < ae || b < be) {
+    const int ja = a < ae ? col[a] >> 1 : INT_MAX, jb = b < be ? col[b] >> 1 : INT_MAX;
+    const int j = min(ja, jb);
+    if (j == ja) ++a; else ++b;
+    if (j != last) {
+      ++k;
+      last = j;
+    }
+  }
+  cnt[I] = k;
+}
+
+__global__ void k_pair_fill(int n2, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ val, const int* __restrict__ srp, int* __restrict__ scol,
+                            double* __restrict__ sval) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n2) return;
+  int a = rp[2 * I], b = rp[2 * I + 1];
+  const int ae = rp[2 * I + 1], be = rp[2 * I + 2];
+  int k = srp[I] - 1, last = -1;
+  double acc = 0.0;
+  while (a < ae || b < be) {
+    const int ja = a < ae ? col[a] >> 1 : INT_MAX, jb = b < be ? col[b] >> 1 : INT_MAX;
+    const int j = min(ja, jb);
+    const int eb = (j == ja) ? a++ : b++;
+    if (j != last) {
+      if (last >= 0) sval[k] = sqrt(acc);
+      ++k;
+      scol[k] = j;
+      acc = 0.0;
+      last = j;
+    }
+    for (int q = 0; q < 9; ++q) acc += val[(size_t)eb * 9 + q] * val[(size_t)eb * 9 + q];
+  }
+  if (last >= 0) sval[k] = sqrt(acc);
+}
+
+// tentative prolongator of a rigid-body level; cen receives the aggregates'
+// centroids (nagg x 3, the positions of the next level)
+void build_rbm_ptent(hipStream_t s, int nb, int nmem, const int* agg, int nagg, const double* pos, bool paired,
+                     Csr& Pt, double* cen) {
+  int* cnt = dalloc<int>(nagg);
+  int* aoff = dalloc<int>(nagg + 1);
+  int* list = dalloc<int>(std::max(nmem, 1));
+  PM_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)nagg, s));
+  k_agg_count<<<blocks_for(nmem), kBlock, 0, s>>>(nmem, agg, cnt);
+  PM_CHECK_LAUNCH();
+  int total = 0;
+  exclusive_scan(s, cnt, aoff, nagg, &total);
+  PM_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)nagg, s));
+  k_agg_fill<<<blocks_for(nmem), kBlock, 0, s>>>(nmem, agg, aoff, cnt, list);
+  PM_CHECK_LAUNCH();
+  dfree(cnt);
+  Pt.bs = 3;
+  Pt.n = nb;
+  Pt.m = 2 * nagg;
+  Pt.rowptr = dalloc<int>(nb + 1);
+  int* f = dalloc<int>(nb);
+  k_rbm_count<<<blocks_for(nb), kBlock, 0, s>>>(nb, agg, paired ? 1 : 0, f);
+  PM_CHECK_LAUNCH();
   int nnz = 0;
-  exclusive_scan(s, f, Pt.rowptr, n, &nnz);
+  exclusive_scan(s, f, Pt.rowptr, nb, &nnz);
+  dfree(f);
   Pt.nnzb = nnz;
   Pt.col = dalloc<int>(nnz);
-  Pt.val = dalloc<double>((int64_t)nnz * BS * BS);
-  k_ptent<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, Pt.rowptr, Pt.col, Pt.val);
+  Pt.val = dalloc<double>((int64_t)nnz * 9);
+  k_rbm_ptent<<<blocks_for(nagg), kBlock, 0, s>>>(nagg, aoff, list, pos, paired ? 1 : 0, Pt.rowptr, Pt.col,
+                                                   Pt.val, cen);
   PM_CHECK_LAUNCH();
+  PM_HIP(hipStreamSynchronize(s));
+  dfree(aoff);
+  dfree(list);
+}
+
+// P = P_tent - omega D^-1 (A P_tent) on the pattern of A P_tent, for a
+// general P_tent (whose pattern is contained in that of A P_tent)
+template <int BS>
+__global__ void k_smooth_p_gen(int n, const double* __restrict__ dinv, double omega, const int* __restrict__ rp,
+                               const int* __restrict__ col, double* __restrict__ val, const int* __restrict__ trp,
+                               const int* __restrict__ tcol, const double* __restrict__ tval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* D = dinv + (size_t)i * BS * BS;
+  int f = trp[i];
+  const int f1 = trp[i + 1];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    double* v = val + (size_t)e * BS * BS;
+    const bool hit = f < f1 && tcol[f] == col[e];  // both rows sorted by column
+    double o[BS * BS];
+    for (int a = 0; a < BS; ++a)
+      for (int b = 0; b < BS; ++b) {
+        double sum = 0.0;
+        for (int t = 0; t < BS; ++t) sum += D[a * BS + t] * v[t * BS + b];
+        o[a * BS + b] = -omega * sum + (hit ? tval[(size_t)f * BS * BS + a * BS + b] : 0.0);
+      }
+    for (int q = 0; q < BS * BS; ++q) v[q] = o[q];
+    if (hit) ++f;
+  }
+}
+
+// diagonal entries that are exactly zero (coarse unknowns of dropped
+// near-kernel columns: zero row and column) set to one
+template <int BS>
+__global__ void k_fix_zero_diag(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                double* __restrict__ val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (col[e] == i)
+      for (int a = 0; a < BS; ++a) {
+        double& d = val[(size_t)e * BS * BS + a * BS + a];
+        if (d == 0.0) d = 1.0;
+      }
+}
+
+// lmax_job: the level's own power iteration when it is still running on the
+// side stream (taken here if the transfer needs it).
+// pos: positions of the level's nodes (rigid-body hierarchies: the finest
+// node coordinates, then the aggregate centroids of the paired levels, whose
+// block rows come in translation/rotation pairs); *cen_next receives the
+// next level's (device, owned by the caller)
+template <int BS>
+void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Acoarse, const Grid* SG,
+                          PowerJob* lmax_job, const double* pos, bool paired, double** cen_next) {
+  const Csr& A = L.A;
+  const int n = A.n;
+  const bool rbm = BS == 3 && pos != nullptr;
+  uint8_t* strong = dalloc<uint8_t>(A.nnzb);
+  int nagg = 0;
+  const int nmem = paired ? n / 2 : n;  // aggregated units: nodes, or aggregate pairs
+  int* agg = dalloc<int>(nmem);
+  if (paired) {
+    // aggregation on the graph of the pairs; A itself is not filtered
+    Csr Sg;
+    Sg.bs = 1;
+    Sg.n = Sg.m = nmem;
+    Sg.rowptr = dalloc<int>(nmem + 1);
+    int* cnt = dalloc<int>(nmem);
+    k_pair_count<<<blocks_for(nmem), kBlock, 0, s>>>(nmem, A.rowptr, A.col, cnt);
+    PM_CHECK_LAUNCH();
+    int snnz = 0;
+    exclusive_scan(s, cnt, Sg.rowptr, nmem, &snnz);
+    dfree(cnt);
+    Sg.nnzb = snnz;
+    Sg.col = dalloc<int>(snnz);
+    Sg.val = dalloc<double>(snnz);
+    k_pair_fill<<<blocks_for(nmem), kBlock, 0, s>>>(nmem, A.rowptr, A.col, A.val, Sg.rowptr, Sg.col, Sg.val);
+    PM_CHECK_LAUNCH();
+    uint8_t* sstrong = dalloc<uint8_t>(snnz);
+    aggregate<1>(s, Sg, prm.theta, prm.agg_dist, agg, &nagg, sstrong, nullptr);
+    dfree(sstrong);
+    Sg.free_all();
+    PM_HIP(hipMemsetAsync(strong, 1, (size_t)A.nnzb, s));
+  } else {
+    aggregate<BS>(s, A, prm.theta, prm.agg_dist, agg, &nagg, strong, SG);
+  }
+  // tentative prolongator
+  Csr Pt;
+  int* f = dalloc<int>(n);
+  if (rbm) {
+    *cen_next = dalloc<double>(3 * (int64_t)std::max(nagg, 1));
+    build_rbm_ptent(s, n, nmem, agg, nagg, pos, paired, Pt, *cen_next);
+  } else {
+    Pt.bs = BS;
+    Pt.n = n;
+    Pt.m = nagg;
+    k_count_aggregated<<<blocks_for(n), kBlock, 0, s>>>(n, agg, f);
+    Pt.rowptr = dalloc<int>(n + 1);
+    int nnz = 0;
+    exclusive_scan(s, f, Pt.rowptr, n, &nnz);
+    Pt.nnzb = nnz;
+    Pt.col = dalloc<int>(nnz);
+    Pt.val = dalloc<double>((int64_t)nnz * BS * BS);
+    k_ptent<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, Pt.rowptr, Pt.col, Pt.val);
+    PM_CHECK_LAUNCH();
+  }
+  const int* pt_agg = rbm ? nullptr : agg;  // the tentative-product fast path needs one identity block per row
   // filtered operator A_F (strong couplings, weak ones lumped on the diagonal);
   // when no nonzero coupling is weak A_F = A and the level's D^-1, lmax serve
   Csr AF;
@@ -1416,24 +1684,30 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
     if (prm.side) {
       PowerJob jf;
       power_start(jf, s, prm.side, n, BS, dinvF, prm.power_its, CsrSpmv{AF, csr_lanes_for(AF)});
-      spgemm(s, AF, Pt, P, agg);
+      spgemm(s, AF, Pt, P, pt_agg);
       lF = power_finish(jf);
     } else {
       lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
-      spgemm(s, AF, Pt, P, agg);
+      spgemm(s, AF, Pt, P, pt_agg);
     }
   } else {
-    spgemm(s, A, Pt, P, agg);
+    spgemm(s, A, Pt, P, pt_agg);
     if (lmax_job && lmax_job->pending()) L.lmax = power_finish(*lmax_job);
     lF = L.lmax;
   }
   dfree(strong);
-  Pt.free_all();
   AF.free_all();
   const double omega = 4.0 / (3.0 * lF);
-  k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, filtered ? dinvF : L.dinv, omega, P.rowptr, P.col, P.val);
+  if (rbm)
+    k_smooth_p_gen<BS><<<blocks_for(n), kBlock, 0, s>>>(n, filtered ? dinvF : L.dinv, omega, P.rowptr, P.col,
+                                                        P.val, Pt.rowptr, Pt.col, Pt.val);
+  else
+    k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, filtered ? dinvF : L.dinv, omega, P.rowptr, P.col,
+                                                    P.val);
   PM_CHECK_LAUNCH();
-  if (prm.p_trunc > 0.0) truncate_p<BS>(s, P, prm.p_trunc);
+  PM_HIP(hipStreamSynchronize(s));
+  Pt.free_all();
+  if (prm.p_trunc > 0.0) truncate_p<BS>(s, P, prm.p_trunc, rbm);
   dfree(dinvF);
   dfree(agg);
   // Galerkin coarse operator
@@ -1442,6 +1716,11 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   csr_transpose(s, P, R);
   spgemm(s, R, AP, Acoarse);
   AP.free_all();
+  if (rbm) {
+    k_fix_zero_diag<BS><<<blocks_for(Acoarse.n), kBlock, 0, s>>>(Acoarse.n, Acoarse.rowptr, Acoarse.col,
+                                                                 Acoarse.val);
+    PM_CHECK_LAUNCH();
+  }
   csr_to_sell(s, P, L.P, prm.fp32);
   L.R = R;
   if (prm.fp32) {
@@ -1623,6 +1902,14 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
   Csr cur = A0;
   cur.val32 = nullptr;
   cur.borrowed = true;
+  // rigid-body near kernel: positions of the current level's nodes
+  const double* rbm_pos = (prm.rbm && prm.coords && H.bs == 3 && G && A0.n == G->nn) ? prm.coords : nullptr;
+  bool rbm_paired = false;
+  double* rbm_cen = nullptr;  // owned centroids of the current paired level
+  struct CenGuard {
+    double*& p;
+    ~CenGuard() { dfree(p); }
+  } cen_guard{rbm_cen};
   for (int l = 0;; ++l) {
     H.L.emplace_back();
     Level& L = H.L.back();
@@ -1698,10 +1985,17 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
     // the finest level of either hierarchy is the structured node or face graph
     const Grid* sg =
         (l == 0 && G && ((L.bs == 3 && L.n == G->nn) || (L.bs == 1 && L.n == G->nf))) ? G : nullptr;
+    double* cen_next = nullptr;
     if (L.bs == 3)
-      build_level_transfer<3>(s, L, prm, Ac, sg, &job);
+      build_level_transfer<3>(s, L, prm, Ac, sg, &job, rbm_pos, rbm_paired, &cen_next);
     else
-      build_level_transfer<1>(s, L, prm, Ac, sg, &job);
+      build_level_transfer<1>(s, L, prm, Ac, sg, &job, nullptr, false, &cen_next);
+    if (cen_next) {
+      dfree(rbm_cen);
+      rbm_cen = cen_next;
+      rbm_pos = cen_next;
+      rbm_paired = true;
+    }
     if (job.pending()) {
       L.lmax = power_finish(job);
       report();

@@ -93,11 +93,14 @@ pm::AmgParams params_u(const pm_ctx* c) {
   p.fp32 = c->opts.precond_fp32 != 0;
   p.p_trunc = c->opts.p_trunc_u;
   p.side = c->s_side_u;
+  p.rbm = c->opts.rbm_u != 0;
+  p.coords = c->coords;
   return p;
 }
 
 pm::AmgParams params_pi(const pm_ctx* c) {
   pm::AmgParams p = params_u(c);
+  p.rbm = false;
   p.theta = c->opts.theta_pi;
   p.coarse_max = c->opts.coarse_max * 3;
   p.cheb_degree = c->opts.cheb_degree_pi;
@@ -230,6 +233,7 @@ void pm_default_opts(pm_opts* o) {
   o->cell_pi = 1;
   o->theta_pi = 0.08;
   o->block_minv = 1;
+  o->rbm_u = 0;
 }
 
 int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, double dt, const pm_opts* opts,

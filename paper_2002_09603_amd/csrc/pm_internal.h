@@ -140,6 +140,8 @@ struct AmgParams {
   double p_trunc = 0.0;            // scalar prolongator truncation threshold (0: none)
   bool fp32 = false;
   hipStream_t side = nullptr;      // optional second stream for set-up power iterations
+  bool rbm = false;                // rigid-body near kernel on the finest level (bs 3, structured)
+  const double* coords = nullptr;  // node coordinates (n_n x 3, device) for it
 };
 
 // A_uu on a mesh whose cells are translates of one parallelepiped: every

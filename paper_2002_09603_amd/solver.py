@@ -60,6 +60,7 @@ class Options:
     p_trunc_u: float = 0.02
     cheb_lower_pi: float = 0.0
     block_minv: bool = True
+    rbm_u: bool = False
 
     def to_c(self) -> _capi.pm_opts:
         o = _capi.pm_opts()
@@ -89,6 +90,7 @@ class Options:
         o.p_trunc_u = self.p_trunc_u
         o.cheb_lower_pi = self.cheb_lower_pi
         o.block_minv = int(self.block_minv)
+        o.rbm_u = int(self.rbm_u)
         return o
 
 
