@@ -30,7 +30,10 @@
  * Boundary conditions: bottom (k=0) nodes fixed (u = 0); top (k=nz) faces
  * drained (pi = p_top) and loaded by a uniform traction; all other boundary
  * parts traction-free and no-flow.  PM_BC_ROLLERS additionally fixes the
- * normal displacement of the four lateral sides.  Dirichlet dofs stay in the
+ * normal displacement of the four lateral sides.  PM_BC_CANTILEVER (the
+ * paper's cantilever test, Sec. 5.2): the nodes of the face x = x_min (i=0)
+ * fixed, the top loaded by the traction, no-flow on the whole boundary (no
+ * drained face; p_top unused).  Dirichlet dofs stay in the
  * system as identity rows and columns, so sizes match the paper's table
  * tab:grids.
  *
@@ -69,7 +72,7 @@ enum {
   PM_EINTERNAL = -7     /* internal capacity exceeded (e.g. AMG row too wide) */
 };
 
-enum { PM_BC_COLUMN = 0, PM_BC_ROLLERS = 1 };
+enum { PM_BC_COLUMN = 0, PM_BC_ROLLERS = 1, PM_BC_CANTILEVER = 2 };
 
 typedef struct pm_ctx pm_ctx;
 
@@ -91,7 +94,7 @@ typedef struct {
 typedef struct {
   double traction_top[3];    /* traction on the top face (e.g. {0,0,-1}) */
   double p_top;              /* prescribed face pressure on the top face */
-  int32_t kind;              /* PM_BC_COLUMN or PM_BC_ROLLERS */
+  int32_t kind;              /* PM_BC_COLUMN, PM_BC_ROLLERS or PM_BC_CANTILEVER */
 } pm_bc;
 
 typedef struct {

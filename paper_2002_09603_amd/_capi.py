@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libporomech
 
 PM_OK, PM_EINVAL, PM_ENOMEM, PM_EHIP, PM_ENOCONV, PM_EBREAKDOWN, PM_ESTATE, PM_EINTERNAL = \
     0, -1, -2, -3, -4, -5, -6, -7
-PM_BC_COLUMN, PM_BC_ROLLERS = 0, 1
+PM_BC_COLUMN, PM_BC_ROLLERS, PM_BC_CANTILEVER = 0, 1, 2
 PM_OP_AH, PM_OP_AHT, PM_OP_MINV, PM_OP_MINVT, PM_OP_CPI, PM_OP_BP, PM_OP_AUU, \
     PM_OP_VCYCLE_U, PM_OP_VCYCLE_PI = range(9)
 

@@ -1623,6 +1623,16 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
   } else {
     aggregate<BS>(s, A, prm.theta, prm.agg_dist, agg, &nagg, strong, SG);
   }
+  if (nagg == 0) {
+    // every row isolated (no strong coupling): no coarser level; the caller
+    // makes this level the coarsest
+    dfree(agg);
+    dfree(strong);
+    if (lmax_job && lmax_job->pending()) L.lmax = power_finish(*lmax_job);
+    Acoarse.free_all();
+    Acoarse = Csr();
+    return;
+  }
   // tentative prolongator
   Csr Pt;
   int* f = dalloc<int>(n);

@@ -369,7 +369,7 @@ __global__ void k_bp(Grid G, const double* __restrict__ ae, const double* __rest
 // 2O+1) and the cell after it (side 1, local face 2O), the 11 candidate
 // columns (side, local face) follow a fixed order, the face itself (both
 // sides' diagonal terms, side 0 first) at its place.  Absent cells and the
-// Dirichlet columns (top face of the top layer) are skipped.  emit(col, v).
+// Dirichlet columns (a drained top face) are skipped.  emit(col, v).
 template <int O, bool VALS, class Emit>
 __device__ __forceinline__ void cpi_row_sorted(const Grid& G, uint32_t i, uint32_t j, uint32_t k, uint32_t f,
                                                const double* __restrict__ Minv, const double* __restrict__ gv,
@@ -414,7 +414,7 @@ __device__ __forceinline__ void cpi_row_sorted(const Grid& G, uint32_t i, uint32
       if (has[0]) v = val(0, L0, L0);
       if (has[1]) v = has[0] ? v + val(1, L1, L1) : val(1, L1, L1);
       emit(f, v);
-    } else if (has[sd] && !(e == 5 && ck[sd] == (uint32_t)G.nz - 1)) {
+    } else if (has[sd] && !pi_fixed_local(G, (int)ck[sd], e)) {
       emit(F[sd][e], val(sd, sd == 0 ? L0 : L1, e));
     }
   }
@@ -568,6 +568,7 @@ Grid grid_of(const pm_ctx* c) {
   G.nx = c->nx;
   G.ny = c->ny;
   G.nz = c->nz;
+  G.drained = c->bc_kind != PM_BC_CANTILEVER;
   G.nn = c->nn;
   G.nc = c->nc;
   G.nfx = c->nfx;

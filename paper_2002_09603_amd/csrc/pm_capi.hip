@@ -257,7 +257,8 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     if (!(mat->mu > 0.0) || !(mat->S_eps >= 0.0) || !std::isfinite(mat->biot))
       throw Error(PM_EINVAL, "pm_setup: mu > 0, S_eps >= 0 and a finite Biot coefficient are required");
     if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(PM_EINVAL, "pm_setup: dt must be positive");
-    if (bc->kind != PM_BC_COLUMN && bc->kind != PM_BC_ROLLERS) throw Error(PM_EINVAL, "pm_setup: unknown bc kind");
+    if (bc->kind != PM_BC_COLUMN && bc->kind != PM_BC_ROLLERS && bc->kind != PM_BC_CANTILEVER)
+      throw Error(PM_EINVAL, "pm_setup: unknown bc kind");
     c->s = (hipStream_t)stream;
     pm::set_alloc_stream(c->s);
     c->nx = mesh->nx;

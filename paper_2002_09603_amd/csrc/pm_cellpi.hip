@@ -88,7 +88,7 @@ struct CpiTerm {
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
       const T v = ld32(C + (size_t)sym6(L < e ? L : e, L < e ? e : L) * G.nc, c) * ld32(x, F[e]);
-      if (e != 5 || ck != (uint32_t)G.nz - 1) acc += v;  // the top face of the top layer is a zero column
+      if (!pi_fixed_local(G, (int)ck, e)) acc += v;  // a drained top face is a zero column
     }
     return acc;
   }
@@ -111,7 +111,7 @@ struct CpiBlockTerm {
     const T sc = ld32(C + (size_t)9 * G.nc, c);
 #pragma unroll
     for (int e = 0; e < 6; ++e) xv[e] = ld32(x, F[e]);
-    if (ck == (uint32_t)G.nz - 1) xv[5] = (T)0;  // the top face of the top layer is a zero column
+    if (pi_fixed_local(G, (int)ck, 5)) xv[5] = (T)0;  // a drained top face is a zero column
     T gx = (T)0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) gx += (m[3 * a] + m[3 * a + 1]) * xv[2 * a] + (m[3 * a + 1] + m[3 * a + 2]) * xv[2 * a + 1];

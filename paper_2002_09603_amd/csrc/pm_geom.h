@@ -30,6 +30,7 @@ struct FastDiv {
 // assumes fewer than 2^31 nodes, cells and faces (checked at set-up).
 struct Grid {
   int nx, ny, nz;
+  int drained;  // 1: the top plane's faces are Dirichlet (drained); 0: no-flow everywhere
   int64_t nn, nc, nfx, nfy, nfz, nf;
   FastDiv dnx, dnx1, dny, dny1;  // division by nx, nx+1, ny, ny+1
   __host__ __device__ int64_t node(int i, int j, int k) const {
@@ -106,8 +107,10 @@ struct Grid {
 };
 
 // Dirichlet displacement components of node (i,j,k): the bottom face is
-// fixed; PM_BC_ROLLERS also fixes the normal component on the lateral faces.
+// fixed; PM_BC_ROLLERS also fixes the normal component on the lateral faces;
+// PM_BC_CANTILEVER fixes the face x = x_min instead.
 __host__ __device__ inline bool u_fixed(const Grid& G, int kind, int i, int j, int k, int comp) {
+  if (kind == PM_BC_CANTILEVER) return i == 0;
   if (k == 0) return true;
   if (kind != PM_BC_ROLLERS) return false;
   if (comp == 0) return i == 0 || i == G.nx;
@@ -115,12 +118,14 @@ __host__ __device__ inline bool u_fixed(const Grid& G, int kind, int i, int j, i
   return false;
 }
 
-// Dirichlet face pressures: the faces of the top plane (drained boundary).
+// Dirichlet face pressures: the faces of the top plane when it is drained.
 __host__ __device__ inline bool pi_fixed(const Grid& G, int64_t f) {
-  return f >= G.nf - (int64_t)G.nx * G.ny;  // z-faces are numbered last, plane k = nz at the end
+  return G.drained && f >= G.nf - (int64_t)G.nx * G.ny;  // z-faces numbered last, plane k = nz at the end
 }
 // the same for local face e of cell (., ., k): only the +z face of a top cell
-__host__ __device__ inline bool pi_fixed_local(const Grid& G, int k, int e) { return e == 5 && k == G.nz - 1; }
+__host__ __device__ inline bool pi_fixed_local(const Grid& G, int k, int e) {
+  return G.drained && e == 5 && k == G.nz - 1;
+}
 
 // packed index of (a, b), a <= b, in the row-major upper triangle of a
 // symmetric 6x6 matrix (21 entries)
@@ -198,7 +203,7 @@ __device__ __forceinline__ void visit_face_cells(const Grid& G, uint32_t i, uint
 // face has one owner.  For each owned face f, out(f, fixed, acc) receives the
 // sum over the (one or two) cells T adjacent to f of
 // term(LocalFace<l>{}, c_T, F_T, k_T), l the local index of f in T, F_T the
-// six faces of T and k_T its layer; fixed marks the Dirichlet faces (the top
+// six faces of T and k_T its layer; fixed marks the Dirichlet faces (a drained top
 // plane), whose acc is not formed.  A thread per cell reads each cell's data
 // for its own faces and its -x/-y/-z neighbours' data for the shared faces
 // (neighbouring threads, so mostly from cache): the per-cell arrays cross HBM
@@ -218,9 +223,9 @@ __device__ __forceinline__ void owned_face_dir(const Grid& G, uint32_t i, uint32
     acc += term(LocalFace<2 * D + 1>{}, bi + nx * (bj + ny * bk), Fb, bk);
   }
   out(F[2 * D], false, acc);
-  // face F[2D+1] on the last layer: this cell only; the top plane is Dirichlet
+  // face F[2D+1] on the last layer: this cell only; a drained top plane is Dirichlet
   if (pos == lim - 1) {
-    if (D == 2)
+    if (D == 2 && G.drained)
       out(F[5], true, (T)0);
     else
       out(F[2 * D + 1], false, term(LocalFace<2 * D + 1>{}, c, F, k));

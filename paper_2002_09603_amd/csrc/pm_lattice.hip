@@ -156,6 +156,7 @@ __device__ __forceinline__ void lattice_rows(const Grid& G, int kind, const T* _
 
 // no Dirichlet component among the 27 neighbours of node (i,j,k)
 __device__ inline bool free_neighbourhood(const Grid& G, int kind, int i, int j, int k) {
+  if (kind == PM_BC_CANTILEVER) return i >= 2;
   if (k < 2) return false;
   if (kind != PM_BC_ROLLERS) return true;
   return i >= 2 && i <= G.nx - 2 && j >= 2 && j <= G.ny - 2;
@@ -183,8 +184,8 @@ __device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const T* __r
 template <class T>
 constexpr int kLatWaves = sizeof(T) == 8 ? 3 : 1;
 
-template <class T>
-__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, int kind, const T* __restrict__ Kh,
+template <class T, int KIND>
+__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, const T* __restrict__ Kh,
                                                   const T* __restrict__ E, const T* __restrict__ dinv,
                                                   const T* __restrict__ b, const T* __restrict__ xin,
                                                   T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, int kind
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   T ax[3];
-  lattice_Ax<T>(G, kind, Kh, E, xin, n, i, j, k, ax);
+  lattice_Ax<T>(G, KIND, Kh, E, xin, n, i, j, k, ax);
   T res[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) res[a] = b[3 * n + a] - ax[a];
@@ -207,38 +208,40 @@ __global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, int kind
   }
 }
 
-template <class T>
-__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_residual(Grid G, int kind, const T* __restrict__ Kh,
+template <class T, int KIND>
+__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_residual(Grid G, const T* __restrict__ Kh,
                                                       const T* __restrict__ E, const T* __restrict__ b,
                                                       const T* __restrict__ x, T* __restrict__ r) {
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   T ax[3];
-  lattice_Ax<T>(G, kind, Kh, E, x, n, i, j, k, ax);
+  lattice_Ax<T>(G, KIND, Kh, E, x, n, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a) r[3 * n + a] = b[3 * n + a] - ax[a];
 }
 
-__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_apply(Grid G, int kind, const double* __restrict__ Kh,
+template <int KIND>
+__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_apply(Grid G, const double* __restrict__ Kh,
                                                    const double* __restrict__ E, const double* __restrict__ x,
                                                    double* __restrict__ y) {
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   double ax[3];
-  lattice_Ax<double>(G, kind, Kh, E, x, n, i, j, k, ax);
+  lattice_Ax<double>(G, KIND, Kh, E, x, n, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a) y[3 * n + a] = ax[a];
 }
 
 // u-rows of A_H (sgn = +1) or A_H^T (sgn = -1): A_uu u + sgn A_up p on free
 // rows, in FP64 from FP64 or FP32 inputs
-template <class TX>
-__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_ah_u(Grid G, int kind, const double* __restrict__ Kh,
+template <class TX, int KIND>
+__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_ah_u(Grid G, const double* __restrict__ Kh,
                                                   const double* __restrict__ ah, const double* __restrict__ E,
                                                   const TX* __restrict__ u, const TX* __restrict__ p, double sgn,
                                                   double* __restrict__ y) {
+  constexpr int kind = KIND;
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
@@ -314,13 +317,27 @@ const double* lat_E<double>(const LatticeOp& op) { return op.E; }
 template <>
 const float* lat_E<float>(const LatticeOp& op) { return op.E32; }
 
+// the stencil kernels are instantiated per boundary-condition kind, so each
+// carries only its own Dirichlet tests (fewer registers than a run-time kind)
+template <class F>
+void with_bc_kind(int kind, F&& f) {
+  if (kind == PM_BC_CANTILEVER)
+    f(std::integral_constant<int, PM_BC_CANTILEVER>{});
+  else if (kind == PM_BC_ROLLERS)
+    f(std::integral_constant<int, PM_BC_ROLLERS>{});
+  else
+    f(std::integral_constant<int, PM_BC_COLUMN>{});
+}
+
 }  // namespace
 
 template <class T>
 void lattice_cheb_step(hipStream_t s, const Grid& G, const LatticeOp& op, const T* dinv, const T* b, const T* xin,
                        T* xout, T* d, T c1, T c2) {
-  k_lat_cheb<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, lat_K<T>(op), lat_E<T>(op), dinv, b, xin, xout, d,
-                                                    c1, c2);
+  with_bc_kind(op.kind, [&](auto kd) {
+    k_lat_cheb<T, decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, lat_K<T>(op), lat_E<T>(op), dinv, b,
+                                                                         xin, xout, d, c1, c2);
+  });
   PM_CHECK_LAUNCH();
 }
 template void lattice_cheb_step<double>(hipStream_t, const Grid&, const LatticeOp&, const double*, const double*,
@@ -330,7 +347,10 @@ template void lattice_cheb_step<float>(hipStream_t, const Grid&, const LatticeOp
 
 template <class T>
 void lattice_residual(hipStream_t s, const Grid& G, const LatticeOp& op, const T* b, const T* x, T* r) {
-  k_lat_residual<T><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, lat_K<T>(op), lat_E<T>(op), b, x, r);
+  with_bc_kind(op.kind, [&](auto kd) {
+    k_lat_residual<T, decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, lat_K<T>(op), lat_E<T>(op), b,
+                                                                             x, r);
+  });
   PM_CHECK_LAUNCH();
 }
 template void lattice_residual<double>(hipStream_t, const Grid&, const LatticeOp&, const double*, const double*,
@@ -339,14 +359,18 @@ template void lattice_residual<float>(hipStream_t, const Grid&, const LatticeOp&
                                       float*);
 
 void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y) {
-  k_lat_apply<<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, op.Kh, op.E, x, y);
+  with_bc_kind(op.kind, [&](auto kd) {
+    k_lat_apply<decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.Kh, op.E, x, y);
+  });
   PM_CHECK_LAUNCH();
 }
 
 template <class TX>
 void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const TX* u, const TX* p, double sgn,
                   double* y) {
-  k_lat_ah_u<TX><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.kind, op.Kh, op.ah, op.E, u, p, sgn, y);
+  with_bc_kind(op.kind, [&](auto kd) {
+    k_lat_ah_u<TX, decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.Kh, op.ah, op.E, u, p, sgn, y);
+  });
   PM_CHECK_LAUNCH();
 }
 template void lattice_ah_u<double>(hipStream_t, const Grid&, const LatticeOp&, const double*, const double*, double,

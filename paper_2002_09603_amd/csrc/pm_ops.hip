@@ -127,7 +127,7 @@ struct AhPiTerm {
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
       const double t = ld32(Mp + (size_t)sym6(L < e ? L : e, L < e ? e : L) * G.nc, c) * (double)ld32(pi, F[e]);
-      if (e != 5 || ck != (uint32_t)G.nz - 1) v += t;  // the top face of the top layer is a zero column
+      if (!pi_fixed_local(G, (int)ck, e)) v += t;  // a drained top face is a zero column
     }
     return v;
   }
@@ -165,8 +165,8 @@ struct AhPiBlockTerm {
     const double gl = sd ? mo + md : md + mo;
     double v = -sp * gl * (double)ld32(p, c);
     v += (sd ? mo : md) * (double)ld32(pi, F[2 * d]);
-    // the top face of the top layer is a zero column
-    if (d != 2 || ck != (uint32_t)G.nz - 1) v += (sd ? md : mo) * (double)ld32(pi, F[2 * d + 1]);
+    // a drained top face is a zero column
+    if (!pi_fixed_local(G, (int)ck, 2 * d + 1)) v += (sd ? md : mo) * (double)ld32(pi, F[2 * d + 1]);
     return v;
   }
 };

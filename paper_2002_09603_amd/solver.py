@@ -103,7 +103,7 @@ class PoroSolver:
 
     def __init__(self, nx, ny, nz, E, kappa, coords=None, L=(1.0, 1.0, 1.0), nu=0.25, biot=1.0,
                  S_eps=0.0, mu=1.0, dt=1e-2, traction=(0.0, 0.0, -1.0), p_top=0.0, rollers=False,
-                 opts: Optional[Options] = None, device="cuda"):
+                 opts: Optional[Options] = None, device="cuda", cantilever=False):
         self.device = torch.device(device)
         self.opts = opts or Options()
         self.dt = float(dt)
@@ -113,8 +113,9 @@ class PoroSolver:
         X_d = None if coords is None else _dev_f64(coords, self.device)
         mesh = _capi.pm_mesh(self.nx, self.ny, self.nz, _ptr(X_d), float(L[0]), float(L[1]), float(L[2]))
         mat = _capi.pm_material(_ptr(E_d), _ptr(k_d), float(nu), float(biot), float(S_eps), float(mu))
-        bc = _capi.pm_bc((C.c_double * 3)(*[float(t) for t in traction]), float(p_top),
-                         _capi.PM_BC_ROLLERS if rollers else _capi.PM_BC_COLUMN)
+        kind = (_capi.PM_BC_CANTILEVER if cantilever else
+                (_capi.PM_BC_ROLLERS if rollers else _capi.PM_BC_COLUMN))
+        bc = _capi.pm_bc((C.c_double * 3)(*[float(t) for t in traction]), float(p_top), kind)
         o = self.opts.to_c()
         self._ctx = C.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -228,4 +229,5 @@ def from_problem(prob, opts: Optional[Options] = None, device="cuda") -> PoroSol
     return PoroSolver(prob.nx, prob.ny, prob.nz, prob.E, prob.kappa, coords=prob.coords, nu=prob.nu,
                       biot=prob.biot, S_eps=prob.S_eps, mu=prob.mu, dt=prob.dt, traction=prob.traction,
                       p_top=prob.p_top, rollers=getattr(prob, "rollers", False),
-                      opts=opts or Options(stabilize=getattr(prob, "stabilize", True)), device=device)
+                      opts=opts or Options(stabilize=getattr(prob, "stabilize", True)), device=device,
+                      cantilever=getattr(prob, "bc", "column") == "cantilever")

@@ -6,15 +6,17 @@ from synth import Problem, uniform_coords, perturbed_coords
 
 
 def box_problem(nx, ny, nz, seed=0, perturb=False, S_eps=0.0, nu=0.25, dt=1e-2, sigma_k=1.0,
-                sigma_E=0.3, p_top=0.0, rollers=False, stabilize=True):
-    """Seeded non-cubic box with log-normal E and anisotropic diagonal kappa."""
+                sigma_E=0.3, p_top=0.0, rollers=False, stabilize=True, bc="column"):
+    """Seeded non-cubic box with log-normal E and anisotropic diagonal kappa
+    (bc "column": bottom fixed, top drained; "cantilever": face x = 0 fixed,
+    no-flow everywhere)."""
     rng = np.random.default_rng(seed)
     nc = nx * ny * nz
     coords = perturbed_coords(nx, ny, nz, seed + 1) if perturb else uniform_coords(nx, ny, nz)
     E = 1e4 * np.exp(sigma_E * rng.standard_normal(nc))
     kappa = 1e-3 * np.exp(sigma_k * rng.standard_normal((nc, 3)))
     return Problem("box", nx, ny, nz, coords, E, kappa, nu=nu, S_eps=S_eps, dt=dt, p_top=p_top,
-                   rollers=rollers, stabilize=stabilize)
+                   rollers=rollers, stabilize=stabilize, bc=bc)
 
 
 def rel(a, b):

@@ -41,6 +41,8 @@ CASES = {
     "box10x6x4": dict(nx=10, ny=6, nz=4, seed=1),
     "perturbed6x8x6": dict(nx=6, ny=8, nz=6, seed=2, perturb=True),
     "rollers4x4x8_ptop": dict(nx=4, ny=4, nz=8, seed=3, rollers=True, p_top=0.3, S_eps=1e-4),
+    "cantilever8x6x4": dict(nx=8, ny=6, nz=4, seed=5, bc="cantilever"),
+    "cantilever_perturbed6x6x4": dict(nx=6, ny=6, nz=4, seed=6, bc="cantilever", perturb=True, dt=1e-5),
 }
 
 
@@ -86,7 +88,8 @@ def test_operator_and_block_parity(name, lattice):
 # (case, FP32 preconditioner, lattice operator, Gram-Schmidt passes); one pass
 # takes the fused orthogonalise-and-normalise path (FP32 preconditioned
 # vectors with the FP32 preconditioner)
-SOLVE_CASES = ([(n, fp32, True, 2) for n in ("unit8", "box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop")
+SOLVE_CASES = ([(n, fp32, True, 2) for n in ("unit8", "box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop",
+                                              "cantilever8x6x4", "cantilever_perturbed6x6x4")
                 for fp32 in (False, True)] + [("box10x6x4", fp32, False, 2) for fp32 in (False, True)]
                + [(n, fp32, True, 1) for n in ("box10x6x4", "perturbed6x8x6") for fp32 in (False, True)])
 
@@ -221,7 +224,7 @@ def test_error_codes():
 
 
 @pytest.mark.parametrize("fp32", [False, True])
-@pytest.mark.parametrize("name", ["box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop"])
+@pytest.mark.parametrize("name", ["box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop", "cantilever8x6x4"])
 def test_matrix_free_finest_levels_match_assembled(name, fp32):
     """The V-cycles with the matrix-free finest levels (A_uu on lattices, C~_pi
     cell by cell, from the full or, on boxes, the direction-block element
@@ -279,7 +282,8 @@ def test_block_minv_matches_full(name):
             assert rel(a[k], b[k]) <= 1e-9
 
 
-RBM_CASES = [(n, fp32) for n in ("box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop") for fp32 in (False, True)]
+RBM_CASES = [(n, fp32) for n in ("box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop", "cantilever8x6x4")
+             for fp32 in (False, True)]
 
 
 @pytest.mark.parametrize("name,fp32", RBM_CASES, ids=[f"{n}-fp32={f}" for n, f in RBM_CASES])

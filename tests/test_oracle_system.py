@@ -315,3 +315,46 @@ def test_sampled_rows_equal_full_assembly():
         Ar, br = system_rows(prob, rows)
         assert abs(Ar - A[rows]).max() <= 1e-12 * abs(A).max()
         assert np.allclose(br, b[rows], rtol=1e-12, atol=1e-15 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("dt", [0.1, 1e-5])
+def test_cantilever_impermeable_volume_conservation(dt):
+    """Cantilever (Sec. 5.2): no face is drained, so summing the p-rows over
+    all cells cancels every flux (interior faces by the pi-rows' continuity,
+    boundary faces by their zero-flux rows) and the stabilization (rows of
+    L_cube sum to zero): from rest, S_eps = 0 leaves sum_T (A_pu u)_T = 0,
+    the discrete undrained volume balance.  The drained column problem of the
+    same size does not satisfy it (fluid leaves through the top)."""
+    from synth import cantilever
+    prob = cantilever(4, dt)
+    A, b, B = build_system(prob)
+    assert not B.pi_fixed.any()
+    fixed_nodes = np.nonzero(B.u_fixed.reshape(-1, 3).all(axis=1))[0]
+    assert len(fixed_nodes) == 5 * 5  # the face x = 0
+    u, p, pi = split(B, direct_solve(A, b))
+    vol = B.A_pu @ u
+    assert abs(vol.sum()) <= 1e-10 * np.abs(vol).sum()
+    col = Problem("c", 4, 4, 4, prob.coords, prob.E, prob.kappa, nu=prob.nu, biot=1.0, S_eps=0.0, mu=prob.mu,
+                  dt=dt)
+    A2, b2, B2 = build_system(col)
+    u2, _, _ = split(B2, direct_solve(A2, b2))
+    v2 = B2.A_pu @ u2
+    assert abs(v2.sum()) > 1e-3 * np.abs(v2).sum()
+
+
+def test_cantilever_mirror_symmetry():
+    """The homogeneous cantilever is symmetric under the reflection y -> 1 - y:
+    u_x, u_z and p are even, u_y is odd (a transposed index or a wrong sign
+    in the face coupling breaks it)."""
+    from synth import cantilever
+    n = 4
+    prob = cantilever(n, 1e-2)
+    A, b, B = build_system(prob)
+    u, p, pi = split(B, direct_solve(A, b))
+    U = u.reshape(n + 1, n + 1, n + 1, 3)  # [k, j, i, comp]
+    P = p.reshape(n, n, n)
+    s = np.abs(U).max()
+    assert np.abs(U[:, ::-1, :, 0] - U[..., 0]).max() <= 1e-9 * s
+    assert np.abs(U[:, ::-1, :, 2] - U[..., 2]).max() <= 1e-9 * s
+    assert np.abs(U[:, ::-1, :, 1] + U[..., 1]).max() <= 1e-9 * s
+    assert np.abs(P[:, ::-1, :] - P).max() <= 1e-9 * np.abs(P).max()
