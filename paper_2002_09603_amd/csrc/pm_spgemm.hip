@@ -3,15 +3,17 @@
 //
 // Symbolic: rows are binned by ub = sum over the row of A of the lengths of
 // the B rows it touches (an upper bound on the row's distinct columns):
-//   small   ub <= 64   16 lanes per row, 128-slot hash
+//   small   ub <= 32, <= 64: 32 or 64 lanes per row, one (A entry, B entry)
+//                      pair per lane, sorted by a bitonic network
 //   medium  ub <= 512  the small configuration first; rows with more than 64
 //                      distinct columns are redone with a wavefront per row
 //                      and a 1024-slot hash
 //   large   otherwise  a wavefront per row, 1024-slot hash first, the rest
 //                      with 8192 slots
-// Each group hashes its row's column ids in LDS, ranks the distinct ids
-// (sorted order) and writes them to a scratch array at the row's ub offset;
-// a compaction copies them into C after a scan of the counts.
+// Otherwise each group hashes its row's column ids in LDS and ranks the
+// distinct ids (sorted order); either way they go to a scratch array at the
+// row's ub offset, and a compaction copies them into C after a scan of the
+// counts.
 // Numeric: rows are binned by their exact number of distinct columns (<= 16,
 // <= 64: 16 lanes per row; <= 512, more: a wavefront per row).  The entries
 // of A's row are taken in order; lanes of the group cover the entries of the
@@ -198,6 +200,76 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
     dst[rank] = key;
   }
   if (lane == 0) cnt[row] = u;
+}
+
+// Symbolic phase for rows with at most G (A entry, B entry) pairs, G lanes
+// per row and one pair per lane: lane q takes pair q (the pairs of A's entries
+// in order, located by a scan of the B-row lengths and a search over the
+// lanes), the G column ids are sorted by a bitonic network over the lanes and
+// the distinct ones written in ascending order (the output of k_sym, without
+// LDS or atomics).
+template <int G>
+__global__ void __launch_bounds__(256) k_sym_sort(int nlist, const int* __restrict__ list,
+                                                  const int* __restrict__ arp, const int* __restrict__ acol,
+                                                  const int* __restrict__ brp, const int* __restrict__ bcol,
+                                                  const int64_t* __restrict__ ubofs, int* __restrict__ tmp,
+                                                  int* __restrict__ cnt) {
+  static_assert(G == 32 || G == 64, "one row per half or whole wavefront");
+  constexpr int LG = G == 32 ? 5 : 6;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int li = (int)(t / G), l = (int)(t % G);
+  const bool valid = li < nlist;
+  const int row = valid ? list[li] : 0;
+  const int e0 = valid ? arp[row] : 0, na = valid ? arp[row + 1] - e0 : 0;
+  int key = INT_MAX;
+  int base = 0;  // pairs of the earlier chunks of A entries
+  for (int c0 = 0; c0 < na; c0 += G) {  // the same trip count on every lane of the row
+    const int q = c0 + l;
+    int fb = 0, len = 0;
+    if (q < na) {
+      const int k = acol[e0 + q];
+      fb = brp[k];
+      len = brp[k + 1] - fb;
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const int v = __shfl_up(incl, o, G);
+      if (l >= o) incl += v;
+    }
+    const int total = __shfl(incl, G - 1, G);
+    const int p = l - base;  // this lane's pair within the chunk, if 0 <= p < total
+    int lo = 0, hi = G - 1;  // first entry lane whose inclusive count exceeds p
+#pragma unroll
+    for (int it = 0; it < LG; ++it) {
+      const int mid = (lo + hi) >> 1;
+      const int v = __shfl(incl, mid, G);
+      if (v > p) hi = mid; else lo = mid + 1;
+      if (lo > hi) lo = hi;
+    }
+    const int fbj = __shfl(fb, lo, G), exj = __shfl(incl - len, lo, G);
+    if (p >= 0 && p < total) key = bcol[fbj + p - exj];
+    base += total;
+  }
+  // bitonic sort (ascending) over the G lanes of the row
+#pragma unroll
+  for (int k = 2; k <= G; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int other = __shfl_xor(key, j, G);
+      const bool up = (l & k) == 0;
+      const bool lower = (l & j) == 0;
+      key = (lower == up) ? min(key, other) : max(key, other);
+    }
+  const int prev = __shfl_up(key, 1, G);
+  const bool first = key != INT_MAX && (l == 0 || prev != key);
+  const int lane = threadIdx.x & 63, gbase = lane & ~(G - 1);
+  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  const unsigned long long grp = (__ballot(first) >> gbase) & gmask;
+  if (valid) {
+    if (first) tmp[ubofs[row] + __popcll(grp & ((1ull << l) - 1ull))] = key;
+    if (l == 0) cnt[row] = __popcll(grp);
+  }
 }
 
 // rows of a list whose symbolic pass overflowed (cnt = -1)
@@ -584,23 +656,27 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
     k_ub<4><<<blocks_for((int64_t)n * 4), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
   else
     k_ub<16><<<blocks_for((int64_t)n * 16), kBlock, 0, s>>>(n, A.rowptr, A.col, B.rowptr, ub);
-  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, ub, kSmallUb, kMediumUb, INT_MAX, counters, lists);
+  k_classify<<<blocks_for(n), kBlock, 0, s>>>(n, ub, kSmallUb / 2, kSmallUb, kMediumUb, counters, lists);
   k_i64_from_i32<<<blocks_for(n), kBlock, 0, s>>>(n, ub, ub64);
   PM_CHECK_LAUNCH();
   int h[4] = {0, 0, 0, 0};
   int64_t tmp_total = 0;
-  PM_HIP(hipMemcpyAsync(h, counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipMemcpyAsync(h, counters, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
   exclusive_scan64(s, ub64, ubofs, n, &tmp_total);
   int* tmp = dalloc<int>(std::max<int64_t>(tmp_total, 1));
   int* status = counters + 4;  // cleared above
+  // bounds <= 32 and <= 64: one pair per lane, sorted
   if (h[0] > 0)
-    k_sym<16, 16, 128, 64><<<(h[0] + 15) / 16, 256, 0, s>>>(h[0], lists, A.rowptr, A.col, B.rowptr, B.col, ubofs,
-                                                            tmp, cnt, status);
+    k_sym_sort<32><<<blocks_for((int64_t)h[0] * 32), kBlock, 0, s>>>(h[0], lists, A.rowptr, A.col, B.rowptr, B.col,
+                                                                    ubofs, tmp, cnt);
+  if (h[1] > 0)
+    k_sym_sort<64><<<blocks_for((int64_t)h[1] * 64), kBlock, 0, s>>>(h[1], lists + (size_t)n, A.rowptr, A.col,
+                                                                    B.rowptr, B.col, ubofs, tmp, cnt);
   // Rows with a larger bound mostly have few distinct columns (Galerkin rows):
   // each class first tries the next smaller configuration, marking the rows
   // that do not fit (cnt = -1), which are redone with its own.
   int* rc = dalloc<int>(2);
-  int* retry = dalloc<int>(std::max(h[1], h[2]));
+  int* retry = dalloc<int>(std::max(h[2], h[3]));
   PM_HIP(hipMemsetAsync(rc, 0, 2 * sizeof(int), s));
   auto retry_rows = [&](const int* rl, int nl, int* counter) {
     k_retry_list<<<blocks_for(nl), kBlock, 0, s>>>(nl, rl, cnt, counter, retry);
@@ -610,22 +686,22 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
     PM_HIP(hipStreamSynchronize(s));
     return nr;
   };
-  if (h[1] > 0) {
-    const int* rl = lists + (size_t)n;
-    k_sym<16, 16, 128, 64, true><<<(h[1] + 15) / 16, 256, 0, s>>>(h[1], rl, A.rowptr, A.col, B.rowptr, B.col,
+  if (h[2] > 0) {
+    const int* rl = lists + 2 * (size_t)n;
+    k_sym<16, 16, 128, 64, true><<<(h[2] + 15) / 16, 256, 0, s>>>(h[2], rl, A.rowptr, A.col, B.rowptr, B.col,
                                                                   ubofs, tmp, cnt, status);
-    const int nr = retry_rows(rl, h[1], rc);
+    const int nr = retry_rows(rl, h[2], rc);
     if (nr > 0)
       k_sym<64, 4, 1024, 512><<<(nr + 3) / 4, 256, 0, s>>>(nr, retry, A.rowptr, A.col, B.rowptr, B.col, ubofs, tmp,
                                                            cnt, status);
     PM_CHECK_LAUNCH();
   }
-  if (h[2] > 0) {
+  if (h[3] > 0) {
     // the 1024-slot hash first, the rest with 8192
-    const int* rl = lists + 2 * (size_t)n;
-    k_sym<64, 4, 1024, 512, true><<<(h[2] + 3) / 4, 256, 0, s>>>(h[2], rl, A.rowptr, A.col, B.rowptr, B.col, ubofs,
+    const int* rl = lists + 3 * (size_t)n;
+    k_sym<64, 4, 1024, 512, true><<<(h[3] + 3) / 4, 256, 0, s>>>(h[3], rl, A.rowptr, A.col, B.rowptr, B.col, ubofs,
                                                                  tmp, cnt, status);
-    const int nr = retry_rows(rl, h[2], rc + 1);
+    const int nr = retry_rows(rl, h[3], rc + 1);
     if (nr > 0)
       k_sym<64, 1, 8192, 6144><<<nr, 64, 0, s>>>(nr, retry, A.rowptr, A.col, B.rowptr, B.col, ubofs, tmp, cnt,
                                                  status);
