@@ -56,6 +56,9 @@ def test_default_options():
     assert o.rtol == 1e-8 and o.restart == 100 and o.max_it == 1000 and o.stabilize == 1
     assert o.precond_fp32 == 0 and o.increment_stab == 1 and o.cheb_degree == 2
     assert o.rtol_transpose == 0.0 and o.restart_transpose == 100 and o.orth_passes_transpose == 2
+    # direction-block M_T^-1 where the cells allow it; translation-only near kernel for A_uu
+    assert o.block_minv == 1 and o.rbm_u == 0 and o.lattice_uu == 1 and o.cell_pi == 1
+    assert _capi.PM_BC_CANTILEVER == 2
 
 
 @pytest.mark.parametrize("dims", [(3, 4, 4), (4, 4, 0), (4, 5, 6)])
@@ -85,6 +88,11 @@ def test_setup_rejects_bad_scalars_without_a_gpu():
         mat = _capi.pm_material(E.ctypes.data, k.ctypes.data, nu, 1.0, 0.0, 1.0)
         rc = _capi.lib.pm_setup(C.byref(mesh), C.byref(mat), C.byref(bc), dt, None, None, C.byref(ctx))
         assert rc == _capi.PM_EINVAL
+    # an unknown boundary-condition kind
+    mat = _capi.pm_material(E.ctypes.data, k.ctypes.data, 0.25, 1.0, 0.0, 1.0)
+    bad = _capi.pm_bc((C.c_double * 3)(0, 0, -1), 0.0, 7)
+    assert _capi.lib.pm_setup(C.byref(mesh), C.byref(mat), C.byref(bad), 1e-2, None, None,
+                              C.byref(ctx)) == _capi.PM_EINVAL
     assert _capi.lib.pm_assemble(None) == _capi.PM_EINVAL
     assert _capi.lib.pm_solve(None, None, None, None, None, None) == _capi.PM_EINVAL
 

@@ -43,6 +43,8 @@ CASES = {
     "rollers4x4x8_ptop": dict(nx=4, ny=4, nz=8, seed=3, rollers=True, p_top=0.3, S_eps=1e-4),
     "cantilever8x6x4": dict(nx=8, ny=6, nz=4, seed=5, bc="cantilever"),
     "cantilever_perturbed6x6x4": dict(nx=6, ny=6, nz=4, seed=6, bc="cantilever", perturb=True, dt=1e-5),
+    "graded8x6x4": dict(nx=8, ny=6, nz=4, seed=7, graded=True),
+    "tiny2x2x2": dict(nx=2, ny=2, nz=2, seed=8),
 }
 
 
@@ -59,7 +61,8 @@ def test_operator_and_block_parity(name, lattice):
     s = from_problem(prob, Options(lattice_uu=lattice)).assemble()
     assert (s.n_u, s.n_p, s.n_pi) == (B.n_u, B.n_p, B.n_pi)
     # uniform boxes take the lattice operator when allowed, perturbed meshes never
-    assert s.info()["lattice_uu"] == int(lattice and not CASES[name].get("perturb", False))
+    translates = not (CASES[name].get("perturb", False) or CASES[name].get("graded", False))
+    assert s.info()["lattice_uu"] == int(lattice and translates)
     # axis-aligned boxes (diagonal permeability) store M_T^-1 by direction blocks
     assert s.info()["block_minv"] == int(not CASES[name].get("perturb", False))
     rng = np.random.default_rng(7)
@@ -89,7 +92,8 @@ def test_operator_and_block_parity(name, lattice):
 # takes the fused orthogonalise-and-normalise path (FP32 preconditioned
 # vectors with the FP32 preconditioner)
 SOLVE_CASES = ([(n, fp32, True, 2) for n in ("unit8", "box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop",
-                                              "cantilever8x6x4", "cantilever_perturbed6x6x4")
+                                              "cantilever8x6x4", "cantilever_perturbed6x6x4", "graded8x6x4",
+                                              "tiny2x2x2")
                 for fp32 in (False, True)] + [("box10x6x4", fp32, False, 2) for fp32 in (False, True)]
                + [(n, fp32, True, 1) for n in ("box10x6x4", "perturbed6x8x6") for fp32 in (False, True)])
 
