@@ -5,6 +5,8 @@
 // floating-point atomics; summation orders are fixed.
 #include <cstdio>
 #include <cstdlib>
+#include <iterator>
+#include <map>
 #include <mutex>
 #include <unordered_map>
 
@@ -13,24 +15,32 @@
 namespace pm {
 
 // Caching device allocator.  Setup rebuilds many temporaries per step;
-// returning freed blocks to per-(stream, size class) free lists avoids the
-// device-wide synchronization of hipFree and repeated hipMalloc calls.  A
-// block freed on one stream is only reused by allocations on the same stream,
-// so stream order protects kernels still reading it.
+// returning freed blocks to per-stream free lists avoids the device-wide
+// synchronization of hipFree and repeated hipMalloc calls.  A block freed on
+// one stream is only reused by allocations on the same stream, so stream
+// order protects kernels still reading it.  A request takes the smallest
+// cached block of at least its size class and at most 5/4 of it, so blocks
+// of nearby sizes (the data-dependent buffers of the Galerkin products) are
+// shared across steps instead of piling up.  When hipMalloc runs out of
+// memory, cached blocks are released largest first only until it succeeds.
 namespace {
 std::mutex g_alloc_mu;
-struct AllocKey {
+struct Block {
   hipStream_t s;
   size_t bytes;
-  bool operator==(const AllocKey& o) const { return s == o.s && bytes == o.bytes; }
 };
-struct AllocKeyHash {
-  size_t operator()(const AllocKey& k) const { return std::hash<size_t>()(k.bytes) ^ (std::hash<void*>()((void*)k.s) << 1); }
-};
-std::unordered_map<AllocKey, std::vector<void*>, AllocKeyHash> g_free;
-std::unordered_map<void*, AllocKey> g_live;
+std::unordered_map<hipStream_t, std::multimap<size_t, void*>> g_free;
+std::unordered_map<void*, Block> g_live;
 size_t g_cached_bytes = 0;
 thread_local hipStream_t g_cur_stream = nullptr;
+
+bool alloc_verbose() {
+  static const bool v = [] {
+    const char* e = getenv("PM_AMG_VERBOSE");
+    return e && e[0] == '1';
+  }();
+  return v;
+}
 
 size_t size_class(size_t b) {
   if (b <= (1u << 20)) {
@@ -44,9 +54,22 @@ size_t size_class(size_t b) {
 
 void release_cached_locked() {
   for (auto& kv : g_free)
-    for (void* p : kv.second) (void)hipFree(p);
+    for (auto& e : kv.second) (void)hipFree(e.second);
   g_free.clear();
   g_cached_bytes = 0;
+}
+
+// free the largest cached block (of any stream); false if none is left
+bool release_largest_locked() {
+  std::multimap<size_t, void*>* best = nullptr;
+  for (auto& kv : g_free)
+    if (!kv.second.empty() && (!best || kv.second.rbegin()->first > best->rbegin()->first)) best = &kv.second;
+  if (!best) return false;
+  auto last = std::prev(best->end());
+  (void)hipFree(last->second);
+  g_cached_bytes -= last->first;
+  best->erase(last);
+  return true;
 }
 }  // namespace
 
@@ -58,28 +81,37 @@ void release_device_cache() {
 }
 
 void* dmalloc(size_t bytes) {
-  const AllocKey key{g_cur_stream, size_class(bytes)};
+  const size_t cls = size_class(bytes);
   std::lock_guard<std::mutex> lk(g_alloc_mu);
-  auto it = g_free.find(key);
-  if (it != g_free.end() && !it->second.empty()) {
-    void* p = it->second.back();
-    it->second.pop_back();
-    g_cached_bytes -= key.bytes;
-    g_live[p] = key;
-    return p;
+  auto fl = g_free.find(g_cur_stream);
+  if (fl != g_free.end()) {
+    auto it = fl->second.lower_bound(cls);
+    if (it != fl->second.end() && it->first <= cls + cls / 4) {
+      void* p = it->second;
+      g_cached_bytes -= it->first;
+      g_live[p] = Block{g_cur_stream, it->first};
+      fl->second.erase(it);
+      return p;
+    }
   }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, key.bytes);
-  if (e != hipSuccess) {
+  hipError_t e = hipMalloc(&p, cls);
+  if (e != hipSuccess && alloc_verbose())
+    fprintf(stderr, "[alloc] hipMalloc of %zu bytes failed with %zu bytes cached: releasing largest first\n", cls,
+            g_cached_bytes);
+  while (e != hipSuccess) {
     (void)hipGetLastError();
-    release_cached_locked();
-    e = hipMalloc(&p, key.bytes);
+    if (!release_largest_locked()) break;
+    e = hipMalloc(&p, cls);
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error(PM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
   }
-  g_live[p] = key;
+  if (alloc_verbose() && cls >= (size_t(1) << 30))
+    fprintf(stderr, "[alloc] new block of %.2f GiB (%.2f GiB cached)\n", cls / 1073741824.0,
+            g_cached_bytes / 1073741824.0);
+  g_live[p] = Block{g_cur_stream, cls};
   return p;
 }
 
@@ -91,7 +123,7 @@ void dfree(void* p) {
     (void)hipFree(p);
     return;
   }
-  g_free[it->second].push_back(p);
+  g_free[it->second.s].emplace(it->second.bytes, p);
   g_cached_bytes += it->second.bytes;
   g_live.erase(it);
 }
