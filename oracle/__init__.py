@@ -19,6 +19,11 @@ mixed finite element coupled poromechanics"):
                 triangular preconditioner with exact inner solves (eq.
                 hybridPrec, variant M_I^(h)), B~_p (eq. app_Bp), C~_pi, FGMRES,
                 flux reconstruction and conservation residuals
+* ``mfe``       the non-hybridized mixed system (eq. mfeSys, MFE_matrix,
+                MFE_vector) with the stabilized pressure block, C~_p and the
+                block triangular preconditioner of eq. prec (variant M_I^(m));
+                pinned to the hybrid oracle by the equivalence of the two
+                formulations
 * ``adjoint``   transposed solve and per-cell gradients w.r.t. log kappa and
                 log E (an extension: the paper has no adjoint)
 * ``terzaghi``  one-dimensional consolidation closed form (pin only)
