@@ -232,9 +232,17 @@ int pm_reconstruct_w(pm_ctx* ctx, const double* p, const double* pi, double* w);
  *   PM_OP_BP       y = B~_p x           (n_p -> n_p, diagonal)
  *   PM_OP_AUU      y = A_uu x           (n_u -> n_u, assembled, Dirichlet rows identity)
  *   PM_OP_VCYCLE_U y = one V-cycle for A_uu applied to x (zero initial guess)
- *   PM_OP_VCYCLE_PI y = one V-cycle for C~_pi applied to x */
+ *   PM_OP_VCYCLE_PI y = one V-cycle for C~_pi applied to x
+ *   PM_OP_MFE      y = A_M x            (N -> N) the non-hybridized mixed system of
+ *                  Sec. 2.1 (eq. mfeSys, Appendix A eq. MFE_matrix) with the stabilized
+ *                  pressure block A_pp + A_stab of Sec. 3, in the order [u; q; p]: q has one
+ *                  flux per face (n_pi of them, same face numbering), oriented by the face's
+ *                  global +x/+y/+z normal; p one pressure per cell.  Fixed displacements and
+ *                  faces on the no-flow boundary are identity rows with zero columns; drained
+ *                  faces carry a free flux.  The first call after pm_assemble stores the
+ *                  per-cell RT0 mass (36 doubles per cell, owned by the context). */
 enum { PM_OP_AH = 0, PM_OP_AHT = 1, PM_OP_MINV = 2, PM_OP_MINVT = 3, PM_OP_CPI = 4,
-       PM_OP_BP = 5, PM_OP_AUU = 6, PM_OP_VCYCLE_U = 7, PM_OP_VCYCLE_PI = 8 };
+       PM_OP_BP = 5, PM_OP_AUU = 6, PM_OP_VCYCLE_U = 7, PM_OP_VCYCLE_PI = 8, PM_OP_MFE = 9 };
 int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
 
 /* Kernel timing for roofline measurements.  pm_profile_begin clears the

@@ -90,13 +90,14 @@ __global__ void k_q1_unit(Grid G, const double* __restrict__ coords, double nu, 
   }
 }
 
-// Per cell: coupling column a_T (24), volume, RT0 mass, its inverse, g, alpha.
+// Per cell: coupling column a_T (24), volume, RT0 mass, its inverse, g, alpha;
+// the mass itself too (36 per cell) when Mfull is not null.
 __global__ void __launch_bounds__(256) k_cell_data(Grid G, const double* __restrict__ coords,
                                                    const double* __restrict__ kappa, double mu_f,
                                                    double biot, double* __restrict__ ae,
                                                    double* __restrict__ vol, double* __restrict__ Minv,
                                                    double* __restrict__ gvec, double* __restrict__ alpha,
-                                                   int* status) {
+                                                   int* status, double* __restrict__ Mfull) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= G.nc) return;
   int i, j, k;
@@ -138,6 +139,9 @@ __global__ void __launch_bounds__(256) k_cell_data(Grid G, const double* __restr
     for (int f = 0; f < 6; ++f)
       for (int h = 0; h < 6; ++h) M[f][h] += cf[f] * cf[h] * JKJ[f >> 1][h >> 1] * rdet;
   }
+  if (Mfull)
+    for (int r = 0; r < 6; ++r)
+      for (int s = 0; s < 6; ++s) Mfull[(size_t)(r * 6 + s) * G.nc + c] = M[r][s];
   // Cholesky M = L L^T, then M^-1 = L^-T L^-1 (symmetric by construction)
   double L[6][6];
   for (int r = 0; r < 6; ++r)
@@ -652,8 +656,9 @@ void assemble_all(pm_ctx* c) {
   k_masks<<<blocks_for(std::max(G.nn, G.nf)), kBlock, 0, s>>>(G, c->bc_kind, c->ufix, c->pifix);
   PM_CHECK_LAUNCH();
   k_cell_data<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->coords, c->kappa, c->mu, c->biot, c->ae, c->vol,
-                                                  c->Minv, c->g, c->alpha, c->status);
+                                                  c->Minv, c->g, c->alpha, c->status, nullptr);
   PM_CHECK_LAUNCH();
+  c->Mq_valid = false;
   if (c->opts.block_minv) {
     k_minv_pattern<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->Minv, c->status);
     PM_CHECK_LAUNCH();
@@ -691,6 +696,18 @@ void assemble_all(pm_ctx* c) {
   else
     k_auu_diag<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->auu_diag);
   PM_CHECK_LAUNCH();
+}
+
+// The per-cell data again, with the RT0 mass stored in Mfull (36 per cell,
+// [r*6+s][cell]); the other outputs are rewritten with the same values.
+void cell_data(pm_ctx* c, double* Mfull) {
+  const Grid G = grid_of(c);
+  hipStream_t s = c->s;
+  PM_HIP(hipMemsetAsync(c->status, 0, sizeof(int), s));
+  k_cell_data<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->coords, c->kappa, c->mu, c->biot, c->ae, c->vol,
+                                                  c->Minv, c->g, c->alpha, c->status, Mfull);
+  PM_CHECK_LAUNCH();
+  check_status(c, "element kernels");
 }
 
 // Values of A_uu, the FP32 lattice data and the packed M_T^-1 (after

@@ -44,7 +44,7 @@ int guarded(pm_ctx* c, F&& f) {
 void free_ctx_buffers(pm_ctx* c) {
   using pm::dfree;
   for (void* p : {(void*)c->coords, (void*)c->E, (void*)c->kappa, (void*)c->Ke, (void*)c->ae, (void*)c->vol,
-                  (void*)c->Minv, (void*)c->Mp, (void*)c->Mb, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
+                  (void*)c->Minv, (void*)c->Mp, (void*)c->Mb, (void*)c->Mq, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
                   (void*)c->ufix, (void*)c->pifix, (void*)c->status, (void*)c->V, (void*)c->Z, (void*)c->Zf, (void*)c->wvec,
                   (void*)c->rvec, (void*)c->xvec, (void*)c->red, (void*)c->hcol, (void*)c->pw64, (void*)c->pw32})
     dfree(p);
@@ -496,6 +496,7 @@ int pm_apply(pm_ctx* c, int which, const double* x, double* y) {
       case PM_OP_AUU: pm::apply_csr(c, c->Auu, x, y); break;
       case PM_OP_VCYCLE_U: pm::amg_vcycle(c->s, c->Hu, x, y); break;
       case PM_OP_VCYCLE_PI: pm::amg_vcycle(c->s, c->Hpi, x, y); break;
+      case PM_OP_MFE: pm::apply_mfe(c, x, y); break;
       default: throw Error(PM_EINVAL, "pm_apply: unknown operator");
     }
     return PM_OK;

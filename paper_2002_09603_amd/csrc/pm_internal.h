@@ -245,6 +245,8 @@ struct pm_ctx {
   double* Minv = nullptr;    // 36*nc inverse RT0 mass
   double* Mp = nullptr;      // 21*nc packed upper triangle of M^-1 (operator pi-rows)
   bool mblock = false;       // M^-1 couples only the two faces of each direction (beyond rounding)
+  double* Mq = nullptr;      // 36*nc RT0 mass M_T, for the MFE operator (built on first use)
+  bool Mq_valid = false;
   double* Mb = nullptr;      // 9*nc its blocks: [3d] (2d,2d), [3d+1] (2d,2d+1), [3d+2] (2d+1,2d+1)
   double* g = nullptr;       // 6*nc  M^-1 1
   double* alpha = nullptr;   // nc    1^T M^-1 1
@@ -297,6 +299,8 @@ int check_status(pm_ctx* c, const char* where);  // throws on error bits, return
 
 // operators (pm_ops.hip)
 void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose);
+void apply_mfe(pm_ctx* c, const double* x, double* y);   // A_M of the MFE system, order [u; q; p]
+void cell_data(pm_ctx* c, double* Mfull);
 void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose);    // FP32 input, FP64 arithmetic
 void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose);
 void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose);   // FP32 hierarchies only
