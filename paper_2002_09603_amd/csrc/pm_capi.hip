@@ -51,6 +51,7 @@ void free_ctx_buffers(pm_ctx* c) {
   if (c->hhost) (void)hipHostFree(c->hhost);
   c->Auu.free_all();
   c->Cpi.free_all();
+  c->Cp.free_all();
   c->Hu.free_all();
   c->Hpi.free_all();
   c->lat.free_all();
@@ -497,6 +498,10 @@ int pm_apply(pm_ctx* c, int which, const double* x, double* y) {
       case PM_OP_VCYCLE_U: pm::amg_vcycle(c->s, c->Hu, x, y); break;
       case PM_OP_VCYCLE_PI: pm::amg_vcycle(c->s, c->Hpi, x, y); break;
       case PM_OP_MFE: pm::apply_mfe(c, x, y); break;
+      case PM_OP_CP:
+        pm::build_cp(c);
+        pm::apply_csr(c, c->Cp, x, y);
+        break;
       default: throw Error(PM_EINVAL, "pm_apply: unknown operator");
     }
     return PM_OK;

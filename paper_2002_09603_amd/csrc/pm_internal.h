@@ -257,7 +257,7 @@ struct pm_ctx {
   uint8_t* pifix = nullptr;  // n_pi
   int* status = nullptr;     // device status word (inverted element, NaN, ...)
   // assembled operators
-  pm::Csr Auu, Cpi;
+  pm::Csr Auu, Cpi, Cp;    // Cp: C~_p of the MFE preconditioner (built on first use)
   pm::Hierarchy Hu, Hpi;
   bool assembled = false;
   bool hier_u_ok = false;
@@ -301,6 +301,7 @@ int check_status(pm_ctx* c, const char* where);  // throws on error bits, return
 void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose);
 void apply_mfe(pm_ctx* c, const double* x, double* y);   // A_M of the MFE system, order [u; q; p]
 void cell_data(pm_ctx* c, double* Mfull);
+void build_cp(pm_ctx* c);                                 // C~_p of the MFE preconditioner into c->Cp
 void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose);    // FP32 input, FP64 arithmetic
 void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose);
 void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose);   // FP32 hierarchies only

@@ -1,7 +1,8 @@
 """HIP operator of the non-hybridized mixed system (MFE, eq. mfeSys with the
 stabilized pressure block) against the oracle's assembled A_M, row block by
-row block, through the C ABI.  FP64 on both sides, only the summation order
-differs: 1e-12 relative per block.
+row block, and the assembled C~_p of its block triangular preconditioner
+(Sec. 5) against the oracle's, through the C ABI.  FP64 on both sides, only
+the summation order differs: 1e-12 relative per block.
 """
 import numpy as np
 import pytest
@@ -12,7 +13,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from oracle.mfe import build_mfe_system, split_mfe  # noqa: E402
+from oracle.mfe import build_mfe_system, cp_tilde, split_mfe  # noqa: E402
 from paper_2002_09603_amd import _capi  # noqa: E402
 from paper_2002_09603_amd.solver import Options, from_problem  # noqa: E402
 
@@ -44,3 +45,17 @@ def test_mfe_operator_parity(name, lattice):
         ref = A @ x
         for got, want in zip(split_mfe(K, y), split_mfe(K, ref)):
             assert rel(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mfe_cp_tilde_parity(name):
+    prob = box_problem(**CASES[name])
+    print(f"[mfe C~_p parity] {name}", flush=True)
+    A, b, K = build_mfe_system(prob)
+    s = from_problem(prob, Options(stabilize=prob.stabilize)).assemble()
+    C = cp_tilde(K)
+    rng = np.random.default_rng(12)
+    for rep in range(2):                       # the second call refills the stored pattern
+        x = rng.standard_normal(s.n_p)
+        y = s.apply(_capi.PM_OP_CP, torch.as_tensor(x, device="cuda")).cpu().numpy()
+        assert rel(y, C @ x) < 1e-12
