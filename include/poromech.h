@@ -245,10 +245,13 @@ int pm_reconstruct_w(pm_ctx* ctx, const double* p, const double* pi, double* w);
  *                  MFE block triangular preconditioner (Sec. 5, eq. prec): A_stab + A_pp +
  *                  the fixed-stress diagonal of B~_p + dt A_qp^T L_qq^-1 A_qp, with L_qq the
  *                  absolute row sums of A_qq (no-flow faces excluded).  Each call assembles it
- *                  as a 7-point CSR held by the context (reused by later calls). */
+ *                  as a 7-point CSR held by the context (reused by later calls).
+ *   PM_OP_VCYCLE_CP y = one V-cycle for C~_p applied to x (zero initial guess): each call
+ *                  rebuilds C~_p and a smoothed-aggregation hierarchy for it with the C~_pi
+ *                  settings in FP64 (the inner C~_p solve of the MFE preconditioner). */
 enum { PM_OP_AH = 0, PM_OP_AHT = 1, PM_OP_MINV = 2, PM_OP_MINVT = 3, PM_OP_CPI = 4,
        PM_OP_BP = 5, PM_OP_AUU = 6, PM_OP_VCYCLE_U = 7, PM_OP_VCYCLE_PI = 8, PM_OP_MFE = 9,
-       PM_OP_CP = 10 };
+       PM_OP_CP = 10, PM_OP_VCYCLE_CP = 11 };
 int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
 
 /* Kernel timing for roofline measurements.  pm_profile_begin clears the

@@ -16,7 +16,8 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EHIP, PM_ENOCONV, PM_EBREAKDOWN, PM_ESTATE, PM_E
     0, -1, -2, -3, -4, -5, -6, -7
 PM_BC_COLUMN, PM_BC_ROLLERS, PM_BC_CANTILEVER = 0, 1, 2
 PM_OP_AH, PM_OP_AHT, PM_OP_MINV, PM_OP_MINVT, PM_OP_CPI, PM_OP_BP, PM_OP_AUU, \
-    PM_OP_VCYCLE_U, PM_OP_VCYCLE_PI, PM_OP_MFE, PM_OP_CP = range(11)
+    PM_OP_VCYCLE_U, PM_OP_VCYCLE_PI, PM_OP_MFE, PM_OP_CP, \
+    PM_OP_VCYCLE_CP = range(12)
 
 PROF_KERNELS = {1: "k_lat_ah_u|k_ah_u (u-rows of A_H, FP64)",
                 2: "k_lat_cheb|k_cheb_step<3> (Chebyshev step, finest A_uu level)",

@@ -54,6 +54,7 @@ void free_ctx_buffers(pm_ctx* c) {
   c->Cp.free_all();
   c->Hu.free_all();
   c->Hpi.free_all();
+  c->Hcp.free_all();
   c->lat.free_all();
   c->cpi.free_all();
   for (hipStream_t* ps : {&c->s_side_u, &c->s_side_pi})
@@ -502,6 +503,17 @@ int pm_apply(pm_ctx* c, int which, const double* x, double* y) {
         pm::build_cp(c);
         pm::apply_csr(c, c->Cp, x, y);
         break;
+      case PM_OP_VCYCLE_CP: {
+        // the C~_pi settings, FP64 levels, no side stream
+        pm::build_cp(c);
+        pm::AmgParams p = params_pi(c);
+        p.fp32 = false;
+        p.side = nullptr;
+        p.cycles = 1;
+        pm::amg_setup(c->s, c->Cp, p, c->Hcp);
+        pm::amg_vcycle(c->s, c->Hcp, x, y);
+        break;
+      }
       default: throw Error(PM_EINVAL, "pm_apply: unknown operator");
     }
     return PM_OK;

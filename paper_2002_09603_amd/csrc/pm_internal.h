@@ -258,7 +258,7 @@ struct pm_ctx {
   int* status = nullptr;     // device status word (inverted element, NaN, ...)
   // assembled operators
   pm::Csr Auu, Cpi, Cp;    // Cp: C~_p of the MFE preconditioner (built on first use)
-  pm::Hierarchy Hu, Hpi;
+  pm::Hierarchy Hu, Hpi, Hcp;  // Hcp: FP64 AMG hierarchy of the MFE C~_p
   bool assembled = false;
   bool hier_u_ok = false;
   // Krylov workspace

@@ -198,7 +198,7 @@ class PoroSolver:
         return w.view(self.n_p, 6)
 
     def apply(self, which, x):
-        n_out = {_capi.PM_OP_CPI: self.n_pi, _capi.PM_OP_BP: self.n_p, _capi.PM_OP_CP: self.n_p, _capi.PM_OP_AUU: self.n_u,
+        n_out = {_capi.PM_OP_CPI: self.n_pi, _capi.PM_OP_BP: self.n_p, _capi.PM_OP_CP: self.n_p, _capi.PM_OP_VCYCLE_CP: self.n_p, _capi.PM_OP_AUU: self.n_u,
                  _capi.PM_OP_VCYCLE_U: self.n_u, _capi.PM_OP_VCYCLE_PI: self.n_pi}.get(which, self.N)
         y = self._empty(n_out)
         check(lib.pm_apply(self._ctx, int(which), _ptr(x), _ptr(y)), self._ctx)

@@ -59,3 +59,23 @@ def test_mfe_cp_tilde_parity(name):
         x = rng.standard_normal(s.n_p)
         y = s.apply(_capi.PM_OP_CP, torch.as_tensor(x, device="cuda")).cpu().numpy()
         assert rel(y, C @ x) < 1e-12
+
+
+@pytest.mark.parametrize("case", [dict(nx=16, ny=16, nz=8, seed=21, perturb=True),
+                                  dict(nx=16, ny=8, nz=8, seed=22, bc="cantilever", dt=1e-5),
+                                  dict(nx=16, ny=16, nz=8, seed=23, graded=True, dt=1.0)])
+def test_mfe_cp_vcycle_converges(case):
+    """The V-cycle for C~_p as a stationary iteration on the oracle's C~_p
+    (a property at any size: the hierarchy itself has no oracle)."""
+    prob = box_problem(**case)
+    print(f"[mfe C~_p V-cycle] {case}", flush=True)
+    K = build_mfe_system(prob)[2]
+    C = cp_tilde(K)
+    s = from_problem(prob, Options()).assemble()
+    rng = np.random.default_rng(13)
+    b = rng.standard_normal(s.n_p)
+    x = np.zeros_like(b)
+    for _ in range(6):
+        r = b - C @ x
+        x = x + s.apply(_capi.PM_OP_VCYCLE_CP, torch.as_tensor(r, device="cuda")).cpu().numpy()
+    assert np.linalg.norm(b - C @ x) < 0.05 * np.linalg.norm(b)
