@@ -43,11 +43,13 @@ class PoroStep(torch.autograd.Function):
         ctx.solver = solver
         ctx.save_for_backward(u, pi, p)
         ctx.info = info
+        ctx.state = _solver_state(solver, E, kappa)
         return u, pi, p
 
     @staticmethod
     def backward(ctx, gu, gpi, gp):
         s: PoroSolver = ctx.solver
+        _restore_state(s, ctx.state)
         u, pi, p = ctx.saved_tensors
         dev = u.device
         z = lambda n: torch.zeros(n, dtype=torch.float64, device=dev)  # noqa: E731
@@ -85,11 +87,13 @@ class PoroTimeLoop(torch.autograd.Function):
         ctx.solver, ctx.dts, ctx.every = solver, list(dts), every
         ctx.ckpt = ckpt
         ctx.infos = None
+        ctx.state = _solver_state(solver, E, kappa)
         return torch.stack(ps)
 
     @staticmethod
     def backward(ctx, gP):
         s: PoroSolver = ctx.solver
+        _restore_state(s, ctx.state)
         dts, every = ctx.dts, ctx.every
         n_steps = len(dts)
         dev = gP.device
@@ -119,6 +123,22 @@ class PoroTimeLoop(torch.autograd.Function):
                 s.grad(lam, x_n.contiguous(), p_prev, dk, dE)
                 lam_next = lam
         return dk, dE, None, None, None, None
+
+
+def _solver_state(s: PoroSolver, E, kappa):
+    """What the backward pass needs the solver to hold: the forward pass's
+    material fields (and the version the solver had right after setting
+    them) and its time step."""
+    return dict(version=s.material_version, E=E, kappa=kappa, dt=s.dt)
+
+
+def _restore_state(s: PoroSolver, st):
+    """Re-apply the forward pass's material and time step when another
+    forward pass, update_material or set_dt has changed the solver since."""
+    if s.material_version != st["version"]:
+        s.update_material(st["E"], st["kappa"])
+        st["version"] = s.material_version
+    s.set_dt(st["dt"])
 
 
 def _step(s: PoroSolver, dt: float, x_prev: Optional[torch.Tensor]) -> torch.Tensor:

@@ -17,12 +17,16 @@ from ._capi import check, lib
 
 
 def _ptr(t) -> Optional[int]:
+    """Pointer of a set-up input (the library copies these with
+    hipMemcpyDefault, so host arrays are allowed here)."""
     if t is None:
         return None
     if isinstance(t, np.ndarray):
-        assert t.dtype == np.float64 and t.flags.c_contiguous
+        if t.dtype != np.float64 or not t.flags.c_contiguous:
+            raise ValueError("expected a C-contiguous float64 array")
         return t.ctypes.data
-    assert t.dtype == torch.float64 and t.is_contiguous(), "expected a contiguous float64 tensor"
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 tensor")
     return t.data_ptr()
 
 
@@ -105,12 +109,20 @@ class PoroSolver:
                  S_eps=0.0, mu=1.0, dt=1e-2, traction=(0.0, 0.0, -1.0), p_top=0.0, rollers=False,
                  opts: Optional[Options] = None, device="cuda", cantilever=False):
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.material_version = 0   # bumped by every call that replaces E or kappa
         self.opts = opts or Options()
         self.dt = float(dt)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
-        E_d = _dev_f64(E, self.device)
-        k_d = _dev_f64(kappa, self.device)
-        X_d = None if coords is None else _dev_f64(coords, self.device)
+        E_d = _dev_f64(E, self.device).reshape(-1)
+        k_d = _dev_f64(kappa, self.device).reshape(-1)
+        X_d = None if coords is None else _dev_f64(coords, self.device).reshape(-1)
+        nc = self.nx * self.ny * self.nz
+        nn = (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+        for t, n, name in ((E_d, nc, "E"), (k_d, 3 * nc, "kappa"), (X_d, 3 * nn, "coords")):
+            if t is not None and t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} values, {n} expected")
         mesh = _capi.pm_mesh(self.nx, self.ny, self.nz, _ptr(X_d), float(L[0]), float(L[1]), float(L[2]))
         mat = _capi.pm_material(_ptr(E_d), _ptr(k_d), float(nu), float(biot), float(S_eps), float(mu))
         kind = (_capi.PM_BC_CANTILEVER if cantilever else
@@ -142,9 +154,28 @@ class PoroSolver:
     def _empty(self, n):
         return torch.empty(n, dtype=torch.float64, device=self.device)
 
+    def _dev(self, t, n, name, optional=False) -> Optional[int]:
+        """Pointer of a vector handed to a device kernel: a contiguous float64
+        tensor on this solver's device with exactly n elements (the kernels
+        read and write it without bounds of their own)."""
+        if t is None:
+            if optional:
+                return None
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name} must be a torch tensor on {self.device}, got {type(t).__name__}")
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, the solver on {self.device}")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, {n} expected")
+        return t.data_ptr()
+
     # -- C ABI calls -------------------------------------------------------------
     def assemble(self):
         check(lib.pm_assemble(self._ctx), self._ctx)
+        self.material_version += 1
         return self
 
     def set_dt(self, dt):
@@ -155,19 +186,26 @@ class PoroSolver:
         self.dt = float(dt)
 
     def update_material(self, E=None, kappa=None):
-        E_d = None if E is None else _dev_f64(E, self.device)
-        k_d = None if kappa is None else _dev_f64(kappa, self.device)
+        E_d = None if E is None else _dev_f64(E, self.device).reshape(-1)
+        k_d = None if kappa is None else _dev_f64(kappa, self.device).reshape(-1)
+        if E_d is not None and E_d.numel() != self.n_p:
+            raise ValueError(f"E has {E_d.numel()} values, {self.n_p} expected")
+        if k_d is not None and k_d.numel() != 3 * self.n_p:
+            raise ValueError(f"kappa has {k_d.numel()} values, {3 * self.n_p} expected")
+        self.material_version += 1
         check(lib.pm_update_material(self._ctx, _ptr(E_d), _ptr(k_d)), self._ctx)
 
     def build_rhs(self, u_prev=None, p_prev=None, out=None):
         b = self._empty(self.N) if out is None else out
-        check(lib.pm_build_rhs(self._ctx, _ptr(u_prev), _ptr(p_prev), _ptr(b)), self._ctx)
+        check(lib.pm_build_rhs(self._ctx, self._dev(u_prev, self.n_u, "u_prev", True),
+                               self._dev(p_prev, self.n_p, "p_prev", True), self._dev(b, self.N, "out")),
+              self._ctx)
         return b
 
     def _solve(self, fn, b, raise_noconv):
         u, pi, p = self._empty(self.n_u), self._empty(self.n_pi), self._empty(self.n_p)
         info = _capi.pm_info()
-        rc = fn(self._ctx, _ptr(b), _ptr(u), _ptr(pi), _ptr(p), C.byref(info))
+        rc = fn(self._ctx, self._dev(b, self.N, "right-hand side"), _ptr(u), _ptr(pi), _ptr(p), C.byref(info))
         if rc != _capi.PM_OK and (rc != _capi.PM_ENOCONV or raise_noconv):
             check(rc, self._ctx)
         d = info.as_dict()
@@ -185,23 +223,37 @@ class PoroSolver:
     def grad(self, lam, x, p_prev=None, dlogk=None, dlogE=None):
         dk = torch.zeros(self.n_p, dtype=torch.float64, device=self.device) if dlogk is None else dlogk
         dE = torch.zeros(self.n_p, dtype=torch.float64, device=self.device) if dlogE is None else dlogE
-        check(lib.pm_grad(self._ctx, _ptr(lam), _ptr(x), _ptr(p_prev), _ptr(dk), _ptr(dE)), self._ctx)
+        check(lib.pm_grad(self._ctx, self._dev(lam, self.N, "lam"), self._dev(x, self.N, "x"),
+                          self._dev(p_prev, self.n_p, "p_prev", True), self._dev(dk, self.n_p, "dlogk"),
+                          self._dev(dE, self.n_p, "dlogE")), self._ctx)
         return dk, dE
 
     def rhs_adjoint(self, lam, c):
-        check(lib.pm_rhs_adjoint(self._ctx, _ptr(lam), _ptr(c)), self._ctx)
+        check(lib.pm_rhs_adjoint(self._ctx, self._dev(lam, self.N, "lam"), self._dev(c, self.N, "c")), self._ctx)
         return c
 
     def reconstruct_w(self, p, pi):
         w = self._empty(6 * self.n_p)
-        check(lib.pm_reconstruct_w(self._ctx, _ptr(p), _ptr(pi), _ptr(w)), self._ctx)
+        check(lib.pm_reconstruct_w(self._ctx, self._dev(p, self.n_p, "p"), self._dev(pi, self.n_pi, "pi"), _ptr(w)),
+              self._ctx)
         return w.view(self.n_p, 6)
 
+    def op_sizes(self, which):
+        """(input length, output length) of pm_apply's operator ``which``."""
+        sizes = {_capi.PM_OP_CPI: (self.n_pi, self.n_pi), _capi.PM_OP_BP: (self.n_p, self.n_p),
+                 _capi.PM_OP_CP: (self.n_p, self.n_p), _capi.PM_OP_VCYCLE_CP: (self.n_p, self.n_p),
+                 _capi.PM_OP_AUU: (self.n_u, self.n_u), _capi.PM_OP_VCYCLE_U: (self.n_u, self.n_u),
+                 _capi.PM_OP_VCYCLE_PI: (self.n_pi, self.n_pi)}
+        if which in sizes:
+            return sizes[which]
+        if which in (_capi.PM_OP_AH, _capi.PM_OP_AHT, _capi.PM_OP_MINV, _capi.PM_OP_MINVT, _capi.PM_OP_MFE):
+            return self.N, self.N
+        raise ValueError(f"unknown operator {which}")
+
     def apply(self, which, x):
-        n_out = {_capi.PM_OP_CPI: self.n_pi, _capi.PM_OP_BP: self.n_p, _capi.PM_OP_CP: self.n_p, _capi.PM_OP_VCYCLE_CP: self.n_p, _capi.PM_OP_AUU: self.n_u,
-                 _capi.PM_OP_VCYCLE_U: self.n_u, _capi.PM_OP_VCYCLE_PI: self.n_pi}.get(which, self.N)
+        n_in, n_out = self.op_sizes(which)
         y = self._empty(n_out)
-        check(lib.pm_apply(self._ctx, int(which), _ptr(x), _ptr(y)), self._ctx)
+        check(lib.pm_apply(self._ctx, int(which), self._dev(x, n_in, "x"), _ptr(y)), self._ctx)
         return y
 
     def profile_begin(self, mask):

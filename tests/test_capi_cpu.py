@@ -101,3 +101,32 @@ def test_binding_has_no_cpu_fallback(monkeypatch, tmp_path):
     from paper_2002_09603_amd import _capi
     with pytest.raises(ImportError):
         _capi.load(str(tmp_path / "missing.so"))
+
+
+def test_binding_validates_device_vectors_without_a_gpu():
+    """Every vector a kernel reads or writes after set-up must be a contiguous
+    float64 tensor on the solver's device with exactly the expected length;
+    anything else is a ValueError before any pointer reaches the library."""
+    import torch
+    from paper_2002_09603_amd.solver import PoroSolver
+    s = object.__new__(PoroSolver)
+    s.device = torch.device("cpu")
+    s.n_u, s.n_p, s.n_pi = 12, 2, 9
+    s.N = 23
+    ok = torch.zeros(23, dtype=torch.float64)
+    assert s._dev(ok, 23, "x") == ok.data_ptr()
+    assert s._dev(None, 23, "x", optional=True) is None
+    for bad, n in ((np.zeros(23), 23),                                   # host array
+                   (torch.zeros(23, dtype=torch.float32), 23),           # wrong dtype
+                   (torch.zeros(22, dtype=torch.float64), 23),           # short
+                   (torch.zeros(46, dtype=torch.float64)[::2], 23),      # not contiguous
+                   (None, 23)):                                          # missing
+        with pytest.raises(ValueError):
+            s._dev(bad, n, "x")
+    # operator input and output lengths of pm_apply
+    from paper_2002_09603_amd import _capi
+    assert s.op_sizes(_capi.PM_OP_MFE) == (23, 23)
+    assert s.op_sizes(_capi.PM_OP_CP) == (2, 2)
+    assert s.op_sizes(_capi.PM_OP_VCYCLE_PI) == (9, 9)
+    with pytest.raises(ValueError):
+        s.op_sizes(99)

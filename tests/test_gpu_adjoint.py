@@ -48,6 +48,30 @@ def test_step_gradients_match_oracle_adjoint():
     s.close()
 
 
+def test_backward_after_other_forward_passes_on_the_same_solver():
+    """Backward re-applies its forward pass's material and time step: two
+    more forward passes (other fields, another dt) and a set_dt on the same
+    solver between forward and backward leave the gradient unchanged."""
+    prob = make_config("perturbed96", n=6)
+    print("[interleaved forwards] perturbed 6^3", flush=True)
+    ref = single_step(prob, prob.obs_cells)
+    s = from_problem(prob, Options(rtol=1e-13, rtol_transpose=1e-10))
+    logk, logE = _logs(prob)
+    u, pi, p = poro_step(s, logk, logE)
+    obs = torch.as_tensor(prob.obs_cells, device=DEV)
+    loss = (p[obs] ** 2).sum()
+    with torch.no_grad():
+        poro_step(s, logk.detach() + 0.7, logE.detach() - 0.2)
+    s.set_dt(3 * prob.dt)
+    lk2, lE2 = (logk.detach() - 0.4).requires_grad_(), logE.detach().clone().requires_grad_()
+    _, _, p2 = poro_step(s, lk2, lE2)
+    loss.backward()
+    assert rel(logk.grad.cpu().numpy(), ref["dlogk"]) <= 1e-7
+    assert rel(logE.grad.cpu().numpy(), ref["dlogE"]) <= 1e-7
+    assert s.dt == prob.dt
+    s.close()
+
+
 def _loss_gpu(s, prob, logk, logE, obs):
     with torch.no_grad():
         u, pi, p = poro_step(s, logk, logE)
