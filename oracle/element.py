@@ -108,7 +108,7 @@ def q1_element(X, E, nu, biot):
         Jinv = np.linalg.inv(J)
         dNx = np.einsum("aj,cji->cai", dNr, Jinv)     # dN_a/dx_i
         B = strain_matrix(dNx)
-        K += np.einsum("cki,ckl,clj->cij", B, D, B) * detJ[:, None, None]
+        K += np.matmul(np.transpose(B, (0, 2, 1)), np.matmul(D, B)) * detJ[:, None, None]   # B^T D B
         a += -biot * dNx.reshape(nc, 24) * detJ[:, None]
         vol += detJ
     return K, a, vol

@@ -71,11 +71,13 @@ def test_local_mass_conservation(name):
     r = solve_step(prob)
     B = r["B"]
     res = mass_residual(B, r["u"], r["p"], r["pi"], include_stab=True)
-    scale = np.abs(B.A_pu @ r["u"]).max()
+    # the balance sums the volumetric, flux and stabilization terms; its
+    # rounding is relative to the largest of them (the face fluxes here)
+    scale = max(np.abs(B.A_pu @ r["u"]).max(), B.dt * np.abs(r["w"]).max(), np.abs(B.A_stab @ r["p"]).max())
     assert np.abs(res).max() < 1e-10 * scale
     # without the fictitious stabilization flux: conserved per macro-element only
     res0 = mass_residual(B, r["u"], r["p"], r["pi"], include_stab=False)
-    assert np.abs(res0).max() > 1e-6 * scale
+    assert np.abs(res0).max() > 1e-3 * scale
     assert np.abs(res0[B.macro].sum(axis=1)).max() < 1e-10 * scale
     # flux continuity on interior faces, zero flux on no-flow faces
     w = r["w"]
@@ -90,7 +92,9 @@ def test_stabilization_conserves_with_storage_per_cell_when_off():
     prob = make_config("cube64", n=4, S_eps=1e-4).with_(stabilize=False)
     r = solve_step(prob)
     res = mass_residual(r["B"], r["u"], r["p"], r["pi"], include_stab=False)
-    assert np.abs(res).max() < 1e-10 * np.abs(r["B"].A_pu @ r["u"]).max()
+    B = r["B"]
+    scale = max(np.abs(B.A_pu @ r["u"]).max(), B.dt * np.abs(r["w"]).max())
+    assert np.abs(res).max() < 1e-10 * scale
 
 
 def test_spurious_pressure_modes_removed_by_stabilization():
@@ -259,19 +263,22 @@ def test_adjoint_matches_central_differences_single_step():
     prob = make_config("perturbed96", n=4)
     r = single_step(prob, prob.obs_cells)
     d = 1e-3
+    # the losses carry a rounding error of ~1e-13 of their value (direct
+    # solves), which their central difference divides by 2d
+    floor = 1e-12 * r["loss"] / d
     for T in prob.fd_cells[:6]:
         kp, km = prob.kappa.copy(), prob.kappa.copy()
         kp[T] *= np.exp(d)
         km[T] *= np.exp(-d)
         fd = (forward_loss(prob.with_(kappa=kp), prob.obs_cells) -
               forward_loss(prob.with_(kappa=km), prob.obs_cells)) / (2 * d)
-        assert abs(fd - r["dlogk"][T]) <= 2e-5 * abs(r["dlogk"][T]) + 1e-12
+        assert abs(fd - r["dlogk"][T]) <= 2e-5 * abs(r["dlogk"][T]) + floor
         Ep, Em = prob.E.copy(), prob.E.copy()
         Ep[T] *= np.exp(d)
         Em[T] *= np.exp(-d)
         fd = (forward_loss(prob.with_(E=Ep), prob.obs_cells) -
               forward_loss(prob.with_(E=Em), prob.obs_cells)) / (2 * d)
-        assert abs(fd - r["dlogE"][T]) <= 2e-5 * abs(r["dlogE"][T]) + 1e-12
+        assert abs(fd - r["dlogE"][T]) <= 2e-5 * abs(r["dlogE"][T]) + floor
 
 
 def test_adjoint_matches_central_differences_multi_step():
@@ -279,19 +286,20 @@ def test_adjoint_matches_central_differences_multi_step():
     dts = prob.dts[:4]
     r = multi_step(prob, dts, prob.obs_cells)
     d = 1e-3
+    floor = 1e-12 * r["loss"] / d
     for T in [0, 5, 11, 30]:
         kp, km = prob.kappa.copy(), prob.kappa.copy()
         kp[T] *= np.exp(d)
         km[T] *= np.exp(-d)
         fd = (forward_loss(prob.with_(kappa=kp), prob.obs_cells, dts) -
               forward_loss(prob.with_(kappa=km), prob.obs_cells, dts)) / (2 * d)
-        assert abs(fd - r["dlogk"][T]) <= 2e-5 * abs(r["dlogk"][T]) + 1e-12
+        assert abs(fd - r["dlogk"][T]) <= 2e-5 * abs(r["dlogk"][T]) + floor
         Ep, Em = prob.E.copy(), prob.E.copy()
         Ep[T] *= np.exp(d)
         Em[T] *= np.exp(-d)
         fd = (forward_loss(prob.with_(E=Ep), prob.obs_cells, dts) -
               forward_loss(prob.with_(E=Em), prob.obs_cells, dts)) / (2 * d)
-        assert abs(fd - r["dlogE"][T]) <= 2e-5 * abs(r["dlogE"][T]) + 1e-12
+        assert abs(fd - r["dlogE"][T]) <= 2e-5 * abs(r["dlogE"][T]) + floor
 
 
 def test_dirichlet_rows_hold_prescribed_values():
