@@ -149,6 +149,7 @@ typedef struct {
   double opcx_u, opcx_pi;    /* AMG operator complexities */
   int32_t lattice_uu;        /* 1 if the finest A_uu level runs on the lattice operator */
   int32_t block_minv;        /* 1 if M_T^-1 is stored and applied by direction blocks */
+  int32_t ncoarse_u, ncoarse_pi;  /* unknowns of the coarsest level (dense FP64 inverse) of each hierarchy */
 } pm_info;
 
 /* Default options: rtol 1e-8, restart 100, max_it 1000, FP64, stabilize,

@@ -172,6 +172,8 @@ void setup_hierarchies(pm_ctx* c, bool with_u) {
   c->info.opcx_pi = c->Hpi.opcx;
   c->info.lattice_uu = c->lattice ? 1 : 0;
   c->info.block_minv = c->mblock ? 1 : 0;
+  c->info.ncoarse_u = c->Hu.ncoarse;
+  c->info.ncoarse_pi = c->Hpi.ncoarse;
 }
 
 void assemble_and_setup(pm_ctx* c) {

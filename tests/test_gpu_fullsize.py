@@ -1,11 +1,14 @@
 """Full-size checks in the launch configurations the benchmark times.
 
-The oracle cannot factor these systems, so it assembles sampled rows of A_H
+The oracle cannot factor these systems.  At 64^3 (both storage values) and
+at the perturbed 96^3 mesh it assembles the whole FP64 system A_H, b and
+evaluates the full residual of the GPU solution, the GPU operator applied to
+it and the per-cell mass balance.  At 128^3 it assembles sampled rows of A_H
 and b one by one from the element integrals of their support cells
-(``oracle.sampled``).  Checked: the GPU right-hand side and the GPU operator
-applied to the GPU solution agree with the oracle's rows entrywise (FP64,
-1e-12 of the row scale), and the sampled residual entries of the GPU solution
-are within the solver tolerance of ||b||."""
+(``oracle.sampled``): the GPU right-hand side and the GPU operator applied to
+the GPU solution agree with the oracle's rows entrywise (FP64, 1e-12 of the
+row scale), and the sampled residual entries of the GPU solution are within
+the solver tolerance of ||b||."""
 import numpy as np
 import pytest
 
@@ -16,6 +19,8 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from oracle.sampled import system_rows  # noqa: E402
+from oracle.solve import mass_residual, reconstruct_w  # noqa: E402
+from oracle.system import build_system, split  # noqa: E402
 from paper_2002_09603_amd import _capi  # noqa: E402
 from paper_2002_09603_amd.solver import Options, from_problem  # noqa: E402
 from synth import make_config  # noqa: E402
@@ -59,6 +64,47 @@ def test_sampled_rows_and_residual_at_full_size(name, n, S, opts):
     assert np.all(np.abs(Ar @ xh - Ax.cpu().numpy()[rows]) <= 1e-12 * scale_b)
     res = br - Ar @ xh
     assert np.abs(res).max() <= 1.5 * opts["rtol"] * np.linalg.norm(bh)
+    s.close()
+
+
+FULL_CASES = [("cube64", 0.0), ("cube64", 1e-4), ("perturbed96", 0.0)]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,S", FULL_CASES, ids=[f"{c[0]}-S{c[1]}" for c in FULL_CASES])
+def test_full_residual_against_oracle_assembly(name, S):
+    """The FP64 GPU solve (plain method: FP64 AMG in the block triangular
+    preconditioner) of the 64^3 workload with S_eps in {0, 1e-4} and of the
+    perturbed 96^3 workload, against the oracle's own assembly of the whole
+    system (eq. stab_A with the Dirichlet identity rows): right-hand side
+    entrywise, A_H applied to the GPU solution entrywise, the full residual
+    ||b - A x|| / ||b|| of the GPU solution at most twice the solver's
+    tolerance, and the mass balance of every cell (Sec. 3)."""
+    prob = make_config(name, S_eps=S)
+    print(f"[full residual] {name} {prob.nx}x{prob.ny}x{prob.nz} S_eps={S} N={prob.n_total}: oracle assembly",
+          flush=True)
+    A, b, B = build_system(prob)
+    print(f"   oracle A_H: {A.nnz} entries", flush=True)
+    rtol = 1e-11
+    s = from_problem(prob, Options(rtol=rtol, restart=50, max_it=3000)).assemble()
+    bg = s.build_rhs().cpu().numpy()
+    assert np.abs(bg - b).max() <= 1e-12 * np.abs(b).max()
+    u, pi, p, info = s.solve(torch.as_tensor(b, device="cuda"))
+    print("   info", {k: info[k] for k in ("iters", "relres_true", "t_setup", "t_solve")}, flush=True)
+    assert info["converged"]
+    x = torch.cat([u, p, pi])
+    xh = x.cpu().numpy()
+    Ax = A @ xh
+    scale = abs(A) @ np.abs(xh)
+    assert np.all(np.abs(s.apply(_capi.PM_OP_AH, x).cpu().numpy() - Ax) <= 1e-12 * scale + 1e-300)
+    relres = np.linalg.norm(b - Ax) / np.linalg.norm(b)
+    print(f"   oracle residual of the GPU solution {relres:.3e}", flush=True)
+    assert relres <= 2 * rtol
+    uh, ph, pih = split(B, xh)
+    res = mass_residual(B, uh, ph, pih)
+    w = reconstruct_w(B, ph, pih)
+    bal = max(np.abs(B.A_pu @ uh).max(), B.dt * np.abs(w).max())
+    assert np.abs(res).max() <= 1e-8 * bal
     s.close()
 
 

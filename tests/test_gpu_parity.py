@@ -121,6 +121,45 @@ def test_solve_parity(name, fp32, lattice, orth):
     s.close()
 
 
+# Multi-level hierarchies against the oracle, with the benchmark's solver
+# settings (FGMRES(24), one Gram-Schmidt pass, V(1,1) Chebyshev on C~_pi
+# over [0.1, 1.1] lambda_max): a small coarse_max makes both hierarchies
+# three or more levels deep (coarse Galerkin products, lanes-per-row
+# restrictions and coarse kernels of every level run), and coarse_max 200
+# leaves a coarsest level above the 142 unknowns that fit the one-workgroup
+# LDS inverse, so the global-memory Gauss-Jordan inverse runs.
+DEEP_CASES = {
+    "deep16x12x8": (dict(nx=16, ny=12, nz=8, seed=12), dict(coarse_max=4), 3),
+    "deep_perturbed12x12x8": (dict(nx=12, ny=12, nz=8, seed=13, perturb=True), dict(coarse_max=4, lattice_uu=False), 3),
+    "deep_cantilever12x12x8": (dict(nx=12, ny=12, nz=8, seed=14, bc="cantilever", dt=1e-5), dict(coarse_max=4), 3),
+    "global_coarse16x12x8": (dict(nx=16, ny=12, nz=8, seed=15), dict(coarse_max=200), 2),
+}
+DEEP_SOLVES = [(n, fp32) for n in DEEP_CASES for fp32 in (False, True)]
+
+
+@pytest.mark.parametrize("name,fp32", DEEP_SOLVES, ids=[f"{n}-fp32={f}" for n, f in DEEP_SOLVES])
+def test_multilevel_solve_parity(name, fp32):
+    pkw, okw, min_levels = DEEP_CASES[name]
+    prob = box_problem(**pkw)
+    print(f"[multilevel solve parity] {name} fp32={fp32}", flush=True)
+    A, b, B = build_system(prob)
+    x = direct_solve(A, b)
+    u0, p0, pi0 = split(B, x)
+    s = from_problem(prob, Options(rtol=1e-13, precond_fp32=fp32, restart=24, max_it=2000, orth_passes=1,
+                                   cheb_degree_pi=1, cheb_lower_pi=0.1, **okw)).assemble()
+    u, pi, p, info = s.solve(s.build_rhs())
+    i = s.info()
+    print(f"   {info['iters']} its, levels {i['levels_u']}/{i['levels_pi']}, coarsest "
+          f"{i['ncoarse_u']}/{i['ncoarse_pi']} unknowns", flush=True)
+    assert i["levels_u"] >= min_levels and i["levels_pi"] >= min_levels
+    if okw["coarse_max"] > 100:
+        assert i["ncoarse_u"] > 142 and i["ncoarse_pi"] > 142
+    assert info["converged"] and info["relres_true"] <= 1e-13
+    for got, ref in ((u, u0), (p, p0), (pi, pi0)):
+        assert rel(_np(got), ref) <= 1e-8
+    s.close()
+
+
 def test_solve_is_deterministic():
     prob = _case("perturbed6x8x6")
     s = from_problem(prob, Options(rtol=1e-10)).assemble()
