@@ -198,6 +198,24 @@ int pm_build_rhs(pm_ctx* ctx, const double* u_prev, const double* p_prev, double
  * NULL.  Returns PM_ENOCONV if max_it is reached (outputs = last iterate). */
 int pm_solve(pm_ctx* ctx, const double* b, double* u, double* pi, double* p, pm_info* info);
 
+/* pm_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same FGMRES and preconditioner kernels, with the Krylov workspace (basis,
+ * preconditioned vectors, reduction partials, device scalars) in a static
+ * device array of 256 MiB per GPU that the library holds until the process
+ * ends, and the host side of the Givens process on the call's stack.  This
+ * call never calls hipMalloc, hipFree or any other allocating routine; the
+ * context's own buffers come from pm_setup / pm_assemble.  Limits: restart
+ * <= 64 and (restart+1) FP64 plus restart FP64 (or, with the FP32
+ * preconditioner and one Gram-Schmidt pass, FP32) vectors of N unknowns
+ * plus 8 MiB of partial sums within the 256 MiB (restart 24: N up to about
+ * 660,000, or 880,000 with the FP32 preconditioner); larger problems return
+ * PM_EINVAL before any work.  Arguments, outputs and return codes as
+ * pm_solve.  Every call on one GPU uses that GPU's one array and leaves its
+ * contents behind: calls that overlap on one GPU (several host threads or
+ * streams) race and must be serialized by the caller. */
+int pm_solve_noalloc(pm_ctx* ctx, const double* b, double* u, double* pi, double* p, pm_info* info);
+
 /* Solve A_H^T lam = g (adjoint) with FGMRES preconditioned by M^T (block
  * lower triangular: forward substitution u -> p -> pi, same V-cycles).
  * g device, N; outputs as in pm_solve. */

@@ -2,6 +2,7 @@
 // lifetime, timing, and conversion of internal errors to return codes.
 #include <chrono>
 #include <exception>
+#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstring>
@@ -26,6 +27,33 @@ double now_s() {
 }
 
 int g_live_contexts = 0;
+
+// Scratch of pm_solve_noalloc: the FGMRES workspace (basis, preconditioned
+// vectors, reduction partials, device scalars) of callers that cannot
+// allocate.  One copy per GPU, held until the process ends; its device
+// address comes from hipGetSymbolAddress (never the host-side name).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+constexpr int kNoallocMaxRestart = 64;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch, looked up once per device
+// (pm_setup calls this with the context's device current).
+void* scratch_base() {
+  int dev = 0;
+  PM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(PM_EINTERNAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error(PM_EHIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 template <class F>
 int guarded(pm_ctx* c, F&& f) {
@@ -342,6 +370,8 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     c->ufix = pm::dalloc<uint8_t>(c->n_u);
     c->pifix = pm::dalloc<uint8_t>(c->n_pi);
     c->status = pm::dalloc<int>(1);
+    (void)scratch_base();  // device address of this GPU's pm_solve_noalloc scratch, once per device
+    pm::krylov_preload(c->s);
     c->wvec = pm::dalloc<double>(c->N);
     c->rvec = pm::dalloc<double>(c->N);
     c->xvec = pm::dalloc<double>(c->N);
@@ -446,6 +476,47 @@ static int solve_common(pm_ctx* c, const double* b, double* u, double* pi, doubl
 
 int pm_solve(pm_ctx* c, const double* b, double* u, double* pi, double* p, pm_info* info) {
   return solve_common(c, b, u, pi, p, info, false);
+}
+
+int pm_solve_noalloc(pm_ctx* c, const double* b, double* u, double* pi, double* p, pm_info* info) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!b) throw Error(PM_EINVAL, "pm_solve_noalloc: b is NULL");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_solve_noalloc: call pm_assemble first");
+    const int m = c->opts.restart;
+    if (m > kNoallocMaxRestart)
+      throw Error(PM_EINVAL, "pm_solve_noalloc: restart " + std::to_string(m) + " exceeds " +
+                                 std::to_string(kNoallocMaxRestart));
+    const pm::KrylovOps op = pm::step_ops(c, false);
+    const bool z32 = c->opts.orth_passes == 1 && op.M32 != nullptr;
+    const size_t need = pm::krylov_device_bytes(c->N, m, z32);
+    if (need > kScratchBytes)
+      throw Error(PM_EINVAL, "pm_solve_noalloc: the Krylov workspace of this problem (" + std::to_string(need) +
+                                 " bytes for " + std::to_string(c->N) + " unknowns, restart " + std::to_string(m) +
+                                 ") exceeds the static scratch of " + std::to_string(kScratchBytes) + " bytes");
+    void* base = scratch_base();
+    const pm::KrylovWs ws0 = pm::krylov_ws_in(base, kScratchBytes, c->N, m, z32);
+    // host arrays of the Givens process and the read-back scalars: on this stack frame
+    double H[(kNoallocMaxRestart + 1) * kNoallocMaxRestart], cs[kNoallocMaxRestart], sn[kNoallocMaxRestart],
+        g[kNoallocMaxRestart + 1], y[kNoallocMaxRestart], hh[kNoallocMaxRestart + 8];
+    pm::KrylovWs ws = ws0;
+    ws.hhost = hh;
+    pm::KrylovHost hw{kNoallocMaxRestart, H, cs, sn, g, y};
+    PM_HIP(hipStreamSynchronize(c->s));
+    const double t0 = now_s();
+    pm_info li = c->info;
+    const int rc = pm::fgmres_ws(c, op, ws, hw, b, c->xvec, &li);
+    if (u) PM_HIP(hipMemcpyAsync(u, c->xvec, sizeof(double) * c->n_u, hipMemcpyDeviceToDevice, c->s));
+    if (p) PM_HIP(hipMemcpyAsync(p, c->xvec + c->n_u, sizeof(double) * c->n_p, hipMemcpyDeviceToDevice, c->s));
+    if (pi)
+      PM_HIP(hipMemcpyAsync(pi, c->xvec + c->n_u + c->n_p, sizeof(double) * c->n_pi, hipMemcpyDeviceToDevice, c->s));
+    PM_HIP(hipStreamSynchronize(c->s));
+    li.t_solve = now_s() - t0;
+    c->info = li;
+    if (info) *info = li;
+    if (rc == PM_ENOCONV) c->err = "FGMRES reached max_it before rtol";
+    return rc;
+  });
 }
 
 int pm_solve_transpose(pm_ctx* c, const double* g, double* lu, double* lpi, double* lp, pm_info* info) {

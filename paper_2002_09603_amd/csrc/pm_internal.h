@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -334,8 +335,39 @@ void amg_vcycle(hipStream_t s, Hierarchy& H, const double* b, double* x);       
 void amg_vcycle32(hipStream_t s, Hierarchy& H, const float* b, float* x);       // FP32 levels
 
 // Krylov (pm_krylov.hip)
-int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info);
-double dot(pm_ctx* c, const double* a, const double* b, int64_t n);
+// Device workspace of one FGMRES run: basis V ((m_cap+1) vectors of stride
+// ld), preconditioned vectors Z (FP64) or Zf (FP32), reduction partial sums,
+// device scalars and a host copy of them.
+struct KrylovWs {
+  int m_cap = 0;
+  int64_t ld = 0;
+  double* V = nullptr;
+  double* Z = nullptr;
+  float* Zf = nullptr;
+  double* red = nullptr;
+  double* hcol = nullptr;
+  double* hhost = nullptr;  // host, m_cap + 8 doubles
+};
+// Host arrays of the Givens process: H ((m_cap+1) x m_cap), cs, sn, y (m_cap), g (m_cap+1)
+struct KrylovHost {
+  int m_cap = 0;
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+};
+// Operator and right preconditioner of the iteration (vectors of length c->N);
+// the FP32 pair is used with one Gram-Schmidt pass when M32 is set.
+struct KrylovOps {
+  std::function<void(const double*, double*)> A64, M64;
+  std::function<void(const float*, double*)> A32;
+  std::function<void(const float*, float*)> M32;
+};
+int64_t krylov_ld(int64_t N);
+void krylov_preload(hipStream_t s);                                // load the Krylov kernels' code object
+size_t krylov_device_bytes(int64_t N, int m, bool z32);           // device bytes of krylov_ws_in
+KrylovWs krylov_ws_in(void* base, size_t bytes, int64_t N, int m, bool z32);  // carve from a buffer
+KrylovOps step_ops(pm_ctx* c, bool transpose);                     // A_H and M^-1 (or transposes)
+int fgmres_ws(pm_ctx* c, const KrylovOps& op, const KrylovWs& ws, KrylovHost& hw, const double* b, double* x,
+              pm_info* info);
+int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info);  // context workspace
 }  // namespace pm
 
 namespace pm {

@@ -317,8 +317,9 @@ int grid_for(int64_t N) { return (int)std::min<int64_t>(kDotBlocks, (N + 255) / 
 }  // namespace
 
 // basis V (m+1 FP64 vectors) and the preconditioned vectors: FP64 Z, or FP32
-// Zf when they come from the FP32 preconditioner (exactly representable)
-static void ensure_krylov(pm_ctx* c, int m, bool z32) {
+// Zf when they come from the FP32 preconditioner (exactly representable);
+// held by the context and grown on demand
+static KrylovWs context_ws(pm_ctx* c, int m, bool z32) {
   c->ld = (c->N + 31) / 32 * 32;  // vectors start 256-byte aligned
   if (z32 ? (c->mzf_alloc < m || !c->Zf) : (c->mz_alloc < m || !c->Z)) {
     if (z32) {
@@ -331,58 +332,96 @@ static void ensure_krylov(pm_ctx* c, int m, bool z32) {
       c->mz_alloc = m;
     }
   }
-  if (c->m_alloc >= m && c->V) return;
-  dfree(c->V);
-  c->V = dalloc<double>((int64_t)(m + 1) * c->ld);
-  if (!c->red) c->red = dalloc<double>((int64_t)kDotBlocks * kPartRows);
-  dfree(c->hcol);
-  c->hcol = dalloc<double>(3 * (m + 2) + 8);
-  if (c->hhost) (void)hipHostFree(c->hhost);
-  PM_HIP(hipHostMalloc((void**)&c->hhost, sizeof(double) * (m + 8), hipHostMallocDefault));
-  c->m_alloc = m;
+  if (c->m_alloc < m || !c->V) {
+    dfree(c->V);
+    c->V = dalloc<double>((int64_t)(m + 1) * c->ld);
+    if (!c->red) c->red = dalloc<double>((int64_t)kDotBlocks * kPartRows);
+    dfree(c->hcol);
+    c->hcol = dalloc<double>(3 * (m + 2) + 8);
+    if (c->hhost) (void)hipHostFree(c->hhost);
+    c->hhost = nullptr;
+    PM_HIP(hipHostMalloc((void**)&c->hhost, sizeof(double) * (m + 8), hipHostMallocDefault));
+    c->m_alloc = m;
+  }
+  KrylovWs w;
+  w.m_cap = m;
+  w.ld = c->ld;
+  w.V = c->V;
+  w.Z = z32 ? nullptr : c->Z;
+  w.Zf = z32 ? c->Zf : nullptr;
+  w.red = c->red;
+  w.hcol = c->hcol;
+  w.hhost = c->hhost;
+  return w;
+}
+
+int64_t krylov_ld(int64_t N) { return (N + 31) / 32 * 32; }
+
+// Loads this file's code object onto the current device: one launch of a
+// kernel over zero elements (no memory access).  The runtime loads a code
+// object at the first launch of one of its kernels and takes device memory
+// for it then; pm_setup calls this so that no later solve does.
+void krylov_preload(hipStream_t s) {
+  k_scale_const<<<1, 64, 0, s>>>(0, nullptr, 1.0, nullptr);
+  PM_CHECK_LAUNCH();
+}
+
+size_t krylov_device_bytes(int64_t N, int m, bool z32) {
+  const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const int64_t ld = krylov_ld(N);
+  return up(sizeof(double) * (size_t)kDotBlocks * kPartRows) + up(sizeof(double) * (3 * (m + 2) + 8)) +
+         up(sizeof(double) * (size_t)(m + 1) * ld) + up((z32 ? sizeof(float) : sizeof(double)) * (size_t)m * ld);
+}
+
+KrylovWs krylov_ws_in(void* base, size_t bytes, int64_t N, int m, bool z32) {
+  const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  if (krylov_device_bytes(N, m, z32) > bytes) throw Error(PM_EINVAL, "Krylov workspace does not fit");
+  char* p = (char*)base;
+  KrylovWs w;
+  w.m_cap = m;
+  w.ld = krylov_ld(N);
+  w.red = (double*)p;
+  p += up(sizeof(double) * (size_t)kDotBlocks * kPartRows);
+  w.hcol = (double*)p;
+  p += up(sizeof(double) * (3 * (m + 2) + 8));
+  w.V = (double*)p;
+  p += up(sizeof(double) * (size_t)(m + 1) * w.ld);
+  if (z32)
+    w.Zf = (float*)p;
+  else
+    w.Z = (double*)p;
+  return w;
 }
 
 // ||x||^2 into dev[0]; optionally returned to the host (synchronizes)
-static double norm_sq(pm_ctx* c, const double* x, double* dev, bool to_host) {
+static double norm_sq(pm_ctx* c, const KrylovWs& w, const double* x, double* dev, bool to_host) {
   const int64_t N = c->N;
   const int gb = grid_for(N);
-  k_sq_part<<<gb, 256, 0, c->s>>>(x, N, c->red);
-  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 0, 1, gb, dev);
+  k_sq_part<<<gb, 256, 0, c->s>>>(x, N, w.red);
+  k_dot_final<<<1, 256, 0, c->s>>>(w.red, 0, 1, gb, dev);
   PM_CHECK_LAUNCH();
   if (!to_host) return 0.0;
-  double h = 0.0;
-  PM_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  PM_HIP(hipMemcpyAsync(w.hhost, dev, sizeof(double), hipMemcpyDeviceToHost, c->s));
   PM_HIP(hipStreamSynchronize(c->s));
-  return h;
-}
-
-double dot(pm_ctx* c, const double* a, const double* b, int64_t n) {
-  const int gb = grid_for(n);
-  k_dot_part<<<gb, 256, 0, c->s>>>(a, b, n, c->red);
-  k_dot_final<<<1, 256, 0, c->s>>>(c->red, 0, 1, gb, c->hcol);
-  PM_CHECK_LAUNCH();
-  double h = 0.0;
-  PM_HIP(hipMemcpyAsync(&h, c->hcol, sizeof(double), hipMemcpyDeviceToHost, c->s));
-  PM_HIP(hipStreamSynchronize(c->s));
-  return h;
+  return w.hhost[0];
 }
 
 // One classical Gram-Schmidt pass against V[0..nv): hpass[0..nv) = V^T w,
 // w -= V hpass.  With self_norm, hpass[nv] = ||w||^2 before the pass.  The
 // partial sums of ||w_new||^2 are left in row nv+1 of the partial buffer.
-static void cgs_pass(pm_ctx* c, int nv, double* hpass, bool self_norm) {
+static void cgs_pass(pm_ctx* c, const KrylovWs& ws, int nv, double* hpass, bool self_norm) {
   const int64_t N = c->N;
   const int gb = grid_for(N);
   for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
     const int cnt = std::min(kDotGroup, nv - i0);
     g_prof.begin(c->s, kProfMultidot);
-    k_multidot<kDotGroup, 8><<<gb, 256, 0, c->s>>>(c->V, N, c->ld, i0, cnt, c->wvec, c->red,
+    k_multidot<kDotGroup, 8><<<gb, 256, 0, c->s>>>(ws.V, N, ws.ld, i0, cnt, c->wvec, ws.red,
                                                    (self_norm && i0 == 0) ? nv : -1);
     g_prof.end(c->s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
   }
-  k_dot_final<<<nv + (self_norm ? 1 : 0), 256, 0, c->s>>>(c->red, 0, nv + (self_norm ? 1 : 0), gb, hpass);
+  k_dot_final<<<nv + (self_norm ? 1 : 0), 256, 0, c->s>>>(ws.red, 0, nv + (self_norm ? 1 : 0), gb, hpass);
   g_prof.begin(c->s, kProfMultiaxpy);
-  k_multiaxpy<double><<<gb, 256, 0, c->s>>>(c->V, N, c->ld, nv, hpass, c->wvec, -1.0, c->red, nv + 1);
+  k_multiaxpy<double><<<gb, 256, 0, c->s>>>(ws.V, N, ws.ld, nv, hpass, c->wvec, -1.0, ws.red, nv + 1);
   g_prof.end(c->s, kProfMultiaxpy, (double)(nv + 2) * N * 8.0);
   PM_CHECK_LAUNCH();
 }
@@ -392,29 +431,33 @@ __global__ void k_add_vec(int n, const double* __restrict__ a, double* __restric
   if (i < n) b[i] += a[i];
 }
 
-int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info) {
+int fgmres_ws(pm_ctx* c, const KrylovOps& op, const KrylovWs& ws, KrylovHost& hw, const double* b, double* x,
+              pm_info* info) {
   const int m = std::max(1, c->opts.restart);
   const int max_it = std::max(1, c->opts.max_it);
   const double rtol = c->opts.rtol;
-  if (m > 500) throw Error(PM_EINVAL, "restart length too large (max 500)");
+  if (m > ws.m_cap || m > hw.m_cap) throw Error(PM_EINVAL, "fgmres: restart length exceeds the workspace");
   // one Gram-Schmidt pass: the norm of the new basis vector comes from the
   // projections (Pythagoras) so one pass orthogonalises, normalises and
   // writes the FP32 preconditioner input; the exact norm from the same pass
   // corrects the scale when they differ
   const bool fused = c->opts.orth_passes == 1;
-  const bool z32 = fused && c->opts.precond_fp32;
-  ensure_krylov(c, m, z32);
+  const bool z32 = fused && op.M32 != nullptr;
+  if (z32 ? !ws.Zf : !ws.Z) throw Error(PM_EINTERNAL, "fgmres: workspace lacks the preconditioned vectors");
   const int64_t N = c->N;
+  const int64_t ld = ws.ld;
   hipStream_t s = c->s;
   const int gN = blocks_for(N);
-  double* h1 = c->hcol;               // pass-1 coefficients + norm (m+2)
-  double* h2 = c->hcol + (m + 2);     // pass-2 coefficients, then y (m+2)
-  double* dev_nrm = c->hcol + 2 * (m + 2);
+  double* h1 = ws.hcol;               // pass-1 coefficients + norm (m+2)
+  double* h2 = ws.hcol + (m + 2);     // pass-2 coefficients, then y (m+2)
+  double* dev_nrm = ws.hcol + 2 * (m + 2);
   double* dev_scale = dev_nrm + 1;
+  double* hhost = ws.hhost;
   float* vf = z32 ? c->pw32 : nullptr;  // FP32 copy of the current basis vector
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  double *H = hw.H, *cs = hw.cs, *sn = hw.sn, *g = hw.g, *y = hw.y;
+  std::fill(H, H + (size_t)(m + 1) * m, 0.0);
   PM_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, s));
-  const double bnorm = std::sqrt(norm_sq(c, b, dev_nrm, true));
+  const double bnorm = std::sqrt(norm_sq(c, ws, b, dev_nrm, true));
   if (!std::isfinite(bnorm)) throw Error(PM_EBREAKDOWN, "fgmres: right-hand side is not finite");
   if (info) {
     info->iters = 0;
@@ -427,22 +470,21 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
   bool converged = false;
   PM_HIP(hipMemcpyAsync(c->rvec, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   while (true) {
-    k_scale2<<<gN, kBlock, 0, s>>>(N, c->rvec, 1.0 / beta, c->V, vf);
+    k_scale2<<<gN, kBlock, 0, s>>>(N, c->rvec, 1.0 / beta, ws.V, vf);
     PM_CHECK_LAUNCH();
-    std::fill(g.begin(), g.end(), 0.0);
+    std::fill(g, g + m + 1, 0.0);
     g[0] = beta;
     int jdone = 0;
     for (int j = 0; j < m && its < max_it; ++j) {
-      const int64_t ld = c->ld;
-      double* vj = c->V + (size_t)j * ld;
+      double* vj = ws.V + (size_t)j * ld;
       if (z32) {
-        float* zj = c->Zf + (size_t)j * ld;
-        apply_Minv32(c, vf, zj, transpose);
-        apply_AH32(c, zj, c->wvec, transpose);
+        float* zj = ws.Zf + (size_t)j * ld;
+        op.M32(vf, zj);
+        op.A32(zj, c->wvec);
       } else {
-        double* zj = c->Z + (size_t)j * ld;
-        apply_Minv(c, vj, zj, transpose);
-        apply_AH(c, zj, c->wvec, transpose);
+        double* zj = ws.Z + (size_t)j * ld;
+        op.M64(vj, zj);
+        op.A64(zj, c->wvec);
       }
       const int nv = j + 1;
       double hn;
@@ -453,10 +495,10 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
         for (int i0 = 0; i0 < nv; i0 += kDotGroupWide) {
           const int cnt = std::min(kDotGroupWide, nv - i0);
           g_prof.begin(s, kProfMultidot);
-          k_multidot<kDotGroupWide, 4><<<gd, 256, 0, s>>>(c->V, N, ld, i0, cnt, c->wvec, c->red, i0 == 0 ? nv : -1);
+          k_multidot<kDotGroupWide, 4><<<gd, 256, 0, s>>>(ws.V, N, ld, i0, cnt, c->wvec, ws.red, i0 == 0 ? nv : -1);
           g_prof.end(s, kProfMultidot, (double)(cnt + 1) * N * 8.0);
         }
-        k_dot_final<<<nv + 1, 256, 0, s>>>(c->red, 0, nv + 1, gd, h1);
+        k_dot_final<<<nv + 1, 256, 0, s>>>(ws.red, 0, nv + 1, gd, h1);
         k_pyth_scale<<<1, 64, 0, s>>>(h1, nv, dev_scale);
         g_prof.begin(s, kProfMultiaxpy);
         int go = gb;
@@ -464,8 +506,8 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
           go = gd;
           auto orth = [&](auto ng) {
             constexpr int NG = decltype(ng)::value;
-            k_orth_normalize_n<NG><<<go, 256, 0, s>>>(c->V, N, ld, nv, h1, dev_scale, c->wvec,
-                                                      c->V + (size_t)(j + 1) * ld, vf, c->red, nv + 1);
+            k_orth_normalize_n<NG><<<go, 256, 0, s>>>(ws.V, N, ld, nv, h1, dev_scale, c->wvec,
+                                                      ws.V + (size_t)(j + 1) * ld, vf, ws.red, nv + 1);
           };
           if (nv <= 4)
             orth(std::integral_constant<int, 4>{});
@@ -476,21 +518,21 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
           else
             orth(std::integral_constant<int, kDotGroupWide>{});
         } else {
-          k_orth_normalize<<<go, 256, 0, s>>>(c->V, N, ld, nv, h1, dev_scale, c->wvec, c->V + (size_t)(j + 1) * ld,
-                                              vf, c->red, nv + 1);
+          k_orth_normalize<<<go, 256, 0, s>>>(ws.V, N, ld, nv, h1, dev_scale, c->wvec, ws.V + (size_t)(j + 1) * ld,
+                                              vf, ws.red, nv + 1);
         }
         g_prof.end(s, kProfMultiaxpy, (double)(nv + 2) * N * 8.0 + (vf ? (double)N * 4.0 : 0.0));
-        k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, go, h1);
+        k_dot_final<<<1, 256, 0, s>>>(ws.red, nv + 1, 1, go, h1);
         PM_CHECK_LAUNCH();
-        PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
-        PM_HIP(hipMemcpyAsync(c->hhost + nv + 2, dev_scale, sizeof(double), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipMemcpyAsync(hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipMemcpyAsync(hhost + nv + 2, dev_scale, sizeof(double), hipMemcpyDeviceToHost, s));
         PM_HIP(hipStreamSynchronize(s));
-        hn = std::sqrt(c->hhost[nv + 1]);
-        const double sc = c->hhost[nv + 2];
+        hn = std::sqrt(hhost[nv + 1]);
+        const double sc = hhost[nv + 2];
         if (hn > 0.0 && std::isfinite(hn)) {
           const double prod = hn * sc;  // norm of the written vector
           if (std::fabs(prod - 1.0) > 1e-10) {
-            k_scale2<<<gN, kBlock, 0, s>>>(N, c->V + (size_t)(j + 1) * ld, 1.0 / prod, c->V + (size_t)(j + 1) * ld,
+            k_scale2<<<gN, kBlock, 0, s>>>(N, ws.V + (size_t)(j + 1) * ld, 1.0 / prod, ws.V + (size_t)(j + 1) * ld,
                                            vf);
             PM_CHECK_LAUNCH();
           } else {
@@ -499,23 +541,23 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
         }
       } else {
         // classical Gram-Schmidt, one or two passes; h1[nv+1] = ||w||^2 after them
-        cgs_pass(c, nv, h1, false);
-        if (c->opts.orth_passes > 1) cgs_pass(c, nv, h2, false);
-        k_dot_final<<<1, 256, 0, s>>>(c->red, nv + 1, 1, grid_for(N), h1);
+        cgs_pass(c, ws, nv, h1, false);
+        if (c->opts.orth_passes > 1) cgs_pass(c, ws, nv, h2, false);
+        k_dot_final<<<1, 256, 0, s>>>(ws.red, nv + 1, 1, grid_for(N), h1);
         if (c->opts.orth_passes > 1) k_add_vec<<<blocks_for(nv), kBlock, 0, s>>>(nv, h2, h1);
         PM_CHECK_LAUNCH();
-        PM_HIP(hipMemcpyAsync(c->hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipMemcpyAsync(hhost, h1, sizeof(double) * (nv + 2), hipMemcpyDeviceToHost, s));
         PM_HIP(hipStreamSynchronize(s));
-        hn = std::sqrt(c->hhost[nv + 1]);
+        hn = std::sqrt(hhost[nv + 1]);
         if (hn > 0.0 && std::isfinite(hn)) {
-          k_scale_const<<<gN, kBlock, 0, s>>>(N, c->wvec, 1.0 / hn, c->V + (size_t)(j + 1) * ld);
+          k_scale_const<<<gN, kBlock, 0, s>>>(N, c->wvec, 1.0 / hn, ws.V + (size_t)(j + 1) * ld);
           PM_CHECK_LAUNCH();
         }
       }
       bool bad = !std::isfinite(hn);
       for (int i = 0; i < nv; ++i) {
-        H[(size_t)i * m + j] = c->hhost[i];
-        bad = bad || !std::isfinite(c->hhost[i]);
+        H[(size_t)i * m + j] = hhost[i];
+        bad = bad || !std::isfinite(hhost[i]);
       }
       if (bad) throw Error(PM_EBREAKDOWN, "fgmres: non-finite value in the Arnoldi process");
       H[(size_t)nv * m + j] = hn;
@@ -546,18 +588,18 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
       y[i] = v / d;
     }
     if (jdone > 0) {
-      PM_HIP(hipMemcpyAsync(h2, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, s));
+      PM_HIP(hipMemcpyAsync(h2, y, sizeof(double) * jdone, hipMemcpyHostToDevice, s));
       if (z32)
-        k_multiaxpy<float><<<grid_for(N), 256, 0, s>>>(c->Zf, N, c->ld, jdone, h2, x, 1.0, c->red, -1);
+        k_multiaxpy<float><<<grid_for(N), 256, 0, s>>>(ws.Zf, N, ld, jdone, h2, x, 1.0, ws.red, -1);
       else
-        k_multiaxpy<double><<<grid_for(N), 256, 0, s>>>(c->Z, N, c->ld, jdone, h2, x, 1.0, c->red, -1);
+        k_multiaxpy<double><<<grid_for(N), 256, 0, s>>>(ws.Z, N, ld, jdone, h2, x, 1.0, ws.red, -1);
       PM_CHECK_LAUNCH();
     }
     // true residual in FP64; restart from it if needed
-    apply_AH(c, x, c->wvec, transpose);
+    op.A64(x, c->wvec);
     k_sub<<<gN, kBlock, 0, s>>>(N, b, c->wvec, c->rvec);
     PM_CHECK_LAUNCH();
-    beta = std::sqrt(norm_sq(c, c->rvec, dev_nrm, true));
+    beta = std::sqrt(norm_sq(c, ws, c->rvec, dev_nrm, true));
     relres_true = beta / bnorm;
     if (!std::isfinite(relres_true)) throw Error(PM_EBREAKDOWN, "fgmres: non-finite residual");
     if (relres_true <= rtol) {
@@ -572,6 +614,28 @@ int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info)
     info->relres_true = relres_true;
   }
   return converged ? PM_OK : PM_ENOCONV;
+}
+
+KrylovOps step_ops(pm_ctx* c, bool transpose) {
+  KrylovOps op;
+  op.A64 = [c, transpose](const double* z, double* w) { apply_AH(c, z, w, transpose); };
+  op.M64 = [c, transpose](const double* v, double* z) { apply_Minv(c, v, z, transpose); };
+  if (c->opts.precond_fp32) {
+    op.A32 = [c, transpose](const float* z, double* w) { apply_AH32(c, z, w, transpose); };
+    op.M32 = [c, transpose](const float* v, float* z) { apply_Minv32(c, v, z, transpose); };
+  }
+  return op;
+}
+
+int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info) {
+  const int m = std::max(1, c->opts.restart);
+  if (m > 500) throw Error(PM_EINVAL, "restart length too large (max 500)");
+  const KrylovOps op = step_ops(c, transpose);
+  const bool z32 = c->opts.orth_passes == 1 && op.M32 != nullptr;
+  const KrylovWs ws = context_ws(c, m, z32);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  KrylovHost hw{m, H.data(), cs.data(), sn.data(), g.data(), y.data()};
+  return fgmres_ws(c, op, ws, hw, b, x, info);
 }
 
 }  // namespace pm

@@ -216,6 +216,18 @@ class PoroSolver:
         """A_H x = b -> (u, pi, p, info)."""
         return self._solve(lib.pm_solve, b, raise_noconv)
 
+    def solve_noalloc(self, b, u, pi, p, raise_noconv=True):
+        """A_H x = b into the caller's u, pi, p through pm_solve_noalloc (no
+        device allocation in the library; workspace in its static scratch)."""
+        info = _capi.pm_info()
+        rc = lib.pm_solve_noalloc(self._ctx, self._dev(b, self.N, "right-hand side"), self._dev(u, self.n_u, "u"),
+                                  self._dev(pi, self.n_pi, "pi"), self._dev(p, self.n_p, "p"), C.byref(info))
+        if rc != _capi.PM_OK and (rc != _capi.PM_ENOCONV or raise_noconv):
+            check(rc, self._ctx)
+        d = info.as_dict()
+        d["converged"] = rc == _capi.PM_OK
+        return d
+
     def solve_transpose(self, g, raise_noconv=True):
         """A_H^T lam = g -> (lam_u, lam_pi, lam_p, info)."""
         return self._solve(lib.pm_solve_transpose, g, raise_noconv)
