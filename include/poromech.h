@@ -216,6 +216,24 @@ int pm_solve(pm_ctx* ctx, const double* b, double* u, double* pi, double* p, pm_
  * streams) race and must be serialized by the caller. */
 int pm_solve_noalloc(pm_ctx* ctx, const double* b, double* u, double* pi, double* p, pm_info* info);
 
+/* Right-hand side [f_u; f_q; f_p] of the step in the non-hybridized mixed
+ * (MFE) form (Sec. 2.1 eq. mfeSys, Appendix A eq. MFE_vector), order
+ * [u; q; p] as PM_OP_MFE: the traction load; f_q = -s p_top on each drained
+ * face (s = +1 for a cell's +x/+y/+z face), 0 elsewhere; f_p = A_pu u_prev +
+ * S_eps|T| p_prev (+ A_stab p_prev in increment form).  u_prev, p_prev device
+ * or NULL; b device, N. */
+int pm_build_rhs_mfe(pm_ctx* ctx, const double* u_prev, const double* p_prev, double* b);
+
+/* Solve A_M x = b, the MFE form of the step (the comparison system of Sec.
+ * 5), by FP64 FGMRES right-preconditioned with PM_OP_BTP (eq. prec), zero
+ * initial guess, with the context's rtol, restart, max_it and Gram-Schmidt
+ * passes.  b device, N, order [u; q; p]; outputs (device, caller-owned, any
+ * may be NULL): u (n_u), q (n_pi face fluxes), p (n_p).  The first call after
+ * pm_assemble or pm_set_dt builds C~_p and its hierarchy (info->t_setup;
+ * info->levels_pi, opcx_pi and ncoarse_pi describe that hierarchy).
+ * Returns PM_ENOCONV if max_it is reached. */
+int pm_solve_mfe(pm_ctx* ctx, const double* b, double* u, double* q, double* p, pm_info* info);
+
 /* Solve A_H^T lam = g (adjoint) with FGMRES preconditioned by M^T (block
  * lower triangular: forward substitution u -> p -> pi, same V-cycles).
  * g device, N; outputs as in pm_solve. */
@@ -263,14 +281,23 @@ int pm_reconstruct_w(pm_ctx* ctx, const double* p, const double* pi, double* w);
  *   PM_OP_CP       y = C~_p x           (n_p -> n_p) the Schur complement approximation of the
  *                  MFE block triangular preconditioner (Sec. 5, eq. prec): A_stab + A_pp +
  *                  the fixed-stress diagonal of B~_p + dt A_qp^T L_qq^-1 A_qp, with L_qq the
- *                  absolute row sums of A_qq (no-flow faces excluded).  Each call assembles it
- *                  as a 7-point CSR held by the context (reused by later calls).
- *   PM_OP_VCYCLE_CP y = one V-cycle for C~_p applied to x (zero initial guess): each call
- *                  rebuilds C~_p and a smoothed-aggregation hierarchy for it with the C~_pi
- *                  settings in FP64 (the inner C~_p solve of the MFE preconditioner). */
+ *                  absolute row sums of A_qq (no-flow faces excluded).  Assembled as a
+ *                  7-point CSR held by the context on the first MFE call after pm_assemble
+ *                  or pm_set_dt, together with the hierarchy below.
+ *   PM_OP_VCYCLE_CP y = one V-cycle for C~_p applied to x (zero initial guess), on the
+ *                  context's smoothed-aggregation hierarchy of C~_p (C~_pi settings, FP64),
+ *                  built once per assembly and dt (the inner C~_p solve of the MFE
+ *                  preconditioner).
+ *   PM_OP_BTP      y = M^-1 x           (N -> N, order [u; q; p]) the block lower triangular
+ *                  preconditioner of the MFE system (Sec. 5, eq. prec, GPU analogue of
+ *                  variant M_II^(m)): y_u = one A_uu V-cycle (the pm_assemble hierarchy, FP64
+ *                  levels) on x_u; y_q = five Chebyshev-Jacobi sweeps on A_qq y_q = x_q from
+ *                  zero (in place of the paper's incomplete Cholesky factor, whose triangular
+ *                  solves are sequential); y_p = one C~_p V-cycle on x_p - A_pu y_u -
+ *                  dt A_pq y_q. */
 enum { PM_OP_AH = 0, PM_OP_AHT = 1, PM_OP_MINV = 2, PM_OP_MINVT = 3, PM_OP_CPI = 4,
        PM_OP_BP = 5, PM_OP_AUU = 6, PM_OP_VCYCLE_U = 7, PM_OP_VCYCLE_PI = 8, PM_OP_MFE = 9,
-       PM_OP_CP = 10, PM_OP_VCYCLE_CP = 11 };
+       PM_OP_CP = 10, PM_OP_VCYCLE_CP = 11, PM_OP_BTP = 12 };
 int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
 
 /* Kernel timing for roofline measurements.  pm_profile_begin clears the

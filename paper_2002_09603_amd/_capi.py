@@ -17,7 +17,7 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EHIP, PM_ENOCONV, PM_EBREAKDOWN, PM_ESTATE, PM_E
 PM_BC_COLUMN, PM_BC_ROLLERS, PM_BC_CANTILEVER = 0, 1, 2
 PM_OP_AH, PM_OP_AHT, PM_OP_MINV, PM_OP_MINVT, PM_OP_CPI, PM_OP_BP, PM_OP_AUU, \
     PM_OP_VCYCLE_U, PM_OP_VCYCLE_PI, PM_OP_MFE, PM_OP_CP, \
-    PM_OP_VCYCLE_CP = range(12)
+    PM_OP_VCYCLE_CP, PM_OP_BTP = range(13)
 
 PROF_KERNELS = {1: "k_lat_ah_u|k_ah_u (u-rows of A_H, FP64)",
                 2: "k_lat_cheb|k_cheb_step<3> (Chebyshev step, finest A_uu level)",
@@ -82,6 +82,8 @@ _SIGS = [
     ("pm_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(pm_info)]),
     ("pm_solve_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(pm_info)]),
+    ("pm_build_rhs_mfe", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pm_solve_mfe", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(pm_info)]),
     ("pm_solve_transpose", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(pm_info)]),
     ("pm_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -659,6 +659,7 @@ void assemble_all(pm_ctx* c) {
                                                   c->Minv, c->g, c->alpha, c->status, nullptr);
   PM_CHECK_LAUNCH();
   c->Mq_valid = false;
+  c->mfe_valid = false;
   if (c->opts.block_minv) {
     k_minv_pattern<<<blocks_for(G.nc), kBlock, 0, s>>>(G, c->Minv, c->status);
     PM_CHECK_LAUNCH();

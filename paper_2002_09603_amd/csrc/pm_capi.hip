@@ -74,7 +74,8 @@ void free_ctx_buffers(pm_ctx* c) {
   for (void* p : {(void*)c->coords, (void*)c->E, (void*)c->kappa, (void*)c->Ke, (void*)c->ae, (void*)c->vol,
                   (void*)c->Minv, (void*)c->Mp, (void*)c->Mb, (void*)c->Mq, (void*)c->g, (void*)c->alpha, (void*)c->stabw, (void*)c->bp, (void*)c->auu_diag,
                   (void*)c->ufix, (void*)c->pifix, (void*)c->status, (void*)c->V, (void*)c->Z, (void*)c->Zf, (void*)c->wvec,
-                  (void*)c->rvec, (void*)c->xvec, (void*)c->red, (void*)c->hcol, (void*)c->pw64, (void*)c->pw32})
+                  (void*)c->rvec, (void*)c->xvec, (void*)c->red, (void*)c->hcol, (void*)c->pw64, (void*)c->pw32,
+                  (void*)c->mfe_lq, (void*)c->mfe_dqinv, (void*)c->mfe_work})
     dfree(p);
   if (c->hhost) (void)hipHostFree(c->hhost);
   c->Auu.free_all();
@@ -140,6 +141,21 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   if (c->opts.cheb_lower_pi > 0.0) p.cheb_lower = c->opts.cheb_lower_pi;
   p.side = c->s_side_pi;
   return p;
+}
+
+// the MFE preconditioner's C~_p hierarchy: the C~_pi settings, FP64 levels,
+// one V-cycle per application, on the caller's stream
+pm::AmgParams params_cp(const pm_ctx* c) {
+  pm::AmgParams p = params_pi(c);
+  p.fp32 = false;
+  p.side = nullptr;
+  p.cycles = 1;
+  return p;
+}
+
+// C~_p, its hierarchy and the A_qq sweep data, once per assembly and dt
+void ensure_mfe_prec(pm_ctx* c) {
+  if (!c->mfe_valid) pm::mfe_prec_setup(c, params_cp(c));
 }
 
 // B~_p, C~_pi (assembled and packed per cell) and C~_pi's AMG hierarchy, on
@@ -403,6 +419,7 @@ int pm_set_dt(pm_ctx* c, double dt) {
   return guarded(c, [&]() -> int {
     if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(PM_EINVAL, "pm_set_dt: dt must be positive");
     c->dt = dt;
+    c->mfe_valid = false;
     if (!c->assembled) return PM_OK;
     PM_HIP(hipStreamSynchronize(c->s));
     const double t0 = now_s();
@@ -523,6 +540,48 @@ int pm_solve_transpose(pm_ctx* c, const double* g, double* lu, double* lpi, doub
   return solve_common(c, g, lu, lpi, lp, info, true);
 }
 
+int pm_build_rhs_mfe(pm_ctx* c, const double* u_prev, const double* p_prev, double* b) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!b) throw Error(PM_EINVAL, "pm_build_rhs_mfe: b is NULL");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_build_rhs_mfe: call pm_assemble first");
+    pm::build_rhs_mfe(c, u_prev, p_prev, b);
+    return PM_OK;
+  });
+}
+
+int pm_solve_mfe(pm_ctx* c, const double* b, double* u, double* q, double* p, pm_info* info) {
+  if (!c) return PM_EINVAL;
+  return guarded(c, [&]() -> int {
+    if (!b) throw Error(PM_EINVAL, "pm_solve_mfe: b is NULL");
+    if (!c->assembled) throw Error(PM_ESTATE, "pm_solve_mfe: call pm_assemble first");
+    PM_HIP(hipStreamSynchronize(c->s));
+    const double t0 = now_s();
+    const bool built = !c->mfe_valid;
+    ensure_mfe_prec(c);
+    PM_HIP(hipStreamSynchronize(c->s));
+    const double t1 = now_s();
+    pm::KrylovOps op;
+    op.A64 = [c](const double* z, double* w) { pm::apply_mfe(c, z, w); };
+    op.M64 = [c](const double* v, double* z) { pm::apply_btp(c, v, z); };
+    pm_info li = c->info;
+    const int rc = pm::fgmres_with(c, op, b, c->xvec, &li);
+    const int64_t nq = c->n_pi;
+    if (u) PM_HIP(hipMemcpyAsync(u, c->xvec, sizeof(double) * c->n_u, hipMemcpyDeviceToDevice, c->s));
+    if (q) PM_HIP(hipMemcpyAsync(q, c->xvec + c->n_u, sizeof(double) * nq, hipMemcpyDeviceToDevice, c->s));
+    if (p) PM_HIP(hipMemcpyAsync(p, c->xvec + c->n_u + nq, sizeof(double) * c->n_p, hipMemcpyDeviceToDevice, c->s));
+    PM_HIP(hipStreamSynchronize(c->s));
+    li.t_solve = now_s() - t1;
+    if (built) li.t_setup = t1 - t0;  // the C~_p hierarchy; the A_uu one is pm_assemble's
+    li.levels_pi = (int)c->Hcp.L.size();
+    li.opcx_pi = c->Hcp.opcx;
+    li.ncoarse_pi = c->Hcp.ncoarse;
+    if (info) *info = li;
+    if (rc == PM_ENOCONV) c->err = "FGMRES reached max_it before rtol";
+    return rc;
+  });
+}
+
 int pm_grad(pm_ctx* c, const double* lam, const double* x, const double* p_prev, double* dlogk, double* dlogE) {
   if (!c) return PM_EINVAL;
   return guarded(c, [&]() -> int {
@@ -573,20 +632,17 @@ int pm_apply(pm_ctx* c, int which, const double* x, double* y) {
       case PM_OP_VCYCLE_PI: pm::amg_vcycle(c->s, c->Hpi, x, y); break;
       case PM_OP_MFE: pm::apply_mfe(c, x, y); break;
       case PM_OP_CP:
-        pm::build_cp(c);
+        ensure_mfe_prec(c);
         pm::apply_csr(c, c->Cp, x, y);
         break;
-      case PM_OP_VCYCLE_CP: {
-        // the C~_pi settings, FP64 levels, no side stream
-        pm::build_cp(c);
-        pm::AmgParams p = params_pi(c);
-        p.fp32 = false;
-        p.side = nullptr;
-        p.cycles = 1;
-        pm::amg_setup(c->s, c->Cp, p, c->Hcp);
+      case PM_OP_VCYCLE_CP:
+        ensure_mfe_prec(c);
         pm::amg_vcycle(c->s, c->Hcp, x, y);
         break;
-      }
+      case PM_OP_BTP:
+        ensure_mfe_prec(c);
+        pm::apply_btp(c, x, y);
+        break;
       default: throw Error(PM_EINVAL, "pm_apply: unknown operator");
     }
     return PM_OK;

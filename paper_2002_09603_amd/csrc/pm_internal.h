@@ -260,6 +260,13 @@ struct pm_ctx {
   // assembled operators
   pm::Csr Auu, Cpi, Cp;    // Cp: C~_p of the MFE preconditioner (built on first use)
   pm::Hierarchy Hu, Hpi, Hcp;  // Hcp: FP64 AMG hierarchy of the MFE C~_p
+  // MFE block triangular preconditioner, built on first use and kept until
+  // the next assembly or change of dt
+  bool mfe_valid = false;
+  double* mfe_lq = nullptr;    // n_pi absolute row sums of the masked A_qq (1 on no-flow faces)
+  double* mfe_dqinv = nullptr; // n_pi inverse diagonal of the masked A_qq
+  double mfe_qmax = 0.0;       // Gershgorin bound of lambda_max(D^-1 A_qq)
+  double* mfe_work = nullptr;  // 3 n_pi + n_p + 256: A_qq sweep vectors, C~_p right-hand side, set-up maxima
   bool assembled = false;
   bool hier_u_ok = false;
   // Krylov workspace
@@ -303,6 +310,12 @@ void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose);
 void apply_mfe(pm_ctx* c, const double* x, double* y);   // A_M of the MFE system, order [u; q; p]
 void cell_data(pm_ctx* c, double* Mfull);
 void build_cp(pm_ctx* c);                                 // C~_p of the MFE preconditioner into c->Cp
+// MFE block triangular preconditioner of eq. prec (pm_mfe.hip): C~_p, its
+// hierarchy (parameters prm) and the Jacobi data of A_qq; then z = M^-1 r
+void mfe_prec_setup(pm_ctx* c, const AmgParams& prm);
+void apply_btp(pm_ctx* c, const double* r, double* z);
+void build_rhs_mfe(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
+constexpr int kQqChebDegree = 5;                          // Chebyshev-Jacobi sweeps of A_qq per application
 void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose);    // FP32 input, FP64 arithmetic
 void apply_Minv(pm_ctx* c, const double* r, double* z, bool transpose);
 void apply_Minv32(pm_ctx* c, const float* r, float* z, bool transpose);   // FP32 hierarchies only
@@ -368,6 +381,7 @@ KrylovOps step_ops(pm_ctx* c, bool transpose);                     // A_H and M^
 int fgmres_ws(pm_ctx* c, const KrylovOps& op, const KrylovWs& ws, KrylovHost& hw, const double* b, double* x,
               pm_info* info);
 int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info);  // context workspace
+int fgmres_with(pm_ctx* c, const KrylovOps& op, const double* b, double* x, pm_info* info);  // same, any operator
 }  // namespace pm
 
 namespace pm {

@@ -628,9 +628,12 @@ KrylovOps step_ops(pm_ctx* c, bool transpose) {
 }
 
 int fgmres(pm_ctx* c, const double* b, double* x, bool transpose, pm_info* info) {
+  return fgmres_with(c, step_ops(c, transpose), b, x, info);
+}
+
+int fgmres_with(pm_ctx* c, const KrylovOps& op, const double* b, double* x, pm_info* info) {
   const int m = std::max(1, c->opts.restart);
   if (m > 500) throw Error(PM_EINVAL, "restart length too large (max 500)");
-  const KrylovOps op = step_ops(c, transpose);
   const bool z32 = c->opts.orth_passes == 1 && op.M32 != nullptr;
   const KrylovWs ws = context_ws(c, m, z32);
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);

@@ -216,6 +216,26 @@ class PoroSolver:
         """A_H x = b -> (u, pi, p, info)."""
         return self._solve(lib.pm_solve, b, raise_noconv)
 
+    def build_rhs_mfe(self, u_prev=None, p_prev=None, out=None):
+        """[f_u; f_q; f_p] of the MFE form of the step (order [u; q; p])."""
+        b = self._empty(self.N) if out is None else out
+        check(lib.pm_build_rhs_mfe(self._ctx, self._dev(u_prev, self.n_u, "u_prev", True),
+                                   self._dev(p_prev, self.n_p, "p_prev", True), self._dev(b, self.N, "out")),
+              self._ctx)
+        return b
+
+    def solve_mfe(self, b, raise_noconv=True):
+        """A_M x = b (MFE form, block triangular preconditioner) -> (u, q, p, info)."""
+        u, q, p = self._empty(self.n_u), self._empty(self.n_pi), self._empty(self.n_p)
+        info = _capi.pm_info()
+        rc = lib.pm_solve_mfe(self._ctx, self._dev(b, self.N, "right-hand side"), _ptr(u), _ptr(q), _ptr(p),
+                              C.byref(info))
+        if rc != _capi.PM_OK and (rc != _capi.PM_ENOCONV or raise_noconv):
+            check(rc, self._ctx)
+        d = info.as_dict()
+        d["converged"] = rc == _capi.PM_OK
+        return u, q, p, d
+
     def solve_noalloc(self, b, u, pi, p, raise_noconv=True):
         """A_H x = b into the caller's u, pi, p through pm_solve_noalloc (no
         device allocation in the library; workspace in its static scratch)."""
@@ -258,7 +278,8 @@ class PoroSolver:
                  _capi.PM_OP_VCYCLE_PI: (self.n_pi, self.n_pi)}
         if which in sizes:
             return sizes[which]
-        if which in (_capi.PM_OP_AH, _capi.PM_OP_AHT, _capi.PM_OP_MINV, _capi.PM_OP_MINVT, _capi.PM_OP_MFE):
+        if which in (_capi.PM_OP_AH, _capi.PM_OP_AHT, _capi.PM_OP_MINV, _capi.PM_OP_MINVT, _capi.PM_OP_MFE,
+                     _capi.PM_OP_BTP):
             return self.N, self.N
         raise ValueError(f"unknown operator {which}")
 
