@@ -15,11 +15,15 @@ element kernels and static condensation, stabilization, assembly, B~_p,
 C~_pi, both AMG setups, right-hand side, the preconditioned FGMRES solve and
 the flux reconstruction.  The metric is the step's time to solution (s).
 
-Also reported: iterations and phase times, the FP64-preconditioned GPU solve
-of the same system (time, iterations, per-field difference), the roofline of
-the dominant kernel (algorithmic bytes over HIP-event durations of its
-launches inside the timed steps), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Also reported: iterations and phase times; the roofline of the dominant
+operator / V-cycle kernel (algorithmic bytes, or stencil flops for the
+matrix-free lattice kernels, over HIP-event durations of its launches inside
+the timed steps) and a roofline entry for every instrumented kernel from the
+last warm-up step (operator and V-cycle kernels, and the FGMRES Gram-Schmidt
+kernels); the FP64-preconditioned GPU solve of the same system (time,
+iterations, per-field difference); the other single-GPU workloads (64^3 with
+S_eps 0 and 1e-4, the perturbed 96^3 mesh with its adjoint) in FP64; and the
+FP64 CPU oracle timed on bounded samples.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -37,33 +41,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# Vector ALU peak of the build: 256 CUs x 64 lanes x 2 flops per fused
+# multiply-add x 2.4 GHz = 78.6 TFLOP/s, in FP64 and in FP32 alike (the HIP
+# code is compiled without packed FP32 instructions, the only way FP32 vector
+# arithmetic reaches the 157.3 TFLOP/s of the data sheet)
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
 def _cpu_baseline(sample_n: int, full_unknowns: int):
-    """FP64 oracle on a bounded sample of the same workload recipe: assembly
-    plus FGMRES with the paper's exact-inner-solve preconditioner M_I^(h),
-    relative residual 1e-8, one thread."""
+    """The FP64 oracle as it stands, on the host's cores (BLAS threads up to
+    16, the GPU machine's CPU share; SuperLU itself is single-threaded):
+    * the 8^3 unit-cube workload: assembly and the direct sparse LU solve that
+      defines the step result;
+    * the layered workload recipe at sample_n^3: assembly and FGMRES with the
+      paper's exact-inner-solve preconditioner M_I^(h), relative residual 1e-8.
+    ``value`` projects the second linearly in unknowns to the full workload (a
+    lower bound: the sparse LU factorizations grow faster than linearly)."""
     from threadpoolctl import threadpool_limits
 
-    from oracle.solve import BlockPrec, fgmres
+    from oracle.solve import BlockPrec, direct_solve, fgmres
     from oracle.system import build_system
     from synth import make_config
 
-    prob = make_config("layered128", n=sample_n)
-    with threadpool_limits(1):
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    with threadpool_limits(threads):
+        small = make_config("unit8")
+        t0 = time.perf_counter()
+        A, b, B = build_system(small)
+        direct_solve(A, b)
+        t_small = time.perf_counter() - t0
+        prob = make_config("layered128", n=sample_n)
         t0 = time.perf_counter()
         A, b, B = build_system(prob)
+        t_asm = time.perf_counter() - t0
         P = BlockPrec(B)
         x, its, _ = fgmres(lambda v: A @ v, b, P.apply, rtol=1e-8, restart=200)
         t = time.perf_counter() - t0
     n = prob.n_total
     return {"value": round(t * full_unknowns / n, 3),
-            "unit": "s (projected linearly in unknowns to the full workload; a lower bound, the "
-                    "oracle's sparse LU work grows faster than linearly)",
-            "cores": 1, "kind": "oracle",
-            "sample": f"layered workload recipe at {sample_n}^3 ({n} unknowns): FP64 assembly + FGMRES "
-                      f"with exact inner LU solves (M_I^(h)), rtol 1e-8, {its} iterations, "
-                      f"{t:.2f} s measured"}
+            "unit": "s (the layered sample projected linearly in unknowns to the full workload; a lower bound, "
+                    "the oracle's sparse LU work grows faster than linearly)",
+            "cores": threads, "kind": "oracle",
+            "sample": f"layered workload recipe at {sample_n}^3 ({n} unknowns): FP64 assembly + FGMRES with exact "
+                      f"inner LU solves (M_I^(h)), rtol 1e-8, {its} iterations",
+            "measured": {f"layered{sample_n}": {"seconds": round(t, 3), "assembly_s": round(t_asm, 3),
+                                                "unknowns": n, "iterations": its},
+                         "unit8": {"seconds": round(t_small, 3), "unknowns": small.n_total,
+                                   "what": "8^3 unit cube: FP64 assembly + direct sparse LU of A_H"}}}
 
 
 def _traffic(kernel: str, n: int):
@@ -255,7 +279,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="cells per axis of the layered workload")
-    ap.add_argument("--cpu-sample", type=int, default=16, help="cells per axis of the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="cells per axis of the oracle sample")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the 64^3 (S_eps 0 and 1e-4) and perturbed 96^3 FP64 solves after the benchmark")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioned comparison solve")
     ap.add_argument("--rbm", action="store_true",
@@ -314,7 +340,9 @@ def main():
         w = s.reconstruct_w(p, pi)
         return u, pi, p, w, info
 
-    # warm-up; the last warm-up step records every instrumented kernel to find the dominant one
+    # warm-up; the last warm-up step records every instrumented kernel: the
+    # per-kernel table, and the dominant operator / V-cycle kernel, which the
+    # timed steps then record alone
     all_mask = sum(1 << k for k in _capi.PROF_KERNELS)
     for i in range(max(args.warmup, 1)):
         if i == max(args.warmup, 1) - 1:
@@ -322,7 +350,8 @@ def main():
         step()
     torch.cuda.synchronize()
     totals = {k: s.profile_end(k) for k in _capi.PROF_KERNELS}
-    dom = max(totals, key=lambda k: totals[k][1])
+    solve_ids = [k for k, (_, role) in _capi.PROF_KERNELS.items() if role == "solve"]
+    dom = max(solve_ids, key=lambda k: totals[k][1])
     s.profile_begin(1 << dom)
 
     torch.cuda.synchronize()
@@ -333,11 +362,12 @@ def main():
         infos.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    n_l, ms_l, by_l = s.profile_end(dom)
+    dom_rec = s.profile_end(dom)
     s.profile_begin(0)
     ms_per_step = 1000.0 * elapsed / args.steps
-    achieved = (by_l / 1e9) / (ms_l / 1e3) if ms_l > 0 else 0.0
     last = infos[-1]
+    head = _roofline(dom, *dom_rec)
+    head["traffic"] = _traffic(_capi.PROF_KERNELS[dom][0], args.n)
 
     out = {
         "metric": "time-to-solution (s) & FGMRES its at relres 1e-8, 128^3 grid; HBM GB/s of SpMV/V-cycle",
@@ -348,7 +378,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 2),
         "higher_is_better": False,
-        "scaling": "weak",
+        "scaling": None,
         "vs_baseline": None,
         "dtype": "f64 Krylov / f32 preconditioner",
         "data": "synthetic",
@@ -366,15 +396,9 @@ def main():
         "t_solve_s": round(last["t_solve"], 4),
         "amg_levels": [last["levels_u"], last["levels_pi"]],
         "amg_operator_complexity": [round(last["opcx_u"], 3), round(last["opcx_pi"], 3)],
-        "roofline": {"bound": "hbm", "kernel": _capi.PROF_KERNELS[dom],
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": _traffic(_capi.PROF_KERNELS[dom], args.n),
-                     "launches": n_l, "avg_launch_us": round(1000.0 * ms_l / max(n_l, 1), 1),
-                     "algorithmic_bytes_per_launch": round(by_l / max(n_l, 1))},
-        "kernel_share_last_warmup": {_capi.PROF_KERNELS[k]: {"launches": v[0], "ms": round(v[1], 2),
-                                                              "GB/s": round(v[2] / 1e6 / v[1], 1) if v[1] else 0}
-                                     for k, v in totals.items()},
+        "roofline": head,
+        "kernels_last_warmup": sorted((_roofline(k, *v) for k, v in totals.items() if v[0] > 0),
+                                      key=lambda e: -e["ms"]),
     }
 
     if not args.no_fp64:
@@ -402,9 +426,99 @@ def main():
         s64.close()
     s.close()
 
+    if not args.no_legs:
+        out["other_configs"] = _legs(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(args.cpu_sample, out["config"]["unknowns"])
     print(json.dumps(out), flush=True)
+
+
+def _roofline(kid, n, ms, by, fl):
+    """Roofline entry of one instrumented kernel from its recorded launches:
+    against the vector ALU peak when the launches carry stencil flops (the
+    matrix-free lattice kernels), else against the HBM peak with the
+    algorithmic bytes."""
+    from paper_2002_09603_amd import _capi
+
+    label, role = _capi.PROF_KERNELS[kid]
+    e = {"kernel": label, "role": role, "launches": n, "ms": round(ms, 3),
+         "avg_launch_us": round(1000.0 * ms / max(n, 1), 1),
+         "algorithmic_bytes_per_launch": round(by / max(n, 1))}
+    if ms <= 0:
+        return e
+    if fl > 0:
+        ach = fl / (ms / 1e3) / 1e12
+        e.update({"bound": "alu", "achieved": round(ach, 2), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                  "frac": round(ach / ALU_PEAK_TFLOPS, 4), "flops_per_launch": round(fl / max(n, 1)),
+                  "hbm_GB_s": round(by / 1e6 / ms, 1)})
+    else:
+        ach = by / 1e6 / ms
+        e.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(ach / HBM_PEAK_GBS, 4)})
+    return e
+
+
+def _legs(dev):
+    """The other single-GPU workloads, measured after the benchmark: the 64^3
+    cube (log-normal kappa sigma 2, nu 0.3) with S_eps 0 and 1e-4 and the
+    perturbed 96^3 mesh (general hexahedra: assembled sliced-ELL A_uu, full
+    6x6 M_T^-1) with its adjoint solve and gradient, all in FP64 (FP64 AMG,
+    FP64 FGMRES(24), one Gram-Schmidt pass, relative residual 1e-8).  Each is
+    timed on a second step after a warm-up step; the per-kernel table comes
+    from the timed step."""
+    import torch
+
+    from paper_2002_09603_amd import _capi
+    from paper_2002_09603_amd.solver import Options, from_problem
+    from synth import make_config
+
+    legs = {}
+    runs = [("cube64_S0", make_config("cube64", S_eps=0.0)), ("cube64_S1e-4", make_config("cube64", S_eps=1e-4)),
+            ("perturbed96", make_config("perturbed96"))]
+    all_mask = sum(1 << k for k in _capi.PROF_KERNELS)
+    for name, prob in runs:
+        s = from_problem(prob, Options(rtol=1e-8, precond_fp32=False, restart=24, max_it=1000, orth_passes=1,
+                                       cheb_degree_pi=1, cheb_lower_pi=0.1, rtol_transpose=1e-8), device=dev)
+        b = torch.empty(s.N, dtype=torch.float64, device=dev)
+        for rep in range(2):
+            if rep == 1:
+                s.profile_begin(all_mask)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.assemble()
+            s.build_rhs(out=b)
+            u, pi, p, info = s.solve(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        totals = {k: s.profile_end(k) for k in _capi.PROF_KERNELS}
+        s.profile_begin(0)
+        i = s.info()
+        rec = {"unknowns": s.N, "time_to_solution_s": round(t, 4), "iterations": info["iters"],
+               "relres_true": info["relres_true"], "t_asm_s": round(info["t_asm"], 4),
+               "t_setup_s": round(info["t_setup"], 4), "t_solve_s": round(info["t_solve"], 4),
+               "lattice_uu": bool(i["lattice_uu"]), "block_minv": bool(i["block_minv"]),
+               "amg_levels": [i["levels_u"], i["levels_pi"]]}
+        solve_ids = [k for k, (_, role) in _capi.PROF_KERNELS.items() if role == "solve" and totals[k][0] > 0]
+        dom = max(solve_ids, key=lambda k: totals[k][1])
+        rec["roofline_dominant_solve_kernel"] = _roofline(dom, *totals[dom])
+        rec["kernels"] = sorted((_roofline(k, *v) for k, v in totals.items() if v[0] > 0), key=lambda e: -e["ms"])
+        if name == "perturbed96":
+            # adjoint of the loss sum of squared pressure at the observation cells
+            obs = torch.as_tensor(prob.obs_cells, device=dev)
+            g = torch.zeros(s.N, dtype=torch.float64, device=dev)
+            g[s.n_u + obs] = 2.0 * p[obs]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lu, lpi, lp, ia = s.solve_transpose(g)
+            dk, dE = s.grad(torch.cat([lu, lp, lpi]), torch.cat([u, p, pi]))
+            torch.cuda.synchronize()
+            rec["adjoint"] = {"time_s": round(time.perf_counter() - t0, 4), "iterations": ia["iters"],
+                              "relres_true": ia["relres_true"]}
+        print(f"   [{name}] {json.dumps({k: v for k, v in rec.items() if k != 'kernels'})}", file=sys.stderr,
+              flush=True)
+        legs[name] = rec
+        s.close()
+    return legs
 
 
 if __name__ == "__main__":

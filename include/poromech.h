@@ -133,11 +133,14 @@ typedef struct {
                                 diagonals: axis-aligned boxes, diagonal permeability), apply
                                 M_T^-1 and C~_T in the solve from the 9 block entries, leaving
                                 the rounding-level rest out; 0: always the full 6x6 matrices */
-  int32_t rbm_u;             /* 1: the A_uu hierarchy's finest tentative prolongator spans the six
-                                rigid-body modes of each aggregate (translations and rotations
-                                about its centroid, orthonormalised; two 3x3 coarse block rows
-                                per aggregate, no prolongator truncation on that level);
-                                0: translations only */
+  int32_t rbm_u;             /* 1: the A_uu hierarchy's tentative prolongators span the six
+                                rigid-body modes of each aggregate on every level (a translation
+                                and a rotation about the aggregate's centroid: two 3x3 coarse
+                                block rows per aggregate, not orthonormalised, so the coarse
+                                near kernel stays the unit vectors); prolongator truncation
+                                compares translation and rotation blocks each with its own kind
+                                and does not rescale (the M_III^(h) variant of Sec. 5);
+                                0: translations only (M_II^(h)) */
 } pm_opts;
 
 typedef struct {
@@ -145,7 +148,12 @@ typedef struct {
   int32_t levels_u, levels_pi;
   double relres_est;         /* Givens residual estimate / ||b|| */
   double relres_true;        /* ||b - A x|| / ||b|| recomputed in FP64 */
-  double t_asm, t_setup, t_solve;   /* seconds: assembly, AMG + B~/C~ setup, Krylov solve */
+  double t_asm, t_setup, t_solve;   /* seconds: assembly (element kernels, condensation,
+                                       stabilization, Dirichlet rows and the A_uu values: the
+                                       kernel time of the value fill, which overlaps the C~_pi
+                                       set-up), preconditioner set-up (B~_p, C~_pi, both AMG
+                                       hierarchies: the rest of the wall time; T_p of Sec. 5),
+                                       Krylov solve (T_s of Sec. 5) */
   double opcx_u, opcx_pi;    /* AMG operator complexities */
   int32_t lattice_uu;        /* 1 if the finest A_uu level runs on the lattice operator */
   int32_t block_minv;        /* 1 if M_T^-1 is stored and applied by direction blocks */
@@ -178,8 +186,10 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
  * hierarchies.  Fails with PM_EINVAL on an inverted hexahedron. */
 int pm_assemble(pm_ctx* ctx);
 
-/* Change dt: rebuilds the dt-dependent blocks, B~_p, C~_pi and the C~_pi
- * hierarchy; the A_uu hierarchy is reused. */
+/* Change dt (backward Euler, Sec. 2.1: dt scales the condensed pressure
+ * block Abar_pp and the coupling dt A_ppi of eq. stab_A): rebuilds the
+ * dt-dependent blocks, B~_p (eq. app_Bp), C~_pi (Sec. 4) and the C~_pi
+ * hierarchy; the A_uu hierarchy, independent of dt, is reused.  dt > 0. */
 int pm_set_dt(pm_ctx* ctx, double dt);
 
 /* Replace E (n_cells) and/or kappa (n_cells x 3) (host or device; NULL keeps
@@ -193,9 +203,14 @@ int pm_update_material(pm_ctx* ctx, const double* E, const double* kappa);
  * b device, N = n_u + n_p + n_pi. */
 int pm_build_rhs(pm_ctx* ctx, const double* u_prev, const double* p_prev, double* b);
 
-/* Solve A_H x = b (device b, N).  Zero initial guess.  Outputs (device,
- * caller-owned): u (n_u), pi (n_pi), p (n_p); any may be NULL.  info may be
- * NULL.  Returns PM_ENOCONV if max_it is reached (outputs = last iterate). */
+/* Solve A_H x = b (eq. stab_A; device b, N) by flexible GMRES with the block
+ * upper triangular preconditioner of eq. hybridPrec applied by back
+ * substitution pi -> p -> u (C~_pi V-cycle, B~_p^-1, A_uu V-cycle), zero
+ * initial guess, stopping at ||b - A x|| <= rtol ||b|| on the recomputed FP64
+ * residual (the solver settings of Sec. 5).  Outputs (device, caller-owned):
+ * u (n_u), pi (n_pi), p (n_p); any may be NULL.  info may be NULL.  Returns
+ * PM_ENOCONV if max_it is reached (outputs = last iterate), PM_EBREAKDOWN on
+ * a non-finite value in the iteration. */
 int pm_solve(pm_ctx* ctx, const double* b, double* u, double* pi, double* p, pm_info* info);
 
 /* pm_solve for callers that cannot allocate device memory (code under HIP
@@ -234,9 +249,11 @@ int pm_build_rhs_mfe(pm_ctx* ctx, const double* u_prev, const double* p_prev, do
  * Returns PM_ENOCONV if max_it is reached. */
 int pm_solve_mfe(pm_ctx* ctx, const double* b, double* u, double* q, double* p, pm_info* info);
 
-/* Solve A_H^T lam = g (adjoint) with FGMRES preconditioned by M^T (block
- * lower triangular: forward substitution u -> p -> pi, same V-cycles).
- * g device, N; outputs as in pm_solve. */
+/* Solve A_H^T lam = g (the adjoint of the step: the transposed system of eq.
+ * stab_A) with FGMRES right-preconditioned by M^T, the transpose of eq.
+ * hybridPrec (block lower triangular: forward substitution u -> p -> pi with
+ * the same, symmetric V-cycles), with rtol_transpose, restart_transpose and
+ * orth_passes_transpose.  g device, N; outputs and return codes as pm_solve. */
 int pm_solve_transpose(pm_ctx* ctx, const double* g, double* lu, double* lpi, double* lp,
                        pm_info* info);
 
@@ -304,10 +321,14 @@ int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
  * records and, for every kernel whose bit (1 << id) is set in mask, records a
  * pair of HIP events on the launching stream around each later launch, with
  * the algorithmic bytes that launch must move (stored values and indices,
- * each input vector read once, each output written once).  pm_profile_end
- * synchronizes the recorded events and returns, for kernel id, the number of
- * launches, their summed duration (ms) and summed algorithmic bytes; it does
- * not stop the recording (call pm_profile_begin(ctx, 0) for that).  Ids:
+ * each input vector read once, each output written once) and, for the
+ * matrix-free lattice stencils on the finest A_uu level, whose arithmetic
+ * bounds them, the flops of their multiply-adds (576 per node: three rows of
+ * the 24x24 element matrix for each of the 8 cells around it; 0 for the
+ * memory-bound kernels).  pm_profile_end synchronizes the recorded events and
+ * returns, for kernel id, the number of launches, their summed duration (ms),
+ * summed algorithmic bytes and summed flops (flops may be NULL); it does not
+ * stop the recording (call pm_profile_begin(ctx, 0) for that).  Ids:
  *   1 u-rows of A_H (FP64; lattice operator or assembled A_uu, with the coupling)
  *   2 fused Chebyshev smoothing step on the finest A_uu level
  *   3 fused Chebyshev smoothing step on the finest C~_pi level
@@ -315,11 +336,20 @@ int pm_apply(pm_ctx* ctx, int which, const double* x, double* y);
  *   5 FGMRES Gram-Schmidt update of the new basis vector (orthogonalise and
  *     normalise in one pass, or the multi-AXPY of the two-pass variant)
  *   6 restriction from the finest A_uu level
+ *   7 p-rows of A_H
+ *   8 pi-rows of A_H
+ *   9 prolongation onto the finest A_uu level (added to the smoothed iterate)
+ *  10 restriction from the finest C~_pi level
+ *  11 prolongation onto the finest C~_pi level
+ *  12 residual on the finest A_uu level
+ *  13 residual on the finest C~_pi level
  * The recorder is process-wide (one context at a time). */
 enum { PM_PROF_AH_U = 1, PM_PROF_CHEB_U0 = 2, PM_PROF_CHEB_PI0 = 3, PM_PROF_MULTIDOT = 4,
-       PM_PROF_MULTIAXPY = 5, PM_PROF_RESTRICT_U0 = 6 };
+       PM_PROF_MULTIAXPY = 5, PM_PROF_RESTRICT_U0 = 6, PM_PROF_AH_P = 7, PM_PROF_AH_PI = 8,
+       PM_PROF_PROLONG_U0 = 9, PM_PROF_RESTRICT_PI0 = 10, PM_PROF_PROLONG_PI0 = 11,
+       PM_PROF_RESID_U0 = 12, PM_PROF_RESID_PI0 = 13 };
 int pm_profile_begin(pm_ctx* ctx, uint32_t mask);
-int pm_profile_end(pm_ctx* ctx, int id, int64_t* launches, double* ms, double* bytes);
+int pm_profile_end(pm_ctx* ctx, int id, int64_t* launches, double* ms, double* bytes, double* flops);
 
 /* Sizes: out[0..5] = n_u, n_p, n_pi, N, n_nodes, n_macro. */
 int pm_sizes(const pm_ctx* ctx, int64_t* out);

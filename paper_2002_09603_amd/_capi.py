@@ -19,11 +19,23 @@ PM_OP_AH, PM_OP_AHT, PM_OP_MINV, PM_OP_MINVT, PM_OP_CPI, PM_OP_BP, PM_OP_AUU, \
     PM_OP_VCYCLE_U, PM_OP_VCYCLE_PI, PM_OP_MFE, PM_OP_CP, \
     PM_OP_VCYCLE_CP, PM_OP_BTP = range(13)
 
-PROF_KERNELS = {1: "k_lat_ah_u|k_ah_u (u-rows of A_H, FP64)",
-                2: "k_lat_cheb|k_cheb_step<3> (Chebyshev step, finest A_uu level)",
-                3: "k_cp_cheb|k_cheb_step<1> (Chebyshev step, finest C~pi level)", 4: "k_multidot",
-                5: "k_orth_normalize_n<NG>|k_orth_normalize|k_multiaxpy (Gram-Schmidt update of the new basis vector)",
-                6: "k_residual_csr<3,float|double,16,false> (restriction from the finest A_uu level)"}
+# kernel ids of pm_profile_begin / pm_profile_end: (label, role); role "solve"
+# marks the operator, smoother and transfer kernels of the preconditioned
+# operator (SpMV and V-cycle), "krylov" the Gram-Schmidt kernels of FGMRES
+PROF_KERNELS = {1: ("k_lat_ah_u|k_ah_u (u-rows of A_H, FP64)", "solve"),
+                2: ("k_lat_cheb|k_cheb_step<3> (Chebyshev step, finest A_uu level)", "solve"),
+                3: ("k_cp_cheb|k_cheb_step<1> (Chebyshev step, finest C~pi level)", "solve"),
+                4: ("k_multidot (Gram-Schmidt projections)", "krylov"),
+                5: ("k_orth_normalize_n<NG>|k_orth_normalize|k_multiaxpy (Gram-Schmidt update of the new basis vector)",
+                    "krylov"),
+                6: ("k_residual_csr<3> (restriction from the finest A_uu level)", "solve"),
+                7: ("k_ah_p (p-rows of A_H)", "solve"),
+                8: ("k_ah_pi_block|k_ah_pi (pi-rows of A_H)", "solve"),
+                9: ("k_sell_apply<3> (prolongation onto the finest A_uu level)", "solve"),
+                10: ("k_residual_csr<1> (restriction from the finest C~pi level)", "solve"),
+                11: ("k_sell_apply<1> (prolongation onto the finest C~pi level)", "solve"),
+                12: ("k_lat_residual (residual on the finest A_uu level)", "solve"),
+                13: ("k_cp_residual (residual on the finest C~pi level)", "solve")}
 
 ERROR_NAMES = {PM_EINVAL: "PM_EINVAL", PM_ENOMEM: "PM_ENOMEM", PM_EHIP: "PM_EHIP",
                PM_ENOCONV: "PM_ENOCONV", PM_EBREAKDOWN: "PM_EBREAKDOWN",
@@ -92,7 +104,7 @@ _SIGS = [
     ("pm_apply", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     ("pm_profile_begin", C.c_int, [C.c_void_p, C.c_uint32]),
     ("pm_profile_end", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
-                                 C.POINTER(C.c_double)]),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("pm_sizes", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("pm_get_info", C.c_int, [C.c_void_p, C.POINTER(pm_info)]),
     ("pm_last_error", C.c_char_p, [C.c_void_p]),

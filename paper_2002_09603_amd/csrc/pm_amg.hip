@@ -1800,9 +1800,10 @@ T* chebyshev(hipStream_t s, const Level& L, const AmgParams& prm, const T* b, T*
       g_prof.end(s, prof_id, (double)G.nc * 21 * sizeof(T) + (double)n * sizeof(T) * 6);
     } else if (BS == 3 && lat) {
       lattice_cheb_step<T>(s, G, *lat, dinv, b, cur, nxt, d, (T)c1, (T)c2);
-      // algorithmic bytes: x/b/d read, x/d written, D^-1 blocks, cell moduli
+      // algorithmic bytes: x/b/d read, x/d written, D^-1 blocks, cell moduli;
+      // flops: 576 stencil multiply-adds per node
       g_prof.end(s, prof_id, (double)n * BS * sizeof(T) * 5 + (double)n * BS * BS * sizeof(T) +
-                                 (double)G.nc * sizeof(T));
+                                 (double)G.nc * sizeof(T), 2.0 * 576 * (double)n);
     } else {
       k_cheb_step<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.perm, L.As.col, val, dinv, b, cur, nxt, d,
                                                             (T)c1, (T)c2);
@@ -1868,9 +1869,15 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
   T* cur = chebyshev<BS, T>(s, L, prm, b, x, t, d, true, AV, DI, prof_id, lat, cpi, H.grid);
   // residual, restriction
   if (lat) {
+    g_prof.begin(s, kProfResidU0);
     lattice_residual<T>(s, H.grid, *lat, b, cur, r);
+    // algorithmic bytes: x, b read, r written, cell moduli; flops: 576 per node
+    g_prof.end(s, kProfResidU0, (double)n * BS * sizeof(T) * 3 + (double)H.grid.nc * sizeof(T), 2.0 * 576 * (double)n);
   } else if (cpi) {
+    g_prof.begin(s, kProfResidPi0);
     cellpi_residual<T>(s, H.grid, *cpi, b, cur, r);
+    // algorithmic bytes: x, b read, r written, the per-cell element matrices
+    g_prof.end(s, kProfResidPi0, (double)n * sizeof(T) * 3 + (double)H.grid.nc * cpi->nvals * sizeof(T));
   } else if (L.csr_cycle) {
     residual_csr<BS, T, true>(s, L.A, L.csr_lanes, AV, b, cur, r);
   } else {
@@ -1878,14 +1885,19 @@ void vcycle_level(hipStream_t s, Hierarchy& H, const AmgParams& prm, int l, cons
     k_residual<BS, T><<<blocks_for(nth), kBlock, 0, s>>>(n, L.As.sptr, L.As.perm, L.As.col, AV, b, cur, r);
   }
   Level& C = H.L[l + 1];
-  const int rprof = (l == 0 && BS == 3) ? kProfRestrictU0 : 0;
+  const int rprof = l == 0 ? (BS == 3 ? kProfRestrictU0 : kProfRestrictPi0) : 0;
   g_prof.begin(s, rprof);
   residual_csr<BS, T, false>(s, L.R, restrict_lanes_for(L.R), LP::CV(L.R), nullptr, r, LP::B(C));
   g_prof.end(s, rprof, (double)L.R.nnzb * (BS * BS * sizeof(T) + 4) + (double)(n + C.n) * BS * sizeof(T));
   vcycle_level<BS, T>(s, H, prm, l + 1, LP::B(C), LP::X(C));
   const int pth = L.P.nslices * kSlice;
+  const int pprof = l == 0 ? (BS == 3 ? kProfProlongU0 : kProfProlongPi0) : 0;
+  g_prof.begin(s, pprof);
   k_sell_apply<BS, T, true><<<blocks_for(pth), kBlock, 0, s>>>(L.P.n, L.P.sptr, L.P.perm, L.P.col, LP::AV(L.P),
                                                                 LP::X(C), cur);
+  // algorithmic bytes: P blocks and column ids, coarse x read, fine x read and written
+  g_prof.end(s, pprof, (double)L.P.nnzb * (BS * BS * sizeof(T) + 4) + (double)C.n * BS * sizeof(T) +
+                           2.0 * n * BS * sizeof(T));
   PM_CHECK_LAUNCH();
   // post-smoothing from the corrected iterate
   T* other = (cur == x) ? t : x;

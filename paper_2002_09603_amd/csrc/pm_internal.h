@@ -50,23 +50,35 @@ enum ProfKernel : int {
   kProfMultidot = 4,     // FGMRES multi-dot (Gram-Schmidt projections)
   kProfMultiaxpy = 5,    // FGMRES Gram-Schmidt update (orthogonalise + normalise, or multi-AXPY)
   kProfRestrictU0 = 6,   // restriction from the finest A_uu level
-  kProfCount = 7
+  kProfAHp = 7,          // p-rows of A_H
+  kProfAHpi = 8,         // pi-rows of A_H
+  kProfProlongU0 = 9,    // prolongation onto the finest A_uu level
+  kProfRestrictPi0 = 10, // restriction from the finest C~_pi level
+  kProfProlongPi0 = 11,  // prolongation onto the finest C~_pi level
+  kProfResidU0 = 12,     // residual on the finest A_uu level
+  kProfResidPi0 = 13,    // residual on the finest C~_pi level
+  kProfCount = 14
 };
 
+// Per launch: algorithmic bytes (stored values and indices, each input vector
+// read once, each output written once) and, for the matrix-free lattice
+// stencils, whose arithmetic bounds them, the multiply-add flops (2 per
+// multiply-add of the stencil; 0 for memory-bound kernels).
 struct Profiler {
   unsigned mask = 0;
   struct Rec {
     hipEvent_t a = nullptr, b = nullptr;
     double bytes = 0.0;
+    double flops = 0.0;
   };
   std::vector<Rec> recs[kProfCount];
   size_t used[kProfCount] = {0};
   bool on(int k) const { return (mask >> k) & 1u; }
   void begin(hipStream_t s, int k);
-  void end(hipStream_t s, int k, double bytes);
+  void end(hipStream_t s, int k, double bytes, double flops = 0.0);
   void reset(unsigned m);
   // sums over recorded launches of kernel k (synchronizes the events)
-  void collect(int k, int64_t* n, double* ms, double* bytes);
+  void collect(int k, int64_t* n, double* ms, double* bytes, double* flops);
 };
 extern Profiler g_prof;
 
@@ -269,6 +281,7 @@ struct pm_ctx {
   double* mfe_work = nullptr;  // 3 n_pi + n_p + 256: A_qq sweep vectors, C~_p right-hand side, set-up maxima
   bool assembled = false;
   bool hier_u_ok = false;
+  double fill_s = 0.0;       // kernel time of the last A_uu value fill (booked as assembly)
   // Krylov workspace
   int m_alloc = 0;
   int64_t ld = 0;            // distance between consecutive Krylov vectors (N rounded up to 32)

@@ -473,8 +473,10 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
   g_prof.begin(c->s, kProfAHu);
   if (c->lat.on) {
     lattice_ah_u<T>(c->s, G, c->lat, u, p, transpose ? -1.0 : 1.0, yu);
-    // algorithmic bytes: u read, y_u written, p and E read
-    g_prof.end(c->s, kProfAHu, (double)c->n_u * (sizeof(T) + 8) + (double)c->nc * (sizeof(T) + 8));
+    // algorithmic bytes: u read, y_u written, p and E read; flops: 576 stencil
+    // and 24 coupling multiply-adds per node
+    g_prof.end(c->s, kProfAHu, (double)c->n_u * (sizeof(T) + 8) + (double)c->nc * (sizeof(T) + 8),
+               2.0 * (576 + 24) * (double)G.nn);
   } else {
     if constexpr (sizeof(T) == 8) {
       const Sell& Auu = c->Hu.L[0].As;
@@ -490,6 +492,7 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
     }
   }
   const double su = transpose ? 1.0 : -1.0, spi = transpose ? 1.0 : c->dt;
+  g_prof.begin(c->s, kProfAHp);
   if (c->lat.on)
     k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->bc_kind, AeLattice{c->lat.ah}, c->vol, c->alpha, c->g,
                                                      c->stabw, u, p, pi, c->S, c->dt, c->opts.stabilize, su, spi,
@@ -498,10 +501,20 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
     k_ah_p<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->bc_kind, AeCells{c->ae, G.nc}, c->vol, c->alpha, c->g,
                                                      c->stabw, u, p, pi, c->S, c->dt, c->opts.stabilize, su, spi,
                                                      yp);
+  // algorithmic bytes: u, p, pi read, y_p written, |T|, alpha_T, g_T (and a_T
+  // off lattices) per cell, beta_M |M| per macro-element
+  g_prof.end(c->s, kProfAHp,
+             (double)(c->n_u + c->n_p + c->n_pi) * sizeof(T) + 8.0 * c->n_p +
+                 (double)G.nc * 8 * (8 + (c->lat.on ? 0 : 24)) + 8.0 * c->nmacro);
+  g_prof.begin(c->s, kProfAHpi);
   if (c->mblock)
     k_ah_pi_block<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Mb, p, pi, transpose ? c->dt : 1.0, ypi);
   else
     k_ah_pi<T><<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->Mp, c->g, p, pi, transpose ? c->dt : 1.0, ypi);
+  // algorithmic bytes: p, pi read, y_pi written, the per-cell matrix entries
+  // (9 direction-block entries, or 21 packed M_T^-1 entries and g_T)
+  g_prof.end(c->s, kProfAHpi,
+             (double)(c->n_p + c->n_pi) * sizeof(T) + 8.0 * c->n_pi + (double)G.nc * 8 * (c->mblock ? 9 : 27));
   PM_CHECK_LAUNCH();
 }
 

@@ -142,11 +142,12 @@ void Profiler::begin(hipStream_t s, int k) {
   PM_HIP(hipEventRecord(v[used[k]].a, s));
 }
 
-void Profiler::end(hipStream_t s, int k, double bytes) {
+void Profiler::end(hipStream_t s, int k, double bytes, double flops) {
   if (!on(k)) return;
   Rec& r = recs[k][used[k]];
   PM_HIP(hipEventRecord(r.b, s));
   r.bytes = bytes;
+  r.flops = flops;
   ++used[k];
 }
 
@@ -155,18 +156,20 @@ void Profiler::reset(unsigned m) {
   for (int k = 0; k < kProfCount; ++k) used[k] = 0;
 }
 
-void Profiler::collect(int k, int64_t* n, double* ms, double* bytes) {
-  double t = 0.0, b = 0.0;
+void Profiler::collect(int k, int64_t* n, double* ms, double* bytes, double* flops) {
+  double t = 0.0, b = 0.0, f = 0.0;
   for (size_t i = 0; i < used[k]; ++i) {
     PM_HIP(hipEventSynchronize(recs[k][i].b));
     float e = 0.0f;
     PM_HIP(hipEventElapsedTime(&e, recs[k][i].a, recs[k][i].b));
     t += e;
     b += recs[k][i].bytes;
+    f += recs[k][i].flops;
   }
   *n = (int64_t)used[k];
   *ms = t;
   *bytes = b;
+  *flops = f;
 }
 
 void Csr::free_all() {

@@ -293,9 +293,11 @@ class PoroSolver:
         check(lib.pm_profile_begin(self._ctx, int(mask)), self._ctx)
 
     def profile_end(self, kernel_id):
-        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
-        check(lib.pm_profile_end(self._ctx, int(kernel_id), C.byref(n), C.byref(ms), C.byref(by)), self._ctx)
-        return int(n.value), float(ms.value), float(by.value)
+        """(launches, summed ms, summed algorithmic bytes, summed stencil flops) of one kernel id."""
+        n, ms, by, fl = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        check(lib.pm_profile_end(self._ctx, int(kernel_id), C.byref(n), C.byref(ms), C.byref(by), C.byref(fl)),
+              self._ctx)
+        return int(n.value), float(ms.value), float(by.value), float(fl.value)
 
     def info(self):
         i = _capi.pm_info()
