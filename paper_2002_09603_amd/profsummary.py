@@ -10,6 +10,7 @@ the finest-level launches can be compared with the per-launch figures that
     python -m paper_2002_09603_amd.profsummary pmc DIR --copy-regex neg_kernel \
         --copy-bytes 1073741824 [--match k_cheb_step]
 
+``counters`` tabulates any counters of a ``--pmc`` run per kernel and grid.
 ``trace`` reads ``*kernel_trace.csv`` (from ``--kernel-trace``), ``pmc`` reads
 ``*counter_collection.csv`` (from ``--pmc FETCH_SIZE`` or ``--pmc
 WRITE_SIZE``).  For ``pmc`` the counter of the largest dispatch matching
@@ -112,6 +113,46 @@ def pmc(d, copy_regex, copy_bytes, match=None):
     print(f"\nsources_sha256 {sources_sha256()}")
 
 
+def counters(d, match=None):
+    """Per (kernel, grid): the average of every collected counter per
+    dispatch, and the ratios used for the stencil kernels: VALU instructions
+    and issue cycles per wave, the share of a wave's lifetime spent issuing
+    VALU instructions, and the mean number of resident waves per busy CU."""
+    per = defaultdict(lambda: defaultdict(lambda: defaultdict(float)))  # key -> counter -> dispatch -> value
+    for fn in _files(d, "counter_collection.csv"):
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                key = (short_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+                per[key][r["Counter_Name"]][(fn, r["Dispatch_Id"])] += float(r["Counter_Value"])
+    rows = sorted(per.items(), key=lambda kv: kv[0])
+    if match:
+        rows = [kv for kv in rows if re.search(match, kv[0][0])]
+    names = sorted({c for _, cs in rows for c in cs})
+    print("| kernel | grid | " + " | ".join(names) + " |")
+    print("|---|---:|" + "---:|" * len(names))
+    avg = {}
+    for key, cs in rows:
+        a = {c: sum(v.values()) / len(v) for c, v in cs.items()}
+        avg[key] = a
+        print(f"| `{key[0]}` | {key[1]} | " + " | ".join(f"{a.get(c, float('nan')):.4g}" for c in names) + " |")
+    print()
+    for key, a in avg.items():
+        w = a.get("SQ_WAVES")
+        out = []
+        if w:
+            if "SQ_INSTS_VALU" in a:
+                out.append(f"VALU instructions per wave {a['SQ_INSTS_VALU'] / w:.0f}")
+            if "SQ_ACTIVE_INST_VALU" in a and "SQ_WAVE_CYCLES" in a and a["SQ_WAVE_CYCLES"] > 0:
+                out.append(f"VALU issue share of wave lifetime {a['SQ_ACTIVE_INST_VALU'] / a['SQ_WAVE_CYCLES']:.3f}")
+            if "SQ_WAVE_CYCLES" in a:
+                out.append(f"wave lifetime {a['SQ_WAVE_CYCLES'] / w:.0f} cycles")
+        if "SQ_LEVEL_WAVES" in a and a.get("SQ_BUSY_CU_CYCLES"):
+            out.append(f"resident waves per busy CU {a['SQ_LEVEL_WAVES'] / a['SQ_BUSY_CU_CYCLES']:.1f}")
+        if out:
+            print(f"* `{key[0]}` grid {key[1]}: " + "; ".join(out))
+    print(f"\nsources_sha256 {sources_sha256()}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="group rocprofv3 CSV output by kernel and grid size")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -124,12 +165,17 @@ def main(argv=None):
     p.add_argument("--copy-regex", required=True)
     p.add_argument("--copy-bytes", type=int, required=True)
     p.add_argument("--match")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--match")
     sub.add_parser("sources")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         trace(a.dir, a.top, a.match)
     elif a.cmd == "pmc":
         pmc(a.dir, a.copy_regex, a.copy_bytes, a.match)
+    elif a.cmd == "counters":
+        counters(a.dir, a.match)
     else:
         print(sources_sha256())
 
