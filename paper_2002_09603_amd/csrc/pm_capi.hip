@@ -385,7 +385,8 @@ int pm_setup(const pm_mesh* mesh, const pm_material* mat, const pm_bc* bc, doubl
     copy_in(c, c->kappa, mat->kappa, 3 * c->nc);
     check_positive(c, c->E, c->nc, "E");
     check_positive(c, c->kappa, 3 * c->nc, "kappa");
-    if (c->opts.lattice_uu && c->nn < (int64_t)INT32_MAX) {
+    // the lattice kernels address neighbours by 32-bit byte offsets
+    if (c->opts.lattice_uu && 3 * c->nn * (int64_t)sizeof(double) < (int64_t)UINT32_MAX) {
       double dev = 0.0, hmin = 0.0;
       pm::lattice_deviation(c->s, pm::grid_of(c), c->coords, &dev, &hmin);
       c->lattice = dev <= 1e-12 * hmin;

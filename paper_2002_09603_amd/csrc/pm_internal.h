@@ -170,6 +170,12 @@ struct LatticeOp {
   double* ah = nullptr;       // 24 coupling column
   const double* E = nullptr;  // n_c moduli (context-owned)
   float* E32 = nullptr;       // FP32 copy for mixed precision
+  // Box cells (mirror-symmetric in each axis): Khat is fixed by the 8 blocks
+  // Khat[0][d], each symmetric up to signs, 48 values in all, passed to the
+  // stencil kernels by value (kept in scalar registers)
+  bool sym = false;
+  double ks64[48] = {};
+  float ks32[48] = {};
   void free_all();
 };
 

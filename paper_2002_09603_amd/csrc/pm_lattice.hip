@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "pm_internal.h"
 
@@ -31,6 +32,22 @@ void LatticeOp::free_all() {
   E32 = nullptr;
   E = nullptr;
   on = false;
+  sym = false;
+}
+
+// Mirror symmetry of a box cell: reflecting across the mid-plane normal to
+// axis r maps corner a to a ^ (1 << r) and flips the r-th displacement
+// component, so Khat[a][b](r,c) = s_r(a) s_c(a) Khat[0][a^b](r,c) with
+// s_r(a) = -1 when bit r of a is set; with Khat symmetric, Khat[0][d](r,c) =
+// s_r(d) s_c(d) Khat[0][d](c,r).  ks[6d + q] holds Khat[0][d](r,c) for
+// r <= c in the order (0,0) (1,1) (2,2) (0,1) (0,2) (1,2).
+__host__ __device__ constexpr int sym_slot(int r, int c) {
+  return r == c ? r : ((r < c ? r : c) == 0 ? 2 + (r < c ? c : r) : 5);
+}
+__host__ __device__ constexpr bool sym_negated(int a, int b, int r, int c) {
+  const int d = a ^ b;
+  const bool n = ((a >> r) ^ (a >> c)) & 1;
+  return (r > c && (((d >> r) ^ (d >> c)) & 1)) ? !n : n;
 }
 
 namespace {
@@ -49,37 +66,64 @@ __device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j,
   return true;
 }
 
-// The clamped 3x3x3 node box and 2x2x2 cell box around node (i,j,k), as one
-// 64-bit base (the lower corner) plus non-negative 32-bit offsets per axis.
-// A neighbour outside the mesh is clamped onto the node itself; it only
-// belongs to cells outside the mesh, whose modulus is taken as zero.
-struct Box {
-  uint32_t nxo[3], nyo[3], nzo[3];  // node offsets (in nodes) of the lower/middle/upper neighbour
-  uint32_t cxo, cyo, czo;           // cell offset of the upper cell along each axis
-  bool inx[2], iny[2], inz[2];      // lower/upper cell inside the mesh
-  int64_t n0, c0;                   // lower-corner node and cell
+// The clamped 3x3x3 node box and 2x2x2 cell box around node (i,j,k): the
+// lower-corner node and cell plus non-negative offsets per axis, all in 32
+// bits (the lattice is used only while 3 n_n doubles stay below 4 GiB), so a
+// neighbour is addressed as the kernel's base pointer plus one 32-bit byte
+// offset.  A neighbour outside the mesh is clamped onto the node itself; it
+// only belongs to cells outside the mesh, whose modulus is taken as zero.
+// explicit fused multiply-add: with entries of Khat repeated (box cells) the
+// compiler would otherwise share products between sums and split the FMAs
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// The 24x24 unit stiffness as read by the stencil: KDense reads all 576
+// entries, KSym rebuilds them from the 48 values of a box cell.
+template <class T>
+struct KDense {
+  const T* __restrict__ p;
+  __device__ __forceinline__ T operator()(int a, int b, int r, int c) const { return p[(3 * a + r) * 24 + 3 * b + c]; }
+};
+template <class T>
+struct KSym {
+  T k[48];
+  __device__ __forceinline__ T operator()(int a, int b, int r, int c) const {
+    const T v = k[6 * (a ^ b) + sym_slot(r, c)];
+    return sym_negated(a, b, r, c) ? -v : v;
+  }
 };
 
+struct Box {
+  uint32_t nxo[3], nyo[3], nzo[3];  // byte offsets of the lower/middle/upper neighbour node
+  uint32_t cxo, cyo, czo;           // cell offset of the upper cell along each axis
+  bool inx[2], iny[2], inz[2];      // lower/upper cell inside the mesh
+  uint32_t n0, c0;                  // lower-corner node (byte offset) and cell (index)
+};
+
+// node offsets in bytes for vectors of TX (3 per node); the strides are
+// wave-uniform, so each offset is a select rather than a multiply
+template <class TX>
 __device__ __forceinline__ Box box_of(const Grid& G, int64_t n, int i, int j, int k) {
+  constexpr uint32_t kNode = 3 * sizeof(TX);
   Box B;
-  const uint32_t sy = (uint32_t)G.nx + 1, sz = sy * ((uint32_t)G.ny + 1);
-  const uint32_t lx = i > 0, ly = j > 0, lz = k > 0;
-  const uint32_t hx = i < G.nx, hy = j < G.ny, hz = k < G.nz;
+  const uint32_t sy = ((uint32_t)G.nx + 1) * kNode, sz = sy * ((uint32_t)G.ny + 1);
+  const bool lx = i > 0, ly = j > 0, lz = k > 0;
+  const bool hx = i < G.nx, hy = j < G.ny, hz = k < G.nz;
   B.nxo[0] = 0;
-  B.nxo[1] = lx;
-  B.nxo[2] = lx + hx;
+  B.nxo[1] = lx ? kNode : 0u;
+  B.nxo[2] = B.nxo[1] + (hx ? kNode : 0u);
   B.nyo[0] = 0;
-  B.nyo[1] = ly * sy;
-  B.nyo[2] = (ly + hy) * sy;
+  B.nyo[1] = ly ? sy : 0u;
+  B.nyo[2] = B.nyo[1] + (hy ? sy : 0u);
   B.nzo[0] = 0;
-  B.nzo[1] = lz * sz;
-  B.nzo[2] = (lz + hz) * sz;
-  B.n0 = n - (int64_t)(B.nxo[1] + B.nyo[1] + B.nzo[1]);
+  B.nzo[1] = lz ? sz : 0u;
+  B.nzo[2] = B.nzo[1] + (hz ? sz : 0u);
+  B.n0 = (uint32_t)n * kNode - (B.nxo[1] + B.nyo[1] + B.nzo[1]);
   // cells i-1 and i along x, clamped into [0, nx-1] (nx >= 1)
-  B.cxo = lx + hx - 1;
-  B.cyo = (ly + hy - 1) * (uint32_t)G.nx;
-  B.czo = (lz + hz - 1) * (uint32_t)G.nx * (uint32_t)G.ny;
-  B.c0 = G.cell(i - (int)lx, j - (int)ly, k - (int)lz);
+  B.cxo = (lx && hx) ? 1u : 0u;
+  B.cyo = (ly && hy) ? (uint32_t)G.nx : 0u;
+  B.czo = (lz && hz) ? (uint32_t)G.nx * (uint32_t)G.ny : 0u;
+  B.c0 = (uint32_t)G.cell(i - (int)lx, j - (int)ly, k - (int)lz);
   B.inx[0] = lx;
   B.inx[1] = hx;
   B.iny[0] = ly;
@@ -89,35 +133,45 @@ __device__ __forceinline__ Box box_of(const Grid& G, int64_t n, int i, int j, in
   return B;
 }
 
+// a 32-bit byte offset from a wave-uniform base (one VGPR offset per load
+// instead of a 64-bit address; constant offsets from it become immediates)
+template <class V>
+__device__ __forceinline__ const V* at_byte(const V* __restrict__ base, uint32_t off) {
+  return reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
+}
+
 // One plane dz of the 3x3 neighbour displacements of node (i,j,k).  MASK
 // zeroes Dirichlet components (zero columns of A_uu).
 template <class T, class TX, bool MASK>
-__device__ __forceinline__ void load_plane(const Grid& G, int kind, const TX* __restrict__ xb, const Box& B, int dz,
+__device__ __forceinline__ void load_plane(const Grid& G, int kind, const TX* __restrict__ x, const Box& B, int dz,
                                            int i, int j, int k, T u[9][3]) {
 #pragma unroll
-  for (int dy = 0; dy < 3; ++dy)
+  for (int dy = 0; dy < 3; ++dy) {
+    const uint32_t row = B.n0 + B.nyo[dy] + B.nzo[dz];
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      const TX* q = xb + 3 * (B.nxo[dx] + B.nyo[dy] + B.nzo[dz]);
+      const uint32_t off = row + B.nxo[dx];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T v = (T)q[c];
+        const T v = (T)at_byte(x, off)[c];
         u[dx + 3 * dy][c] = (MASK && u_fixed(G, kind, i + dx - 1, j + dy - 1, k + dz - 1, c)) ? (T)0 : v;
       }
     }
+  }
 }
 
 // acc += contributions of the 4 cells of layer oz around the node; lo and hi
 // are the neighbour planes below and above that cell layer
-template <class T>
-__device__ __forceinline__ void cell_layer(const T* __restrict__ Kh, const T* __restrict__ Eb, const Box& B,
+template <class T, class KS>
+__device__ __forceinline__ void cell_layer(const KS& Kh, const T* __restrict__ E, const Box& B,
                                            const T lo[9][3], const T hi[9][3], int oz, T acc[3]) {
 #pragma unroll
   for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
     for (int ox = 0; ox < 2; ++ox) {
       const bool in = B.inz[oz] && B.iny[oy] && B.inx[ox];
-      const T ev = Eb[(ox ? B.cxo : 0u) + (oy ? B.cyo : 0u) + (oz ? B.czo : 0u)];
+      const T ev = *at_byte(E, (B.c0 + (ox ? B.cxo : 0u) + (oy ? B.cyo : 0u) + (oz ? B.czo : 0u)) *
+                                  (uint32_t)sizeof(T));
       const T e = in ? ev : (T)0;
       const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
 #pragma unroll
@@ -129,7 +183,7 @@ __device__ __forceinline__ void cell_layer(const T* __restrict__ Kh, const T* __
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const T uv = ((b >> 2) & 1) ? hi[q][c] : lo[q][c];
-            sum += Kh[(3 * a + r) * 24 + 3 * b + c] * uv;
+            sum = fmadd(Kh(a, b, r, c), uv, sum);
           }
         }
         acc[r] += e * sum;
@@ -139,19 +193,17 @@ __device__ __forceinline__ void cell_layer(const T* __restrict__ Kh, const T* __
 
 // acc = sum over the cells T around node (i,j,k) of E_T Khat[3a..3a+2, :] u_T,
 // the neighbour planes loaded one at a time
-template <class T, class TX, bool MASK>
-__device__ __forceinline__ void lattice_rows(const Grid& G, int kind, const T* __restrict__ Kh,
+template <class T, class TX, bool MASK, class KS>
+__device__ __forceinline__ void lattice_rows(const Grid& G, int kind, const KS& Kh,
                                              const T* __restrict__ E, const TX* __restrict__ x, const Box& B, int i,
                                              int j, int k, T acc[3]) {
   acc[0] = acc[1] = acc[2] = (T)0;
-  const TX* xb = x + 3 * B.n0;
-  const T* Eb = E + B.c0;
   T pa[9][3], pb[9][3];
-  load_plane<T, TX, MASK>(G, kind, xb, B, 0, i, j, k, pa);
-  load_plane<T, TX, MASK>(G, kind, xb, B, 1, i, j, k, pb);
-  cell_layer<T>(Kh, Eb, B, pa, pb, 0, acc);
-  load_plane<T, TX, MASK>(G, kind, xb, B, 2, i, j, k, pa);
-  cell_layer<T>(Kh, Eb, B, pb, pa, 1, acc);
+  load_plane<T, TX, MASK>(G, kind, x, B, 0, i, j, k, pa);
+  load_plane<T, TX, MASK>(G, kind, x, B, 1, i, j, k, pb);
+  cell_layer<T, KS>(Kh, E, B, pa, pb, 0, acc);
+  load_plane<T, TX, MASK>(G, kind, x, B, 2, i, j, k, pa);
+  cell_layer<T, KS>(Kh, E, B, pb, pa, 1, acc);
 }
 
 // no Dirichlet component among the 27 neighbours of node (i,j,k)
@@ -163,15 +215,15 @@ __device__ inline bool free_neighbourhood(const Grid& G, int kind, int i, int j,
 }
 
 // (A x) at node n: Dirichlet rows are identity
-template <class T>
-__device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const T* __restrict__ Kh,
+template <class T, class KS>
+__device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const KS& Kh,
                                            const T* __restrict__ E, const T* __restrict__ x, int64_t n, int i, int j,
                                            int k, T ax[3]) {
-  const Box B = box_of(G, n, i, j, k);
+  const Box B = box_of<T>(G, n, i, j, k);
   if (free_neighbourhood(G, kind, i, j, k))
-    lattice_rows<T, T, false>(G, kind, Kh, E, x, B, i, j, k, ax);
+    lattice_rows<T, T, false, KS>(G, kind, Kh, E, x, B, i, j, k, ax);
   else
-    lattice_rows<T, T, true>(G, kind, Kh, E, x, B, i, j, k, ax);
+    lattice_rows<T, T, true, KS>(G, kind, Kh, E, x, B, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
     if (u_fixed(G, kind, i, j, k, a)) ax[a] = x[3 * n + a];
@@ -180,12 +232,13 @@ __device__ __forceinline__ void lattice_Ax(const Grid& G, int kind, const T* __r
 // Minimum waves per SIMD for the stencil kernels.  In FP64 the neighbour
 // planes in flight take about 170 vector registers, one over the limit for
 // three resident waves; capping the allocation there costs a few spilled
-// values and runs faster than two waves.
+// values and runs faster than two waves.  In FP32 the cap at 96 registers
+// (five waves) spills a few values and runs about 6% faster than four waves.
 template <class T>
-constexpr int kLatWaves = sizeof(T) == 8 ? 3 : 1;
+constexpr int kLatWaves = sizeof(T) == 8 ? 3 : 5;
 
-template <class T, int KIND>
-__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, const T* __restrict__ Kh,
+template <class T, int KIND, class KS>
+__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, const KS Kh,
                                                   const T* __restrict__ E, const T* __restrict__ dinv,
                                                   const T* __restrict__ b, const T* __restrict__ xin,
                                                   T* __restrict__ xout, T* __restrict__ d, T c1, T c2) {
@@ -193,7 +246,7 @@ __global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, const T*
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   T ax[3];
-  lattice_Ax<T>(G, KIND, Kh, E, xin, n, i, j, k, ax);
+  lattice_Ax<T, KS>(G, KIND, Kh, E, xin, n, i, j, k, ax);
   T res[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) res[a] = b[3 * n + a] - ax[a];
@@ -208,36 +261,36 @@ __global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_cheb(Grid G, const T*
   }
 }
 
-template <class T, int KIND>
-__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_residual(Grid G, const T* __restrict__ Kh,
+template <class T, int KIND, class KS>
+__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_residual(Grid G, const KS Kh,
                                                       const T* __restrict__ E, const T* __restrict__ b,
                                                       const T* __restrict__ x, T* __restrict__ r) {
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   T ax[3];
-  lattice_Ax<T>(G, KIND, Kh, E, x, n, i, j, k, ax);
+  lattice_Ax<T, KS>(G, KIND, Kh, E, x, n, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a) r[3 * n + a] = b[3 * n + a] - ax[a];
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_apply(Grid G, const double* __restrict__ Kh,
+template <int KIND, class KS>
+__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_apply(Grid G, const KS Kh,
                                                    const double* __restrict__ E, const double* __restrict__ x,
                                                    double* __restrict__ y) {
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   double ax[3];
-  lattice_Ax<double>(G, KIND, Kh, E, x, n, i, j, k, ax);
+  lattice_Ax<double, KS>(G, KIND, Kh, E, x, n, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a) y[3 * n + a] = ax[a];
 }
 
 // u-rows of A_H (sgn = +1) or A_H^T (sgn = -1): A_uu u + sgn A_up p on free
 // rows, in FP64 from FP64 or FP32 inputs
-template <class TX, int KIND>
-__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_ah_u(Grid G, const double* __restrict__ Kh,
+template <class TX, int KIND, class KS>
+__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_ah_u(Grid G, const KS Kh,
                                                   const double* __restrict__ ah, const double* __restrict__ E,
                                                   const TX* __restrict__ u, const TX* __restrict__ p, double sgn,
                                                   double* __restrict__ y) {
@@ -246,13 +299,12 @@ __global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_ah_u(Grid G, con
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
   double acc[3];
-  const Box B = box_of(G, n, i, j, k);
+  const Box B = box_of<TX>(G, n, i, j, k);
   if (free_neighbourhood(G, kind, i, j, k))
-    lattice_rows<double, TX, false>(G, kind, Kh, E, u, B, i, j, k, acc);
+    lattice_rows<double, TX, false, KS>(G, kind, Kh, E, u, B, i, j, k, acc);
   else
-    lattice_rows<double, TX, true>(G, kind, Kh, E, u, B, i, j, k, acc);
+    lattice_rows<double, TX, true, KS>(G, kind, Kh, E, u, B, i, j, k, acc);
   double cp[3] = {0.0, 0.0, 0.0};
-  const TX* pb = p + B.c0;
 #pragma unroll
   for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
@@ -260,7 +312,8 @@ __global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_ah_u(Grid G, con
 #pragma unroll
       for (int ox = 0; ox < 2; ++ox) {
         const bool in = B.inz[oz] && B.iny[oy] && B.inx[ox];
-        const double pv = (double)pb[(ox ? B.cxo : 0u) + (oy ? B.cyo : 0u) + (oz ? B.czo : 0u)];
+        const double pv =
+            (double)*at_byte(p, (B.c0 + (ox ? B.cxo : 0u) + (oy ? B.cyo : 0u) + (oz ? B.czo : 0u)) * (uint32_t)sizeof(TX));
         const double pc = in ? pv : 0.0;
         const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
 #pragma unroll
@@ -329,14 +382,34 @@ void with_bc_kind(int kind, F&& f) {
     f(std::integral_constant<int, PM_BC_COLUMN>{});
 }
 
+// The unit stiffness in the form the kernel reads: the FP32 stencils on box
+// cells take the 48 values by value (scalar registers, loaded once per wave);
+// the FP64 stencils read the 576-entry table, since 48 doubles would take
+// nearly all scalar registers and the compiler then spills them to vector
+// lanes.
+template <class T, class F>
+void with_coeffs(const LatticeOp& op, F&& f) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (op.sym) {
+      KSym<float> K;
+      memcpy(K.k, op.ks32, sizeof(K.k));
+      f(K);
+      return;
+    }
+  }
+  f(KDense<T>{lat_K<T>(op)});
+}
+
 }  // namespace
 
 template <class T>
 void lattice_cheb_step(hipStream_t s, const Grid& G, const LatticeOp& op, const T* dinv, const T* b, const T* xin,
                        T* xout, T* d, T c1, T c2) {
   with_bc_kind(op.kind, [&](auto kd) {
-    k_lat_cheb<T, decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, lat_K<T>(op), lat_E<T>(op), dinv, b,
-                                                                         xin, xout, d, c1, c2);
+    with_coeffs<T>(op, [&](auto K) {
+      k_lat_cheb<T, decltype(kd)::value, decltype(K)><<<blocks_for(G.nn), kBlock, 0, s>>>(G, K, lat_E<T>(op), dinv, b,
+                                                                                       xin, xout, d, c1, c2);
+    });
   });
   PM_CHECK_LAUNCH();
 }
@@ -348,8 +421,10 @@ template void lattice_cheb_step<float>(hipStream_t, const Grid&, const LatticeOp
 template <class T>
 void lattice_residual(hipStream_t s, const Grid& G, const LatticeOp& op, const T* b, const T* x, T* r) {
   with_bc_kind(op.kind, [&](auto kd) {
-    k_lat_residual<T, decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, lat_K<T>(op), lat_E<T>(op), b,
-                                                                             x, r);
+    with_coeffs<T>(op, [&](auto K) {
+      k_lat_residual<T, decltype(kd)::value, decltype(K)><<<blocks_for(G.nn), kBlock, 0, s>>>(G, K, lat_E<T>(op), b,
+                                                                                           x, r);
+    });
   });
   PM_CHECK_LAUNCH();
 }
@@ -360,7 +435,9 @@ template void lattice_residual<float>(hipStream_t, const Grid&, const LatticeOp&
 
 void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y) {
   with_bc_kind(op.kind, [&](auto kd) {
-    k_lat_apply<decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.Kh, op.E, x, y);
+    with_coeffs<double>(op, [&](auto K) {
+      k_lat_apply<decltype(kd)::value, decltype(K)><<<blocks_for(G.nn), kBlock, 0, s>>>(G, K, op.E, x, y);
+    });
   });
   PM_CHECK_LAUNCH();
 }
@@ -369,7 +446,10 @@ template <class TX>
 void lattice_ah_u(hipStream_t s, const Grid& G, const LatticeOp& op, const TX* u, const TX* p, double sgn,
                   double* y) {
   with_bc_kind(op.kind, [&](auto kd) {
-    k_lat_ah_u<TX, decltype(kd)::value><<<blocks_for(G.nn), kBlock, 0, s>>>(G, op.Kh, op.ah, op.E, u, p, sgn, y);
+    with_coeffs<double>(op, [&](auto K) {
+      k_lat_ah_u<TX, decltype(kd)::value, decltype(K)><<<blocks_for(G.nn), kBlock, 0, s>>>(G, K, op.ah, op.E, u, p,
+                                                                                          sgn, y);
+    });
   });
   PM_CHECK_LAUNCH();
 }
@@ -408,6 +488,26 @@ void lattice_finish(pm_ctx* c) {
   LatticeOp& op = c->lat;
   op.kind = c->bc_kind;
   op.E = c->E;
+  // box cells: take the 48 values and check that they rebuild every entry
+  double K[576];
+  PM_HIP(hipMemcpyAsync(K, op.Kh, sizeof(K), hipMemcpyDeviceToHost, c->s));
+  PM_HIP(hipStreamSynchronize(c->s));
+  double kmax = 0.0;
+  for (double v : K) kmax = std::max(kmax, std::fabs(v));
+  for (int d = 0; d < 8; ++d)
+    for (int r = 0; r < 3; ++r)
+      for (int q = r; q < 3; ++q) op.ks64[6 * d + sym_slot(r, q)] = K[r * 24 + 3 * d + q];
+  bool sym = kmax > 0.0;
+  for (int a = 0; a < 8 && sym; ++a)
+    for (int b = 0; b < 8; ++b)
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+          const double v = op.ks64[6 * (a ^ b) + sym_slot(r, q)];
+          const double want = sym_negated(a, b, r, q) ? -v : v;
+          if (std::fabs(K[(3 * a + r) * 24 + 3 * b + q] - want) > 1e-13 * kmax) sym = false;
+        }
+  op.sym = sym;
+  for (int i = 0; i < 48; ++i) op.ks32[i] = (float)op.ks64[i];
   if (c->opts.precond_fp32) {
     if (!op.Kh32) op.Kh32 = dalloc<float>(576);
     if (!op.E32) op.E32 = dalloc<float>(c->nc);
