@@ -241,80 +241,116 @@ __global__ void k_auu_count(Grid G, int* __restrict__ cnt) {
 // sum over the cells containing both nodes of K_T[a(n), b(m)], then the
 // Dirichlet identity rows / zero columns.  Blocks are placed in the row in
 // (dk, dj, di) order, so consecutive threads write consecutive blocks.
-// element stiffness sources: per-cell array, or E_T times the lattice matrix
+// Element stiffness sources: K_T[3a+r][3b+s] = scale(T) * unit(a, b, r, s, T).
+//   KeCells:   per-cell matrices, scale 1;
+//   KeLattice: E_T times the 576 entries of the unit-modulus matrix (read
+//              through the cache; staging them in LDS per workgroup is
+//              slower).
+// (On box cells the 48-value form of the unit matrix would make mirror
+// images exactly equal; the A_uu hierarchy's aggregation then breaks its
+// ties differently and the benchmark solve takes 84 FGMRES iterations
+// instead of 81, so the assembled matrix keeps the 576 computed entries.)
 struct KeCells {
   const double* Ke;
   int64_t nc;
-  __device__ double operator()(int row, int col, int64_t c) const { return Ke[((size_t)row * 24 + col) * nc + c]; }
+  __device__ double scale(int64_t) const { return 1.0; }
+  __device__ double unit(int a, int b, int r, int s, int64_t c) const {
+    return Ke[((size_t)(3 * a + r) * 24 + 3 * b + s) * nc + c];
+  }
 };
 struct KeLattice {
   const double* Kh;
   const double* E;
-  __device__ double operator()(int row, int col, int64_t c) const { return E[c] * Kh[row * 24 + col]; }
+  __device__ double scale(int64_t c) const { return E[c]; }
+  __device__ double unit(int a, int b, int r, int s, int64_t) const { return Kh[(3 * a + r) * 24 + 3 * b + s]; }
 };
 
 // A_uu blocks, one thread per (node, neighbour slot), a workgroup per
-// kFillNodes consecutive nodes (27 threads each).  The workgroup's blocks
-// are the contiguous rows rowptr[n0] .. rowptr[n0 + kFillNodes]: each thread
-// sums its 3x3 block over the cells the two nodes share and stages it in LDS,
-// and the workgroup then writes the whole range with consecutive 8-byte
-// stores (a thread's own 72-byte block would make every store instruction
-// touch 64 scattered words).  On lattices the unit-modulus element matrix is
-// read from LDS.
-constexpr int kFillNodes = 16, kFillThreads = 27 * kFillNodes;
+// kFillNodes consecutive nodes (27 threads each).  The workgroup first
+// stages, for each of its nodes, the scale and index of the 8 surrounding
+// cells in LDS; each thread loads its row
+// position and Dirichlet flags before that barrier, then sums its 3x3 block
+// over the shared cells from LDS into an LDS copy of the workgroup's rows,
+// which the workgroup writes out with consecutive 8-byte stores.  Small
+// workgroups (one wave) keep the barriers cheap and the LDS footprint
+// small.  The column indices are written only when col is given (the
+// pattern does not change between assemblies).
+constexpr int kFillNodes = 2, kFillThreads = 27 * kFillNodes;
 
 template <class KS>
 __global__ void __launch_bounds__(kFillThreads) k_auu_fill(Grid G, KS Ke, const uint8_t* __restrict__ ufix,
                                                            const int* __restrict__ rowptr, int* __restrict__ col,
                                                            double* __restrict__ val) {
-  constexpr bool kLat = std::is_same<KS, KeLattice>::value;
-  __shared__ double kh[kLat ? 576 : 1];
+  __shared__ double cw[kFillNodes][8];
+  __shared__ int64_t cid[kFillNodes][8];
   __shared__ double stage[kFillThreads * 9];
   const int n0 = blockIdx.x * kFillNodes;  // < nn (grid = ceil(nn / kFillNodes))
-  if constexpr (kLat)
-    for (int q = threadIdx.x; q < 576; q += kFillThreads) kh[q] = Ke.Kh[q];
   const int base = rowptr[n0];
   const int end = rowptr[min((int64_t)n0 + kFillNodes, G.nn)];
-  __syncthreads();
-  const KS K = [&] {
-    if constexpr (kLat)
-      return KeLattice{kh, Ke.E};
-    else
-      return Ke;
-  }();
+  // the 8 cells around each of the workgroup's nodes, (ox, oy, oz) order:
+  // scale (E_T on lattices, 1 otherwise; 0 outside the grid) and index
+  if (threadIdx.x < 8 * kFillNodes) {
+    const int ln = (int)threadIdx.x >> 3, o = (int)threadIdx.x & 7;
+    const int64_t n = (int64_t)n0 + ln;
+    double w = 0.0;
+    int64_t c = 0;
+    if (n < G.nn) {
+      int i, j, k;
+      G.node_ijk(n, i, j, k);
+      const int ci = i - 1 + (o & 1), cj = j - 1 + ((o >> 1) & 1), ck = k - 1 + (o >> 2);
+      if (ci >= 0 && ci < G.nx && cj >= 0 && cj < G.ny && ck >= 0 && ck < G.nz) {
+        c = G.cell(ci, cj, ck);
+        w = Ke.scale(c);
+      }
+    }
+    cw[ln][o] = w;
+    cid[ln][o] = c;
+  }
   const int ln = (int)threadIdx.x / 27, q = (int)threadIdx.x - 27 * ln;
   const int64_t n = (int64_t)n0 + ln;
   const int di = q % 3 - 1, dj = (q / 3) % 3 - 1, dk = q / 9 - 1;
   int i = 0, j = 0, k = 0;
   if (n < G.nn) G.node_ijk(n, i, j, k);
   const int i2 = i + di, j2 = j + dj, k2 = k + dk;
-  if (n < G.nn && i2 >= 0 && i2 <= G.nx && j2 >= 0 && j2 <= G.ny && k2 >= 0 && k2 <= G.nz) {
+  const bool live = n < G.nn && i2 >= 0 && i2 <= G.nx && j2 >= 0 && j2 <= G.ny && k2 >= 0 && k2 <= G.nz;
+  // the row position and the Dirichlet flags are loaded before the barrier
+  int pos = 0;
+  int64_t m = 0;
+  bool fr[3] = {false, false, false}, fm[3] = {false, false, false};
+  if (live) {
     const int xlo = i > 0 ? -1 : 0, ylo = j > 0 ? -1 : 0, zlo = k > 0 ? -1 : 0;
     const int nxc = (i < G.nx ? 1 : 0) - xlo + 1, nyc = (j < G.ny ? 1 : 0) - ylo + 1;
-    const int pos = rowptr[n] + ((dk - zlo) * nyc + (dj - ylo)) * nxc + (di - xlo);
-    const int64_t m = G.node(i2, j2, k2);
-    double B[9];
-    for (int e = 0; e < 9; ++e) B[e] = 0.0;
-    // cells containing both nodes: ci in {i-1,i} and {i2-1,i2}, inside the grid
-    for (int ck = max(max(k, k2) - 1, 0); ck <= min(min(k, k2), G.nz - 1); ++ck)
-      for (int cj = max(max(j, j2) - 1, 0); cj <= min(min(j, j2), G.ny - 1); ++cj)
-        for (int ci = max(max(i, i2) - 1, 0); ci <= min(min(i, i2), G.nx - 1); ++ci) {
-          const int64_t c = G.cell(ci, cj, ck);
-          const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
-          const int b = (i2 - ci) + 2 * (j2 - cj) + 4 * (k2 - ck);
-          for (int r = 0; r < 3; ++r)
-            for (int s = 0; s < 3; ++s) B[r * 3 + s] += K(3 * a + r, 3 * b + s, c);
-        }
+    pos = rowptr[n] + ((dk - zlo) * nyc + (dj - ylo)) * nxc + (di - xlo);
+    m = G.node(i2, j2, k2);
     for (int r = 0; r < 3; ++r) {
-      const bool fr = ufix[3 * n + r];
+      fr[r] = ufix[3 * n + r];
+      fm[r] = ufix[3 * m + r];
+    }
+  }
+  __syncthreads();
+  double B[9];
+  for (int e = 0; e < 9; ++e) B[e] = 0.0;
+  // cells (i-1+ox, j-1+oy, k-1+oz) that also contain node m, in the same
+  // order (x fastest) as the diagonal kernel; corner of n: 1-o, of m: d+1-o
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+    const double w = live ? cw[ln][o] : 0.0;
+    if (w == 0.0 || ox < di || ox > di + 1 || oy < dj || oy > dj + 1 || oz < dk || oz > dk + 1) continue;
+    const int64_t c = cid[ln][o];
+    const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+    const int b = (di + 1 - ox) + 2 * (dj + 1 - oy) + 4 * (dk + 1 - oz);
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s) B[r * 3 + s] += w * Ke.unit(a, b, r, s, c);
+  }
+  if (live) {
+    for (int r = 0; r < 3; ++r)
       for (int s = 0; s < 3; ++s) {
-        const bool fixed = fr || ufix[3 * m + s];
-        double v = fixed ? 0.0 : B[r * 3 + s];
-        if (m == n && r == s && fr) v = 1.0;
+        double v = (fr[r] || fm[s]) ? 0.0 : B[r * 3 + s];
+        if (m == n && r == s && fr[r]) v = 1.0;
         stage[(pos - base) * 9 + r * 3 + s] = v;
       }
-    }
-    col[pos] = (int)m;
+    if (col) col[pos] = (int)m;
   }
   __syncthreads();
   const int cnt = (end - base) * 9;
@@ -338,7 +374,8 @@ __global__ void __launch_bounds__(256) k_auu_diag(Grid G, KS Ke, const uint8_t* 
       for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
         const int64_t c = G.cell(ci, cj, ck);
         const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
-        for (int r = 0; r < 3; ++r) d[r] += Ke(3 * a + r, 3 * a + r, c);
+        const double w = Ke.scale(c);
+        for (int r = 0; r < 3; ++r) d[r] += w * Ke.unit(a, a, r, r, c);
       }
   for (int r = 0; r < 3; ++r) diag[3 * n + r] = ufix[3 * n + r] ? 1.0 : d[r];
 }
@@ -567,6 +604,15 @@ __global__ void k_rhs_pi(Grid G, const double* __restrict__ Minv, const uint8_t*
 
 }  // namespace
 
+// the element stiffness source of the context (see KeCells / KeLattice)
+template <class F>
+void with_element_source(const pm_ctx* c, F&& f) {
+  if (c->lattice)
+    f(KeLattice{c->lat.Kh, c->E});
+  else
+    f(KeCells{c->Ke, c->nc});
+}
+
 Grid grid_of(const pm_ctx* c) {
   Grid G;
   G.nx = c->nx;
@@ -675,6 +721,7 @@ void assemble_all(pm_ctx* c) {
   }
   PM_CHECK_LAUNCH();
   const int st = check_status(c, "element kernels");
+  if (c->lattice) lattice_unit(c);
   c->mblock = c->opts.block_minv && !(st & kStatusFullMinv);
   k_stab_weights<<<blocks_for(c->nmacro), kBlock, 0, s>>>(G, c->E, c->vol, c->nu, c->biot, c->stabw);
   PM_CHECK_LAUNCH();
@@ -690,12 +737,12 @@ void assemble_all(pm_ctx* c) {
     dfree(cnt);
     c->Auu.nnzb = total;
     c->Auu.col = dalloc<int>(total);
+    c->auu_cols_set = false;
     c->Auu.val = dalloc<double>((int64_t)total * 9);
   }
-  if (c->lattice)
-    k_auu_diag<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->auu_diag);
-  else
-    k_auu_diag<<<blocks_for(G.nn), kBlock, 0, s>>>(G, KeCells{c->Ke, G.nc}, c->ufix, c->auu_diag);
+  with_element_source(c, [&](auto K) {
+    k_auu_diag<<<blocks_for(G.nn), kBlock, 0, s>>>(G, K, c->ufix, c->auu_diag);
+  });
   PM_CHECK_LAUNCH();
 }
 
@@ -716,12 +763,12 @@ void cell_data(pm_ctx* c, double* Mfull) {
 void assemble_auu(pm_ctx* c) {
   const Grid G = grid_of(c);
   hipStream_t s = c->s;
-  if (c->lattice)
-    k_auu_fill<<<(G.nn + kFillNodes - 1) / kFillNodes, kFillThreads, 0, s>>>(
-        G, KeLattice{c->lat.Kh, c->E}, c->ufix, c->Auu.rowptr, c->Auu.col, c->Auu.val);
-  else
-    k_auu_fill<<<(G.nn + kFillNodes - 1) / kFillNodes, kFillThreads, 0, s>>>(
-        G, KeCells{c->Ke, G.nc}, c->ufix, c->Auu.rowptr, c->Auu.col, c->Auu.val);
+  int* col = c->auu_cols_set ? nullptr : c->Auu.col;
+  with_element_source(c, [&](auto K) {
+    k_auu_fill<<<(G.nn + kFillNodes - 1) / kFillNodes, kFillThreads, 0, s>>>(G, K, c->ufix, c->Auu.rowptr, col,
+                                                                           c->Auu.val);
+  });
+  c->auu_cols_set = true;
   PM_CHECK_LAUNCH();
   if (c->lattice) lattice_finish(c);
   pack_minv(c);

@@ -162,6 +162,22 @@ struct AmgParams {
 // cell and every coupling column is ahat, so the finest level is applied from
 // Khat, ahat and E without an assembled matrix.  Dirichlet rows and columns
 // follow u_fixed (identity rows, zero columns).
+// Mirror symmetry of a box cell: reflecting across the mid-plane normal to
+// axis r maps corner a to a ^ (1 << r) and flips the r-th displacement
+// component, so Khat[a][b](r,c) = s_r(a) s_c(a) Khat[0][a^b](r,c) with
+// s_r(a) = -1 when bit r of a is set; with Khat symmetric, Khat[0][d](r,c) =
+// s_r(d) s_c(d) Khat[0][d](c,r).  A table of 48 holds Khat[0][d](r,c) for
+// r <= c at 6d + sym_slot(r,c), in the order (0,0) (1,1) (2,2) (0,1) (0,2)
+// (1,2).
+__host__ __device__ constexpr int sym_slot(int r, int c) {
+  return r == c ? r : ((r < c ? r : c) == 0 ? 2 + (r < c ? c : r) : 5);
+}
+__host__ __device__ constexpr bool sym_negated(int a, int b, int r, int c) {
+  const int d = a ^ b;
+  const bool n = ((a >> r) ^ (a >> c)) & 1;
+  return (r > c && (((d >> r) ^ (d >> c)) & 1)) ? !n : n;
+}
+
 struct LatticeOp {
   bool on = false;
   int kind = 0;               // boundary-condition kind
@@ -281,6 +297,7 @@ struct pm_ctx {
   // MFE block triangular preconditioner, built on first use and kept until
   // the next assembly or change of dt
   bool mfe_valid = false;
+  bool auu_cols_set = false;  // A_uu column indices written (fixed pattern)
   double* mfe_lq = nullptr;    // n_pi absolute row sums of the masked A_qq (1 on no-flow faces)
   double* mfe_dqinv = nullptr; // n_pi inverse diagonal of the masked A_qq
   double mfe_qmax = 0.0;       // Gershgorin bound of lambda_max(D^-1 A_qq)
@@ -318,6 +335,7 @@ inline int64_t node_id(const pm_ctx* c, int i, int j, int k) {
 Grid grid_of(const pm_ctx* c);
 void assemble_all(pm_ctx* c);          // element kernels, masks, A_uu pattern and diagonal
 void assemble_auu(pm_ctx* c);          // A_uu values, FP32 lattice data, packed M^-1 (after assemble_all)
+void lattice_unit(pm_ctx* c);          // box-cell symmetry of Khat (pm_lattice.hip, synchronizes)
 void lattice_finish(pm_ctx* c);        // lattice operator tables after assembly (pm_lattice.hip)
 void cellpi_build(pm_ctx* c, hipStream_t s);          // packed C~_pi element matrices (pm_cellpi.hip)
 void build_cpi(pm_ctx* c, hipStream_t s);  // B~p, assembled C~pi for the current dt (after assemble_all)

@@ -35,21 +35,6 @@ void LatticeOp::free_all() {
   sym = false;
 }
 
-// Mirror symmetry of a box cell: reflecting across the mid-plane normal to
-// axis r maps corner a to a ^ (1 << r) and flips the r-th displacement
-// component, so Khat[a][b](r,c) = s_r(a) s_c(a) Khat[0][a^b](r,c) with
-// s_r(a) = -1 when bit r of a is set; with Khat symmetric, Khat[0][d](r,c) =
-// s_r(d) s_c(d) Khat[0][d](c,r).  ks[6d + q] holds Khat[0][d](r,c) for
-// r <= c in the order (0,0) (1,1) (2,2) (0,1) (0,2) (1,2).
-__host__ __device__ constexpr int sym_slot(int r, int c) {
-  return r == c ? r : ((r < c ? r : c) == 0 ? 2 + (r < c ? c : r) : 5);
-}
-__host__ __device__ constexpr bool sym_negated(int a, int b, int r, int c) {
-  const int d = a ^ b;
-  const bool n = ((a >> r) ^ (a >> c)) & 1;
-  return (r > c && (((d >> r) ^ (d >> c)) & 1)) ? !n : n;
-}
-
 namespace {
 
 __device__ inline bool node_of_thread(const Grid& G, int64_t& n, int& i, int& j, int& k) {
@@ -483,12 +468,10 @@ void lattice_deviation(hipStream_t s, const Grid& G, const double* coords, doubl
   *hmin = h;
 }
 
-// After assembly on a lattice: FP32 copies and the operator description.
-void lattice_finish(pm_ctx* c) {
+// After the unit element matrix is computed: whether the cell is a box (the
+// 48 values rebuild every entry of Khat), and those values (synchronizes).
+void lattice_unit(pm_ctx* c) {
   LatticeOp& op = c->lat;
-  op.kind = c->bc_kind;
-  op.E = c->E;
-  // box cells: take the 48 values and check that they rebuild every entry
   double K[576];
   PM_HIP(hipMemcpyAsync(K, op.Kh, sizeof(K), hipMemcpyDeviceToHost, c->s));
   PM_HIP(hipStreamSynchronize(c->s));
@@ -508,6 +491,13 @@ void lattice_finish(pm_ctx* c) {
         }
   op.sym = sym;
   for (int i = 0; i < 48; ++i) op.ks32[i] = (float)op.ks64[i];
+}
+
+// After assembly on a lattice: FP32 copies and the operator description.
+void lattice_finish(pm_ctx* c) {
+  LatticeOp& op = c->lat;
+  op.kind = c->bc_kind;
+  op.E = c->E;
   if (c->opts.precond_fp32) {
     if (!op.Kh32) op.Kh32 = dalloc<float>(576);
     if (!op.E32) op.E32 = dalloc<float>(c->nc);
