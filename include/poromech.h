@@ -108,7 +108,7 @@ typedef struct {
   int32_t coarse_max;        /* AMG: stop coarsening below this many block rows */
   int32_t cheb_degree_pi;    /* Chebyshev smoother degree, C~_pi hierarchy (>= 1) */
   int32_t cycles_u;          /* V-cycles per application of the A_uu block (>= 1) */
-  int32_t cycles_pi;         /* V-cycles per application of the C~_pi block (>= 1) */
+  int32_t cycles_pi;         /* V-cycles per application of the C~_pi block, and of the MFE C~_p block (>= 1) */
   int32_t orth_passes;       /* classical Gram-Schmidt passes per Arnoldi step: 1 or 2 */
   double theta_u;            /* AMG strength threshold, displacement block */
   double theta_pi;           /* AMG strength threshold, face-pressure Schur block */
@@ -301,17 +301,17 @@ int pm_reconstruct_w(pm_ctx* ctx, const double* p, const double* pi, double* w);
  *                  absolute row sums of A_qq (no-flow faces excluded).  Assembled as a
  *                  7-point CSR held by the context on the first MFE call after pm_assemble
  *                  or pm_set_dt, together with the hierarchy below.
- *   PM_OP_VCYCLE_CP y = one V-cycle for C~_p applied to x (zero initial guess), on the
- *                  context's smoothed-aggregation hierarchy of C~_p (C~_pi settings, FP64),
+ *   PM_OP_VCYCLE_CP y = cycles_pi V-cycles for C~_p applied to x (zero initial guess), on
+ *                  the context's smoothed-aggregation hierarchy of C~_p (C~_pi settings, FP64),
  *                  built once per assembly and dt (the inner C~_p solve of the MFE
  *                  preconditioner).
  *   PM_OP_BTP      y = M^-1 x           (N -> N, order [u; q; p]) the block lower triangular
  *                  preconditioner of the MFE system (Sec. 5, eq. prec, GPU analogue of
- *                  variant M_II^(m)): y_u = one A_uu V-cycle (the pm_assemble hierarchy, FP64
- *                  levels) on x_u; y_q = five Chebyshev-Jacobi sweeps on A_qq y_q = x_q from
- *                  zero (in place of the paper's incomplete Cholesky factor, whose triangular
- *                  solves are sequential); y_p = one C~_p V-cycle on x_p - A_pu y_u -
- *                  dt A_pq y_q. */
+ *                  variant M_II^(m)): y_u = cycles_u A_uu V-cycles (the pm_assemble
+ *                  hierarchy, FP64 levels) on x_u; y_q = five Chebyshev-Jacobi sweeps on
+ *                  A_qq y_q = x_q from zero (in place of the paper's incomplete Cholesky
+ *                  factor, whose triangular solves are sequential); y_p = cycles_pi C~_p
+ *                  V-cycles on x_p - A_pu y_u - dt A_pq y_q. */
 enum { PM_OP_AH = 0, PM_OP_AHT = 1, PM_OP_MINV = 2, PM_OP_MINVT = 3, PM_OP_CPI = 4,
        PM_OP_BP = 5, PM_OP_AUU = 6, PM_OP_VCYCLE_U = 7, PM_OP_VCYCLE_PI = 8, PM_OP_MFE = 9,
        PM_OP_CP = 10, PM_OP_VCYCLE_CP = 11, PM_OP_BTP = 12 };

@@ -143,13 +143,12 @@ pm::AmgParams params_pi(const pm_ctx* c) {
   return p;
 }
 
-// the MFE preconditioner's C~_p hierarchy: the C~_pi settings, FP64 levels,
-// one V-cycle per application, on the caller's stream
+// the MFE preconditioner's C~_p hierarchy: the C~_pi settings (V-cycles per
+// application included), FP64 levels, on the caller's stream
 pm::AmgParams params_cp(const pm_ctx* c) {
   pm::AmgParams p = params_pi(c);
   p.fp32 = false;
   p.side = nullptr;
-  p.cycles = 1;
   return p;
 }
 

@@ -455,9 +455,10 @@ void mfe_prec_setup(pm_ctx* c, const AmgParams& prm) {
 }
 
 // z = M^-1 r for M = [[M_uu, 0, 0], [0, M_qq, 0], [A_pu, dt A_pq, M_Cp]]
-// (eq. prec), order [u; q; p]: z_u = one A_uu V-cycle (FP64 levels) on r_u,
-// z_q = kQqChebDegree Chebyshev-Jacobi sweeps on A_qq z_q = r_q from zero
-// over [qmax/5, qmax], z_p = one C~_p V-cycle on r_p - A_pu z_u - dt A_pq z_q.
+// (eq. prec), order [u; q; p]: z_u = the A_uu V-cycles (cycles_u, FP64
+// levels) on r_u, z_q = kQqChebDegree Chebyshev-Jacobi sweeps on A_qq z_q =
+// r_q from zero over [qmax/5, qmax], z_p = the C~_p V-cycles (cycles_pi) on
+// r_p - A_pu z_u - dt A_pq z_q.
 void apply_btp(pm_ctx* c, const double* r, double* z) {
   const Grid G = grid_of(c);
   hipStream_t s = c->s;
