@@ -426,8 +426,8 @@ def main():
         "amg_levels": [last["levels_u"], last["levels_pi"]],
         "amg_operator_complexity": [round(last["opcx_u"], 3), round(last["opcx_pi"], 3)],
         "roofline": head,
-        "kernels_last_warmup": sorted((_roofline(k, *v) for k, v in totals.items() if v[0] > 0),
-                                      key=lambda e: -e["ms"]),
+        "kernels_last_warmup": sorted(({**_roofline(k, *v), "traffic": _traffic(_capi.PROF_KERNELS[k][0], args.n)}
+                                       for k, v in totals.items() if v[0] > 0), key=lambda e: -e["ms"]),
     }
 
     if not args.no_fp64:
