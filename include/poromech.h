@@ -158,6 +158,10 @@ typedef struct {
   int32_t lattice_uu;        /* 1 if the finest A_uu level runs on the lattice operator */
   int32_t block_minv;        /* 1 if M_T^-1 is stored and applied by direction blocks */
   int32_t ncoarse_u, ncoarse_pi;  /* unknowns of the coarsest level (dense FP64 inverse) of each hierarchy */
+  int32_t lattice_form;      /* unit element matrix the lattice stencils read: 0 no lattice operator;
+                                1 its 576 entries; 2 box cells (mirror symmetry): 48 values in the
+                                FP32 stencils, 576 entries in the FP64 ones; 3 cubic cells (mirror
+                                and axis-permutation symmetry): 12 values in all stencils */
 } pm_info;
 
 /* Default options: rtol 1e-8, restart 100, max_it 1000, FP64, stabilize,

@@ -76,7 +76,8 @@ class pm_info(C.Structure):
                 ("relres_est", C.c_double), ("relres_true", C.c_double),
                 ("t_asm", C.c_double), ("t_setup", C.c_double), ("t_solve", C.c_double),
                 ("opcx_u", C.c_double), ("opcx_pi", C.c_double), ("lattice_uu", C.c_int32),
-                ("block_minv", C.c_int32), ("ncoarse_u", C.c_int32), ("ncoarse_pi", C.c_int32)]
+                ("block_minv", C.c_int32), ("ncoarse_u", C.c_int32), ("ncoarse_pi", C.c_int32),
+                ("lattice_form", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -229,6 +229,7 @@ void setup_hierarchies(pm_ctx* c, bool with_u) {
   c->info.opcx_u = c->Hu.opcx;
   c->info.opcx_pi = c->Hpi.opcx;
   c->info.lattice_uu = c->lattice ? 1 : 0;
+  c->info.lattice_form = !c->lattice ? 0 : c->lat.cube ? 3 : c->lat.sym ? 2 : 1;
   c->info.block_minv = c->mblock ? 1 : 0;
   c->info.ncoarse_u = c->Hu.ncoarse;
   c->info.ncoarse_pi = c->Hpi.ncoarse;

@@ -178,6 +178,21 @@ __host__ __device__ constexpr bool sym_negated(int a, int b, int r, int c) {
   return (r > c && (((d >> r) ^ (d >> c)) & 1)) ? !n : n;
 }
 
+// Cubic cells add the axis permutations: Khat[0][d](r,c) for r <= c takes 12
+// values, by the number of axes in d and whether r and c are among them
+// (cube_slot); where exactly one of r, c is among them the value changes sign
+// with the order of the pair (positive when r, the smaller, is).
+__host__ __device__ constexpr int cube_slot(int d, int r, int c) {
+  return ((d & 1) + ((d >> 1) & 1) + ((d >> 2) & 1)) == 0   ? (r == c ? 0 : 1)
+         : ((d & 1) + ((d >> 1) & 1) + ((d >> 2) & 1)) == 3 ? (r == c ? 10 : 11)
+         : ((d & 1) + ((d >> 1) & 1) + ((d >> 2) & 1)) == 1
+             ? (r == c ? (((d >> r) & 1) ? 2 : 3) : ((((d >> r) | (d >> c)) & 1) ? 4 : 5))
+             : (r == c ? (((d >> r) & 1) ? 6 : 7) : ((((d >> r) & (d >> c)) & 1) ? 8 : 9));
+}
+__host__ __device__ constexpr bool cube_negated(int d, int r, int c) {
+  return (cube_slot(d, r, c) == 4 || cube_slot(d, r, c) == 9) && !((d >> r) & 1);
+}
+
 struct LatticeOp {
   bool on = false;
   int kind = 0;               // boundary-condition kind
@@ -192,6 +207,9 @@ struct LatticeOp {
   bool sym = false;
   double ks64[48] = {};
   float ks32[48] = {};
+  bool cube = false;  // cubic cells: the 12 values kc64/kc32 rebuild Khat
+  double kc64[12] = {};
+  float kc32[12] = {};
   void free_all();
 };
 

@@ -33,6 +33,7 @@ void LatticeOp::free_all() {
   E = nullptr;
   on = false;
   sym = false;
+  cube = false;
 }
 
 namespace {
@@ -75,6 +76,16 @@ struct KSym {
   __device__ __forceinline__ T operator()(int a, int b, int r, int c) const {
     const T v = k[6 * (a ^ b) + sym_slot(r, c)];
     return sym_negated(a, b, r, c) ? -v : v;
+  }
+};
+
+template <class T>
+struct KCube {
+  T k[12];
+  __device__ __forceinline__ T operator()(int a, int b, int r, int c) const {
+    const int d = a ^ b, lo = r < c ? r : c, hi = r < c ? c : r;
+    const T v = k[cube_slot(d, lo, hi)];
+    return (sym_negated(a, b, r, c) != cube_negated(d, lo, hi)) ? -v : v;
   }
 };
 
@@ -374,6 +385,12 @@ void with_bc_kind(int kind, F&& f) {
 // lanes.
 template <class T, class F>
 void with_coeffs(const LatticeOp& op, F&& f) {
+  if (op.cube) {
+    KCube<T> K;
+    memcpy(K.k, std::is_same<T, float>::value ? (const void*)op.kc32 : (const void*)op.kc64, sizeof(K.k));
+    f(K);
+    return;
+  }
   if constexpr (std::is_same<T, float>::value) {
     if (op.sym) {
       KSym<float> K;
@@ -491,6 +508,30 @@ void lattice_unit(pm_ctx* c) {
         }
   op.sym = sym;
   for (int i = 0; i < 48; ++i) op.ks32[i] = (float)op.ks64[i];
+  // cubic cells: one value per slot, from the first entry that has it
+  bool have[12] = {};
+  for (int d = 0; d < 8; ++d)
+    for (int r = 0; r < 3; ++r)
+      for (int q = r; q < 3; ++q) {
+        const int sl = cube_slot(d, r, q);
+        if (!have[sl]) {
+          const double v = K[r * 24 + 3 * d + q];
+          op.kc64[sl] = cube_negated(d, r, q) ? -v : v;
+          have[sl] = true;
+        }
+      }
+  bool cube = sym;
+  for (int a = 0; a < 8 && cube; ++a)
+    for (int b = 0; b < 8; ++b)
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+          const int d = a ^ b, lo = r < q ? r : q, hi = r < q ? q : r;
+          const double v = op.kc64[cube_slot(d, lo, hi)];
+          const double want = (sym_negated(a, b, r, q) != cube_negated(d, lo, hi)) ? -v : v;
+          if (std::fabs(K[(3 * a + r) * 24 + 3 * b + q] - want) > 1e-13 * kmax) cube = false;
+        }
+  op.cube = cube;
+  for (int i = 0; i < 12; ++i) op.kc32[i] = (float)op.kc64[i];
 }
 
 // After assembly on a lattice: FP32 copies and the operator description.

@@ -166,6 +166,7 @@ def test_lattice_operator_matches_assembled_matrix_at_64():
     for lattice in (True, False):
         s = from_problem(prob, Options(rtol=1e-11, restart=50, lattice_uu=lattice)).assemble()
         assert s.info()["lattice_uu"] == int(lattice)
+        assert s.info()["lattice_form"] == (3 if lattice else 0)  # cubic cells: the 12-value form
         g = torch.Generator(device="cpu").manual_seed(5)
         x = torch.randn(s.N, generator=g, dtype=torch.float64).cuda()
         y = s.apply(_capi.PM_OP_AH, x)

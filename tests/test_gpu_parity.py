@@ -45,7 +45,18 @@ CASES = {
     "cantilever_perturbed6x6x4": dict(nx=6, ny=6, nz=4, seed=6, bc="cantilever", perturb=True, dt=1e-5),
     "graded8x6x4": dict(nx=8, ny=6, nz=4, seed=7, graded=True),
     "tiny2x2x2": dict(nx=2, ny=2, nz=2, seed=8),
+    "cube6x6x6": dict(nx=6, ny=6, nz=6, seed=10),
+    "cantilever_cube6x6x6": dict(nx=6, ny=6, nz=6, seed=11, bc="cantilever", dt=1e-5),
 }
+
+
+def _lattice_form(name, lattice):
+    """Unit-matrix form the lattice stencils use: 0 none, 2 box cells (48
+    values in FP32, 576 in FP64), 3 cubic cells (12 values)."""
+    c = CASES[name]
+    if not lattice or c.get("perturb", False) or c.get("graded", False):
+        return 0
+    return 3 if c["nx"] == c["ny"] == c["nz"] else 2
 
 
 def _case(name):
@@ -63,6 +74,7 @@ def test_operator_and_block_parity(name, lattice):
     # uniform boxes take the lattice operator when allowed, perturbed meshes never
     translates = not (CASES[name].get("perturb", False) or CASES[name].get("graded", False))
     assert s.info()["lattice_uu"] == int(lattice and translates)
+    assert s.info()["lattice_form"] == _lattice_form(name, lattice)
     # axis-aligned boxes (diagonal permeability) store M_T^-1 by direction blocks
     assert s.info()["block_minv"] == int(not CASES[name].get("perturb", False))
     rng = np.random.default_rng(7)
@@ -267,7 +279,8 @@ def test_error_codes():
 
 
 @pytest.mark.parametrize("fp32", [False, True])
-@pytest.mark.parametrize("name", ["box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop", "cantilever8x6x4"])
+@pytest.mark.parametrize("name", ["box10x6x4", "perturbed6x8x6", "rollers4x4x8_ptop", "cantilever8x6x4",
+                                  "cube6x6x6", "cantilever_cube6x6x6"])
 def test_matrix_free_finest_levels_match_assembled(name, fp32):
     """The V-cycles with the matrix-free finest levels (A_uu on lattices, C~_pi
     cell by cell, from the full or, on boxes, the direction-block element
