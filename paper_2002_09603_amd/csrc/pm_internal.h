@@ -368,6 +368,8 @@ void build_cp(pm_ctx* c);                                 // C~_p of the MFE pre
 // MFE block triangular preconditioner of eq. prec (pm_mfe.hip): C~_p, its
 // hierarchy (parameters prm) and the Jacobi data of A_qq; then z = M^-1 r
 void mfe_prec_setup(pm_ctx* c, const AmgParams& prm);
+// u-rows of A_H (and of A_M) in FP64: A_uu u + A_up p, Dirichlet rows identity (pm_ops.hip)
+void apply_ah_u(pm_ctx* c, const double* u, const double* p, double* yu);
 void apply_btp(pm_ctx* c, const double* r, double* z);
 void build_rhs_mfe(pm_ctx* c, const double* u_prev, const double* p_prev, double* b);
 constexpr int kQqChebDegree = 5;                          // Chebyshev-Jacobi sweeps of A_qq per application

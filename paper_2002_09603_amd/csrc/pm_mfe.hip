@@ -27,25 +27,6 @@ __device__ __forceinline__ bool q_fixed(const Grid& G, int64_t f) {
   return (cc[0] < 0 || cc[1] < 0) && !pi_fixed(G, f);
 }
 
-// y_u += A_up p on the free displacement dofs (y_u holds A_uu u)
-__global__ void __launch_bounds__(256) k_mfe_up(Grid G, int kind, const double* __restrict__ ae,
-                                                const double* __restrict__ p, double* __restrict__ yu) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= G.nn) return;
-  int i, j, k;
-  G.node_ijk(n, i, j, k);
-  double cp[3] = {0.0, 0.0, 0.0};
-  for (int ck = max(k - 1, 0); ck <= min(k, G.nz - 1); ++ck)
-    for (int cj = max(j - 1, 0); cj <= min(j, G.ny - 1); ++cj)
-      for (int ci = max(i - 1, 0); ci <= min(i, G.nx - 1); ++ci) {
-        const int64_t c = G.cell(ci, cj, ck);
-        const int a = (i - ci) + 2 * (j - cj) + 4 * (k - ck);
-        for (int d = 0; d < 3; ++d) cp[d] += ae[(size_t)(3 * a + d) * G.nc + c] * p[c];
-      }
-  for (int d = 0; d < 3; ++d)
-    if (!u_fixed(G, kind, i, j, k, d)) yu[3 * n + d] += cp[d];
-}
-
 // face rows: y_e = sum_T s_L (sum_h s_h M_T[L][h] q_{F_T[h]} - p_T);  fixed: y_e = q_e
 __global__ void __launch_bounds__(256) k_mfe_q(Grid G, const double* __restrict__ Mq, const double* __restrict__ q,
                                                const double* __restrict__ p, double* __restrict__ yq) {
@@ -526,9 +507,9 @@ void apply_mfe(pm_ctx* c, const double* x, double* y) {
   double* yu = y;
   double* yq = y + c->n_u;
   double* yp = y + c->n_u + nq;
-  apply_csr(c, c->Auu, u, yu);
-  k_mfe_up<<<blocks_for(G.nn), kBlock, 0, c->s>>>(G, c->bc_kind, c->ae, p, yu);
-  PM_CHECK_LAUNCH();
+  // u-rows A_uu u + A_up p: the hybrid operator's kernels (the matrix-free
+  // stencil on lattices, the sliced ELL level 0 otherwise)
+  apply_ah_u(c, u, p, yu);
   k_mfe_q<<<blocks_for(G.nf), kBlock, 0, c->s>>>(G, c->Mq, q, p, yq);
   PM_CHECK_LAUNCH();
   k_mfe_p<<<blocks_for(G.nc), kBlock, 0, c->s>>>(G, c->bc_kind, c->ae, c->vol, c->stabw, u, q, p, c->S, c->dt,

@@ -520,6 +520,22 @@ void ah_launch(pm_ctx* c, const T* x, double* y, bool transpose) {
 
 }  // namespace
 
+// u-rows of A_H in FP64: y_u = A_uu u + A_up p on free rows, y_u = u on
+// Dirichlet rows; the MFE system's u-rows are the same block rows
+void apply_ah_u(pm_ctx* c, const double* u, const double* p, double* yu) {
+  const Grid G = grid_of(c);
+  if (c->lat.on) {
+    lattice_ah_u<double>(c->s, G, c->lat, u, p, 1.0, yu);
+  } else {
+    const Sell& Auu = c->Hu.L[0].As;
+    const int nth = Auu.nslices * kSlice;
+    k_ah_u<double><<<blocks_for(nth), kBlock, 0, c->s>>>(G, Auu.n, Auu.sptr, Auu.perm, Auu.col, Auu.val, c->ae,
+                                                         c->ufix, u, p, 1.0, yu);
+    PM_CHECK_LAUNCH();
+  }
+}
+
+
 void apply_AH(pm_ctx* c, const double* x, double* y, bool transpose) { ah_launch<double>(c, x, y, transpose); }
 
 void apply_AH32(pm_ctx* c, const float* x, double* y, bool transpose) {
