@@ -14,8 +14,8 @@
 // distinct ids (sorted order); either way they go to a scratch array at the
 // row's ub offset, and a compaction copies them into C after a scan of the
 // counts.
-// Numeric: rows are binned by their exact number of distinct columns (<= 16,
-// <= 64: 16 lanes per row; <= 512, more: a wavefront per row).  The entries
+// Numeric: rows are binned by their exact number of distinct columns (<= 16:
+// 4 lanes per row; <= 64: 16 lanes; <= 512, more: a wavefront per row).  The entries
 // of A's row are taken in order; lanes of the group cover the entries of the
 // corresponding B row, whose columns are distinct, so each accumulator slot
 // has one writer per step and the summation order is fixed (bitwise
@@ -300,15 +300,13 @@ __global__ void __launch_bounds__(G* GPB) k_num(int nlist, const int* __restrict
                                                  const int* __restrict__ acol, const double* __restrict__ aval,
                                                  const int* __restrict__ brp, const int* __restrict__ bcol,
                                                  const double* __restrict__ bval, const int* __restrict__ crp,
-                                                 const int* __restrict__ ccol, double* __restrict__ cval,
-                                                 int min_na = 0) {
+                                                 const int* __restrict__ ccol, double* __restrict__ cval) {
   __shared__ int cols_l[GPB][CAP];
   __shared__ double acc_l[GPB][CAP * BS * BS];
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int li = blockIdx.x * GPB + grp;
   if (li >= nlist) return;  // groups never synchronize across rows: per-wave ordering only
   const int row = list[li];
-  if (arp[row + 1] - arp[row] < min_na) return;  // rows handled by k_num_small
   const int c0 = crp[row], u = crp[row + 1] - c0;
   const bool in_lds = u <= CAP;
   const int* cols = in_lds ? (const int*)cols_l[grp] : ccol + c0;
@@ -346,14 +344,16 @@ __global__ void __launch_bounds__(G* GPB) k_num(int nlist, const int* __restrict
     for (int i = lane; i < u * BS * BS; i += G) cval[(size_t)c0 * BS * BS + i] = acc[i];
 }
 
-// Numeric phase for rows with at most CAP <= 64 distinct columns, 16 lanes
-// per row, 4 rows per wavefront (the LDS accumulators are sized by CAP: the
-// rows of the Galerkin products of the block operator mostly have <= 16, and
-// the smaller footprint keeps more wavefronts resident).  Same order of summation as k_num (entries of A in
-// order, lanes over the B row), with the latency of the dependent loads
-// hidden: a prologue stages the B-row extents of every entry of the A row in
-// LDS, and the B-row entries and A block of the next entry are loaded while
-// the current one is accumulated.
+// Numeric phase for rows with at most CAP <= 64 distinct columns, G lanes
+// per row, 64/G rows per wavefront (the LDS accumulators are sized by CAP:
+// the rows of the Galerkin products of the block operator mostly have <= 16,
+// and the smaller footprint keeps more wavefronts resident).  Same order of
+// summation as k_num (entries of A in order, lanes over the B row), with the
+// latency of the dependent loads hidden: the B-row extents of the next AMAX
+// entries of the A row are staged in LDS, and the B-row entries and A block of
+// the next entry are loaded while the current one is accumulated.  G = 4 suits
+// A P_smoothed (prolongator rows of ~4 blocks), G = 16 the restriction
+// R (A P) (rows of A P of ~16 blocks).
 template <int BS>
 __device__ inline int slot_in(const int* __restrict__ cols, int u, int key) {
   int lo = 0, hi = u - 1;
@@ -364,18 +364,18 @@ __device__ inline int slot_in(const int* __restrict__ cols, int u, int key) {
   return lo;
 }
 
-template <int BS, int CAP>
+template <int BS, int CAP, int G>
 __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restrict__ list,
                                                   const int* __restrict__ arp, const int* __restrict__ acol,
                                                   const double* __restrict__ aval, const int* __restrict__ brp,
                                                   const int* __restrict__ bcol, const double* __restrict__ bval,
                                                   const int* __restrict__ crp, const int* __restrict__ ccol,
                                                   double* __restrict__ cval) {
-  constexpr int G = 16, GPB = 4, AMAX = 64, B2 = BS * BS;
+  constexpr int GPB = 64 / G, AMAX = 32, B2 = BS * BS;
   __shared__ int cols_l[GPB][CAP];
   __shared__ double acc_l[GPB][CAP * B2];
-  __shared__ int fb_l[GPB][AMAX + 1];
-  __shared__ int fe_l[GPB][AMAX + 1];
+  __shared__ int fb_l[GPB][AMAX];
+  __shared__ int fe_l[GPB][AMAX];
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int li = blockIdx.x * GPB + grp;
   if (li >= nlist) return;  // groups never synchronize across rows: per-wave ordering only
@@ -384,20 +384,6 @@ __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restri
   const int e0 = arp[row], na = arp[row + 1] - e0;
   for (int i = lane; i < u; i += G) cols_l[grp][i] = ccol[c0 + i];
   for (int i = lane; i < u * B2; i += G) acc_l[grp][i] = 0.0;
-  // rows with more than AMAX entries in A are left to k_num (rare)
-  if (na > AMAX) return;
-  // B-row extents of the row's A entries
-  for (int q = lane; q < na; q += G) {
-    const int k = acol[e0 + q];
-    fb_l[grp][q] = brp[k];
-    fe_l[grp][q] = brp[k + 1];
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  if (na == 0) {
-    for (int i = lane; i < u * B2; i += G) cval[(size_t)c0 * B2 + i] = 0.0;
-    return;
-  }
   // Two register sets alternate (loop unrolled by two): the operands of entry
   // e+1 are loaded, with clamped always-valid indices, before entry e is
   // accumulated, and no register copies tie the loads to the loop back edge.
@@ -406,15 +392,17 @@ __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restri
     bool v;
     double a[B2], b[B2];
   };
+  // entries cb .. cb+nc-1 of the row, their extents staged
+  int cb = 0, nc = 0;
   auto load = [&](int e, Ops& o) {
-    const int ec = min(e, na - 1);
+    const int ec = min(e, nc - 1);
     o.fb = fb_l[grp][ec];
     o.fe = fe_l[grp][ec];
-    o.v = (e < na) && (o.fb + lane < o.fe);
+    o.v = (e < nc) && (o.fb + lane < o.fe);
     const int fs = o.v ? o.fb + lane : 0;
     o.key = bcol[fs];
     for (int q = 0; q < B2; ++q) {
-      o.a[q] = aval[(size_t)(e0 + ec) * B2 + q];
+      o.a[q] = aval[(size_t)(e0 + cb + ec) * B2 + q];
       o.b[q] = bval[(size_t)fs * B2 + q];
     }
   };
@@ -445,32 +433,42 @@ __global__ void __launch_bounds__(64) k_num_small(int nlist, const int* __restri
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   };
-  Ops p0, p1;
-  load(0, p0);
-  for (int e = 0; e < na; e += 2) {
-    load(e + 1, p1);
-    accumulate(p0);
-    if (e + 1 >= na) break;
-    load(e + 2, p0);
-    accumulate(p1);
+  for (cb = 0; cb < na; cb += AMAX) {
+    nc = min(AMAX, na - cb);
+    // B-row extents of this chunk of the row's A entries (the previous
+    // chunk's reads of the staging arrays precede this in wavefront order)
+    for (int q = lane; q < nc; q += G) {
+      const int k = acol[e0 + cb + q];
+      fb_l[grp][q] = brp[k];
+      fe_l[grp][q] = brp[k + 1];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    Ops p0, p1;
+    load(0, p0);
+    for (int e = 0; e < nc; e += 2) {
+      load(e + 1, p1);
+      accumulate(p0);
+      if (e + 1 >= nc) break;
+      load(e + 2, p0);
+      accumulate(p1);
+    }
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
   for (int i = lane; i < u * B2; i += G) cval[(size_t)c0 * B2 + i] = acc_l[grp][i];
 }
 
 // classes by the exact number of distinct columns: <= 16, <= 64, <= 512, more
 template <int BS>
 void numeric_launch(hipStream_t s, const int* counts, const int* lists, int n, const Csr& A, const Csr& B, Csr& C) {
-  auto small = [&](auto cap, int cnt, const int* list) {
-    constexpr int CAP = decltype(cap)::value;
-    if (cnt <= 0) return;
-    k_num_small<BS, CAP><<<(cnt + 3) / 4, 64, 0, s>>>(cnt, list, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
-                                                      C.rowptr, C.col, C.val);
-    // the few rows with more than 64 entries in A
-    k_num<BS, 16, 4, CAP><<<(cnt + 3) / 4, 64, 0, s>>>(cnt, list, A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
-                                                       C.rowptr, C.col, C.val, 65);
-  };
-  small(std::integral_constant<int, 16>{}, counts[0], lists);
-  small(std::integral_constant<int, 64>{}, counts[1], lists + (size_t)n);
+  if (counts[0] > 0)
+    k_num_small<BS, 16, 4><<<(counts[0] + 15) / 16, 64, 0, s>>>(counts[0], lists, A.rowptr, A.col, A.val, B.rowptr,
+                                                               B.col, B.val, C.rowptr, C.col, C.val);
+  if (counts[1] > 0)
+    k_num_small<BS, 64, 16><<<(counts[1] + 3) / 4, 64, 0, s>>>(counts[1], lists + (size_t)n, A.rowptr, A.col,
+                                                               A.val, B.rowptr, B.col, B.val, C.rowptr, C.col,
+                                                               C.val);
   if (counts[2] > 0)
     k_num<BS, 64, 1, 512><<<counts[2], 64, 0, s>>>(counts[2], lists + 2 * (size_t)n, A.rowptr, A.col, A.val,
                                                    B.rowptr, B.col, B.val, C.rowptr, C.col, C.val);
