@@ -852,7 +852,26 @@ __device__ inline void csr_row_lanes(int row, int lane, const int* __restrict__ 
                                      const T* __restrict__ val, const T* __restrict__ x, T acc[BS]) {
   for (int a = 0; a < BS; ++a) acc[a] = 0;
   const int e1 = rp[row + 1];
-  for (int e = rp[row] + lane; e < e1; e += G) {
+  int e = rp[row] + lane;
+  // two entries of the lane per step, both loaded before either is summed
+  // (the same order of summation as one at a time)
+  for (; e + G < e1; e += 2 * G) {
+    const int j0 = col[e], j1 = col[e + G];
+    T v0[BS * BS], v1[BS * BS], x0[BS], x1[BS];
+    for (int q = 0; q < BS * BS; ++q) {
+      v0[q] = val[(size_t)e * BS * BS + q];
+      v1[q] = val[(size_t)(e + G) * BS * BS + q];
+    }
+    for (int q = 0; q < BS; ++q) {
+      x0[q] = x[(size_t)j0 * BS + q];
+      x1[q] = x[(size_t)j1 * BS + q];
+    }
+    for (int a = 0; a < BS; ++a)
+      for (int q = 0; q < BS; ++q) acc[a] += v0[a * BS + q] * x0[q];
+    for (int a = 0; a < BS; ++a)
+      for (int q = 0; q < BS; ++q) acc[a] += v1[a * BS + q] * x1[q];
+  }
+  if (e < e1) {
     const int j = col[e];
     const T* v = val + (size_t)e * BS * BS;
     T xj[BS];
