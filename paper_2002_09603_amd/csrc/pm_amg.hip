@@ -1555,7 +1555,6 @@ void build_rbm_ptent(hipStream_t s, int nb, int nmem, const int* agg, int nagg, 
   k_rbm_ptent<<<blocks_for(nagg), kBlock, 0, s>>>(nagg, aoff, list, pos, paired ? 1 : 0, Pt.rowptr, Pt.col,
                                                    Pt.val, cen);
   PM_CHECK_LAUNCH();
-  PM_HIP(hipStreamSynchronize(s));
   dfree(aoff);
   dfree(list);
 }
@@ -1734,7 +1733,6 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
     k_smooth_p<BS><<<blocks_for(n), kBlock, 0, s>>>(n, agg, filtered ? dinvF : L.dinv, omega, P.rowptr, P.col,
                                                     P.val);
   PM_CHECK_LAUNCH();
-  PM_HIP(hipStreamSynchronize(s));
   Pt.free_all();
   if (prm.p_trunc > 0.0) truncate_p<BS>(s, P, prm.p_trunc, rbm);
   dfree(dinvF);

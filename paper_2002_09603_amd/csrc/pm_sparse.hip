@@ -286,8 +286,12 @@ void scan_impl(hipStream_t s, const T* in, T* out, int64_t n, T* total_host) {
   PM_CHECK_LAUNCH();
   k_scan_add<T><<<blocks_for(std::max<int64_t>(n, 1)), kBlock, 0, s>>>(out, tiles, n, total);
   PM_CHECK_LAUNCH();
-  if (total_host) PM_HIP(hipMemcpyAsync(total_host, total, sizeof(T), hipMemcpyDeviceToHost, s));
-  PM_HIP(hipStreamSynchronize(s));
+  // the temporaries go back to this stream's cache: a later allocation on the
+  // stream is ordered after these kernels, so only a total read back waits
+  if (total_host) {
+    PM_HIP(hipMemcpyAsync(total_host, total, sizeof(T), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+  }
   dfree(tiles);
   dfree(total);
 }
@@ -570,7 +574,6 @@ void csr_transpose(hipStream_t s, const Csr& A, Csr& T) {
       k_tr_sort<1><<<A.m, 64, 0, s>>>(T.rowptr, tsrc, ttmp, A.val, T.col, T.val, A.m);
     PM_CHECK_LAUNCH();
   }
-  PM_HIP(hipStreamSynchronize(s));
   dfree(cnt);
   dfree(tsrc);
   dfree(ttmp);

@@ -637,7 +637,6 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
         k_num_ptent<1, 8><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, ptent_agg,
                                                                         C.rowptr, C.col, C.val);
       PM_CHECK_LAUNCH();
-      PM_HIP(hipStreamSynchronize(s));
       dfree(tmp);
       dfree(cnt);
       return;
@@ -730,7 +729,6 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
       k_num_ptent<1, 8><<<blocks_for((int64_t)n * 8), kBlock, 0, s>>>(n, A.rowptr, A.col, A.val, ptent_agg,
                                                                       C.rowptr, C.col, C.val);
     PM_CHECK_LAUNCH();
-    PM_HIP(hipStreamSynchronize(s));
     for (void* p : {(void*)ub, (void*)counters, (void*)lists, (void*)ub64, (void*)ubofs, (void*)cnt, (void*)tmp})
       dfree(p);
     return;
@@ -745,7 +743,6 @@ void spgemm(hipStream_t s, const Csr& A, const Csr& B, Csr& C, const int* ptent_
     numeric_launch<3>(s, h, lists, n, A, B, C);
   else
     numeric_launch<1>(s, h, lists, n, A, B, C);
-  PM_HIP(hipStreamSynchronize(s));
   for (void* p : {(void*)ub, (void*)counters, (void*)lists, (void*)ub64, (void*)ubofs, (void*)cnt, (void*)tmp})
     dfree(p);
 }
