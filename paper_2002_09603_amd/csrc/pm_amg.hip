@@ -203,11 +203,19 @@ __global__ void __launch_bounds__(256) k_mis_max(int n, const int* __restrict__ 
   if (i < n) {
     if (l == 0) m = Tin[i];
     const int e1 = rp[i + 1];
-    for (int e = rp[i] + l; e < e1; e += G)
-      if (strong[e] == 1) {
-        const uint64_t v = Tin[col[e]];
-        m = v > m ? v : m;
-      }
+    int e = rp[i] + l;
+    // two entries per lane and step, loaded before either is compared
+    for (; e + G < e1; e += 2 * G) {
+      const bool s0 = strong[e] == 1, s1 = strong[e + G] == 1;
+      const int c0 = col[e], c1 = col[e + G];
+      const uint64_t v0 = s0 ? Tin[c0] : 0, v1 = s1 ? Tin[c1] : 0;
+      m = v0 > m ? v0 : m;
+      m = v1 > m ? v1 : m;
+    }
+    if (e < e1 && strong[e] == 1) {
+      const uint64_t v = Tin[col[e]];
+      m = v > m ? v : m;
+    }
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) {

@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
                                                  const int* __restrict__ bcol, const int64_t* __restrict__ ubofs,
                                                  int* __restrict__ tmp, int* __restrict__ cnt,
                                                  int* __restrict__ status) {
-  constexpr int AMAX = 64;  // rows of A up to this long have their pairs spread over the lanes
+  constexpr int AMAX = 64;  // entries of A per chunk: their pairs are spread over the lanes
   __shared__ int tab[GPB][H];
   __shared__ int keys[GPB][KM];
   __shared__ int nk[GPB];
@@ -106,48 +106,15 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
   __shared__ int fb_l[GPB][AMAX];
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int li = blockIdx.x * GPB + grp;
-  const bool valid = li < nlist;
-  const int row = valid ? list[li] : 0;
+  // a group (G <= 64 lanes, within one wavefront) shares LDS only with
+  // itself: the ordering points below are per wavefront, so groups never
+  // synchronize across rows
+  if (li >= nlist) return;
+  const int row = list[li];
   for (int q = lane; q < H; q += G) tab[grp][q] = -1;
   if (lane == 0) nk[grp] = 0;
-  const int e0 = valid ? arp[row] : 0;
-  const int na = valid ? arp[row + 1] - e0 : 0;
-  const bool staged = valid && na <= AMAX;
-  // B-row extents and their prefix sums: each lane takes AMAX/G consecutive
-  // entries, sums them, and the lane sums are scanned with shuffles
-  {
-    constexpr int CH = AMAX / G;
-    int len[CH], run = 0;
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int q = lane * CH + u;
-      len[u] = 0;
-      if (staged && q < na) {
-        const int k = acol[e0 + q];
-        const int b0 = brp[k];
-        fb_l[grp][q] = b0;
-        len[u] = brp[k + 1] - b0;
-      }
-      run += len[u];
-    }
-    int incl = run;  // inclusive scan of the lane sums within the group
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) {
-      const int v = __shfl_up(incl, o, G);
-      if (lane >= o) incl += v;
-    }
-    int acc = incl - run;
-    if (staged) {
-      if (lane == 0) pre_l[grp][0] = 0;
-#pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        const int q = lane * CH + u;
-        acc += len[u];
-        if (q < na) pre_l[grp][q + 1] = acc;
-      }
-    }
-  }
-  __syncthreads();
+  const int e0 = arp[row];
+  const int na = arp[row + 1] - e0;
   auto insert = [&](int key) {
     int h = hslot<H>(key);
     for (int probe = 0; probe < H; ++probe) {
@@ -162,26 +129,62 @@ __global__ void __launch_bounds__(G* GPB) k_sym(int nlist, const int* __restrict
     }
     atomicAdd(&nk[grp], KM + 1);
   };
-  if (staged) {
-    // the (entry of A, entry of its B row) pairs of the row, spread over the lanes
+  // the row's entries of A in chunks of AMAX (the set of distinct keys does
+  // not depend on the order of insertion)
+  for (int cb = 0; cb < na; cb += AMAX) {
+    const int nc = min(AMAX, na - cb);
+    // B-row extents of the chunk and their prefix sums: each lane takes
+    // AMAX/G consecutive entries, sums them, and the lane sums are scanned
+    // with shuffles
+    {
+      constexpr int CH = AMAX / G;
+      int len[CH], run = 0;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int q = lane * CH + u;
+        len[u] = 0;
+        if (q < nc) {
+          const int k = acol[e0 + cb + q];
+          const int b0 = brp[k];
+          fb_l[grp][q] = b0;
+          len[u] = brp[k + 1] - b0;
+        }
+        run += len[u];
+      }
+      int incl = run;  // inclusive scan of the lane sums within the group
+#pragma unroll
+      for (int o = 1; o < G; o <<= 1) {
+        const int v = __shfl_up(incl, o, G);
+        if (lane >= o) incl += v;
+      }
+      int acc = incl - run;
+      if (lane == 0) pre_l[grp][0] = 0;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int q = lane * CH + u;
+        acc += len[u];
+        if (q < nc) pre_l[grp][q + 1] = acc;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    // the (entry of A, entry of its B row) pairs of the chunk, spread over the lanes
     const int* pre = pre_l[grp];
-    const int tot = pre[na];
+    const int tot = pre[nc];
     for (int pq = lane; pq < tot; pq += G) {
-      int lo = 0, hi = na - 1;  // largest e with pre[e] <= pq
+      int lo = 0, hi = nc - 1;  // largest e with pre[e] <= pq
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (pre[mid] <= pq) lo = mid; else hi = mid - 1;
       }
       insert(bcol[fb_l[grp][lo] + (pq - pre[lo])]);
     }
-  } else if (valid) {
-    for (int e = e0; e < e0 + na; ++e) {
-      const int k = acol[e];
-      for (int f = brp[k] + lane; f < brp[k + 1]; f += G) insert(bcol[f]);
-    }
+    // every lane's reads of the staging arrays precede the next chunk's writes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();
-  if (!valid) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
   const int u = nk[grp];
   if (u > KM) {
     if (lane == 0) {
