@@ -711,20 +711,22 @@ __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ pa
   if (threadIdx.x == 0) *out = sh[0];
 }
 
-__global__ void k_rand_vec(int64_t n, double* __restrict__ x, uint32_t salt) {
+template <class T>
+__global__ void k_rand_vec(int64_t n, T* __restrict__ x, uint32_t salt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = (double)(mix32((uint32_t)i ^ salt) & 0xFFFFFF) / 16777216.0 + 0.5;
+  if (i < n) x[i] = (T)((double)(mix32((uint32_t)i ^ salt) & 0xFFFFFF) / 16777216.0 + 0.5);
 }
 
 // One power-iteration step after the operator product w = A v: nsq = the sum
 // of the previous step's partial sums (in k_sum_final's order), v = D^-1 w /
 // sqrt(nsq), and this step's partial sums of v^2 (in k_sumsq_part's order,
 // so with kRedBlocks workgroups the iterates equal those of the separate
-// kernels bit for bit).
-template <int BS>
-__global__ void __launch_bounds__(256) k_power_step(int64_t n, const double* __restrict__ dinv,
-                                                    const double* __restrict__ w, const double* __restrict__ part_in,
-                                                    double* __restrict__ v, double* __restrict__ part_out) {
+// kernels bit for bit).  TV: the iterates (double, or float on the FP32
+// operators), TD: the block-diagonal inverse; products and sums in FP64.
+template <int BS, class TV, class TD>
+__global__ void __launch_bounds__(256) k_power_step(int64_t n, const TD* __restrict__ dinv,
+                                                    const TV* __restrict__ w, const double* __restrict__ part_in,
+                                                    TV* __restrict__ v, double* __restrict__ part_out) {
   __shared__ double sh[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < kRedBlocks; i += 256) s += part_in[i];
@@ -741,12 +743,12 @@ __global__ void __launch_bounds__(256) k_power_step(int64_t n, const double* __r
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const int64_t node = i / BS;
     const int a = (int)(i - node * BS);
-    const double* D = dinv + (size_t)node * BS * BS + a * BS;
+    const TD* D = dinv + (size_t)node * BS * BS + a * BS;
     double t = 0.0;
-    for (int b = 0; b < BS; ++b) t += D[b] * w[(size_t)node * BS + b];
-    const double x = t * scale;
+    for (int b = 0; b < BS; ++b) t += (double)D[b] * (double)w[(size_t)node * BS + b];
+    const TV x = (TV)(t * scale);
     v[i] = x;
-    acc += x * x;
+    acc += (double)x * (double)x;
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -1166,19 +1168,23 @@ struct PowerJob {
   ~PowerJob() { release(); }
 };
 
-template <class F>
-void power_launch(hipStream_t s, const PowerJob& j, int64_t nb, int bs, const double* dinv, int its, F spmv) {
+// the job's vectors hold n doubles, or n floats when the iteration runs on
+// the FP32 copies of the operator (TV = float)
+template <class TV, class TD, class F>
+void power_launch(hipStream_t s, const PowerJob& j, int64_t nb, int bs, const TD* dinv, int its, F spmv) {
   const int64_t n = nb * bs;
   double *part = j.pbuf, *part2 = j.pbuf + kRedBlocks;
-  k_rand_vec<<<blocks_for(n), kBlock, 0, s>>>(n, j.v, 0x9e3779b9u);
+  TV* v = reinterpret_cast<TV*>(j.v);
+  TV* w = reinterpret_cast<TV*>(j.w);
+  k_rand_vec<TV><<<blocks_for(n), kBlock, 0, s>>>(n, v, 0x9e3779b9u);
   // ||v|| stays on the device: lambda ~ ||D^-1 A v|| / ||v|| with v normalised
-  k_sumsq_part<double><<<kRedBlocks, 256, 0, s>>>(j.v, n, part);
+  k_sumsq_part<TV><<<kRedBlocks, 256, 0, s>>>(v, n, part);
   for (int k = 0; k < its; ++k) {
-    spmv(s, j.v, j.w);
+    spmv(s, v, w);
     if (bs == 3)
-      k_power_step<3><<<kRedBlocks, 256, 0, s>>>(n, dinv, j.w, part, j.v, part2);
+      k_power_step<3, TV, TD><<<kRedBlocks, 256, 0, s>>>(n, dinv, w, part, v, part2);
     else
-      k_power_step<1><<<kRedBlocks, 256, 0, s>>>(n, dinv, j.w, part, j.v, part2);
+      k_power_step<1, TV, TD><<<kRedBlocks, 256, 0, s>>>(n, dinv, w, part, v, part2);
     std::swap(part, part2);
   }
   k_sum_final<<<1, 256, 0, s>>>(part, kRedBlocks, j.nsq);
@@ -1192,11 +1198,11 @@ void power_alloc(PowerJob& j, int64_t n) {
   j.nsq = dalloc<double>(1);
 }
 
-template <class F>
-double power_lmax(hipStream_t s, int64_t nb, int bs, const double* dinv, int its, F spmv) {
+template <class TV = double, class TD = double, class F>
+double power_lmax(hipStream_t s, int64_t nb, int bs, const TD* dinv, int its, F spmv) {
   PowerJob j;
   power_alloc(j, nb * bs);
-  power_launch(s, j, nb, bs, dinv, its, spmv);
+  power_launch<TV>(s, j, nb, bs, dinv, its, spmv);
   double h = 0.0;
   PM_HIP(hipMemcpyAsync(&h, j.nsq, sizeof(double), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
@@ -1204,8 +1210,8 @@ double power_lmax(hipStream_t s, int64_t nb, int bs, const double* dinv, int its
 }
 
 // the same on stream s2, after the work queued so far on s
-template <class F>
-void power_start(PowerJob& j, hipStream_t s, hipStream_t s2, int64_t nb, int bs, const double* dinv, int its,
+template <class TV = double, class TD = double, class F>
+void power_start(PowerJob& j, hipStream_t s, hipStream_t s2, int64_t nb, int bs, const TD* dinv, int its,
                  F spmv) {
   j.release();
   power_alloc(j, nb * bs);
@@ -1214,7 +1220,7 @@ void power_start(PowerJob& j, hipStream_t s, hipStream_t s2, int64_t nb, int bs,
   PM_HIP(hipEventCreateWithFlags(&j.done, hipEventDisableTiming));
   PM_HIP(hipEventRecord(j.ready, s));
   PM_HIP(hipStreamWaitEvent(s2, j.ready, 0));
-  power_launch(s2, j, nb, bs, dinv, its, spmv);
+  power_launch<TV>(s2, j, nb, bs, dinv, its, spmv);
   PM_HIP(hipEventRecord(j.done, s2));
 }
 
@@ -1242,6 +1248,18 @@ struct CsrSpmv {
       residual_csr<3, double, false>(ss, A, lanes, A.val, nullptr, v, w);
     else
       residual_csr<1, double, false>(ss, A, lanes, A.val, nullptr, v, w);
+  }
+};
+
+// the same on the FP32 copy of the values (A.val32)
+struct CsrSpmv32 {
+  const Csr& A;
+  int lanes;
+  void operator()(hipStream_t ss, const float* v, float* w) const {
+    if (A.bs == 3)
+      residual_csr<3, float, false>(ss, A, lanes, A.val32, nullptr, v, w);
+    else
+      residual_csr<1, float, false>(ss, A, lanes, A.val32, nullptr, v, w);
   }
 };
 
@@ -1717,13 +1735,25 @@ void build_level_transfer(hipStream_t s, Level& L, const AmgParams& prm, Csr& Ac
     block_diag_inverse(s, AF, dinvF);
     // smoothed prolongator P = (I - 4/(3 lmax) D_F^-1 A_F) P_tent on the pattern of A_F P_tent;
     // lambda_max(D_F^-1 A_F) on the side stream, if any, during the product
+    // (in mixed precision on an FP32 copy of A_F, as the V-cycles apply theirs)
+    const int lanesF = csr_lanes_for(AF);
+    if (prm.fp32) {
+      const int64_t nv = AF.nnzb * BS * BS;
+      AF.val32 = dalloc<float>(nv);
+      k_to_float<<<blocks_for(nv), kBlock, 0, s>>>(nv, AF.val, AF.val32);
+      PM_CHECK_LAUNCH();
+    }
     if (prm.side) {
       PowerJob jf;
-      power_start(jf, s, prm.side, n, BS, dinvF, prm.power_its, CsrSpmv{AF, csr_lanes_for(AF)});
+      if (prm.fp32)
+        power_start<float>(jf, s, prm.side, n, BS, dinvF, prm.power_its, CsrSpmv32{AF, lanesF});
+      else
+        power_start(jf, s, prm.side, n, BS, dinvF, prm.power_its, CsrSpmv{AF, lanesF});
       spgemm(s, AF, Pt, P, pt_agg);
       lF = power_finish(jf);
     } else {
-      lF = estimate_lmax_csr(s, AF, dinvF, prm.power_its);
+      lF = prm.fp32 ? power_lmax<float>(s, n, BS, dinvF, prm.power_its, CsrSpmv32{AF, lanesF})
+                    : estimate_lmax_csr(s, AF, dinvF, prm.power_its);
       spgemm(s, AF, Pt, P, pt_agg);
     }
   } else {
@@ -1996,9 +2026,22 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
       PM_CHECK_LAUNCH();
     }
     // the finest level's lambda_max runs on the side stream, if any, during
-    // the aggregation (the transfer takes it when it needs it)
+    // the aggregation (the transfer takes it when it needs it).  In mixed
+    // precision every level's iteration runs on the FP32 operator and D^-1
+    // that its V-cycle applies.
     PowerJob job;
-    if (on_lattice) {
+    if (on_lattice && prm.fp32) {
+      auto op = [&](hipStream_t ss, const float* v, float* w) {
+        if (H.lat)
+          lattice_apply(ss, H.grid, *H.lat, v, w);
+        else
+          cellpi_apply(ss, H.grid, *H.cpi, v, w);
+      };
+      if (prm.side)
+        power_start<float>(job, s, prm.side, L.n, L.bs, L.dinv32, prm.power_its, op);
+      else
+        L.lmax = power_lmax<float>(s, L.n, L.bs, L.dinv32, prm.power_its, op);
+    } else if (on_lattice) {
       auto op = [&](hipStream_t ss, const double* v, double* w) {
         if (H.lat)
           lattice_apply(ss, H.grid, *H.lat, v, w);
@@ -2009,6 +2052,12 @@ void amg_setup(hipStream_t s, const Csr& A0, const AmgParams& prm, Hierarchy& H,
         power_start(job, s, prm.side, L.n, L.bs, L.dinv, prm.power_its, op);
       else
         L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, op);
+    } else if (L.csr_cycle && prm.fp32) {
+      L.lmax = power_lmax<float>(s, L.n, L.bs, L.dinv32, prm.power_its, CsrSpmv32{L.A, L.csr_lanes});
+    } else if (prm.fp32) {
+      const Sell& As = L.As;
+      L.lmax = power_lmax<float>(s, L.n, L.bs, L.dinv32, prm.power_its,
+                                 [&](hipStream_t ss, const float* v, float* w) { sell_spmv32(ss, As, v, w); });
     } else if (L.csr_cycle) {
       const Csr& A = L.A;
       L.lmax = power_lmax(s, L.n, L.bs, L.dinv, prm.power_its, [&](hipStream_t ss, const double* v, double* w) {

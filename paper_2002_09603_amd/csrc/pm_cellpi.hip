@@ -149,13 +149,13 @@ __global__ void __launch_bounds__(256) k_cp_residual(Grid G, const T* __restrict
                      [&](uint32_t f, bool fixed, T acc) { r[f] = b[f] - (fixed ? x[f] : acc); });
 }
 
-template <bool BLOCK>
-__global__ void __launch_bounds__(256) k_cp_apply(Grid G, const double* __restrict__ C,
-                                                  const double* __restrict__ x, double* __restrict__ y) {
+template <class T, bool BLOCK>
+__global__ void __launch_bounds__(256) k_cp_apply(Grid G, const T* __restrict__ C, const T* __restrict__ x,
+                                                  T* __restrict__ y) {
   uint32_t i, j, k;
   if (!cell_of_thread(G, i, j, k)) return;
-  owned_face_rows<double>(G, i, j, k, CpiTermOf<double, BLOCK>{G, C, x},
-                          [&](uint32_t f, bool fixed, double acc) { y[f] = fixed ? x[f] : acc; });
+  owned_face_rows<T>(G, i, j, k, CpiTermOf<T, BLOCK>{G, C, x},
+                     [&](uint32_t f, bool fixed, T acc) { y[f] = fixed ? x[f] : acc; });
 }
 
 template <class T>
@@ -220,12 +220,19 @@ template void cellpi_residual<double>(hipStream_t, const Grid&, const CellPiOp&,
 template void cellpi_residual<float>(hipStream_t, const Grid&, const CellPiOp&, const float*, const float*,
                                      float*);
 
-void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const double* x, double* y) {
+template <class T>
+void cellpi_apply_t(hipStream_t s, const Grid& G, const CellPiOp& op, const T* x, T* y) {
   if (op.block)
-    k_cp_apply<true><<<blocks_for(G.nc), kBlock, 0, s>>>(G, op.C, x, y);
+    k_cp_apply<T, true><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), x, y);
   else
-    k_cp_apply<false><<<blocks_for(G.nc), kBlock, 0, s>>>(G, op.C, x, y);
+    k_cp_apply<T, false><<<blocks_for(G.nc), kBlock, 0, s>>>(G, cp_C<T>(op), x, y);
   PM_CHECK_LAUNCH();
+}
+void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const double* x, double* y) {
+  cellpi_apply_t<double>(s, G, op, x, y);
+}
+void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const float* x, float* y) {
+  cellpi_apply_t<float>(s, G, op, x, y);
 }
 
 }  // namespace pm

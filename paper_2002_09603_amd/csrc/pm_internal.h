@@ -221,6 +221,7 @@ void lattice_cheb_step(hipStream_t s, const Grid& G, const LatticeOp& op, const 
 template <class T>
 void lattice_residual(hipStream_t s, const Grid& G, const LatticeOp& op, const T* b, const T* x, T* r);
 void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y);
+void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const float* x, float* y);  // E32, FP32 unit matrix
 // u-rows of A_H: y_u = A_uu u + sgn A_up p (free rows), y_u = u (Dirichlet rows);
 // FP64 arithmetic, FP64 or FP32 inputs
 template <class TX>
@@ -250,6 +251,7 @@ void cellpi_cheb_step(hipStream_t s, const Grid& G, const CellPiOp& op, const T*
 template <class T>
 void cellpi_residual(hipStream_t s, const Grid& G, const CellPiOp& op, const T* b, const T* x, T* r);
 void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const double* x, double* y);
+void cellpi_apply(hipStream_t s, const Grid& G, const CellPiOp& op, const float* x, float* y);  // C32
 
 struct Hierarchy {
   int bs = 1;

@@ -270,15 +270,14 @@ __global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_residual(Grid G, cons
   for (int a = 0; a < 3; ++a) r[3 * n + a] = b[3 * n + a] - ax[a];
 }
 
-template <int KIND, class KS>
-__global__ void __launch_bounds__(256, kLatWaves<double>) k_lat_apply(Grid G, const KS Kh,
-                                                   const double* __restrict__ E, const double* __restrict__ x,
-                                                   double* __restrict__ y) {
+template <class T, int KIND, class KS>
+__global__ void __launch_bounds__(256, kLatWaves<T>) k_lat_apply(Grid G, const KS Kh, const T* __restrict__ E,
+                                                              const T* __restrict__ x, T* __restrict__ y) {
   int64_t n;
   int i, j, k;
   if (!node_of_thread(G, n, i, j, k)) return;
-  double ax[3];
-  lattice_Ax<double, KS>(G, KIND, Kh, E, x, n, i, j, k, ax);
+  T ax[3];
+  lattice_Ax<T, KS>(G, KIND, Kh, E, x, n, i, j, k, ax);
 #pragma unroll
   for (int a = 0; a < 3; ++a) y[3 * n + a] = ax[a];
 }
@@ -435,13 +434,21 @@ template void lattice_residual<double>(hipStream_t, const Grid&, const LatticeOp
 template void lattice_residual<float>(hipStream_t, const Grid&, const LatticeOp&, const float*, const float*,
                                       float*);
 
-void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y) {
+template <class T>
+void lattice_apply_t(hipStream_t s, const Grid& G, const LatticeOp& op, const T* x, T* y) {
   with_bc_kind(op.kind, [&](auto kd) {
-    with_coeffs<double>(op, [&](auto K) {
-      k_lat_apply<decltype(kd)::value, decltype(K)><<<blocks_for(G.nn), kBlock, 0, s>>>(G, K, op.E, x, y);
+    with_coeffs<T>(op, [&](auto K) {
+      k_lat_apply<T, decltype(kd)::value, decltype(K)><<<blocks_for(G.nn), kBlock, 0, s>>>(G, K, lat_E<T>(op), x,
+                                                                                           y);
     });
   });
   PM_CHECK_LAUNCH();
+}
+void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const double* x, double* y) {
+  lattice_apply_t<double>(s, G, op, x, y);
+}
+void lattice_apply(hipStream_t s, const Grid& G, const LatticeOp& op, const float* x, float* y) {
+  lattice_apply_t<float>(s, G, op, x, y);
 }
 
 template <class TX>

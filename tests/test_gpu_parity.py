@@ -308,7 +308,10 @@ def test_block_minv_matches_full(name):
     cell, the rounding-level rest left out of the operator applications)
     gives the operators of the full 6x6 form to FP64 rounding, the same AMG
     hierarchies (built from the full matrices either way), hence the same
-    V-cycles to rounding, and the solved fields to the solver tolerance."""
+    V-cycles to rounding, and the solved fields to the solver tolerance.  With
+    the FP32 preconditioner the power iterations for lambda_max run on each
+    form's FP32 cell operator, so the smoothers' intervals, and with them the
+    C~_pi V-cycles, agree to FP32 rounding."""
     prob = _case(name)
     print(f"[block M^-1] {name}", flush=True)
     rng = np.random.default_rng(5)
@@ -332,7 +335,7 @@ def test_block_minv_matches_full(name):
         a, b = out[True, fp32], out[False, fp32]
         for k in range(3):
             assert rel(a[k], b[k]) <= 1e-14
-        assert rel(a[3], b[3]) <= 1e-12
+        assert rel(a[3], b[3]) <= (1e-6 if fp32 else 1e-12)
         assert rel(a[4], b[4]) <= (1e-5 if fp32 else 1e-12)
         for k in range(5, 8):
             assert rel(a[k], b[k]) <= 1e-9
