@@ -101,7 +101,8 @@ typedef struct {
   double rtol;               /* FGMRES stop: ||b - A x||_2 <= rtol ||b||_2 */
   int32_t restart;           /* FGMRES restart length m (>= 1) */
   int32_t max_it;            /* iteration cap */
-  int32_t precond_fp32;      /* 1: AMG hierarchies, V-cycles and Schur apply in FP32 */
+  int32_t precond_fp32;      /* 1: AMG hierarchies, V-cycles and Schur apply in FP32 (the set-up's
+                                lambda_max power iterations on those FP32 operators) */
   int32_t stabilize;         /* 1: add the macro-element pressure-jump term */
   int32_t increment_stab;    /* 1: stabilization acts on p_n - p_{n-1} (RHS term A_stab p_{n-1}) */
   int32_t cheb_degree;       /* Chebyshev smoother degree per pre/post smoothing, A_uu (>= 1) */
