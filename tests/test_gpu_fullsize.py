@@ -67,6 +67,25 @@ def test_sampled_rows_and_residual_at_full_size(name, n, S, opts):
     s.close()
 
 
+def test_mixed_precision_matches_fp64_preconditioner_at_128():
+    """The layered 128^3 step with the benchmark's options: the FP32
+    preconditioner inside FP64 FGMRES reaches the fields of the FP64
+    preconditioner's solve of the same system to 1e-8 relative (L2) per field
+    (both to relative residual 1e-8)."""
+    prob = make_config("layered128")
+    print(f"[mixed vs fp64] layered128 N={prob.n_total}", flush=True)
+    fields = {}
+    for fp32 in (True, False):
+        s = from_problem(prob, Options(**dict(BENCH_OPTS, precond_fp32=fp32))).assemble()
+        u, pi, p, info = s.solve(s.build_rhs())
+        print("   fp32" if fp32 else "   fp64", {k: info[k] for k in ("iters", "relres_true")}, flush=True)
+        assert info["converged"] and info["relres_true"] <= BENCH_OPTS["rtol"]
+        fields[fp32] = [f.cpu().numpy() for f in (u, p, pi)]
+        s.close()
+    for a, b in zip(fields[True], fields[False]):
+        assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
+
+
 FULL_CASES = [("cube64", 0.0), ("cube64", 1e-4), ("perturbed96", 0.0)]
 
 
